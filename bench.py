@@ -1,0 +1,198 @@
+"""Throughput of the HIP renewal tau-leap step on one MI355X.
+
+Workload: a seeded random 10-regular graph with N = 1e6 (configuration model
+with double-edge-swap repair), SEIR with log-normal E (mu = ln 3, sigma = 0.5)
+and I (mu = ln 5, sigma = 0.6) holding times, beta = 0.06 per edge per day,
+dt = 0.1 d, 100 initially exposed nodes, FP32 storage, one replica, a
+captured hipGraph of 50 steps per replay.  A step is one fused launch over
+all N nodes; the timed region is K steps of the trajectory from the seeded
+start (K = 500 by default: the whole 50-day run), inputs resident in HBM.
+
+Prints one JSON line: GNUPS (node-updates per second / 1e9), the roofline
+record of the step kernel (algorithmic bytes per launch over the measured
+per-launch time against the 8 TB/s HBM peak) and the single-core FP64 oracle
+timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import glob
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GNUPS & % HBM roofline; batched-serving scenarios/s + p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "regular10_n1e6"
+STEPS_PER_GRAPH = 50
+
+
+def bytes_per_update(d_mean: float, storage: str) -> float:
+    """Algorithmic bytes per node-update: every per-node array moved once per
+    step (state r/w, age r/w, row_ptr, next infectivity write, one unique
+    infectivity read) plus the col_ind stream of the row (4 B per edge).
+    FP32 storage: 28 + 4 d; compact: 14 + 4 d."""
+    return (28.0 if storage == "fp32" else 14.0) + 4.0 * d_mean
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2604_22092_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(os.path.basename(p).encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    p = os.path.join(ROOT, "profiles", f"step_kernel_{workload}_counters.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(rp, ci, model, seeds, budget_s: float):
+    """The FP64 oracle (single thread) on the first steps of the same run."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+
+    n = len(rp) - 1
+    st = W.initial_state(n, seeds)
+    age = np.zeros(n, np.float32)
+    oracle.run((rp, ci), model, st, age, 1)  # load + first touch
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        st, age, _ = oracle.run((rp, ci), model, st, age, 5, step0=1 + steps)
+        steps += 5
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {"value": n * steps / el / 1e9, "unit": "GNUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} steps (steps 1..{steps}) of the same N=1e6 trajectory, "
+                      f"single-threaded FP64 oracle, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of oracle time for the CPU baseline (0 = skip)")
+    ap.add_argument("--variant", choices=["auto", "stream", "resident"], default="auto",
+                    help="step kernel variant (auto: LDS-resident bitmap when N*R <= 2^20)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
+              "(replicas and scenarios shard across GPUs without exchange; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2604_22092_amd as fs
+    import workloads as W
+
+    fs.lib()  # fail loudly without the HIP library
+    wl = W.WORKLOADS[WORKLOAD]
+    model = wl["model"]
+    t0 = time.perf_counter()
+    rp, ci = W.workload_graph(wl["graph"])
+    n = len(rp) - 1
+    seeds = W.seed_nodes(n, wl["seeds"], wl["seed_rng"])
+    print(f"[bench] graph {WORKLOAD}: N={n} E={len(ci)} built in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(device=dev)
+    g = fs.Graph(rp, ci)
+    variant = {"auto": fs.VARIANT_AUTO, "stream": fs.VARIANT_STREAM,
+               "resident": fs.VARIANT_RESIDENT}[args.variant]
+    sim = fs.Sim.from_model(g, model, steps_per_graph=STEPS_PER_GRAPH, stream=stream.cuda_stream,
+                            variant=variant)
+    init_state = W.initial_state(n, seeds)
+    init_age = np.zeros(n, np.float32)
+
+    # warm-up (graph instantiation, clocks), then restart the trajectory
+    sim.set_state(init_state, init_age, 0, step_index=0)
+    sim.step(args.warmup)
+    sim.sync()
+    sim.set_state(init_state, init_age, 0, step_index=0)
+    torch.cuda.synchronize()
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = e0.elapsed_time(e1)
+    hist = sim.history(0, args.steps)
+    assert np.all(hist.sum(1) == n)
+    final = sim.counts(0)
+    sim.close()
+    g.close()
+
+    sec = ms / 1e3
+    gnups = n * args.steps / sec / 1e9
+    d_mean = len(ci) / n
+    b_alg = bytes_per_update(d_mean, "fp32")
+    per_launch_s = sec / args.steps
+    achieved = b_alg * n / per_launch_s / 1e9
+    traffic = measured_traffic(WORKLOAD)
+    s_frac = float(hist[:, 0].mean() / n)
+    print(f"[bench] {args.steps} steps: {ms:.3f} ms (wall {wall * 1e3:.1f} ms), {gnups:.2f} GNUPS, "
+          f"final counts {final.tolist()}, mean S fraction {s_frac:.3f}", file=sys.stderr, flush=True)
+
+    cpu = None
+    if args.cpu_budget > 0:
+        cpu = cpu_baseline(rp, ci, model, seeds, args.cpu_budget)
+        print(f"[bench] cpu baseline {cpu['value'] * 1e3:.1f} MNUPS", file=sys.stderr, flush=True)
+
+    rec = {
+        "metric": METRIC,
+        "value": round(gnups, 4),
+        "unit": "GNUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "graph": "random 10-regular, N=1e6, seed 1",
+                   "laws": "E~LN(ln3,0.5), I~LN(ln5,0.6)", "beta": 0.06, "dt": 0.1,
+                   "seeds": wl["seeds"], "replicas": 1, "storage": "fp32",
+                   "steps_per_graph": STEPS_PER_GRAPH, "kernel_variant": args.variant,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "bytes_per_update": b_alg,
+                     "per_launch_us": round(per_launch_s * 1e6, 3)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

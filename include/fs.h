@@ -1,0 +1,246 @@
+/*
+ * fs.h - C ABI of the MI355X (gfx950) renewal tau-leap SEIR step.
+ *
+ * The library runs the per-step renewal tau-leaping update of FlashSpread
+ * (arXiv 2604.22092): the problem statement of Section "Problem formulation"
+ * (graph G = (V, E, W), state (X, tau), Eq. (general_rate), Eq. (influence)),
+ * one step per Algorithm 3 ("per-call replay of b fused steps"), the stable
+ * log-normal hazard of Proposition 1, the Bernoulli tau-leap rule of Section
+ * "Bernoulli tau-leaping" and the source-node infectivity of Eq. (infectivity)
+ * with constant shedding s = 1.
+ *
+ * Conventions for every call:
+ *  - All pointers in signatures are HOST pointers unless stated otherwise;
+ *    the library copies what it needs before returning and never keeps a
+ *    caller pointer.
+ *  - Every call returns an fs_status.  No C++ exception crosses the ABI.  On
+ *    failure an `out` handle is set to NULL, nothing is leaked, and
+ *    fs_last_error() holds a thread-local message.
+ *  - Handles are owned by the library and released by the matching
+ *    *_destroy call.  One handle must not be used from two threads at once;
+ *    distinct handles are independent.  A graph may back many sims.
+ *  - Device work is queued on the sim's HIP stream.  Calls that return data
+ *    to the host (fs_counts, fs_history, fs_get_state, fs_get_rates,
+ *    fs_sync) synchronise that stream; fs_step does not, and an error raised
+ *    by device work surfaces at the next synchronising call.
+ *  - The device is the HIP device current when fs_graph_create is called;
+ *    sims inherit it from their graph.
+ */
+#ifndef FS_H
+#define FS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+typedef int32_t fs_status;
+#define FS_OK 0
+#define FS_ERR_INVALID_ARG 1   /* a scalar argument or pointer is invalid           */
+#define FS_ERR_INVALID_CSR 2   /* the CSR arrays violate the rules of fs_graph_create */
+#define FS_ERR_OUT_OF_MEMORY 3 /* a device or host allocation failed                 */
+#define FS_ERR_DEVICE 4        /* a HIP runtime call or a kernel failed               */
+#define FS_ERR_BUSY 5          /* the graph is still referenced by a sim              */
+#define FS_ERR_BUDGET 6        /* the request exceeds the configured memory budget    */
+
+/* Short name of a status code (static string). */
+const char* fs_status_string(fs_status s);
+/* Detail of the last failure on the calling thread (valid until the next call). */
+const char* fs_last_error(void);
+
+/* ------------------------------------------------------- compartments, laws */
+/* Compartments of the SEIR model (Fig. SEIR): S -> E -> I -> R, R absorbing. */
+#define FS_S 0
+#define FS_E 1
+#define FS_I 2
+#define FS_R 3
+
+/* Holding-time laws of the renewal transitions E -> I and I -> R.  The hazard
+ * h(tau) = f(tau)/S(tau) (Section "Problem formulation") is evaluated at the
+ * node's age at the start of the step.
+ *   FS_DIST_EXP:        a = rate >= 0 (constant hazard; the Markovian case)
+ *   FS_DIST_LOGNORMAL:  a = mu, b = sigma > 0, parameters of ln(tau) (Proposition 1)
+ *   FS_DIST_WEIBULL:    a = shape >= 1, b = scale > 0 (days)
+ *   FS_DIST_ERLANG:     k = integer shape in [1, 64], a = rate > 0 (per day);
+ *                       "mean m" corresponds to rate = k/m
+ * Weibull shapes below 1 are rejected: their hazard is infinite at age 0. */
+#define FS_DIST_EXP 0
+#define FS_DIST_LOGNORMAL 1
+#define FS_DIST_WEIBULL 2
+#define FS_DIST_ERLANG 3
+
+typedef struct fs_dist {
+    int32_t kind;
+    int32_t k;
+    double a;
+    double b;
+} fs_dist;
+
+/* Storage of the per-unit state (mixed-precision storage, Section
+ * "Mixed-precision storage with an fp32 accumulator"); arithmetic is FP32 in
+ * both.
+ *   FS_STORAGE_FP32:    int32 state, float32 age in days
+ *   FS_STORAGE_COMPACT: uint8 state, uint16 age in whole steps (tau = n*dt,
+ *                       saturating at 65535)
+ * In both, the next-step infectivity of Eq. (infectivity) is kept as one bit
+ * per unit, 1{X = I}: with constant shedding s = 1 that bit is its exact value
+ * (beta multiplies the pressure instead). */
+#define FS_STORAGE_FP32 0
+#define FS_STORAGE_COMPACT 1
+
+/* ------------------------------------------------------------------- graph */
+typedef struct fs_graph fs_graph;
+
+/*
+ * Uploads an incoming-edge CSR graph (Appendix "Data layout": row i lists the
+ * nodes j with an edge j -> i; undirected graphs are passed symmetric).
+ *   n        number of nodes, 1 <= n < 2^31
+ *   row_ptr  n+1 int32, row_ptr[0] == 0, non-decreasing
+ *   col_ind  row_ptr[n] int32 source ids, each in [0, n)
+ *   weights  row_ptr[n] float32 edge weights w_ji, or NULL for unit weights
+ * Self-loops and repeated edges are accepted and count with multiplicity.
+ * Errors: FS_ERR_INVALID_ARG (n out of range, NULL arrays), FS_ERR_INVALID_CSR
+ * (any CSR rule broken), FS_ERR_OUT_OF_MEMORY, FS_ERR_DEVICE.
+ */
+fs_status fs_graph_create(int64_t n, const int32_t* row_ptr, const int32_t* col_ind,
+                          const float* weights, fs_graph** out);
+
+/* Releases a graph.  FS_ERR_BUSY (graph untouched) while a sim still uses it. */
+fs_status fs_graph_destroy(fs_graph* g);
+
+typedef struct fs_graph_info {
+    int64_t n;       /* nodes */
+    int64_t nnz;     /* directed edges (CSR entries) */
+    int32_t max_degree;
+    int32_t weighted;
+    double mean_degree;
+} fs_graph_info;
+
+fs_status fs_graph_get_info(const fs_graph* g, fs_graph_info* out);
+
+/* --------------------------------------------------------------------- sim */
+typedef struct fs_sim fs_sim;
+
+typedef struct fs_sim_params {
+    fs_dist ei;              /* E -> I holding-time law */
+    fs_dist ir;              /* I -> R holding-time law */
+    double beta;             /* per-edge transmission rate (per day), >= 0 */
+    double dt;               /* fixed step (days), > 0 */
+    uint64_t seed;           /* Philox key: draws are keyed by (seed, replica, step, node) */
+    int32_t n_replicas;      /* independent replicas R, a power of two in [1, 64];
+                                n * R must stay below 2^31 */
+    int32_t storage;         /* FS_STORAGE_FP32 or FS_STORAGE_COMPACT */
+    int32_t steps_per_graph; /* b: steps per captured hipGraph replay; 0 = launch eagerly */
+    int32_t history_len;     /* per-step count ring length (>= 2); 0 = 1024 */
+    int32_t record_rates;    /* nonzero: keep each unit's rate lambda of the last step */
+    int32_t variant;         /* step kernel: 0 = automatic, 1 = streaming (bitmap read
+                                through the caches), 2 = resident (bitmap held in LDS;
+                                n * n_replicas <= 2^20).  Results are identical. */
+    void* stream;            /* hipStream_t to run on; NULL = a stream owned by the sim */
+} fs_sim_params;
+
+/*
+ * Creates a simulation of R replicas on a graph.  Every unit starts in S with
+ * age 0 and infectivity 0; the step index starts at 0.
+ * Errors: FS_ERR_INVALID_ARG (bad law parameters, dt <= 0, beta < 0, R not a
+ * power of two in [1, 64], n*R >= 2^31, history_len == 1, unknown storage),
+ * FS_ERR_OUT_OF_MEMORY, FS_ERR_DEVICE.
+ */
+fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out);
+
+/* Releases a sim (synchronises its stream first). */
+fs_status fs_sim_destroy(fs_sim* s);
+
+/*
+ * Puts `count` listed nodes of one replica (replica = -1: every replica) into
+ * `compartment` with age 0 and rebuilds their infectivity.  Seeds of the
+ * paper's runs are exposed nodes (compartment FS_E; Listing "python_api").
+ *   nodes  count int64 node ids, each in [0, n)
+ */
+fs_status fs_sim_seed(fs_sim* s, int32_t replica, int64_t count, const int64_t* nodes,
+                      int32_t compartment);
+
+/*
+ * Queues n_steps steps (Algorithm 3, fixed dt) on the sim's stream and
+ * returns without waiting.  With steps_per_graph = b > 0, floor(n/b) replays
+ * of a captured hipGraph of b steps run first, then n mod b single launches
+ * (Algorithm 2 captures the step loop the same way).  Step k of replica r
+ * draws from Philox4x32-10 at counter (node, k mod 2^32, r, 0) under key
+ * (seed low, seed high).
+ */
+fs_status fs_step(fs_sim* s, int64_t n_steps);
+
+/* Waits for all queued work of the sim; reports device errors. */
+fs_status fs_sync(fs_sim* s);
+
+/* Index of the next step (= steps run since creation or the last set_state). */
+fs_status fs_step_index(fs_sim* s, int64_t* out);
+
+/*
+ * Exact S, E, I, R counts of one replica after the latest queued step,
+ * recounted from the stored states (synchronises).  out: 4 int64.
+ */
+fs_status fs_counts(fs_sim* s, int32_t replica, int64_t out[4]);
+
+/*
+ * Per-step counts (the S, E, I, R tallies each step kernel records) for steps
+ * first_step .. first_step+n-1, where step k's row holds the counts after
+ * step k ran.  Only the last history_len steps since creation or the last
+ * fs_set_state are kept; older or future rows give FS_ERR_INVALID_ARG.
+ *   out: n x 4 int64, row-major.  Synchronises.
+ */
+fs_status fs_history(fs_sim* s, int32_t replica, int64_t first_step, int64_t n, int64_t* out);
+
+/*
+ * Copies one replica's state out (synchronises).
+ *   state       n int32 compartments
+ *   age_days    n float32 ages in days   (FS_STORAGE_FP32; NULL otherwise)
+ *   age_steps   n uint16 ages in steps   (FS_STORAGE_COMPACT; NULL otherwise)
+ *   step_index  receives the index of the next step (may be NULL)
+ */
+fs_status fs_get_state(fs_sim* s, int32_t replica, int32_t* state, float* age_days,
+                       uint16_t* age_steps, int64_t* step_index);
+
+/*
+ * Overwrites one replica's state and age and rebuilds its infectivity
+ * (checkpoint restore; test set-up).  step_index >= 0 also sets the sim-wide
+ * step index (all replicas share it) and resets the count history; -1 keeps
+ * it.  Argument formats as in fs_get_state; states must lie in [0, 3].
+ */
+fs_status fs_set_state(fs_sim* s, int32_t replica, const int32_t* state, const float* age_days,
+                       const uint16_t* age_steps, int64_t step_index);
+
+/*
+ * Rates lambda_i of the latest step for one replica (beta*pressure for S,
+ * the hazard for E and I, 0 for R), as the step kernel computed them in FP32.
+ * Requires record_rates at creation.  out: n float32.  Synchronises.
+ */
+fs_status fs_get_rates(fs_sim* s, int32_t replica, float* out);
+
+/* ------------------------------------------------- building-block checks */
+/*
+ * Evaluates the device hazard of `law` at n ages with the same code the step
+ * kernel runs.  storage FS_STORAGE_FP32: ages are float32 days;
+ * FS_STORAGE_COMPACT: ages are uint16 step counts with tau = n*dt.
+ *   ages: n values (host), out: n float32 hazards per day (host).
+ */
+fs_status fs_eval_hazard(const fs_dist* law, int32_t storage, double dt, int64_t n,
+                         const void* ages, float* out);
+
+/*
+ * Evaluates Philox4x32-10 on the device for n counters (n x 4 uint32, host)
+ * under key (seed low, seed high); out: n x 4 uint32 (host).
+ */
+fs_status fs_eval_philox(int64_t n, const uint32_t* ctr, uint64_t seed, uint32_t* out);
+
+/* Library version string. */
+const char* fs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FS_H */

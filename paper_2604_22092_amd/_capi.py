@@ -1,0 +1,331 @@
+"""ctypes binding of include/fs.h: argument marshalling only.
+
+Every function named ``fs_*`` here calls the C function of the same name in
+libflashspread.so and raises :class:`FsError` on a non-OK status.  The
+:class:`Graph` and :class:`Sim` wrappers only hold handles and convert numpy
+arrays; all of the step's work runs in the library's HIP kernels.  There is no
+fallback: when the library is missing or cannot be loaded, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libflashspread.so")
+
+FS_OK = 0
+STATUS_NAMES = {0: "FS_OK", 1: "FS_ERR_INVALID_ARG", 2: "FS_ERR_INVALID_CSR",
+                3: "FS_ERR_OUT_OF_MEMORY", 4: "FS_ERR_DEVICE", 5: "FS_ERR_BUSY",
+                6: "FS_ERR_BUDGET"}
+FS_S, FS_E, FS_I, FS_R = 0, 1, 2, 3
+FS_DIST_EXP, FS_DIST_LOGNORMAL, FS_DIST_WEIBULL, FS_DIST_ERLANG = 0, 1, 2, 3
+FS_STORAGE_FP32, FS_STORAGE_COMPACT = 0, 1
+VARIANT_AUTO, VARIANT_STREAM, VARIANT_RESIDENT = 0, 1, 2
+
+# Every symbol include/fs.h declares.
+EXPORTS = [
+    "fs_status_string", "fs_last_error", "fs_graph_create", "fs_graph_destroy",
+    "fs_graph_get_info", "fs_sim_create", "fs_sim_destroy", "fs_sim_seed", "fs_step",
+    "fs_sync", "fs_step_index", "fs_counts", "fs_history", "fs_get_state", "fs_set_state",
+    "fs_get_rates", "fs_eval_hazard", "fs_eval_philox", "fs_version",
+]
+
+
+class FsError(RuntimeError):
+    def __init__(self, status: int, func: str, detail: str):
+        self.status = status
+        super().__init__(f"{func}: {STATUS_NAMES.get(status, status)}: {detail}")
+
+
+class fs_dist(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("a", ctypes.c_double), ("b", ctypes.c_double)]
+
+
+class fs_graph_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("max_degree", ctypes.c_int32),
+                ("weighted", ctypes.c_int32), ("mean_degree", ctypes.c_double)]
+
+
+class fs_sim_params(ctypes.Structure):
+    _fields_ = [("ei", fs_dist), ("ir", fs_dist), ("beta", ctypes.c_double),
+                ("dt", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("n_replicas", ctypes.c_int32), ("storage", ctypes.c_int32),
+                ("steps_per_graph", ctypes.c_int32), ("history_len", ctypes.c_int32),
+                ("record_rates", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libflashspread.so; raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        _declare(L)
+        _lib = L
+    return _lib
+
+
+def _declare(L):
+    P, I32, I64, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "fs_status_string": ([I32], ctypes.c_char_p),
+        "fs_last_error": ([], ctypes.c_char_p),
+        "fs_version": ([], ctypes.c_char_p),
+        "fs_graph_create": ([I64, P, P, P, PP], I32),
+        "fs_graph_destroy": ([P], I32),
+        "fs_graph_get_info": ([P, ctypes.POINTER(fs_graph_info)], I32),
+        "fs_sim_create": ([P, ctypes.POINTER(fs_sim_params), PP], I32),
+        "fs_sim_destroy": ([P], I32),
+        "fs_sim_seed": ([P, I32, I64, P, I32], I32),
+        "fs_step": ([P, I64], I32),
+        "fs_sync": ([P], I32),
+        "fs_step_index": ([P, ctypes.POINTER(ctypes.c_int64)], I32),
+        "fs_counts": ([P, I32, P], I32),
+        "fs_history": ([P, I32, I64, I64, P], I32),
+        "fs_get_state": ([P, I32, P, P, P, ctypes.POINTER(ctypes.c_int64)], I32),
+        "fs_set_state": ([P, I32, P, P, P, I64], I32),
+        "fs_get_rates": ([P, I32, P], I32),
+        "fs_eval_hazard": ([ctypes.POINTER(fs_dist), I32, ctypes.c_double, I64, P, P], I32),
+        "fs_eval_philox": ([I64, P, U64, P], I32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+
+
+def _check(status: int, func: str):
+    if status != FS_OK:
+        detail = lib().fs_last_error()
+        raise FsError(status, func, detail.decode() if detail else "")
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def make_dist(spec) -> fs_dist:
+    """("exp", rate) | ("lognormal", mu, sigma) | ("weibull", shape, scale) | ("erlang", k, rate)"""
+    kind = spec[0]
+    if kind == "exp":
+        return fs_dist(FS_DIST_EXP, 0, float(spec[1]), 0.0)
+    if kind == "lognormal":
+        return fs_dist(FS_DIST_LOGNORMAL, 0, float(spec[1]), float(spec[2]))
+    if kind == "weibull":
+        return fs_dist(FS_DIST_WEIBULL, 0, float(spec[1]), float(spec[2]))
+    if kind == "erlang":
+        return fs_dist(FS_DIST_ERLANG, int(spec[1]), float(spec[2]), 0.0)
+    raise ValueError(f"unknown holding-time law {spec!r}")
+
+
+# ------------------------------------------------------------- raw C names
+
+def fs_version() -> str:
+    return lib().fs_version().decode()
+
+
+def fs_graph_create(row_ptr, col_ind, weights=None) -> ctypes.c_void_p:
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_ind, dtype=np.int32)
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float32)
+    h = ctypes.c_void_p()
+    _check(lib().fs_graph_create(len(rp) - 1, _ptr(rp), _ptr(ci), _ptr(w), ctypes.byref(h)),
+           "fs_graph_create")
+    return h
+
+
+def fs_graph_destroy(h):
+    _check(lib().fs_graph_destroy(h), "fs_graph_destroy")
+
+
+def fs_graph_get_info(h) -> dict:
+    info = fs_graph_info()
+    _check(lib().fs_graph_get_info(h, ctypes.byref(info)), "fs_graph_get_info")
+    return {f: getattr(info, f) for f, _ in fs_graph_info._fields_}
+
+
+def fs_sim_create(graph, params: fs_sim_params) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().fs_sim_create(graph, ctypes.byref(params), ctypes.byref(h)), "fs_sim_create")
+    return h
+
+
+def fs_sim_destroy(h):
+    _check(lib().fs_sim_destroy(h), "fs_sim_destroy")
+
+
+def fs_sim_seed(h, replica: int, nodes, compartment: int = FS_E):
+    nd = np.ascontiguousarray(nodes, dtype=np.int64)
+    _check(lib().fs_sim_seed(h, int(replica), len(nd), _ptr(nd), int(compartment)), "fs_sim_seed")
+
+
+def fs_step(h, n_steps: int):
+    _check(lib().fs_step(h, int(n_steps)), "fs_step")
+
+
+def fs_sync(h):
+    _check(lib().fs_sync(h), "fs_sync")
+
+
+def fs_step_index(h) -> int:
+    v = ctypes.c_int64()
+    _check(lib().fs_step_index(h, ctypes.byref(v)), "fs_step_index")
+    return v.value
+
+
+def fs_counts(h, replica: int = 0) -> np.ndarray:
+    out = np.zeros(4, dtype=np.int64)
+    _check(lib().fs_counts(h, int(replica), _ptr(out)), "fs_counts")
+    return out
+
+
+def fs_history(h, replica: int, first_step: int, n: int) -> np.ndarray:
+    out = np.zeros((n, 4), dtype=np.int64)
+    _check(lib().fs_history(h, int(replica), int(first_step), int(n), _ptr(out)), "fs_history")
+    return out
+
+
+def fs_get_state(h, replica: int, n: int, storage: int):
+    st = np.empty(n, dtype=np.int32)
+    ad = np.empty(n, dtype=np.float32) if storage == FS_STORAGE_FP32 else None
+    ag = np.empty(n, dtype=np.uint16) if storage == FS_STORAGE_COMPACT else None
+    k = ctypes.c_int64()
+    _check(lib().fs_get_state(h, int(replica), _ptr(st), _ptr(ad), _ptr(ag), ctypes.byref(k)),
+           "fs_get_state")
+    return st, (ad if ad is not None else ag), k.value
+
+
+def fs_set_state(h, replica: int, state, age, storage: int, step_index: int = -1):
+    st = np.ascontiguousarray(state, dtype=np.int32)
+    ad = np.ascontiguousarray(age, dtype=np.float32) if storage == FS_STORAGE_FP32 else None
+    ag = np.ascontiguousarray(age, dtype=np.uint16) if storage == FS_STORAGE_COMPACT else None
+    _check(lib().fs_set_state(h, int(replica), _ptr(st), _ptr(ad), _ptr(ag), int(step_index)),
+           "fs_set_state")
+
+
+def fs_get_rates(h, replica: int, n: int) -> np.ndarray:
+    out = np.empty(n, dtype=np.float32)
+    _check(lib().fs_get_rates(h, int(replica), _ptr(out)), "fs_get_rates")
+    return out
+
+
+def fs_eval_hazard(spec, ages, storage: int = FS_STORAGE_FP32, dt: float = 1.0) -> np.ndarray:
+    a = np.ascontiguousarray(ages, dtype=np.float32 if storage == FS_STORAGE_FP32 else np.uint16)
+    out = np.empty(len(a), dtype=np.float32)
+    d = make_dist(spec)
+    _check(lib().fs_eval_hazard(ctypes.byref(d), int(storage), float(dt), len(a), _ptr(a),
+                                _ptr(out)), "fs_eval_hazard")
+    return out
+
+
+def fs_eval_philox(ctr, seed: int) -> np.ndarray:
+    c = np.ascontiguousarray(np.atleast_2d(ctr), dtype=np.uint32)
+    out = np.empty_like(c)
+    _check(lib().fs_eval_philox(len(c), _ptr(c), int(seed) & (2**64 - 1), _ptr(out)),
+           "fs_eval_philox")
+    return out
+
+
+# ------------------------------------------------------------- handle wrappers
+
+class Graph:
+    """An incoming-edge CSR graph resident on the current HIP device."""
+
+    def __init__(self, row_ptr, col_ind, weights=None):
+        self.n = len(row_ptr) - 1
+        self.handle = fs_graph_create(row_ptr, col_ind, weights)
+
+    def info(self) -> dict:
+        return fs_graph_get_info(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            fs_graph_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Sim:
+    """R replicas of the SEIR renewal process on one Graph."""
+
+    def __init__(self, graph: Graph, ei, ir, beta: float, dt: float, seed: int = 0,
+                 replicas: int = 1, storage: int = FS_STORAGE_FP32, steps_per_graph: int = 0,
+                 history_len: int = 0, record_rates: bool = False, variant: int = 0,
+                 stream=None):
+        p = fs_sim_params()
+        p.ei = make_dist(ei)
+        p.ir = make_dist(ir)
+        p.beta = float(beta)
+        p.dt = float(dt)
+        p.seed = int(seed) & (2**64 - 1)
+        p.n_replicas = int(replicas)
+        p.storage = int(storage)
+        p.steps_per_graph = int(steps_per_graph)
+        p.history_len = int(history_len)
+        p.record_rates = 1 if record_rates else 0
+        p.variant = int(variant)
+        p.stream = None if stream is None else ctypes.c_void_p(int(stream))
+        self.graph = graph
+        self.n = graph.n
+        self.replicas = int(replicas)
+        self.storage = int(storage)
+        self.handle = fs_sim_create(graph.handle, p)
+
+    @classmethod
+    def from_model(cls, graph: Graph, model: dict, **kw):
+        return cls(graph, model["ei"], model["ir"], model["beta"], model["dt"],
+                   seed=model.get("seed", 0), **kw)
+
+    def seed(self, nodes, replica: int = -1, compartment: int = FS_E):
+        fs_sim_seed(self.handle, replica, nodes, compartment)
+
+    def step(self, n_steps: int = 1):
+        fs_step(self.handle, n_steps)
+
+    def sync(self):
+        fs_sync(self.handle)
+
+    def step_index(self) -> int:
+        return fs_step_index(self.handle)
+
+    def counts(self, replica: int = 0) -> np.ndarray:
+        return fs_counts(self.handle, replica)
+
+    def history(self, first_step: int, n: int, replica: int = 0) -> np.ndarray:
+        return fs_history(self.handle, replica, first_step, n)
+
+    def get_state(self, replica: int = 0):
+        return fs_get_state(self.handle, replica, self.n, self.storage)
+
+    def set_state(self, state, age, replica: int = 0, step_index: int = -1):
+        fs_set_state(self.handle, replica, state, age, self.storage, step_index)
+
+    def rates(self, replica: int = 0) -> np.ndarray:
+        return fs_get_rates(self.handle, replica, self.n)
+
+    def close(self):
+        if self.handle is not None:
+            fs_sim_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,80 @@
+// Layouts shared by the step kernels and the host runtime of the library.
+#pragma once
+
+#include <stdint.h>
+
+namespace fsi {
+
+enum : int32_t { ST_S = 0, ST_E = 1, ST_I = 2, ST_R = 3 };
+enum : int32_t { K_EXP = 0, K_LN = 1, K_WB = 2, K_ERL = 3 };
+
+// Workgroup size of the helper kernels (four wave64 wavefronts).
+constexpr int WG = 256;
+// Step kernel variants: the streaming variant (bitmap read through the
+// caches) runs STREAM_TPB threads per workgroup; the resident variant (bitmap
+// held in LDS, one workgroup per compute unit) runs RESIDENT_TPB threads and
+// holds up to RESIDENT_BITS units.  Both walk 64-unit chunks per wavefront.
+constexpr int STREAM_TPB = 256;
+constexpr int RESIDENT_TPB = 1024;
+constexpr uint32_t RESIDENT_BITS = 1u << 20;
+// Bitmaps are allocated in whole 512-unit tiles (8 words of 64 bits).
+constexpr uint32_t BITMAP_TILE = 512;
+
+// Hazard parameters, prepared on the host in double precision and rounded
+// once.  Ages reach the device in a unit u: days (FP32 storage) or steps of
+// dt (compact storage, integer ages n with tau = n*dt).
+//   log-normal: h = K / (x * erfcx(z)),  z = (ln x + c) * g
+//               K = sqrt(2/pi)/(sigma*u), c = ln u - mu, g = 1/(sigma sqrt 2)
+//   Weibull:    h = K * exp((ln x + c) * g)
+//               K = shape/scale, c = ln(u/scale), g = shape - 1
+//   Erlang:     h = K / R(1/(xr*x)), xr = rate*u, K = rate,
+//               R(y) = sum_{j<k} (k-1)!/j! y^(k-1-j)
+//   exponential h = K
+struct HazardDev {
+    int32_t kind;
+    int32_t k;
+    float K;
+    float c_hi, c_lo;
+    float g_hi, g_lo;
+    float x_hi, x_lo;
+};
+
+// Device-resident control block of a simulation.  `step` is the index of the
+// first step of the launch sequence being run: step launch j of a sequence
+// runs step (step + j), and a single-thread advance kernel at the end of the
+// sequence adds its length.  Captured sequences therefore need no per-replay
+// arguments and no step kernel touches a shared counter.
+struct Ctl {
+    unsigned long long step;
+    unsigned long long pad;
+};
+
+// Kernel arguments of one fused step launch.
+struct StepArgs {
+    const int32_t* row_ptr;
+    const int32_t* col_ind;
+    const float* weights; // nullptr: unit weights
+    void* state;          // int32 (FP32 storage) or uint8 (compact), [n][R]
+    void* age;            // float days or uint16 steps, [n][R]
+    void* iota0;          // infectivity bitmaps, bit u = 1{X_u = I}; step k reads
+    void* iota1;          // iota[k & 1] and writes iota[(k + 1) & 1]
+    float* rates;         // optional per-unit lambda (debug), [n][R]
+    const Ctl* ctl;
+    uint32_t* part;       // per-workgroup counts [chunk slot][grid][R][4]
+    int32_t n;
+    int32_t lgR;          // R = 1 << lgR replicas
+    uint32_t step_off;    // j: this launch runs step ctl->step + j, partial slot j
+    uint32_t ntiles;      // unused (kept for layout stability)
+    int32_t same_kind;    // E and I laws share a kind: one hazard call per lane
+    int32_t pad0;
+    HazardDev hz[2];      // [0] E -> I, [1] I -> R
+    float beta;
+    float dt;
+    uint32_t key0, key1;  // Philox key = (seed low, seed high)
+};
+
+// Upper bound on step workgroups (they loop over tiles beyond it), chosen so
+// the per-workgroup count partials of a launch sequence stay small.
+inline uint32_t max_step_grid(int R) { return R <= 4 ? 16384u : (R <= 16 ? 4096u : 2048u); }
+
+} // namespace fsi

@@ -1,0 +1,42 @@
+// Host-side entry points into the kernels of fs_kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fs_internal.hpp"
+
+namespace fsk {
+
+// Address of the fused step kernel for a storage/weights/rates combination
+// (launched with one StepArgs argument); resident selects the LDS-bitmap
+// variant (RESIDENT_TPB threads, one workgroup per compute unit), otherwise
+// STREAM_TPB threads per workgroup.
+const void* step_kernel_fn(int storage, bool weighted, bool rates, bool resident);
+
+// Exact counts of one replica: per-workgroup partials (at most max_grid rows
+// of 4 in `part`) reduced into out4.
+hipError_t launch_recount(int storage, const void* state, int32_t n, int32_t lgR, int32_t replica,
+                          uint32_t* part, uint32_t max_grid, uint32_t* out4, hipStream_t s);
+// reduce_kernel(const Ctl*, const uint32_t* part, uint32_t G, uint32_t C, uint32_t* out, uint32_t H):
+// one block per slot, WG threads.
+const void* reduce_kernel_fn();
+// advance_kernel(Ctl*, uint32_t r): adds r to the step index; one thread.
+const void* advance_kernel_fn();
+hipError_t launch_put_replica(int storage, void* state, void* age, const int32_t* src_state, const void* src_age,
+                              int32_t n, int32_t lgR, int32_t replica, hipStream_t s);
+hipError_t launch_rebuild_bits(int storage, const void* state, uint32_t total, unsigned long long* bits,
+                               uint32_t words, hipStream_t s);
+hipError_t launch_get_replica(int storage, const void* state, const void* age, int32_t* dst_state,
+                              void* dst_age, int32_t n, int32_t lgR, int32_t replica, hipStream_t s);
+hipError_t launch_get_rates(const float* rates, float* dst, int32_t n, int32_t lgR, int32_t replica,
+                            hipStream_t s);
+hipError_t launch_seed(int storage, void* state, void* age, const int64_t* nodes, int64_t count, int32_t lgR,
+                       int32_t replica, int32_t comp, hipStream_t s);
+hipError_t launch_clear_u32(uint32_t* p, size_t n, hipStream_t s);
+hipError_t launch_set_ctl(fsi::Ctl* ctl, unsigned long long step, hipStream_t s);
+hipError_t launch_eval_hazard(const fsi::HazardDev& h, int32_t storage, const void* ages, float* out, int64_t n,
+                              hipStream_t s);
+hipError_t launch_eval_philox(const uint4* ctr, uint32_t k0, uint32_t k1, uint4* out, int64_t n, hipStream_t s);
+
+} // namespace fsk

@@ -1,0 +1,741 @@
+// Host runtime of the C ABI declared in include/fs.h: validation, device
+// memory, the device-resident step index, eager and hipGraph step loops,
+// state transfer and counts.  No exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fs.h"
+#include "fs_internal.hpp"
+#include "fs_kernels.hpp"
+
+using fsi::HazardDev;
+using fsi::StepArgs;
+using fsi::WG;
+
+struct fs_graph {
+    int device = 0;
+    int64_t n = 0, nnz = 0;
+    int32_t* d_row_ptr = nullptr;
+    int32_t* d_col_ind = nullptr;
+    float* d_weights = nullptr;
+    int32_t max_degree = 0;
+    double mean_degree = 0.0;
+    std::atomic<int> users{0};
+};
+
+struct fs_sim {
+    fs_graph* g = nullptr;
+    fs_sim_params p{};
+    int device = 0;
+    int lgR = 0, R = 1;
+    int storage = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void* d_state = nullptr;
+    void* d_age = nullptr;
+    void* d_iota[2] = {nullptr, nullptr};
+    float* d_rates = nullptr;
+    fsi::Ctl* d_ctl = nullptr;
+    uint32_t* d_hist = nullptr;    // [H][R][4] counts after each step
+    uint32_t* d_part = nullptr;    // [chunk][G][R][4] per-workgroup partials
+    uint32_t* d_rc_part = nullptr; // recount partials [RC_GRID][4]
+    uint32_t* d_cnt4 = nullptr;
+    int H = 1024;
+    uint32_t G = 0;                // step workgroups
+    uint32_t tpb = 0;              // threads (units) per step workgroup / tile
+    bool resident = false;         // bitmap held in LDS
+    uint32_t bit_words = 0;        // 64-bit words per infectivity bitmap
+    uint32_t chunk = 0;            // steps per launch sequence (partial slots)
+    int64_t step = 0;      // index of the next step (host mirror of ctl->step)
+    int64_t hist_from = 0; // first step whose count row is recorded
+    StepArgs args{};
+    const void* kfn = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+fs_status fail(fs_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+#define FS_HIP(call)                                                                           \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(e_ == hipErrorOutOfMemory ? FS_ERR_OUT_OF_MEMORY : FS_ERR_DEVICE,      \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                    \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int d)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != d) (void)hipSetDevice(d);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// Device allocations go through hipMalloc; a failed allocation reports
+// FS_ERR_OUT_OF_MEMORY and the caller releases what it already holds.
+hipError_t dev_alloc(void** p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    return hipMalloc(p, bytes);
+}
+
+void dev_free(void* p)
+{
+    if (p) (void)hipFree(p);
+}
+
+// RAII device buffer for call-local temporaries.
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() { dev_free(p); }
+};
+
+void split(double v, float& hi, float& lo)
+{
+    hi = (float)v;
+    lo = (float)(v - (double)hi);
+}
+
+fs_status prep_hazard(const fs_dist& d, int storage, double dt, HazardDev* h, const char* which)
+{
+    std::memset(h, 0, sizeof *h);
+    const double unit = storage == FS_STORAGE_COMPACT ? dt : 1.0;
+    h->kind = d.kind;
+    h->k = d.k;
+    switch (d.kind) {
+    case FS_DIST_EXP:
+        if (!(d.a >= 0.0) || !std::isfinite(d.a))
+            return fail(FS_ERR_INVALID_ARG, std::string(which) + ": exponential rate must be finite and >= 0");
+        h->K = (float)d.a;
+        return FS_OK;
+    case FS_DIST_LOGNORMAL:
+        if (!std::isfinite(d.a) || !(d.b > 0.0) || !std::isfinite(d.b))
+            return fail(FS_ERR_INVALID_ARG, std::string(which) + ": log-normal needs finite mu and sigma > 0");
+        h->K = (float)(std::sqrt(2.0 / M_PI) / (d.b * unit));
+        split(std::log(unit) - d.a, h->c_hi, h->c_lo);
+        split(1.0 / (d.b * std::sqrt(2.0)), h->g_hi, h->g_lo);
+        return FS_OK;
+    case FS_DIST_WEIBULL:
+        if (!(d.a >= 1.0) || !std::isfinite(d.a) || !(d.b > 0.0) || !std::isfinite(d.b))
+            return fail(FS_ERR_INVALID_ARG, std::string(which) + ": Weibull needs shape >= 1 and scale > 0");
+        h->K = (float)(d.a / d.b);
+        split(std::log(unit / d.b), h->c_hi, h->c_lo);
+        split(d.a - 1.0, h->g_hi, h->g_lo);
+        return FS_OK;
+    case FS_DIST_ERLANG:
+        if (d.k < 1 || d.k > 64 || !(d.a > 0.0) || !std::isfinite(d.a))
+            return fail(FS_ERR_INVALID_ARG, std::string(which) + ": Erlang needs k in [1, 64] and rate > 0");
+        h->K = (float)d.a;
+        split(d.a * unit, h->x_hi, h->x_lo);
+        return FS_OK;
+    default:
+        return fail(FS_ERR_INVALID_ARG, std::string(which) + ": unknown holding-time law");
+    }
+}
+
+size_t state_bytes(int storage) { return storage == FS_STORAGE_FP32 ? 4 : 1; }
+size_t age_bytes(int storage) { return storage == FS_STORAGE_FP32 ? 4 : 2; }
+// 64-bit words of an infectivity bitmap of `units` bits, in whole tiles.
+size_t bitmap_words(size_t units) { return (units + fsi::BITMAP_TILE - 1) / fsi::BITMAP_TILE * (fsi::BITMAP_TILE / 64); }
+
+void release_sim(fs_sim* s)
+{
+    if (!s) return;
+    if (s->exec) (void)hipGraphExecDestroy(s->exec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    dev_free(s->d_state);
+    dev_free(s->d_age);
+    dev_free(s->d_iota[0]);
+    dev_free(s->d_iota[1]);
+    dev_free(s->d_rates);
+    dev_free(s->d_ctl);
+    dev_free(s->d_hist);
+    dev_free(s->d_part);
+    dev_free(s->d_rc_part);
+    dev_free(s->d_cnt4);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->g) s->g->users.fetch_sub(1);
+    delete s;
+}
+
+fs_status check_replica(const fs_sim* s, int32_t replica, bool allow_all)
+{
+    if (replica >= 0 && replica < s->R) return FS_OK;
+    if (allow_all && replica == -1) return FS_OK;
+    return fail(FS_ERR_INVALID_ARG, "replica index out of range");
+}
+
+constexpr uint32_t RC_GRID = 1024;
+
+// Launch sequence of r steps: r step launches, one reduce, one advance.
+struct SeqArgs {
+    std::vector<StepArgs> step;
+    const fsi::Ctl* ctl_c;
+    fsi::Ctl* ctl;
+    const uint32_t* part;
+    uint32_t G, C, H, r;
+    uint32_t* hist;
+};
+
+void make_seq(fs_sim* s, uint32_t r, SeqArgs& q)
+{
+    q.step.assign(r, s->args);
+    for (uint32_t j = 0; j < r; ++j) q.step[j].step_off = j;
+    q.ctl_c = s->d_ctl;
+    q.ctl = s->d_ctl;
+    q.part = s->d_part;
+    q.G = s->G;
+    q.C = 4u * (uint32_t)s->R;
+    q.H = (uint32_t)s->H;
+    q.r = r;
+    q.hist = s->d_hist;
+}
+
+fs_status build_graph_exec(fs_sim* s, int b)
+{
+    SeqArgs q;
+    make_seq(s, (uint32_t)b, q);
+    FS_HIP(hipGraphCreate(&s->graph, 0));
+    hipGraphNode_t prev = nullptr;
+    auto add = [&](const void* fn, dim3 grid, dim3 block, void** argv) -> fs_status {
+        hipKernelNodeParams kp{};
+        kp.func = const_cast<void*>(fn);
+        kp.gridDim = grid;
+        kp.blockDim = block;
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = argv;
+        kp.extra = nullptr;
+        hipGraphNode_t node;
+        FS_HIP(hipGraphAddKernelNode(&node, s->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+        prev = node;
+        return FS_OK;
+    };
+    fs_status st;
+    for (int j = 0; j < b; ++j) {
+        void* argv[] = {&q.step[j]};
+        if ((st = add(s->kfn, dim3(s->G), dim3(s->tpb), argv)) != FS_OK) return st;
+    }
+    void* rargv[] = {&q.ctl_c, &q.part, &q.G, &q.C, &q.hist, &q.H};
+    if ((st = add(fsk::reduce_kernel_fn(), dim3(q.r), dim3(WG), rargv)) != FS_OK) return st;
+    void* aargv[] = {&q.ctl, &q.r};
+    if ((st = add(fsk::advance_kernel_fn(), dim3(1), dim3(64), aargv)) != FS_OK) return st;
+    FS_HIP(hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0));
+    return FS_OK;
+}
+
+fs_status launch_sequence(fs_sim* s, uint32_t r)
+{
+    SeqArgs q;
+    make_seq(s, r, q);
+    for (uint32_t j = 0; j < r; ++j) {
+        void* argv[] = {&q.step[j]};
+        FS_HIP(hipLaunchKernel(s->kfn, dim3(s->G), dim3(s->tpb), argv, 0, s->stream));
+    }
+    void* rargv[] = {&q.ctl_c, &q.part, &q.G, &q.C, &q.hist, &q.H};
+    FS_HIP(hipLaunchKernel(fsk::reduce_kernel_fn(), dim3(r), dim3(WG), rargv, 0, s->stream));
+    void* aargv[] = {&q.ctl, &q.r};
+    FS_HIP(hipLaunchKernel(fsk::advance_kernel_fn(), dim3(1), dim3(64), aargv, 0, s->stream));
+    return FS_OK;
+}
+
+} // namespace
+
+#define FS_GUARD_BEGIN try {
+#define FS_GUARD_END                                                        \
+    }                                                                       \
+    catch (const std::bad_alloc&) { return fail(FS_ERR_OUT_OF_MEMORY, "host allocation failed"); } \
+    catch (const std::exception& e) { return fail(FS_ERR_DEVICE, e.what()); }                   \
+    catch (...) { return fail(FS_ERR_DEVICE, "unknown exception"); }
+
+extern "C" {
+
+const char* fs_version(void) { return "flashspread-hip 0.1 (gfx950)"; }
+
+const char* fs_status_string(fs_status s)
+{
+    switch (s) {
+    case FS_OK: return "FS_OK";
+    case FS_ERR_INVALID_ARG: return "FS_ERR_INVALID_ARG";
+    case FS_ERR_INVALID_CSR: return "FS_ERR_INVALID_CSR";
+    case FS_ERR_OUT_OF_MEMORY: return "FS_ERR_OUT_OF_MEMORY";
+    case FS_ERR_DEVICE: return "FS_ERR_DEVICE";
+    case FS_ERR_BUSY: return "FS_ERR_BUSY";
+    case FS_ERR_BUDGET: return "FS_ERR_BUDGET";
+    default: return "FS_ERR_UNKNOWN";
+    }
+}
+
+const char* fs_last_error(void) { return g_err.c_str(); }
+
+fs_status fs_graph_create(int64_t n, const int32_t* row_ptr, const int32_t* col_ind, const float* weights,
+                          fs_graph** out)
+{
+    FS_GUARD_BEGIN
+    if (!out) return fail(FS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n >= (int64_t)1 << 31) return fail(FS_ERR_INVALID_ARG, "n must satisfy 1 <= n < 2^31");
+    if (!row_ptr) return fail(FS_ERR_INVALID_ARG, "row_ptr is NULL");
+    if (row_ptr[0] != 0) return fail(FS_ERR_INVALID_CSR, "row_ptr[0] must be 0");
+    int32_t maxd = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t d = (int64_t)row_ptr[i + 1] - (int64_t)row_ptr[i];
+        if (d < 0)
+            return fail(FS_ERR_INVALID_CSR, "row_ptr decreases at row " + std::to_string(i));
+        if (d > maxd) maxd = (int32_t)d;
+    }
+    const int64_t nnz = row_ptr[n];
+    if (nnz > 0 && !col_ind) return fail(FS_ERR_INVALID_ARG, "col_ind is NULL");
+    for (int64_t e = 0; e < nnz; ++e)
+        if (col_ind[e] < 0 || (int64_t)col_ind[e] >= n)
+            return fail(FS_ERR_INVALID_CSR, "col_ind[" + std::to_string(e) + "] out of range");
+    int dev = 0;
+    FS_HIP(hipGetDevice(&dev));
+    fs_graph* g = new fs_graph();
+    g->device = dev;
+    g->n = n;
+    g->nnz = nnz;
+    g->max_degree = maxd;
+    g->mean_degree = (double)nnz / (double)n;
+    auto cleanup = [&](fs_status st) {
+        dev_free(g->d_row_ptr);
+        dev_free(g->d_col_ind);
+        dev_free(g->d_weights);
+        delete g;
+        return st;
+    };
+    hipError_t e;
+    if ((e = dev_alloc((void**)&g->d_row_ptr, sizeof(int32_t) * (size_t)(n + 1))) != hipSuccess ||
+        (e = dev_alloc((void**)&g->d_col_ind, sizeof(int32_t) * (size_t)nnz)) != hipSuccess ||
+        (weights && (e = dev_alloc((void**)&g->d_weights, sizeof(float) * (size_t)nnz)) != hipSuccess))
+        return cleanup(fail(FS_ERR_OUT_OF_MEMORY, std::string("device allocation: ") + hipGetErrorString(e)));
+    if ((e = hipMemcpy(g->d_row_ptr, row_ptr, sizeof(int32_t) * (size_t)(n + 1), hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (nnz && (e = hipMemcpy(g->d_col_ind, col_ind, sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice)) !=
+                    hipSuccess) ||
+        (weights && nnz &&
+         (e = hipMemcpy(g->d_weights, weights, sizeof(float) * (size_t)nnz, hipMemcpyHostToDevice)) != hipSuccess))
+        return cleanup(fail(FS_ERR_DEVICE, std::string("upload: ") + hipGetErrorString(e)));
+    *out = g;
+    return FS_OK;
+    FS_GUARD_END
+}
+
+fs_status fs_graph_destroy(fs_graph* g)
+{
+    FS_GUARD_BEGIN
+    if (!g) return fail(FS_ERR_INVALID_ARG, "graph is NULL");
+    if (g->users.load() > 0) return fail(FS_ERR_BUSY, "graph is still used by a sim");
+    DeviceGuard dg(g->device);
+    dev_free(g->d_row_ptr);
+    dev_free(g->d_col_ind);
+    dev_free(g->d_weights);
+    delete g;
+    return FS_OK;
+    FS_GUARD_END
+}
+
+fs_status fs_graph_get_info(const fs_graph* g, fs_graph_info* out)
+{
+    if (!g || !out) return fail(FS_ERR_INVALID_ARG, "NULL argument");
+    out->n = g->n;
+    out->nnz = g->nnz;
+    out->max_degree = g->max_degree;
+    out->weighted = g->d_weights != nullptr;
+    out->mean_degree = g->mean_degree;
+    return FS_OK;
+}
+
+fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
+{
+    FS_GUARD_BEGIN
+    if (!out) return fail(FS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!g || !p) return fail(FS_ERR_INVALID_ARG, "NULL graph or params");
+    if (p->storage != FS_STORAGE_FP32 && p->storage != FS_STORAGE_COMPACT)
+        return fail(FS_ERR_INVALID_ARG, "unknown storage");
+    if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(FS_ERR_INVALID_ARG, "dt must be finite and > 0");
+    if (!(p->beta >= 0.0) || !std::isfinite(p->beta)) return fail(FS_ERR_INVALID_ARG, "beta must be finite and >= 0");
+    const int R = p->n_replicas;
+    if (R < 1 || R > 64 || (R & (R - 1))) return fail(FS_ERR_INVALID_ARG, "n_replicas must be a power of two in [1, 64]");
+    if ((int64_t)g->n * R >= (int64_t)1 << 31) return fail(FS_ERR_INVALID_ARG, "n * n_replicas must be below 2^31");
+    if (p->history_len < 0 || p->history_len == 1) return fail(FS_ERR_INVALID_ARG, "history_len must be 0 or >= 2");
+    if (p->steps_per_graph < 0 || p->steps_per_graph > 100000)
+        return fail(FS_ERR_INVALID_ARG, "steps_per_graph out of range");
+    HazardDev hz[2];
+    fs_status st;
+    if ((st = prep_hazard(p->ei, p->storage, p->dt, &hz[0], "ei")) != FS_OK) return st;
+    if ((st = prep_hazard(p->ir, p->storage, p->dt, &hz[1], "ir")) != FS_OK) return st;
+
+    DeviceGuard dg(g->device);
+    fs_sim* s = new fs_sim();
+    s->g = g;
+    g->users.fetch_add(1);
+    s->p = *p;
+    s->device = g->device;
+    s->R = R;
+    while ((1 << s->lgR) < R) ++s->lgR;
+    s->storage = p->storage;
+    s->H = p->history_len ? p->history_len : 1024;
+    const size_t units = (size_t)g->n * (size_t)R;
+    hipError_t e = hipSuccess;
+    auto bad = [&](hipError_t err, const char* what) {
+        release_sim(s);
+        return fail(err == hipErrorOutOfMemory ? FS_ERR_OUT_OF_MEMORY : FS_ERR_DEVICE,
+                    std::string(what) + ": " + hipGetErrorString(err));
+    };
+    if (p->stream) {
+        s->stream = (hipStream_t)p->stream;
+    } else {
+        if ((e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking)) != hipSuccess)
+            return bad(e, "stream");
+        s->own_stream = true;
+    }
+    if (p->variant < 0 || p->variant > 2) {
+        release_sim(s);
+        return fail(FS_ERR_INVALID_ARG, "variant must be 0 (auto), 1 (stream) or 2 (resident)");
+    }
+    const bool fits_lds = units <= fsi::RESIDENT_BITS;
+    if (p->variant == 2 && !fits_lds) {
+        release_sim(s);
+        return fail(FS_ERR_INVALID_ARG, "the resident variant holds at most 2^20 units (n * n_replicas)");
+    }
+    s->resident = p->variant == 2 || (p->variant == 0 && fits_lds);
+    s->tpb = s->resident ? fsi::RESIDENT_TPB : fsi::STREAM_TPB;
+    const size_t chunks = (units + 63) / 64;
+    const size_t tiles = (chunks + s->tpb / 64 - 1) / (s->tpb / 64); // workgroups with work
+    if (s->resident) {
+        int cus = 0;
+        if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device)) != hipSuccess)
+            return bad(e, "device attribute");
+        s->G = (uint32_t)std::min<size_t>(tiles, (size_t)std::max(cus, 1));
+    } else {
+        s->G = (uint32_t)std::min<size_t>(tiles, fsi::max_step_grid(R));
+    }
+    s->bit_words = (uint32_t)bitmap_words(units);
+    s->chunk = (uint32_t)std::max(p->steps_per_graph, 64);
+    const size_t hist_words = (size_t)s->H * R * 4;
+    const size_t part_words = (size_t)s->chunk * s->G * R * 4;
+    if ((e = dev_alloc(&s->d_state, units * state_bytes(s->storage))) != hipSuccess ||
+        (e = dev_alloc(&s->d_age, units * age_bytes(s->storage))) != hipSuccess ||
+        (e = dev_alloc(&s->d_iota[0], (size_t)s->bit_words * 8)) != hipSuccess ||
+        (e = dev_alloc(&s->d_iota[1], (size_t)s->bit_words * 8)) != hipSuccess ||
+        (p->record_rates && (e = dev_alloc((void**)&s->d_rates, units * sizeof(float))) != hipSuccess) ||
+        (e = dev_alloc((void**)&s->d_ctl, sizeof(fsi::Ctl))) != hipSuccess ||
+        (e = dev_alloc((void**)&s->d_hist, hist_words * sizeof(uint32_t))) != hipSuccess ||
+        (e = dev_alloc((void**)&s->d_part, part_words * sizeof(uint32_t))) != hipSuccess ||
+        (e = dev_alloc((void**)&s->d_rc_part, RC_GRID * 4 * sizeof(uint32_t))) != hipSuccess ||
+        (e = dev_alloc((void**)&s->d_cnt4, 4 * sizeof(uint32_t))) != hipSuccess)
+        return bad(e, "device allocation");
+    if ((e = hipMemsetAsync(s->d_state, 0, units * state_bytes(s->storage), s->stream)) != hipSuccess ||
+        (e = hipMemsetAsync(s->d_age, 0, units * age_bytes(s->storage), s->stream)) != hipSuccess ||
+        (e = hipMemsetAsync(s->d_iota[0], 0, (size_t)s->bit_words * 8, s->stream)) != hipSuccess ||
+        (e = hipMemsetAsync(s->d_iota[1], 0, (size_t)s->bit_words * 8, s->stream)) != hipSuccess ||
+        (s->d_rates && (e = hipMemsetAsync(s->d_rates, 0, units * sizeof(float), s->stream)) != hipSuccess) ||
+        (e = hipMemsetAsync(s->d_ctl, 0, sizeof(fsi::Ctl), s->stream)) != hipSuccess ||
+        (e = hipMemsetAsync(s->d_hist, 0, hist_words * sizeof(uint32_t), s->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(s->stream)) != hipSuccess)
+        return bad(e, "initialisation");
+
+    StepArgs& a = s->args;
+    a.row_ptr = g->d_row_ptr;
+    a.col_ind = g->d_col_ind;
+    a.weights = g->d_weights;
+    a.state = s->d_state;
+    a.age = s->d_age;
+    a.iota0 = s->d_iota[0];
+    a.iota1 = s->d_iota[1];
+    a.rates = s->d_rates;
+    a.ctl = s->d_ctl;
+    a.part = s->d_part;
+    a.n = (int32_t)g->n;
+    a.lgR = s->lgR;
+    a.step_off = 0;
+    a.ntiles = 0;
+    a.same_kind = hz[0].kind == hz[1].kind;
+    a.hz[0] = hz[0];
+    a.hz[1] = hz[1];
+    a.beta = (float)p->beta;
+    a.dt = (float)p->dt;
+    a.key0 = (uint32_t)p->seed;
+    a.key1 = (uint32_t)(p->seed >> 32);
+    s->kfn = fsk::step_kernel_fn(s->storage, g->d_weights != nullptr, p->record_rates != 0, s->resident);
+    if (!s->kfn) {
+        release_sim(s);
+        return fail(FS_ERR_DEVICE, "no step kernel for this configuration");
+    }
+    *out = s;
+    return FS_OK;
+    FS_GUARD_END
+}
+
+fs_status fs_sim_destroy(fs_sim* s)
+{
+    FS_GUARD_BEGIN
+    if (!s) return fail(FS_ERR_INVALID_ARG, "sim is NULL");
+    DeviceGuard dg(s->device);
+    hipError_t e = hipStreamSynchronize(s->stream);
+    release_sim(s);
+    if (e != hipSuccess) return fail(FS_ERR_DEVICE, std::string("pending work failed: ") + hipGetErrorString(e));
+    return FS_OK;
+    FS_GUARD_END
+}
+
+fs_status fs_sim_seed(fs_sim* s, int32_t replica, int64_t count, const int64_t* nodes, int32_t compartment)
+{
+    FS_GUARD_BEGIN
+    if (!s) return fail(FS_ERR_INVALID_ARG, "sim is NULL");
+    fs_status st = check_replica(s, replica, true);
+    if (st != FS_OK) return st;
+    if (compartment < 0 || compartment > 3) return fail(FS_ERR_INVALID_ARG, "compartment must be in [0, 3]");
+    if (count < 0) return fail(FS_ERR_INVALID_ARG, "count < 0");
+    if (count == 0) return FS_OK;
+    if (!nodes) return fail(FS_ERR_INVALID_ARG, "nodes is NULL");
+    for (int64_t j = 0; j < count; ++j)
+        if (nodes[j] < 0 || nodes[j] >= s->g->n) return fail(FS_ERR_INVALID_ARG, "seed node out of range");
+    DeviceGuard dg(s->device);
+    DevBuf tmp;
+    FS_HIP(dev_alloc(&tmp.p, sizeof(int64_t) * (size_t)count));
+    FS_HIP(hipMemcpyAsync(tmp.p, nodes, sizeof(int64_t) * (size_t)count, hipMemcpyHostToDevice, s->stream));
+    FS_HIP(fsk::launch_seed(s->storage, s->d_state, s->d_age, (const int64_t*)tmp.p, count, s->lgR, replica,
+                            compartment, s->stream));
+    FS_HIP(fsk::launch_rebuild_bits(s->storage, s->d_state, (uint32_t)(s->g->n * s->R),
+                                    (unsigned long long*)s->d_iota[s->step & 1], s->bit_words, s->stream));
+    FS_HIP(hipStreamSynchronize(s->stream));
+    return FS_OK;
+    FS_GUARD_END
+}
+
+fs_status fs_step(fs_sim* s, int64_t n_steps)
+{
+    FS_GUARD_BEGIN
+    if (!s) return fail(FS_ERR_INVALID_ARG, "sim is NULL");
+    if (n_steps < 0) return fail(FS_ERR_INVALID_ARG, "n_steps < 0");
+    if (n_steps == 0) return FS_OK;
+    DeviceGuard dg(s->device);
+    const int b = s->p.steps_per_graph;
+    int64_t rem = n_steps;
+    if (b > 0 && n_steps >= b) {
+        if (!s->exec) {
+            fs_status st = build_graph_exec(s, b);
+            if (st != FS_OK) return st;
+        }
+        for (int64_t r = 0; r < n_steps / b; ++r) FS_HIP(hipGraphLaunch(s->exec, s->stream));
+        rem = n_steps % b;
+    }
+    while (rem > 0) {
+        const uint32_t r = (uint32_t)std::min<int64_t>(rem, s->chunk);
+        fs_status st = launch_sequence(s, r);
+        if (st != FS_OK) return st;
+        rem -= r;
+    }
+    s->step += n_steps;
+    return FS_OK;
+    FS_GUARD_END
+}
+
+fs_status fs_sync(fs_sim* s)
+{
+    if (!s) return fail(FS_ERR_INVALID_ARG, "sim is NULL");
+    DeviceGuard dg(s->device);
+    FS_HIP(hipStreamSynchronize(s->stream));
+    return FS_OK;
+}
+
+fs_status fs_step_index(fs_sim* s, int64_t* out)
+{
+    if (!s || !out) return fail(FS_ERR_INVALID_ARG, "NULL argument");
+    *out = s->step;
+    return FS_OK;
+}
+
+fs_status fs_counts(fs_sim* s, int32_t replica, int64_t out[4])
+{
+    FS_GUARD_BEGIN
+    if (!s || !out) return fail(FS_ERR_INVALID_ARG, "NULL argument");
+    fs_status st = check_replica(s, replica, false);
+    if (st != FS_OK) return st;
+    DeviceGuard dg(s->device);
+    uint32_t h[4];
+    FS_HIP(fsk::launch_recount(s->storage, s->d_state, (int32_t)s->g->n, s->lgR, replica, s->d_rc_part, RC_GRID,
+                               s->d_cnt4, s->stream));
+    FS_HIP(hipMemcpyAsync(h, s->d_cnt4, sizeof h, hipMemcpyDeviceToHost, s->stream));
+    FS_HIP(hipStreamSynchronize(s->stream));
+    for (int c = 0; c < 4; ++c) out[c] = h[c];
+    return FS_OK;
+    FS_GUARD_END
+}
+
+fs_status fs_history(fs_sim* s, int32_t replica, int64_t first_step, int64_t n, int64_t* out)
+{
+    FS_GUARD_BEGIN
+    if (!s || (n > 0 && !out)) return fail(FS_ERR_INVALID_ARG, "NULL argument");
+    fs_status st = check_replica(s, replica, false);
+    if (st != FS_OK) return st;
+    if (n < 0) return fail(FS_ERR_INVALID_ARG, "n < 0");
+    if (n == 0) return FS_OK;
+    const int64_t lo = std::max(s->hist_from, s->step - (int64_t)s->H);
+    if (first_step < lo || first_step + n > s->step)
+        return fail(FS_ERR_INVALID_ARG, "requested steps are not in the kept history [" + std::to_string(lo) +
+                                            ", " + std::to_string(s->step) + ")");
+    DeviceGuard dg(s->device);
+    const size_t row = (size_t)s->R * 4;
+    std::vector<uint32_t> h((size_t)s->H * row);
+    FS_HIP(hipMemcpyAsync(h.data(), s->d_hist, h.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s->stream));
+    FS_HIP(hipStreamSynchronize(s->stream));
+    for (int64_t j = 0; j < n; ++j) {
+        const size_t slot = (size_t)((first_step + j) % s->H);
+        for (int c = 0; c < 4; ++c) out[4 * j + c] = (int64_t)h[slot * row + (size_t)replica * 4 + c];
+    }
+    return FS_OK;
+    FS_GUARD_END
+}
+
+fs_status fs_get_state(fs_sim* s, int32_t replica, int32_t* state, float* age_days, uint16_t* age_steps,
+                       int64_t* step_index)
+{
+    FS_GUARD_BEGIN
+    if (!s || !state) return fail(FS_ERR_INVALID_ARG, "NULL argument");
+    fs_status st = check_replica(s, replica, false);
+    if (st != FS_OK) return st;
+    void* age_out = s->storage == FS_STORAGE_FP32 ? (void*)age_days : (void*)age_steps;
+    if (!age_out || (s->storage == FS_STORAGE_FP32 ? age_steps != nullptr : age_days != nullptr))
+        return fail(FS_ERR_INVALID_ARG, "pass exactly the age array of the sim's storage");
+    DeviceGuard dg(s->device);
+    const size_t n = (size_t)s->g->n;
+    DevBuf ds, da;
+    FS_HIP(dev_alloc(&ds.p, n * sizeof(int32_t)));
+    FS_HIP(dev_alloc(&da.p, n * age_bytes(s->storage)));
+    FS_HIP(fsk::launch_get_replica(s->storage, s->d_state, s->d_age, (int32_t*)ds.p, da.p, (int32_t)n, s->lgR,
+                                   replica, s->stream));
+    FS_HIP(hipMemcpyAsync(state, ds.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s->stream));
+    FS_HIP(hipMemcpyAsync(age_out, da.p, n * age_bytes(s->storage), hipMemcpyDeviceToHost, s->stream));
+    FS_HIP(hipStreamSynchronize(s->stream));
+    if (step_index) *step_index = s->step;
+    return FS_OK;
+    FS_GUARD_END
+}
+
+fs_status fs_set_state(fs_sim* s, int32_t replica, const int32_t* state, const float* age_days,
+                       const uint16_t* age_steps, int64_t step_index)
+{
+    FS_GUARD_BEGIN
+    if (!s || !state) return fail(FS_ERR_INVALID_ARG, "NULL argument");
+    fs_status st = check_replica(s, replica, false);
+    if (st != FS_OK) return st;
+    const void* age_in = s->storage == FS_STORAGE_FP32 ? (const void*)age_days : (const void*)age_steps;
+    if (!age_in || (s->storage == FS_STORAGE_FP32 ? age_steps != nullptr : age_days != nullptr))
+        return fail(FS_ERR_INVALID_ARG, "pass exactly the age array of the sim's storage");
+    if (step_index < -1) return fail(FS_ERR_INVALID_ARG, "step_index must be >= -1");
+    const size_t n = (size_t)s->g->n;
+    for (size_t i = 0; i < n; ++i)
+        if (state[i] < 0 || state[i] > 3) return fail(FS_ERR_INVALID_ARG, "state values must lie in [0, 3]");
+    if (s->storage == FS_STORAGE_FP32)
+        for (size_t i = 0; i < n; ++i)
+            if (!(age_days[i] >= 0.0f) || !std::isfinite(age_days[i]))
+                return fail(FS_ERR_INVALID_ARG, "ages must be finite and >= 0");
+    DeviceGuard dg(s->device);
+    const int64_t new_step = step_index >= 0 ? step_index : s->step;
+    const size_t units = n * (size_t)s->R;
+    DevBuf ds, da;
+    FS_HIP(dev_alloc(&ds.p, n * sizeof(int32_t)));
+    FS_HIP(dev_alloc(&da.p, n * age_bytes(s->storage)));
+    FS_HIP(hipMemcpyAsync(ds.p, state, n * sizeof(int32_t), hipMemcpyHostToDevice, s->stream));
+    FS_HIP(hipMemcpyAsync(da.p, age_in, n * age_bytes(s->storage), hipMemcpyHostToDevice, s->stream));
+    FS_HIP(fsk::launch_put_replica(s->storage, s->d_state, s->d_age, (const int32_t*)ds.p, da.p, (int32_t)n, s->lgR,
+                                   replica, s->stream));
+    FS_HIP(fsk::launch_rebuild_bits(s->storage, s->d_state, (uint32_t)units,
+                                    (unsigned long long*)s->d_iota[new_step & 1], s->bit_words, s->stream));
+    if (step_index >= 0) FS_HIP(fsk::launch_set_ctl(s->d_ctl, (unsigned long long)step_index, s->stream));
+    FS_HIP(hipStreamSynchronize(s->stream));
+    if (step_index >= 0) {
+        s->step = step_index;
+        s->hist_from = step_index;
+    }
+    return FS_OK;
+    FS_GUARD_END
+}
+
+fs_status fs_get_rates(fs_sim* s, int32_t replica, float* out)
+{
+    FS_GUARD_BEGIN
+    if (!s || !out) return fail(FS_ERR_INVALID_ARG, "NULL argument");
+    fs_status st = check_replica(s, replica, false);
+    if (st != FS_OK) return st;
+    if (!s->d_rates) return fail(FS_ERR_INVALID_ARG, "sim was created without record_rates");
+    DeviceGuard dg(s->device);
+    const size_t n = (size_t)s->g->n;
+    DevBuf d;
+    FS_HIP(dev_alloc(&d.p, n * sizeof(float)));
+    FS_HIP(fsk::launch_get_rates(s->d_rates, (float*)d.p, (int32_t)n, s->lgR, replica, s->stream));
+    FS_HIP(hipMemcpyAsync(out, d.p, n * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+    FS_HIP(hipStreamSynchronize(s->stream));
+    return FS_OK;
+    FS_GUARD_END
+}
+
+fs_status fs_eval_hazard(const fs_dist* law, int32_t storage, double dt, int64_t n, const void* ages, float* out)
+{
+    FS_GUARD_BEGIN
+    if (!law || (n > 0 && (!ages || !out))) return fail(FS_ERR_INVALID_ARG, "NULL argument");
+    if (storage != FS_STORAGE_FP32 && storage != FS_STORAGE_COMPACT) return fail(FS_ERR_INVALID_ARG, "unknown storage");
+    if (!(dt > 0.0)) return fail(FS_ERR_INVALID_ARG, "dt must be > 0");
+    if (n < 0) return fail(FS_ERR_INVALID_ARG, "n < 0");
+    HazardDev h;
+    fs_status st = prep_hazard(*law, storage, dt, &h, "law");
+    if (st != FS_OK) return st;
+    if (n == 0) return FS_OK;
+    const size_t ab = storage == FS_STORAGE_FP32 ? 4 : 2;
+    DevBuf da, dout;
+    FS_HIP(dev_alloc(&da.p, (size_t)n * ab));
+    FS_HIP(dev_alloc(&dout.p, (size_t)n * sizeof(float)));
+    FS_HIP(hipMemcpy(da.p, ages, (size_t)n * ab, hipMemcpyHostToDevice));
+    FS_HIP(fsk::launch_eval_hazard(h, storage, da.p, (float*)dout.p, n, nullptr));
+    FS_HIP(hipMemcpy(out, dout.p, (size_t)n * sizeof(float), hipMemcpyDeviceToHost));
+    FS_HIP(hipDeviceSynchronize());
+    return FS_OK;
+    FS_GUARD_END
+}
+
+fs_status fs_eval_philox(int64_t n, const uint32_t* ctr, uint64_t seed, uint32_t* out)
+{
+    FS_GUARD_BEGIN
+    if (n < 0 || (n > 0 && (!ctr || !out))) return fail(FS_ERR_INVALID_ARG, "bad argument");
+    if (n == 0) return FS_OK;
+    DevBuf dc, dout;
+    FS_HIP(dev_alloc(&dc.p, (size_t)n * 16));
+    FS_HIP(dev_alloc(&dout.p, (size_t)n * 16));
+    FS_HIP(hipMemcpy(dc.p, ctr, (size_t)n * 16, hipMemcpyHostToDevice));
+    FS_HIP(fsk::launch_eval_philox((const uint4*)dc.p, (uint32_t)seed, (uint32_t)(seed >> 32), (uint4*)dout.p, n,
+                                   nullptr));
+    FS_HIP(hipMemcpy(out, dout.p, (size_t)n * 16, hipMemcpyDeviceToHost));
+    FS_HIP(hipDeviceSynchronize());
+    return FS_OK;
+    FS_GUARD_END
+}
+
+} // extern "C"

@@ -18,3 +18,7 @@ def orc():
     import oracle
     oracle.lib()
     return oracle
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+if HERE not in sys.path:
+    sys.path.insert(0, HERE)

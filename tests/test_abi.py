@@ -1,0 +1,88 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and its host-side validation rejects bad input with the
+documented status codes before touching a device."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2604_22092_amd as fs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "fs.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fs_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_the_documented_api():
+    decl = declared_symbols()
+    for name in ["fs_graph_create", "fs_sim_create", "fs_step", "fs_counts", "fs_history",
+                 "fs_get_state", "fs_set_state", "fs_sim_seed"]:
+        assert name in decl
+    assert sorted(fs.EXPORTS) == decl
+
+
+def test_library_exports_every_declared_symbol():
+    L = fs.lib()
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+
+
+def test_status_strings_and_version():
+    L = fs.lib()
+    assert L.fs_status_string(0) == b"FS_OK"
+    assert L.fs_status_string(2) == b"FS_ERR_INVALID_CSR"
+    assert L.fs_status_string(5) == b"FS_ERR_BUSY"
+    assert "gfx950" in fs.fs_version()
+
+
+@pytest.mark.parametrize("rp,ci,msg", [
+    ([1, 2, 2], [0, 1], "row_ptr[0]"),
+    ([0, 2, 1], [1, 0], "decreases"),
+    ([0, 1, 2], [1, 2], "out of range"),
+    ([0, 1, 2], [-1, 0], "out of range"),
+])
+def test_invalid_csr_rejected(rp, ci, msg):
+    with pytest.raises(fs.FsError) as ei:
+        fs.fs_graph_create(np.array(rp), np.array(ci))
+    assert ei.value.status == 2 and msg in str(ei.value)
+
+
+def test_invalid_n_rejected():
+    L = fs.lib()
+    import ctypes
+    h = ctypes.c_void_p()
+    assert L.fs_graph_create(0, None, None, None, ctypes.byref(h)) == 1
+    assert h.value is None
+    assert L.fs_graph_create(1, None, None, None, ctypes.byref(h)) == 1
+    assert b"row_ptr" in L.fs_last_error()
+
+
+def test_null_handles_rejected():
+    L = fs.lib()
+    assert L.fs_step(None, 1) == 1
+    assert L.fs_sync(None) == 1
+    assert L.fs_sim_destroy(None) == 1
+    assert L.fs_graph_destroy(None) == 1
+    assert L.fs_counts(None, 0, None) == 1
+
+
+def test_bad_hazard_parameters_rejected_on_host():
+    # parameter validation happens before any device work
+    for spec in [("weibull", 0.5, 3.0), ("lognormal", 0.0, 0.0), ("erlang", 0, 1.0),
+                 ("erlang", 3, -1.0), ("exp", -1.0)]:
+        with pytest.raises(fs.FsError) as ei:
+            fs.fs_eval_hazard(spec, np.array([1.0], np.float32))
+        assert ei.value.status == 1
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    from paper_2604_22092_amd import _capi
+    monkeypatch.setattr(_capi, "_lib", None)
+    monkeypatch.setattr(_capi, "LIB_PATH", str(tmp_path / "absent.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        _capi.lib()

@@ -1,0 +1,424 @@
+"""Parity of the HIP step (through the C ABI) with the FP64 oracle.
+
+Inputs are the seeded synthetic graphs of workloads/: the random 10-regular
+graph with N = 1e4 (log-normal E and I, beta = 0.06, dt = 0.1, ten exposed
+seeds) is the small case the oracle finishes in seconds; other sizes cover
+ragged tails, replicas and the other holding-time laws.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2604_22092_amd as fs
+import workloads as W
+from _parity import check_mismatch_budget, check_one_step, check_rates, guard_band_mismatches
+
+pytestmark = pytest.mark.gpu
+
+SMALL = W.WORKLOADS["regular10_n1e4"]
+
+
+@pytest.fixture(scope="module")
+def small_graph():
+    rp, ci = W.workload_graph(SMALL["graph"])
+    g = fs.Graph(rp, ci)
+    yield rp, ci, g
+    g.close()
+
+
+def storage_of(compact):
+    return fs.FS_STORAGE_COMPACT if compact else fs.FS_STORAGE_FP32
+
+
+def zero_age(n, compact):
+    return np.zeros(n, np.uint16 if compact else np.float32)
+
+
+# ------------------------------------------------------------ building blocks
+
+def test_device_philox_matches_oracle():
+    rng = np.random.default_rng(5)
+    n = 1_000_000
+    ctr = rng.integers(0, 2**32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    for seed in [0, 0x0123456789ABCDEF]:
+        key = np.array([seed & 0xFFFFFFFF, seed >> 32], np.uint32)
+        np.testing.assert_array_equal(fs.fs_eval_philox(ctr, seed), oracle.philox4x32(ctr, key))
+
+
+HAZARD_LAWS = [
+    W.LN_E, W.LN_I, ("lognormal", math.log(4.0), 0.668), ("lognormal", math.log(2.0), 0.3),
+    ("lognormal", math.log(6.0), 0.8), ("weibull", 2.0, 6.0), ("weibull", 1.5, 3.0),
+    ("weibull", 3.0, 8.0), ("weibull", 1.0, 4.0), ("erlang", 3, 1.0), ("erlang", 2, 1.0 / 3.0),
+    ("erlang", 5, 5.0 / 6.0), ("erlang", 1, 0.5), ("exp", 0.25),
+]
+
+
+@pytest.mark.parametrize("law", HAZARD_LAWS, ids=lambda l: "-".join(str(x)[:6] for x in l))
+def test_device_hazard_fp32_days_within_2e6(law):
+    # float32 ages: every multiple-of-dt age the FP32 path accumulates over 400
+    # days for dt = 0.1 and 0.2, plus a dense log grid
+    ages = [np.zeros(1, np.float32)]
+    for dt in [np.float32(0.1), np.float32(0.2)]:
+        a = np.cumsum(np.full(4000, dt, np.float32), dtype=np.float32)
+        ages.append(a)
+    ages.append(np.geomspace(1e-3, 1e3, 200_000).astype(np.float32))
+    tau = np.concatenate(ages)
+    got = fs.fs_eval_hazard(law, tau, fs.FS_STORAGE_FP32)
+    ref = oracle.hazard(law, tau.astype(np.float64))
+    worst = check_rates(got, ref, f"hazard {law}")
+    print(f"hazard {law}: max rel err {worst:.3e}")
+
+
+@pytest.mark.parametrize("law", HAZARD_LAWS, ids=lambda l: "-".join(str(x)[:6] for x in l))
+@pytest.mark.parametrize("dt", [0.1, 0.2])
+def test_device_hazard_compact_steps_within_2e6(law, dt):
+    n = np.arange(65536, dtype=np.uint16)
+    got = fs.fs_eval_hazard(law, n, fs.FS_STORAGE_COMPACT, dt)
+    ref = oracle.hazard(law, n.astype(np.float64) * dt)
+    check_rates(got, ref, f"hazard {law} steps dt={dt}")
+
+
+# ----------------------------------------------------------- one-step parity
+
+def oracle_checkpoints(rp, ci, model, seeds, ks, compact):
+    n = len(rp) - 1
+    st = W.initial_state(n, seeds)
+    age = zero_age(n, compact)
+    out = {}
+    k0 = 0
+    for k in ks:
+        if k > k0:
+            st, age, _ = oracle.run((rp, ci), model, st, age, k - k0, step0=k0, compact=compact)
+            k0 = k
+        out[k] = (st.copy(), age.copy())
+    return out
+
+
+@pytest.mark.parametrize("compact", [False, True], ids=["fp32", "compact"])
+def test_one_step_parity_at_checkpoints(small_graph, compact):
+    rp, ci, g = small_graph
+    n = len(rp) - 1
+    ks = [0, 50, 100, 150, 200, 250]
+    total_upd, total_mism = 0, 0
+    for seed in [0, 1, 2**40 + 3]:
+        model = dict(SMALL["model"], seed=seed)
+        seeds = W.seed_nodes(n, SMALL["seeds"], SMALL["seed_rng"] + seed % 7)
+        cps = oracle_checkpoints(rp, ci, model, seeds, ks, compact)
+        sim = fs.Sim.from_model(g, model, storage=storage_of(compact), record_rates=True)
+        try:
+            for k in ks:
+                st, age = cps[k]
+                sim.set_state(st, age, 0, step_index=k)
+                sim.step(1)
+                gst, gage, gk = sim.get_state(0)
+                assert gk == k + 1
+                ora = oracle.step((rp, ci), model, st, age, (st == 2).astype(np.float64), k,
+                                  compact=compact)
+                label = f"seed={seed} k={k} {'compact' if compact else 'fp32'}"
+                nm, worst = check_one_step({"state": gst, "age": gage, "rates": sim.rates(0)},
+                                           ora, st, label)
+                total_upd += n
+                total_mism += nm
+                # per-step counts recorded by the kernel equal an exact recount
+                np.testing.assert_array_equal(sim.history(k, 1)[0], np.bincount(gst, minlength=4))
+                np.testing.assert_array_equal(sim.counts(0), np.bincount(gst, minlength=4))
+        finally:
+            sim.close()
+    check_mismatch_budget(total_mism, total_upd, "checkpoints")
+
+
+# ------------------------------------------------------- whole trajectories
+
+VARIANTS = {"stream": fs.VARIANT_STREAM, "resident": fs.VARIANT_RESIDENT}
+
+
+def run_gpu(g, model, seeds, steps, n, compact=False, b=0, replicas=1, variant=0):
+    sim = fs.Sim.from_model(g, model, storage=storage_of(compact), steps_per_graph=b,
+                            replicas=replicas, variant=variant)
+    sim.seed(seeds, replica=-1, compartment=fs.FS_E)
+    sim.step(steps)
+    res = [(*sim.get_state(r)[:2], sim.history(0, steps, r)) for r in range(replicas)]
+    sim.close()
+    return res
+
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
+@pytest.mark.parametrize("compact", [False, True], ids=["fp32", "compact"])
+def test_trajectory_matches_oracle(small_graph, compact, variant):
+    rp, ci, g = small_graph
+    n = len(rp) - 1
+    model = SMALL["model"]
+    seeds = W.seed_nodes(n, SMALL["seeds"], SMALL["seed_rng"])
+    steps = SMALL["steps"]
+    (gst, gage, ghist), = run_gpu(g, model, seeds, steps, n, compact, b=50,
+                                  variant=VARIANTS[variant])
+    ost, oage, ohist = oracle.run((rp, ci), model, W.initial_state(n, seeds), zero_age(n, compact),
+                                  steps, compact=compact)
+    # a divergence would have to start at a guard-band draw; none is expected
+    # (about 1e-3 over the whole run), so the trajectories are compared exactly
+    np.testing.assert_array_equal(ghist, ohist)
+    np.testing.assert_array_equal(gst, ost)
+    np.testing.assert_array_equal(gage, oage)
+    np.testing.assert_array_equal(ghist.sum(1), n)
+
+
+def test_graph_replay_equals_eager(small_graph):
+    rp, ci, g = small_graph
+    n = len(rp) - 1
+    model = dict(SMALL["model"], beta=0.15)
+    seeds = W.seed_nodes(n, 40, 3)
+    ref = run_gpu(g, model, seeds, 137, n, b=0)[0]
+    for b in [50, 7, 1]:
+        got = run_gpu(g, model, seeds, 137, n, b=b)[0]
+        for x, y in zip(got, ref):
+            np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("compact", [False, True], ids=["fp32", "compact"])
+def test_stream_and_resident_variants_identical(compact):
+    # a scale-free graph whose hub tiles overflow the LDS column stage
+    n = 20_000
+    rp, ci = W.barabasi_albert(n, 4, 6)
+    model = {"ei": ("erlang", 3, 1.0), "ir": ("weibull", 2.0, 6.0), "beta": 0.08, "dt": 0.1,
+             "seed": 21}
+    seeds = W.seed_nodes(n, 30, 1)
+    with fs.Graph(rp, ci) as g:
+        a = run_gpu(g, model, seeds, 150, n, compact, b=25, replicas=2, variant=fs.VARIANT_STREAM)
+        b = run_gpu(g, model, seeds, 150, n, compact, b=25, replicas=2, variant=fs.VARIANT_RESIDENT)
+    for ra, rb in zip(a, b):
+        for x, y in zip(ra, rb):
+            np.testing.assert_array_equal(x, y)
+
+
+def test_resident_variant_size_limit():
+    # the LDS-resident bitmap holds at most 2^20 units; larger sims take the
+    # streaming variant automatically and refuse an explicit resident request
+    n = (1 << 20) + 1
+    rp = np.zeros(n + 1, np.int32)
+    with fs.Graph(rp, np.zeros(0, np.int32)) as g:
+        with pytest.raises(fs.FsError):
+            fs.Sim(g, W.LN_E, W.LN_I, 0.1, 0.1, variant=fs.VARIANT_RESIDENT)
+        sim = fs.Sim(g, W.LN_E, W.LN_I, 0.1, 0.1, variant=fs.VARIANT_AUTO)
+        sim.seed([0, n - 1], replica=0, compartment=fs.FS_I)
+        sim.step(3)
+        assert sim.counts(0)[2] + sim.counts(0)[3] == 2
+        sim.close()
+
+
+def test_split_step_calls_equal_one_call(small_graph):
+    rp, ci, g = small_graph
+    n = len(rp) - 1
+    model = SMALL["model"]
+    seeds = W.seed_nodes(n, 10, 9)
+    sim = fs.Sim.from_model(g, model, steps_per_graph=10)
+    sim.seed(seeds, replica=0)
+    for chunk in [3, 10, 25, 1, 61]:
+        sim.step(chunk)
+    a = sim.get_state(0)
+    ha = sim.history(0, 100)
+    sim.close()
+    (st, age, hist), = run_gpu(g, model, seeds, 100, n, b=0)
+    np.testing.assert_array_equal(a[0], st)
+    np.testing.assert_array_equal(a[1], age)
+    np.testing.assert_array_equal(ha, hist)
+
+
+def test_checkpoint_resume_is_bit_exact(small_graph):
+    rp, ci, g = small_graph
+    n = len(rp) - 1
+    model = dict(SMALL["model"], beta=0.12, seed=77)
+    seeds = W.seed_nodes(n, 25, 4)
+    sim = fs.Sim.from_model(g, model, steps_per_graph=20)
+    sim.seed(seeds, replica=0)
+    sim.step(120)
+    st, age, k = sim.get_state(0)
+    sim.step(80)
+    final = sim.get_state(0)
+    h_tail = sim.history(120, 80)
+    sim.close()
+    sim2 = fs.Sim.from_model(g, model, steps_per_graph=20)
+    sim2.set_state(st, age, 0, step_index=k)
+    sim2.step(80)
+    resumed = sim2.get_state(0)
+    np.testing.assert_array_equal(sim2.history(120, 80), h_tail)
+    sim2.close()
+    np.testing.assert_array_equal(resumed[0], final[0])
+    np.testing.assert_array_equal(resumed[1], final[1])
+    assert resumed[2] == final[2] == 200
+
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
+@pytest.mark.parametrize("replicas", [4, 16, 64])
+def test_replicas_match_oracle_per_replica(replicas, variant):
+    n = 1500  # not a multiple of the workgroup size
+    rp, ci = W.random_regular(n, 10, 11)
+    model = {"ei": W.LN_E, "ir": W.LN_I, "beta": 0.15, "dt": 0.1, "seed": 5}
+    seeds = W.seed_nodes(n, 15, 2)
+    steps = 120
+    with fs.Graph(rp, ci) as g:
+        res = run_gpu(g, model, seeds, steps, n, b=30, replicas=replicas,
+                      variant=VARIANTS[variant])
+    check = range(replicas) if replicas <= 16 else [0, 1, 31, 63]
+    for r in check:
+        ost, oage, ohist = oracle.run((rp, ci), model, W.initial_state(n, seeds),
+                                      np.zeros(n, np.float32), steps, replica=r)
+        np.testing.assert_array_equal(res[r][2], ohist, err_msg=f"replica {r}")
+        np.testing.assert_array_equal(res[r][0], ost)
+        np.testing.assert_array_equal(res[r][1], oage)
+
+
+def test_other_laws_on_scale_free_graph():
+    # Erlang(k=3, mean 3 d) and Weibull(2, 6 d) on a small Barabasi-Albert graph
+    n = 5000
+    rp, ci = W.barabasi_albert(n, 5, 2)
+    model = W.WORKLOADS["ba5_n1e6"]["model"]
+    seeds = W.seed_nodes(n, 20, 8)
+    for compact in [False, True]:
+        with fs.Graph(rp, ci) as g:
+            (gst, gage, ghist), = run_gpu(g, model, seeds, 200, n, compact, b=25)
+        ost, oage, ohist = oracle.run((rp, ci), model, W.initial_state(n, seeds),
+                                      zero_age(n, compact), 200, compact=compact)
+        np.testing.assert_array_equal(ghist, ohist)
+        np.testing.assert_array_equal(gst, ost)
+        np.testing.assert_array_equal(gage, oage)
+
+
+def test_weighted_graph_one_step():
+    n = 3000
+    rp, ci = W.random_regular(n, 8, 12)
+    w = np.random.default_rng(1).random(len(ci)).astype(np.float32) * 2
+    model = {"ei": W.LN_E, "ir": W.LN_I, "beta": 0.3, "dt": 0.1, "seed": 3}
+    rng = np.random.default_rng(4)
+    st = rng.choice(4, size=n, p=[0.6, 0.1, 0.2, 0.1]).astype(np.int32)
+    age = (rng.integers(0, 200, n) * np.float32(0.1)).astype(np.float32)
+    with fs.Graph(rp, ci, w) as g:
+        sim = fs.Sim.from_model(g, model, record_rates=True)
+        sim.set_state(st, age, 0, step_index=42)
+        sim.step(1)
+        gst, gage, _ = sim.get_state(0)
+        rates = sim.rates(0)
+        sim.close()
+    ora = oracle.step((rp, ci, w), model, st, age, (st == 2).astype(np.float64), 42)
+    # weighted pressures are sums of float32 products: rounding order differs
+    # from the oracle's FP64 sum, so rates agree to ~d ulps rather than exactly
+    check_one_step({"state": gst, "age": gage, "rates": rates}, ora, st, "weighted")
+
+
+# ------------------------------------------------------------- edge cases
+
+def test_edge_cases_tiny_graphs():
+    model = {"ei": W.LN_E, "ir": W.LN_I, "beta": 0.5, "dt": 0.1, "seed": 1}
+    cases = {
+        "single isolated node": (np.array([0, 0]), np.zeros(0)),
+        "single self-loop": (np.array([0, 1]), np.array([0])),
+        "empty rows and a multi-edge": (np.array([0, 0, 3, 3, 4]), np.array([0, 0, 3, 1])),
+        "ragged 257": W.random_regular(257, 4, 1),
+    }
+    for name, (rp, ci) in cases.items():
+        n = len(rp) - 1
+        rng = np.random.default_rng(n)
+        st = rng.integers(0, 4, n).astype(np.int32)
+        age = (rng.integers(0, 100, n) * np.float32(0.1)).astype(np.float32)
+        with fs.Graph(rp, ci) as g:
+            sim = fs.Sim.from_model(g, model, record_rates=True)
+            sim.set_state(st, age, 0, step_index=3)
+            sim.step(1)
+            gst, gage, _ = sim.get_state(0)
+            rates = sim.rates(0)
+            np.testing.assert_array_equal(sim.counts(0), np.bincount(gst, minlength=4))
+            sim.close()
+        ora = oracle.step((rp, ci), model, st, age, (st == 2).astype(np.float64), 3)
+        check_one_step({"state": gst, "age": gage, "rates": rates}, ora, st, name)
+
+
+def test_all_recovered_is_a_fixed_point():
+    n = 1000
+    rp, ci = W.random_regular(n, 6, 3)
+    with fs.Graph(rp, ci) as g:
+        sim = fs.Sim(g, W.LN_E, W.LN_I, 0.5, 0.1, steps_per_graph=5)
+        sim.set_state(np.full(n, 3, np.int32), np.zeros(n, np.float32), 0, step_index=0)
+        sim.step(12)
+        st, age, _ = sim.get_state(0)
+        hist = sim.history(0, 12)
+        sim.close()
+    assert np.all(st == 3)
+    np.testing.assert_array_equal(hist, np.tile([0, 0, 0, n], (12, 1)))
+    a = np.float32(0.0)
+    for _ in range(12):
+        a = np.float32(a + np.float32(0.1))
+    np.testing.assert_array_equal(age, a)  # ages of R nodes still advance (never used)
+
+
+def test_history_window_and_errors(small_graph):
+    rp, ci, g = small_graph
+    sim = fs.Sim.from_model(g, SMALL["model"], history_len=8)
+    try:
+        sim.seed([1, 2, 3], replica=0)
+        sim.step(20)
+        h = sim.history(12, 8)  # the last history_len steps are kept
+        st, _, _ = sim.get_state(0)
+        np.testing.assert_array_equal(h[-1], np.bincount(st, minlength=4))
+        with pytest.raises(fs.FsError):
+            sim.history(11, 2)
+        with pytest.raises(fs.FsError):
+            sim.history(15, 6)
+        with pytest.raises(fs.FsError):
+            fs.fs_graph_destroy(g.handle)  # still used by the sim
+    finally:
+        sim.close()
+
+
+# ----------------------------------------------- full size, sampled parity
+
+def test_full_size_regular10_n1e6_sampled_parity():
+    wl = W.WORKLOADS["regular10_n1e6"]
+    rp, ci = W.workload_graph(wl["graph"])
+    n = len(rp) - 1
+    model = wl["model"]
+    seeds = W.seed_nodes(n, wl["seeds"], wl["seed_rng"])
+    with fs.Graph(rp, ci) as g:
+        sim = fs.Sim.from_model(g, model, steps_per_graph=50, record_rates=True)
+        sim.seed(seeds, replica=0)
+        sim.step(400)  # the launch configuration of the benchmark: captured b = 50 steps
+        st, age, k = sim.get_state(0)
+        hist = sim.history(0, 400)
+        np.testing.assert_array_equal(hist[-1], np.bincount(st, minlength=4))
+        np.testing.assert_array_equal(hist.sum(1), n)
+        sim.step(1)
+        gst, gage, _ = sim.get_state(0)
+        rates = sim.rates(0)
+        sim.close()
+    nodes = np.random.default_rng(0).choice(n, 100_000, replace=False)
+    iota = (st == 2).astype(np.float64)
+    ora = oracle.step_nodes((rp, ci), model, st, age, iota, k, nodes)
+    nm = guard_band_mismatches(gst[nodes], ora["state"], ora["u"], ora["q"], "N=1e6 sample")
+    check_mismatch_budget(nm, len(nodes), "N=1e6 sample")
+    same = gst[nodes] == ora["state"]
+    np.testing.assert_array_equal(gage[nodes][same], ora["age"][same])
+    check_rates(rates[nodes], ora["lam"], "N=1e6 sample")
+    assert (st != 0).sum() > 1000  # the epidemic is under way at the checkpoint
+
+
+# ------------------------------------------------------ ensemble statistics
+
+def test_ensemble_peak_prevalence_and_attack_rate(small_graph):
+    rp, ci, g = small_graph
+    n = len(rp) - 1
+    model = dict(SMALL["model"], beta=0.08, seed=1234)
+    seeds = W.seed_nodes(n, SMALL["seeds"], SMALL["seed_rng"])
+    steps, R = 300, 64
+    res = run_gpu(g, model, seeds, steps, n, b=50, replicas=R)
+    gpk = np.array([h[:, 2].max() / n for _, _, h in res])
+    gar = np.array([1 - h[-1, 0] / n for _, _, h in res])
+    opk, oar = [], []
+    for r in range(R, 2 * R):  # independent oracle replicas (other Philox streams)
+        _, _, h = oracle.run((rp, ci), model, W.initial_state(n, seeds), np.zeros(n, np.float32),
+                             steps, replica=r)
+        opk.append(h[:, 2].max() / n)
+        oar.append(1 - h[-1, 0] / n)
+    opk, oar = np.array(opk), np.array(oar)
+    for a, b, name in [(gpk, opk, "peak prevalence"), (gar, oar, "attack rate")]:
+        se = math.sqrt(a.var(ddof=1) / len(a) + b.var(ddof=1) / len(b))
+        assert abs(a.mean() - b.mean()) < 3 * se, (name, a.mean(), b.mean(), se)
