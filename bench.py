@@ -94,6 +94,9 @@ def main():
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
     ap.add_argument("--variant", choices=["auto", "stream", "resident"], default="auto",
                     help="step kernel variant (auto: LDS-resident bitmap when N*R <= 2^20)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB, so a "
+                         "counter profile of the same process can scale HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
@@ -120,6 +123,16 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.Stream(device=dev)
+    if args.copy_calibration_mib > 0:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print(f"[bench] calibration copy of {args.copy_calibration_mib} MiB done", file=sys.stderr,
+              flush=True)
     g = fs.Graph(rp, ci)
     variant = {"auto": fs.VARIANT_AUTO, "stream": fs.VARIANT_STREAM,
                "resident": fs.VARIANT_RESIDENT}[args.variant]

@@ -139,6 +139,11 @@ typedef struct fs_sim_params {
     int32_t variant;         /* step kernel: 0 = automatic, 1 = streaming (bitmap read
                                 through the caches), 2 = resident (bitmap held in LDS;
                                 n * n_replicas <= 2^20).  Results are identical. */
+    int32_t heavy_degree;    /* degree bins: rows with more incoming edges than this get
+                                their pressure from the heavy-row kernel (segments of
+                                segment_edges edges, one wavefront each); 0 = 64,
+                                -1 = no bins.  Results are identical for unit weights. */
+    int32_t segment_edges;   /* edges per heavy-row segment, in [64, 2^20]; 0 = 512 */
     void* stream;            /* hipStream_t to run on; NULL = a stream owned by the sim */
 } fs_sim_params;
 
@@ -219,6 +224,22 @@ fs_status fs_set_state(fs_sim* s, int32_t replica, const int32_t* state, const f
  * Requires record_rates at creation.  out: n float32.  Synchronises.
  */
 fs_status fs_get_rates(fs_sim* s, int32_t replica, float* out);
+
+/*
+ * Degree-binned dispatch (Section "CSR traversal strategies and
+ * auto-dispatch", Appendix "Degree-heterogeneous graphs"): rows of degree >
+ * heavy_degree are split into segments of segment_edges edges whose partial
+ * pressures a separate wavefront-per-segment launch computes before each
+ * step launch; the other rows gather in the step kernel itself.
+ * fs_sim_set_bins sets the thresholds (0 selects the defaults, heavy_degree
+ * -1 disables the bins); fs_sim_get_bins reports them and the segment count.
+ * fs_sim_tune times trial_steps steps for each candidate threshold pair from
+ * the current state, restores the state after each trial (the step index and
+ * history are left as they were) and keeps the fastest.  Synchronises.
+ */
+fs_status fs_sim_set_bins(fs_sim* s, int32_t heavy_degree, int32_t segment_edges);
+fs_status fs_sim_get_bins(fs_sim* s, int32_t* heavy_degree, int32_t* segment_edges, int64_t* segments);
+fs_status fs_sim_tune(fs_sim* s, int32_t trial_steps, int32_t* heavy_degree, int32_t* segment_edges);
 
 /* ------------------------------------------------- building-block checks */
 /*

@@ -10,7 +10,7 @@ from ._capi import (FS_DIST_ERLANG, FS_DIST_EXP, FS_DIST_LOGNORMAL, FS_DIST_WEIB
                     Graph, LIB_PATH, Sim, VARIANT_AUTO, VARIANT_RESIDENT, VARIANT_STREAM, fs_counts, fs_eval_hazard, fs_eval_philox,
                     fs_get_rates, fs_get_state, fs_graph_create, fs_graph_destroy,
                     fs_graph_get_info, fs_history, fs_set_state, fs_sim_create,
-                    fs_sim_destroy, fs_sim_seed, fs_step, fs_step_index, fs_sync, fs_version,
+                    fs_sim_destroy, fs_sim_get_bins, fs_sim_seed, fs_sim_set_bins, fs_sim_tune, fs_step, fs_step_index, fs_sync, fs_version,
                     lib, make_dist)
 
 __all__ = [n for n in dir() if not n.startswith("_")]

@@ -30,7 +30,8 @@ EXPORTS = [
     "fs_status_string", "fs_last_error", "fs_graph_create", "fs_graph_destroy",
     "fs_graph_get_info", "fs_sim_create", "fs_sim_destroy", "fs_sim_seed", "fs_step",
     "fs_sync", "fs_step_index", "fs_counts", "fs_history", "fs_get_state", "fs_set_state",
-    "fs_get_rates", "fs_eval_hazard", "fs_eval_philox", "fs_version",
+    "fs_get_rates", "fs_eval_hazard", "fs_eval_philox", "fs_version", "fs_sim_set_bins",
+    "fs_sim_get_bins", "fs_sim_tune",
 ]
 
 
@@ -56,6 +57,7 @@ class fs_sim_params(ctypes.Structure):
                 ("n_replicas", ctypes.c_int32), ("storage", ctypes.c_int32),
                 ("steps_per_graph", ctypes.c_int32), ("history_len", ctypes.c_int32),
                 ("record_rates", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("heavy_degree", ctypes.c_int32), ("segment_edges", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -98,6 +100,10 @@ def _declare(L):
         "fs_get_rates": ([P, I32, P], I32),
         "fs_eval_hazard": ([ctypes.POINTER(fs_dist), I32, ctypes.c_double, I64, P, P], I32),
         "fs_eval_philox": ([I64, P, U64, P], I32),
+        "fs_sim_set_bins": ([P, I32, I32], I32),
+        "fs_sim_get_bins": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                             ctypes.POINTER(ctypes.c_int64)], I32),
+        "fs_sim_tune": ([P, I32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -220,6 +226,23 @@ def fs_get_rates(h, replica: int, n: int) -> np.ndarray:
     return out
 
 
+def fs_sim_set_bins(h, heavy_degree: int, segment_edges: int = 0):
+    _check(lib().fs_sim_set_bins(h, int(heavy_degree), int(segment_edges)), "fs_sim_set_bins")
+
+
+def fs_sim_get_bins(h) -> tuple:
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    _check(lib().fs_sim_get_bins(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+           "fs_sim_get_bins")
+    return a.value, b.value, c.value
+
+
+def fs_sim_tune(h, trial_steps: int) -> tuple:
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().fs_sim_tune(h, int(trial_steps), ctypes.byref(a), ctypes.byref(b)), "fs_sim_tune")
+    return a.value, b.value
+
+
 def fs_eval_hazard(spec, ages, storage: int = FS_STORAGE_FP32, dt: float = 1.0) -> np.ndarray:
     a = np.ascontiguousarray(ages, dtype=np.float32 if storage == FS_STORAGE_FP32 else np.uint16)
     out = np.empty(len(a), dtype=np.float32)
@@ -267,7 +290,7 @@ class Sim:
     def __init__(self, graph: Graph, ei, ir, beta: float, dt: float, seed: int = 0,
                  replicas: int = 1, storage: int = FS_STORAGE_FP32, steps_per_graph: int = 0,
                  history_len: int = 0, record_rates: bool = False, variant: int = 0,
-                 stream=None):
+                 heavy_degree: int = 0, segment_edges: int = 0, stream=None):
         p = fs_sim_params()
         p.ei = make_dist(ei)
         p.ir = make_dist(ir)
@@ -280,6 +303,8 @@ class Sim:
         p.history_len = int(history_len)
         p.record_rates = 1 if record_rates else 0
         p.variant = int(variant)
+        p.heavy_degree = int(heavy_degree)
+        p.segment_edges = int(segment_edges)
         p.stream = None if stream is None else ctypes.c_void_p(int(stream))
         self.graph = graph
         self.n = graph.n
@@ -318,6 +343,16 @@ class Sim:
 
     def rates(self, replica: int = 0) -> np.ndarray:
         return fs_get_rates(self.handle, replica, self.n)
+
+    def set_bins(self, heavy_degree: int, segment_edges: int = 0):
+        fs_sim_set_bins(self.handle, heavy_degree, segment_edges)
+
+    def bins(self) -> tuple:
+        """(heavy_degree, segment_edges, segments)"""
+        return fs_sim_get_bins(self.handle)
+
+    def tune(self, trial_steps: int = 20) -> tuple:
+        return fs_sim_tune(self.handle, trial_steps)
 
     def close(self):
         if self.handle is not None:

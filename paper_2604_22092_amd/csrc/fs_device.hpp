@@ -174,10 +174,11 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        uint32_t hi0 = __umulhi(PH_M0, c.x);
-        uint32_t lo0 = PH_M0 * c.x;
-        uint32_t hi1 = __umulhi(PH_M1, c.z);
-        uint32_t lo1 = PH_M1 * c.z;
+        // one 32x32 -> 64-bit product per multiplier (a single v_mad_u64_u32)
+        const unsigned long long p0 = (unsigned long long)PH_M0 * c.x;
+        const unsigned long long p1 = (unsigned long long)PH_M1 * c.z;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
         k0 += PH_W0;
         k1 += PH_W1;

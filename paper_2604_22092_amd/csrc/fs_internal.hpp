@@ -71,6 +71,44 @@ struct StepArgs {
     float beta;
     float dt;
     uint32_t key0, key1;  // Philox key = (seed low, seed high)
+    // degree bins: rows with degree > heavy_deg take their pressure from the
+    // segment partials of the heavy-row kernel (first segment heavy_first[node],
+    // ceil(degree / seg_edges) segments); nullptr heavy_first: no such rows
+    const int32_t* heavy_first;
+    const void* seg_part; // [segment][R]: uint32 counts, or float with weights
+    int32_t heavy_deg;
+    int32_t seg_edges;
+    // light rows in wavefront-transposed order: for the Q = 64/R nodes of chunk
+    // c, edge j of every row with more than j light edges is stored at
+    // chunk_base[c] + (edges j' < j of the chunk) + (rank of the row among the
+    // chunk's rows with more than j edges).  ldeg[node] is the row's degree,
+    // or HEAVY_ROW for a binned row.
+    const uint16_t* ldeg;
+    const uint32_t* chunk_base;
+    const int32_t* col_t;
+    const float* w_t;
+};
+
+constexpr uint16_t HEAVY_ROW = 0xFFFF;
+
+// One segment of a heavy row: edges [e_begin, e_end) of row `row`.
+struct Segment {
+    int32_t row, e_begin, e_end, pad;
+};
+
+// Kernel arguments of the heavy-row pressure launch of one step.
+struct HeavyArgs {
+    const int32_t* col_ind;
+    const float* weights;
+    const Segment* segs;
+    void* seg_part;
+    const void* iota0;
+    const void* iota1;
+    const Ctl* ctl;
+    uint32_t nseg;
+    int32_t lgR;
+    uint32_t step_off;
+    uint32_t pad;
 };
 
 // Upper bound on step workgroups (they loop over tiles beyond it), chosen so

@@ -34,6 +34,14 @@ struct Store<1> {
     using age_t = uint16_t;
 };
 
+__device__ __forceinline__ uint32_t age_bits(float a) { return __float_as_uint(a); }
+__device__ __forceinline__ uint32_t age_bits(uint16_t a) { return a; }
+template <class T>
+__device__ __forceinline__ float age_from_bits(uint32_t w);
+template <>
+__device__ __forceinline__ float age_from_bits<float>(uint32_t w) { return __uint_as_float(w); }
+template <>
+__device__ __forceinline__ float age_from_bits<uint16_t>(uint32_t w) { return (float)w; }
 __device__ __forceinline__ float age_units(float a) { return a; }
 __device__ __forceinline__ float age_units(uint16_t a) { return (float)a; }
 __device__ __forceinline__ float age_next(float a, float dt) { return a + dt; }
@@ -46,37 +54,162 @@ __device__ __forceinline__ uint32_t bit_at(const uint32_t* __restrict__ w, uint3
     return (w[b >> 5] >> (b & 31)) & 1u;
 }
 
-// Pressure of one row (Eq. (influence) without beta): the sum over its edges
-// of w_e * bit[col_e * R + rep].  Columns are fetched PB at a time with
-// clamped, unconditional loads so one round trip covers a whole batch (the
-// surplus lanes re-read the row's last entry and are masked out).  Unit
-// weights count bits exactly in an integer.
-constexpr int PB = 16;
+// Chunks of 64 units each wavefront takes per pass; the hazards and draws of
+// a pass are evaluated on compacted lanes.
+constexpr int CU = 4;
 
-template <bool WEIGHTED>
-__device__ __forceinline__ float pressure(const int32_t* __restrict__ col_ind, const float* __restrict__ w,
-                                          int32_t e0, int32_t e1, const uint32_t* __restrict__ bits,
-                                          int32_t lgR, uint32_t rep)
+// Pressure of the light rows of CU chunks (lam[u] = beta * pressure for S
+// units, 0 otherwise) from the wavefront-transposed column layout: edge slot j
+// of the chunk's rows is one contiguous run, so every slot is one coalesced
+// load.  When all rows of a chunk have the same light degree d (regular
+// graphs), slot j of row q sits at base + j*Q + q; otherwise a row's position
+// in run j is its rank among the rows with more than j edges (ballot prefix
+// count).  Loads are issued JB slots at a time before they are consumed.
+// Binned rows read their segment partials in segment order.
+constexpr int JB = 8;
+
+__device__ __forceinline__ uint32_t lds_bit(const uint32_t* __restrict__ w, uint32_t b)
 {
-    uint32_t pi = 0;
-    float pw = 0.0f;
-    for (int32_t base = e0; base < e1; base += PB) {
-        int32_t c[PB];
-        float wv[PB];
+    return __builtin_amdgcn_ubfe(w[b >> 5], b & 31, 1);
+}
+
+template <bool WEIGHTED, int CU>
+__device__ __forceinline__ void pressure_multi(const StepArgs& a, const uint32_t* chunk, const int* x,
+                                               const uint32_t* node, const uint16_t* deg,
+                                               const uint32_t* __restrict__ bits, const uint32_t* rep,
+                                               uint32_t lane, float* lam)
+{
+    const int32_t lgR = a.lgR;
+    const uint32_t R = 1u << lgR;
+    const uint32_t q = lane >> lgR; // row of this lane within the chunk
+    // lanes below this lane's row leader (the lane of replica 0 of its node)
+    const unsigned long long below = (1ull << (lane & ~(R - 1))) - 1ull;
 #pragma unroll
-        for (int j = 0; j < PB; ++j) {
-            const int32_t idx = min(base + j, e1 - 1);
-            c[j] = col_ind[idx];
-            if (WEIGHTED) wv[j] = w[idx];
+    for (int u = 0; u < CU; ++u) {
+        lam[u] = 0.0f;
+        const bool heavy = deg[u] == HEAVY_ROW;
+        const uint32_t d = heavy ? 0u : deg[u];
+        const bool want = x[u] == ST_S && !heavy;
+        const uint32_t base = a.chunk_base[chunk[u]];
+        // chunk-wide degree structure (wave-uniform)
+        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+        const bool uniform = __ballot(d != d0) == 0ull;
+        const uint32_t rows = (uint32_t)__popcll(__ballot(rep[u] == 0 && d > 0));
+        uint32_t pi = 0;
+        float pw = 0.0f;
+        if (uniform) {
+            for (uint32_t j0 = 0; j0 < d0; j0 += JB) {
+                int32_t c[JB];
+                float wv[JB];
+#pragma unroll
+                for (int jj = 0; jj < JB; ++jj) {
+                    c[jj] = 0;
+                    wv[jj] = 0.0f;
+                    if (want && j0 + jj < d0) {
+                        const uint32_t idx = base + (j0 + jj) * rows + q;
+                        c[jj] = a.col_t[idx];
+                        if (WEIGHTED) wv[jj] = a.w_t[idx];
+                    }
+                }
+#pragma unroll
+                for (int jj = 0; jj < JB; ++jj) {
+                    if (want && j0 + jj < d0) {
+                        const uint32_t b = lds_bit(bits, ((uint32_t)c[jj] << lgR) + rep[u]);
+                        if (WEIGHTED) pw = __builtin_fmaf(wv[jj], (float)b, pw);
+                        else pi += b;
+                    }
+                }
+            }
+        } else {
+            uint32_t off = base;
+            for (uint32_t j0 = 0;; j0 += JB) {
+                if (__ballot(rep[u] == 0 && d > j0) == 0ull) break;
+                int32_t c[JB];
+                float wv[JB];
+#pragma unroll
+                for (int jj = 0; jj < JB; ++jj) {
+                    const unsigned long long m = __ballot(rep[u] == 0 && d > j0 + jj);
+                    c[jj] = 0;
+                    wv[jj] = 0.0f;
+                    if (want && d > j0 + jj) {
+                        const uint32_t idx = off + (uint32_t)__popcll(m & below);
+                        c[jj] = a.col_t[idx];
+                        if (WEIGHTED) wv[jj] = a.w_t[idx];
+                    }
+                    off += (uint32_t)__popcll(m);
+                }
+#pragma unroll
+                for (int jj = 0; jj < JB; ++jj) {
+                    if (want && d > j0 + jj) {
+                        const uint32_t b = lds_bit(bits, ((uint32_t)c[jj] << lgR) + rep[u]);
+                        if (WEIGHTED) pw = __builtin_fmaf(wv[jj], (float)b, pw);
+                        else pi += b;
+                    }
+                }
+            }
         }
-#pragma unroll
-        for (int j = 0; j < PB; ++j) {
-            const uint32_t b = (base + j < e1) ? bit_at(bits, ((uint32_t)c[j] << lgR) + rep) : 0u;
-            if (WEIGHTED) pw = __builtin_fmaf(wv[j], (float)b, pw);
-            else pi += b;
+        if (want) lam[u] = a.beta * (WEIGHTED ? pw : (float)pi);
+        if (heavy && x[u] == ST_S) {
+            // degree-binned row: partials of its segments, summed in segment order
+            const int32_t dg = a.row_ptr[node[u] + 1] - a.row_ptr[node[u]];
+            const int32_t first = a.heavy_first[node[u]];
+            const int32_t nseg = (dg + a.seg_edges - 1) / a.seg_edges;
+            float p;
+            if (WEIGHTED) {
+                const float* sp = (const float*)a.seg_part;
+                p = 0.0f;
+                for (int32_t j = 0; j < nseg; ++j) p += sp[(size_t)(first + j) * R + rep[u]];
+            } else {
+                const uint32_t* sp = (const uint32_t*)a.seg_part;
+                uint32_t q = 0;
+                for (int32_t j = 0; j < nseg; ++j) q += sp[(size_t)(first + j) * R + rep[u]];
+                p = (float)q;
+            }
+            lam[u] = a.beta * p;
         }
     }
-    return WEIGHTED ? pw : (float)pi;
+}
+
+// Evaluates f on the flagged items of CU chunks with the items packed into
+// consecutive lanes (64 per round), so a computation most lanes skip costs one
+// wavefront pass per 64 items instead of one per chunk.  xch is this
+// wavefront's 64-entry LDS exchange row; f maps a payload word to a result
+// word.  Only flagged items receive a result.
+template <int CU, class F>
+__device__ __forceinline__ void compact_apply(uint32_t* xch, uint32_t lane, const bool* flag,
+                                              const uint32_t* payload, uint32_t* result, F f)
+{
+    unsigned long long m[CU];
+    uint32_t pre[CU + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int u = 0; u < CU; ++u) {
+        m[u] = __ballot(flag[u]);
+        pre[u + 1] = pre[u] + (uint32_t)__popcll(m[u]);
+    }
+    const uint32_t total = pre[CU];
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    uint32_t slot[CU];
+#pragma unroll
+    for (int u = 0; u < CU; ++u) slot[u] = pre[u] + (uint32_t)__popcll(m[u] & lt);
+    for (uint32_t r0 = 0; r0 < total; r0 += 64) {
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+            if (flag[u] && slot[u] >= r0 && slot[u] < r0 + 64) xch[slot[u] - r0] = payload[u];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (r0 + lane < total) xch[lane] = f(xch[lane]);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+            if (flag[u] && slot[u] >= r0 && slot[u] < r0 + 64) result[u] = xch[slot[u] - r0];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
 }
 
 // One fused step.  Units are processed in chunks of 64 (one wavefront, one
@@ -97,6 +230,7 @@ __global__ __launch_bounds__(TPB) void step_kernel(StepArgs a)
 
     __shared__ uint32_t s_cnt[4 * 64];
     __shared__ uint32_t s_bits[RESIDENT ? RESIDENT_BITS / 32 : 1];
+    __shared__ uint32_t s_xch[NW][64];
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63;
@@ -122,63 +256,117 @@ __global__ __launch_bounds__(TPB) void step_kernel(StepArgs a)
 
     uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0; // per-wave counts (R == 1)
 
-    for (uint32_t chunk = blockIdx.x * NW + (tid >> 6); chunk < nchunks; chunk += gridDim.x * NW) {
-        const uint32_t unit = (chunk << 6) + lane;
-        const bool valid = unit < total;
-        const uint32_t node = unit >> a.lgR;
-        const uint32_t rep = unit & (R - 1);
-
-        int x = ST_R;
-        age_t ag = 0;
-        int32_t e0 = 0, e1 = 0;
-        if (valid) {
-            x = (int)state[unit];
-            ag = age[unit];
-            e0 = a.row_ptr[node];
-            e1 = a.row_ptr[node + 1];
+    // Each wavefront takes CU chunks per pass (stride `pass` apart) and runs
+    // every phase for all of them before the next phase, so the loads of the
+    // chunks are in flight together.
+    const uint32_t wave_id = blockIdx.x * NW + (tid >> 6);
+    const uint32_t nwaves = gridDim.x * NW;
+    for (uint32_t base = wave_id; base < nchunks; base += nwaves * CU) {
+        uint32_t chk[CU], unit[CU], node[CU], rep[CU];
+        bool valid[CU];
+        int x[CU];
+        age_t ag[CU];
+        uint16_t dg[CU];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            chk[u] = base + (uint32_t)u * nwaves;
+            const bool live = chk[u] < nchunks;
+            if (!live) chk[u] = nchunks - 1; // a real chunk for the uniform layout walk
+            unit[u] = (chk[u] << 6) + lane;
+            valid[u] = live && unit[u] < total;
+            node[u] = unit[u] >> a.lgR;
+            rep[u] = unit[u] & (R - 1);
+            x[u] = ST_R;
+            ag[u] = 0;
+            dg[u] = 0;
+            if (valid[u]) {
+                x[u] = (int)state[unit[u]];
+                ag[u] = age[unit[u]];
+                dg[u] = a.ldeg[node[u]];
+            }
         }
 
         // 1.-2. rate: beta * pressure for S; hazard at the start-of-step age for E/I; 0 for R
-        float lam = 0.0f;
-        if (x == ST_S) lam = a.beta * pressure<WEIGHTED>(a.col_ind, a.weights, e0, e1, gbits, a.lgR, rep);
-        if (a.same_kind) {
-            if (x == ST_E || x == ST_I) {
-                HazardDev h = a.hz[0];
-                if (x == ST_I) h = a.hz[1];
-                h.kind = a.hz[0].kind;
-                lam = fsd::hazard(h, age_units(ag));
+        float lam[CU];
+        pressure_multi<WEIGHTED, CU>(a, chk, x, node, dg, gbits, rep, lane, lam);
+        // hazards of the E/I units of the pass, on compacted lanes; the payload
+        // is the age bit pattern with bit 31 marking the I -> R law (ages are
+        // non-negative, so bit 31 is free)
+        {
+            bool need[CU];
+            uint32_t pay[CU], res[CU];
+#pragma unroll
+            for (int u = 0; u < CU; ++u) {
+                need[u] = x[u] == ST_E || x[u] == ST_I;
+                pay[u] = age_bits(ag[u]) | (x[u] == ST_I ? 0x80000000u : 0u);
+                res[u] = 0;
             }
-        } else {
-            if (x == ST_E) lam = fsd::hazard(a.hz[0], age_units(ag));
-            if (x == ST_I) lam = fsd::hazard(a.hz[1], age_units(ag));
+            compact_apply<CU>(s_xch[tid >> 6], lane, need, pay, res, [&](uint32_t w) {
+                const bool isI = (w & 0x80000000u) != 0u;
+                const float xa = age_from_bits<age_t>(w & 0x7FFFFFFFu);
+                float h;
+                if (a.same_kind) {
+                    HazardDev hd = a.hz[0];
+                    if (isI) hd = a.hz[1];
+                    hd.kind = a.hz[0].kind;
+                    h = fsd::hazard(hd, xa);
+                } else {
+                    h = isI ? fsd::hazard(a.hz[1], xa) : fsd::hazard(a.hz[0], xa);
+                }
+                return __float_as_uint(h);
+            });
+#pragma unroll
+            for (int u = 0; u < CU; ++u)
+                if (need[u]) lam[u] = __uint_as_float(res[u]);
         }
 
-        // 3.-4. Bernoulli tau-leap: fire when u < 1 - exp(-lambda dt); no draw at lambda = 0
-        bool fire = false;
-        if (lam > 0.0f) {
-            const float u = fsd::step_uniform(node, (uint32_t)k, rep, a.key0, a.key1);
-            const float q = -expm1f(-lam * a.dt);
-            fire = u < q;
+        // 3.-4. Bernoulli tau-leap: fire when u < 1 - exp(-lambda dt); no draw at
+        // lambda = 0.  The Philox draws of the pass run on compacted lanes.
+        bool fire[CU];
+        {
+            bool need[CU];
+            uint32_t pay[CU], res[CU];
+#pragma unroll
+            for (int u = 0; u < CU; ++u) {
+                need[u] = lam[u] > 0.0f;
+                pay[u] = unit[u];
+                res[u] = 0;
+            }
+            const uint32_t kk = (uint32_t)k;
+            compact_apply<CU>(s_xch[tid >> 6], lane, need, pay, res, [&](uint32_t un) {
+                return fsd::philox4x32_10(make_uint4(un >> a.lgR, kk, un & (R - 1), 0u), a.key0, a.key1).x >> 8;
+            });
+#pragma unroll
+            for (int u = 0; u < CU; ++u) {
+                fire[u] = false;
+                if (need[u]) {
+                    const float uu = (float)res[u] * 0x1p-24f;
+                    const float q = -expm1f(-lam[u] * a.dt);
+                    fire[u] = uu < q;
+                }
+            }
         }
 
-        // 5.-6. advance state and age in place
-        const int xn = x + (fire ? 1 : 0);
-        if (valid) {
-            if (fire) state[unit] = (state_t)xn;
-            age[unit] = fire ? (age_t)0 : age_next(ag, a.dt);
-            if (RATES) a.rates[unit] = lam;
-        }
-
-        // 7. next-step infectivity bits (one 64-bit word per chunk) and 8. counts
-        const unsigned long long mI = __ballot(valid && xn == ST_I);
-        if (lane == 0) bits_out[chunk] = mI;
-        if (R == 1) {
-            c0 += (uint32_t)__popcll(__ballot(valid && xn == ST_S));
-            c1 += (uint32_t)__popcll(__ballot(valid && xn == ST_E));
-            c2 += (uint32_t)__popcll(mI);
-            c3 += (uint32_t)__popcll(__ballot(valid && xn == ST_R));
-        } else if (valid) {
-            atomicAdd(&s_cnt[rep * 4 + xn], 1u); // LDS
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            // 5.-6. advance state and age in place
+            const int xn = x[u] + (fire[u] ? 1 : 0);
+            if (valid[u]) {
+                if (fire[u]) state[unit[u]] = (state_t)xn;
+                age[unit[u]] = fire[u] ? (age_t)0 : age_next(ag[u], a.dt);
+                if (RATES) a.rates[unit[u]] = lam[u];
+            }
+            // 7. next-step infectivity bits (one 64-bit word per chunk) and 8. counts
+            const unsigned long long mI = __ballot(valid[u] && xn == ST_I);
+            if (lane == 0 && base + (uint32_t)u * nwaves < nchunks) bits_out[chk[u]] = mI;
+            if (R == 1) {
+                c0 += (uint32_t)__popcll(__ballot(valid[u] && xn == ST_S));
+                c1 += (uint32_t)__popcll(__ballot(valid[u] && xn == ST_E));
+                c2 += (uint32_t)__popcll(mI);
+                c3 += (uint32_t)__popcll(__ballot(valid[u] && xn == ST_R));
+            } else if (valid[u]) {
+                atomicAdd(&s_cnt[rep[u] * 4 + xn], 1u); // LDS
+            }
         }
     }
 
@@ -236,6 +424,42 @@ __global__ __launch_bounds__(WG) void reduce_kernel(const Ctl* ctl, const uint32
 __global__ void advance_kernel(Ctl* ctl, uint32_t r)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) ctl->step = ctl->step + r;
+}
+
+// Pressure partials of heavy-row segments (degree-binned dispatch).  One
+// wavefront per segment: lane l covers edge offset l / R and replica l % R,
+// so the 64 lanes read 64 / R edges per pass; the per-replica totals are
+// folded with a fixed shuffle tree (deterministic) and lanes 0..R-1 store
+// them.  Reads the same start-of-step bitmap as the step launch that follows.
+template <bool WEIGHTED>
+__global__ __launch_bounds__(WG) void heavy_pressure_kernel(HeavyArgs h)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t R = 1u << h.lgR;
+    const uint32_t per = 64u >> h.lgR; // edges per pass
+    const uint32_t eoff = lane >> h.lgR;
+    const uint32_t rep = lane & (R - 1);
+    const unsigned long long k = h.ctl->step + h.step_off;
+    const uint32_t* __restrict__ bits = (const uint32_t*)((k & 1) ? h.iota1 : h.iota0);
+    const uint32_t nwaves = gridDim.x * (WG / 64);
+    for (uint32_t s = blockIdx.x * (WG / 64) + (threadIdx.x >> 6); s < h.nseg; s += nwaves) {
+        const Segment sg = h.segs[s];
+        uint32_t ci = 0;
+        float cw = 0.0f;
+        for (int32_t e = sg.e_begin + (int32_t)eoff; e < sg.e_end; e += (int32_t)per) {
+            const uint32_t b = bit_at(bits, ((uint32_t)h.col_ind[e] << h.lgR) + rep);
+            if (WEIGHTED) cw = __builtin_fmaf(h.weights[e], (float)b, cw);
+            else ci += b;
+        }
+        for (uint32_t off = 32; off >= R && off > 0; off >>= 1) {
+            if (WEIGHTED) cw += __shfl_down(cw, off, 64);
+            else ci += __shfl_down(ci, off, 64);
+        }
+        if (lane < R) {
+            if (WEIGHTED) ((float*)h.seg_part)[(size_t)s * R + lane] = cw;
+            else ((uint32_t*)h.seg_part)[(size_t)s * R + lane] = ci;
+        }
+    }
 }
 
 template <int STORAGE>
@@ -385,6 +609,10 @@ hipError_t launch_recount(int storage, const void* state, int32_t n, int32_t lgR
 }
 
 const void* reduce_kernel_fn() { return (const void*)&reduce_kernel; }
+const void* heavy_kernel_fn(bool weighted)
+{
+    return weighted ? (const void*)&heavy_pressure_kernel<true> : (const void*)&heavy_pressure_kernel<false>;
+}
 const void* advance_kernel_fn() { return (const void*)&advance_kernel; }
 
 hipError_t launch_put_replica(int storage, void* state, void* age, const int32_t* src_state, const void* src_age,

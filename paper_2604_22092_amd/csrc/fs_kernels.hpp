@@ -21,6 +21,8 @@ hipError_t launch_recount(int storage, const void* state, int32_t n, int32_t lgR
 // reduce_kernel(const Ctl*, const uint32_t* part, uint32_t G, uint32_t C, uint32_t* out, uint32_t H):
 // one block per slot, WG threads.
 const void* reduce_kernel_fn();
+// heavy_pressure_kernel(HeavyArgs): segment partials of degree-binned rows; WG threads.
+const void* heavy_kernel_fn(bool weighted);
 // advance_kernel(Ctl*, uint32_t r): adds r to the step index; one thread.
 const void* advance_kernel_fn();
 hipError_t launch_put_replica(int storage, void* state, void* age, const int32_t* src_state, const void* src_age,

@@ -29,6 +29,9 @@ struct fs_graph {
     float* d_weights = nullptr;
     int32_t max_degree = 0;
     double mean_degree = 0.0;
+    std::vector<int32_t> h_row_ptr; // host copies for degree binning and layouts
+    std::vector<int32_t> h_col_ind;
+    std::vector<float> h_weights;
     std::atomic<int> users{0};
 };
 
@@ -59,6 +62,18 @@ struct fs_sim {
     int64_t hist_from = 0; // first step whose count row is recorded
     StepArgs args{};
     const void* kfn = nullptr;
+    // degree bins
+    int32_t heavy_deg = 0;         // rows with degree > heavy_deg are binned; < 0: none
+    int32_t seg_edges = 512;
+    uint32_t nseg = 0;
+    int32_t* d_heavy_first = nullptr;
+    fsi::Segment* d_segs = nullptr;
+    void* d_seg_part = nullptr;
+    uint16_t* d_ldeg = nullptr;       // light degree per node, HEAVY_ROW for binned rows
+    uint32_t* d_chunk_base = nullptr; // wavefront-transposed layout of the light rows
+    int32_t* d_col_t = nullptr;
+    float* d_w_t = nullptr;
+    const void* hfn = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -168,6 +183,8 @@ void release_sim(fs_sim* s)
     if (!s) return;
     if (s->exec) (void)hipGraphExecDestroy(s->exec);
     if (s->graph) (void)hipGraphDestroy(s->graph);
+    s->exec = nullptr;
+    s->graph = nullptr;
     dev_free(s->d_state);
     dev_free(s->d_age);
     dev_free(s->d_iota[0]);
@@ -178,6 +195,13 @@ void release_sim(fs_sim* s)
     dev_free(s->d_part);
     dev_free(s->d_rc_part);
     dev_free(s->d_cnt4);
+    dev_free(s->d_heavy_first);
+    dev_free(s->d_segs);
+    dev_free(s->d_seg_part);
+    dev_free(s->d_ldeg);
+    dev_free(s->d_chunk_base);
+    dev_free(s->d_col_t);
+    dev_free(s->d_w_t);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     if (s->g) s->g->users.fetch_sub(1);
     delete s;
@@ -195,6 +219,7 @@ constexpr uint32_t RC_GRID = 1024;
 // Launch sequence of r steps: r step launches, one reduce, one advance.
 struct SeqArgs {
     std::vector<StepArgs> step;
+    std::vector<fsi::HeavyArgs> heavy;
     const fsi::Ctl* ctl_c;
     fsi::Ctl* ctl;
     const uint32_t* part;
@@ -202,10 +227,130 @@ struct SeqArgs {
     uint32_t* hist;
 };
 
+uint32_t heavy_grid(const fs_sim* s)
+{
+    const uint32_t per_wg = WG / 64;
+    return std::max(1u, std::min((s->nseg + per_wg - 1) / per_wg, 8192u));
+}
+
+void drop_graph_exec(fs_sim* s)
+{
+    if (s->exec) (void)hipGraphExecDestroy(s->exec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    s->exec = nullptr;
+    s->graph = nullptr;
+}
+
+// (Re)builds the degree bins: rows with degree > heavy_deg (and any row of
+// 65535 or more edges) are cut into segments of at most seg_edges edges for
+// the heavy-row kernel; the other rows are laid out wavefront-transposed for
+// the step kernel (see StepArgs::col_t).
+fs_status apply_bins(fs_sim* s, int32_t heavy_deg, int32_t seg_edges)
+{
+    const fs_graph* g = s->g;
+    if (seg_edges < 64 || seg_edges > (1 << 20)) return fail(FS_ERR_INVALID_ARG, "segment_edges must be in [64, 2^20]");
+    const int32_t cap = 65534; // largest light degree a uint16 entry holds
+    const int32_t limit = heavy_deg < 0 ? cap : std::min(heavy_deg, cap);
+    const int64_t n = g->n;
+    const std::vector<int32_t>& rp = g->h_row_ptr;
+    std::vector<int32_t> first;
+    std::vector<fsi::Segment> segs;
+    std::vector<uint16_t> ldeg((size_t)n);
+    if (g->max_degree > limit) first.assign((size_t)n, -1);
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t b = rp[i], e = rp[i + 1];
+        if (e - b <= limit) {
+            ldeg[i] = (uint16_t)(e - b);
+            continue;
+        }
+        ldeg[i] = fsi::HEAVY_ROW;
+        first[i] = (int32_t)segs.size();
+        for (int32_t x = b; x < e; x += seg_edges) segs.push_back({(int32_t)i, x, std::min(e, x + seg_edges), 0});
+    }
+    // wavefront-transposed light layout: Q nodes per 64-unit chunk
+    const int64_t Q = 64 / s->R;
+    const int64_t nch = (n + Q - 1) / Q;
+    std::vector<uint32_t> cbase((size_t)nch + 1);
+    std::vector<int32_t> colt;
+    std::vector<float> wt;
+    colt.reserve((size_t)g->nnz);
+    const bool weighted = g->d_weights != nullptr;
+    for (int64_t c = 0; c < nch; ++c) {
+        cbase[c] = (uint32_t)colt.size();
+        const int64_t n0 = c * Q, n1 = std::min(n, n0 + Q);
+        int32_t maxd = 0;
+        for (int64_t i = n0; i < n1; ++i)
+            if (ldeg[i] != fsi::HEAVY_ROW) maxd = std::max<int32_t>(maxd, ldeg[i]);
+        for (int32_t j = 0; j < maxd; ++j)
+            for (int64_t i = n0; i < n1; ++i)
+                if (ldeg[i] != fsi::HEAVY_ROW && ldeg[i] > j) {
+                    colt.push_back(g->h_col_ind[rp[i] + j]);
+                    if (weighted) wt.push_back(g->h_weights[rp[i] + j]);
+                }
+    }
+    cbase[nch] = (uint32_t)colt.size();
+    drop_graph_exec(s);
+    for (void* p : {(void*)s->d_heavy_first, (void*)s->d_segs, s->d_seg_part, (void*)s->d_ldeg,
+                    (void*)s->d_chunk_base, (void*)s->d_col_t, (void*)s->d_w_t})
+        dev_free(p);
+    s->d_heavy_first = nullptr;
+    s->d_segs = nullptr;
+    s->d_seg_part = nullptr;
+    s->d_ldeg = nullptr;
+    s->d_chunk_base = nullptr;
+    s->d_col_t = nullptr;
+    s->d_w_t = nullptr;
+    s->nseg = (uint32_t)segs.size();
+    s->heavy_deg = heavy_deg;
+    s->seg_edges = seg_edges;
+    if (s->nseg) {
+        FS_HIP(dev_alloc((void**)&s->d_heavy_first, first.size() * sizeof(int32_t)));
+        FS_HIP(dev_alloc((void**)&s->d_segs, segs.size() * sizeof(fsi::Segment)));
+        FS_HIP(dev_alloc(&s->d_seg_part, segs.size() * (size_t)s->R * sizeof(uint32_t)));
+        FS_HIP(hipMemcpy(s->d_heavy_first, first.data(), first.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        FS_HIP(hipMemcpy(s->d_segs, segs.data(), segs.size() * sizeof(fsi::Segment), hipMemcpyHostToDevice));
+    }
+    FS_HIP(dev_alloc((void**)&s->d_ldeg, ldeg.size() * sizeof(uint16_t)));
+    FS_HIP(dev_alloc((void**)&s->d_chunk_base, cbase.size() * sizeof(uint32_t)));
+    FS_HIP(dev_alloc((void**)&s->d_col_t, colt.size() * sizeof(int32_t)));
+    FS_HIP(hipMemcpy(s->d_ldeg, ldeg.data(), ldeg.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+    FS_HIP(hipMemcpy(s->d_chunk_base, cbase.data(), cbase.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    if (!colt.empty())
+        FS_HIP(hipMemcpy(s->d_col_t, colt.data(), colt.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (weighted) {
+        FS_HIP(dev_alloc((void**)&s->d_w_t, wt.size() * sizeof(float)));
+        if (!wt.empty()) FS_HIP(hipMemcpy(s->d_w_t, wt.data(), wt.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    s->args.heavy_first = s->d_heavy_first;
+    s->args.seg_part = s->d_seg_part;
+    s->args.heavy_deg = limit;
+    s->args.seg_edges = seg_edges;
+    s->args.ldeg = s->d_ldeg;
+    s->args.chunk_base = s->d_chunk_base;
+    s->args.col_t = s->d_col_t;
+    s->args.w_t = s->d_w_t;
+    return FS_OK;
+}
+
 void make_seq(fs_sim* s, uint32_t r, SeqArgs& q)
 {
     q.step.assign(r, s->args);
     for (uint32_t j = 0; j < r; ++j) q.step[j].step_off = j;
+    q.heavy.clear();
+    if (s->nseg) {
+        fsi::HeavyArgs h{};
+        h.col_ind = s->g->d_col_ind;
+        h.weights = s->g->d_weights;
+        h.segs = s->d_segs;
+        h.seg_part = s->d_seg_part;
+        h.iota0 = s->d_iota[0];
+        h.iota1 = s->d_iota[1];
+        h.ctl = s->d_ctl;
+        h.nseg = s->nseg;
+        h.lgR = s->lgR;
+        q.heavy.assign(r, h);
+        for (uint32_t j = 0; j < r; ++j) q.heavy[j].step_off = j;
+    }
     q.ctl_c = s->d_ctl;
     q.ctl = s->d_ctl;
     q.part = s->d_part;
@@ -237,6 +382,10 @@ fs_status build_graph_exec(fs_sim* s, int b)
     };
     fs_status st;
     for (int j = 0; j < b; ++j) {
+        if (s->nseg) {
+            void* hargv[] = {&q.heavy[j]};
+            if ((st = add(s->hfn, dim3(heavy_grid(s)), dim3(WG), hargv)) != FS_OK) return st;
+        }
         void* argv[] = {&q.step[j]};
         if ((st = add(s->kfn, dim3(s->G), dim3(s->tpb), argv)) != FS_OK) return st;
     }
@@ -253,6 +402,10 @@ fs_status launch_sequence(fs_sim* s, uint32_t r)
     SeqArgs q;
     make_seq(s, r, q);
     for (uint32_t j = 0; j < r; ++j) {
+        if (s->nseg) {
+            void* hargv[] = {&q.heavy[j]};
+            FS_HIP(hipLaunchKernel(s->hfn, dim3(heavy_grid(s)), dim3(WG), hargv, 0, s->stream));
+        }
         void* argv[] = {&q.step[j]};
         FS_HIP(hipLaunchKernel(s->kfn, dim3(s->G), dim3(s->tpb), argv, 0, s->stream));
     }
@@ -321,6 +474,9 @@ fs_status fs_graph_create(int64_t n, const int32_t* row_ptr, const int32_t* col_
     g->nnz = nnz;
     g->max_degree = maxd;
     g->mean_degree = (double)nnz / (double)n;
+    g->h_row_ptr.assign(row_ptr, row_ptr + n + 1);
+    if (nnz) g->h_col_ind.assign(col_ind, col_ind + nnz);
+    if (weights && nnz) g->h_weights.assign(weights, weights + nnz);
     auto cleanup = [&](fs_status st) {
         dev_free(g->d_row_ptr);
         dev_free(g->d_col_ind);
@@ -386,6 +542,9 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
     if (p->history_len < 0 || p->history_len == 1) return fail(FS_ERR_INVALID_ARG, "history_len must be 0 or >= 2");
     if (p->steps_per_graph < 0 || p->steps_per_graph > 100000)
         return fail(FS_ERR_INVALID_ARG, "steps_per_graph out of range");
+    if (p->heavy_degree < -1) return fail(FS_ERR_INVALID_ARG, "heavy_degree must be -1, 0 or positive");
+    if (p->segment_edges != 0 && (p->segment_edges < 64 || p->segment_edges > (1 << 20)))
+        return fail(FS_ERR_INVALID_ARG, "segment_edges must be 0 or in [64, 2^20]");
     HazardDev hz[2];
     fs_status st;
     if ((st = prep_hazard(p->ei, p->storage, p->dt, &hz[0], "ei")) != FS_OK) return st;
@@ -484,9 +643,20 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
     a.key0 = (uint32_t)p->seed;
     a.key1 = (uint32_t)(p->seed >> 32);
     s->kfn = fsk::step_kernel_fn(s->storage, g->d_weights != nullptr, p->record_rates != 0, s->resident);
-    if (!s->kfn) {
+    s->hfn = fsk::heavy_kernel_fn(g->d_weights != nullptr);
+    if (!s->kfn || !s->hfn) {
         release_sim(s);
         return fail(FS_ERR_DEVICE, "no step kernel for this configuration");
+    }
+    {
+        const int32_t hd = p->heavy_degree == 0 ? 64 : p->heavy_degree;
+        const int32_t se = p->segment_edges == 0 ? 512 : p->segment_edges;
+        fs_status bst = apply_bins(s, hd, se);
+        if (bst != FS_OK) {
+            const std::string msg = g_err;
+            release_sim(s);
+            return fail(bst, msg);
+        }
     }
     *out = s;
     return FS_OK;
@@ -694,6 +864,101 @@ fs_status fs_get_rates(fs_sim* s, int32_t replica, float* out)
     FS_HIP(fsk::launch_get_rates(s->d_rates, (float*)d.p, (int32_t)n, s->lgR, replica, s->stream));
     FS_HIP(hipMemcpyAsync(out, d.p, n * sizeof(float), hipMemcpyDeviceToHost, s->stream));
     FS_HIP(hipStreamSynchronize(s->stream));
+    return FS_OK;
+    FS_GUARD_END
+}
+
+fs_status fs_sim_set_bins(fs_sim* s, int32_t heavy_degree, int32_t segment_edges)
+{
+    FS_GUARD_BEGIN
+    if (!s) return fail(FS_ERR_INVALID_ARG, "sim is NULL");
+    if (heavy_degree < -1) return fail(FS_ERR_INVALID_ARG, "heavy_degree must be >= -1");
+    DeviceGuard dg(s->device);
+    FS_HIP(hipStreamSynchronize(s->stream));
+    return apply_bins(s, heavy_degree == 0 ? 64 : heavy_degree, segment_edges == 0 ? 512 : segment_edges);
+    FS_GUARD_END
+}
+
+fs_status fs_sim_get_bins(fs_sim* s, int32_t* heavy_degree, int32_t* segment_edges, int64_t* segments)
+{
+    if (!s) return fail(FS_ERR_INVALID_ARG, "sim is NULL");
+    if (heavy_degree) *heavy_degree = s->heavy_deg;
+    if (segment_edges) *segment_edges = s->seg_edges;
+    if (segments) *segments = s->nseg;
+    return FS_OK;
+}
+
+fs_status fs_sim_tune(fs_sim* s, int32_t trial_steps, int32_t* heavy_degree, int32_t* segment_edges)
+{
+    FS_GUARD_BEGIN
+    if (!s) return fail(FS_ERR_INVALID_ARG, "sim is NULL");
+    if (trial_steps < 1 || trial_steps > 4096) return fail(FS_ERR_INVALID_ARG, "trial_steps must be in [1, 4096]");
+    DeviceGuard dg(s->device);
+    FS_HIP(hipStreamSynchronize(s->stream));
+    const size_t units = (size_t)s->g->n * s->R;
+    // snapshot everything a step changes (cf. Algorithm 2: snapshot, warm up, restore)
+    struct Buf {
+        void* live;
+        size_t bytes;
+        DevBuf copy;
+    };
+    Buf bufs[] = {{s->d_state, units * state_bytes(s->storage), {}},
+                  {s->d_age, units * age_bytes(s->storage), {}},
+                  {s->d_iota[0], (size_t)s->bit_words * 8, {}},
+                  {s->d_iota[1], (size_t)s->bit_words * 8, {}},
+                  {s->d_ctl, sizeof(fsi::Ctl), {}},
+                  {s->d_hist, (size_t)s->H * s->R * 4 * sizeof(uint32_t), {}}};
+    for (auto& b : bufs) {
+        FS_HIP(dev_alloc(&b.copy.p, b.bytes));
+        FS_HIP(hipMemcpyAsync(b.copy.p, b.live, b.bytes, hipMemcpyDeviceToDevice, s->stream));
+    }
+    std::vector<std::pair<int32_t, int32_t>> cands;
+    cands.push_back({-1, 512});
+    for (int32_t t : {16, 32, 64, 128, 256})
+        if (t < s->g->max_degree)
+            for (int32_t c : {256, 1024}) cands.push_back({t, c});
+    hipEvent_t e0, e1;
+    FS_HIP(hipEventCreate(&e0));
+    FS_HIP(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    std::pair<int32_t, int32_t> best = {s->heavy_deg, s->seg_edges};
+    fs_status st = FS_OK;
+    for (const auto& c : cands) {
+        if ((st = apply_bins(s, c.first, c.second)) != FS_OK) break;
+        // one untimed warm-up step, then the timed trial, then restore
+        uint32_t done = 0;
+        if ((st = launch_sequence(s, 1)) != FS_OK) break;
+        if (hipEventRecord(e0, s->stream) != hipSuccess) { st = fail(FS_ERR_DEVICE, "event"); break; }
+        while (done < (uint32_t)trial_steps && st == FS_OK) {
+            const uint32_t r = std::min<uint32_t>(s->chunk, (uint32_t)trial_steps - done);
+            st = launch_sequence(s, r);
+            done += r;
+        }
+        if (st != FS_OK) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, s->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = fail(FS_ERR_DEVICE, "event timing");
+            break;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+        for (auto& b : bufs)
+            if (hipMemcpyAsync(b.live, b.copy.p, b.bytes, hipMemcpyDeviceToDevice, s->stream) != hipSuccess) {
+                st = fail(FS_ERR_DEVICE, "restore");
+                break;
+            }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (auto& b : bufs) (void)hipMemcpyAsync(b.live, b.copy.p, b.bytes, hipMemcpyDeviceToDevice, s->stream);
+    FS_HIP(hipStreamSynchronize(s->stream));
+    if (st != FS_OK) return st;
+    if ((st = apply_bins(s, best.first, best.second)) != FS_OK) return st;
+    if (heavy_degree) *heavy_degree = best.first;
+    if (segment_edges) *segment_edges = best.second;
     return FS_OK;
     FS_GUARD_END
 }

@@ -178,7 +178,7 @@ def test_graph_replay_equals_eager(small_graph):
 
 @pytest.mark.parametrize("compact", [False, True], ids=["fp32", "compact"])
 def test_stream_and_resident_variants_identical(compact):
-    # a scale-free graph whose hub tiles overflow the LDS column stage
+    # a scale-free graph (hub rows take the degree-binned path)
     n = 20_000
     rp, ci = W.barabasi_albert(n, 4, 6)
     model = {"ei": ("erlang", 3, 1.0), "ir": ("weibull", 2.0, 6.0), "beta": 0.08, "dt": 0.1,
@@ -422,3 +422,83 @@ def test_ensemble_peak_prevalence_and_attack_rate(small_graph):
     for a, b, name in [(gpk, opk, "peak prevalence"), (gar, oar, "attack rate")]:
         se = math.sqrt(a.var(ddof=1) / len(a) + b.var(ddof=1) / len(b))
         assert abs(a.mean() - b.mean()) < 3 * se, (name, a.mean(), b.mean(), se)
+
+
+# ------------------------------------------------------ degree-binned rows
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
+@pytest.mark.parametrize("replicas", [1, 4])
+def test_degree_bins_give_identical_results(variant, replicas):
+    # Barabasi-Albert hubs: the same trajectory with no bins, with fine bins
+    # (many multi-segment rows) and with the defaults; unit weights make the
+    # pressures exact integers in any summation order
+    n = 20_000
+    rp, ci = W.barabasi_albert(n, 5, 9)
+    model = W.WORKLOADS["ba5_n1e6"]["model"]
+    seeds = W.seed_nodes(n, 40, 3)
+    outs = []
+    with fs.Graph(rp, ci) as g:
+        for hd, se in [(-1, 0), (8, 64), (0, 0)]:
+            sim = fs.Sim.from_model(g, model, steps_per_graph=20, replicas=replicas,
+                                    variant=VARIANTS[variant], heavy_degree=hd, segment_edges=se)
+            b = sim.bins()
+            if hd == 8:
+                assert b[2] > 1000  # segments
+            sim.seed(seeds, replica=-1)
+            sim.step(150)
+            outs.append([(*sim.get_state(r)[:2], sim.history(0, 150, r)) for r in range(replicas)])
+            sim.close()
+    for other in outs[1:]:
+        for ra, rb in zip(outs[0], other):
+            for x, y in zip(ra, rb):
+                np.testing.assert_array_equal(x, y)
+    ost, oage, ohist = oracle.run((rp, ci), model, W.initial_state(n, seeds), np.zeros(n, np.float32),
+                                  150, replica=0)
+    np.testing.assert_array_equal(outs[0][0][2], ohist)
+
+
+def test_degree_bins_weighted_one_step():
+    n = 8000
+    rp, ci = W.barabasi_albert(n, 4, 10)
+    w = np.random.default_rng(2).random(len(ci)).astype(np.float32)
+    model = {"ei": W.LN_E, "ir": W.LN_I, "beta": 0.05, "dt": 0.1, "seed": 8}
+    rng = np.random.default_rng(5)
+    st = rng.choice(4, size=n, p=[0.5, 0.1, 0.3, 0.1]).astype(np.int32)
+    age = (rng.integers(0, 200, n) * np.float32(0.1)).astype(np.float32)
+    with fs.Graph(rp, ci, w) as g:
+        sim = fs.Sim.from_model(g, model, record_rates=True, heavy_degree=16, segment_edges=64)
+        sim.set_state(st, age, 0, step_index=5)
+        sim.step(1)
+        gst, gage, _ = sim.get_state(0)
+        rates = sim.rates(0)
+        sim.close()
+    ora = oracle.step((rp, ci, w), model, st, age, (st == 2).astype(np.float64), 5)
+    check_one_step({"state": gst, "age": gage, "rates": rates}, ora, st, "weighted bins")
+
+
+def test_tune_restores_state_and_keeps_results():
+    n = 30_000
+    rp, ci = W.barabasi_albert(n, 5, 4)
+    model = W.WORKLOADS["ba5_n1e6"]["model"]
+    seeds = W.seed_nodes(n, 50, 6)
+    with fs.Graph(rp, ci) as g:
+        sim = fs.Sim.from_model(g, model, steps_per_graph=10)
+        sim.seed(seeds, replica=0)
+        sim.step(30)
+        before = sim.get_state(0)
+        hd, se = sim.tune(5)
+        after = sim.get_state(0)
+        assert sim.bins()[:2] == (hd, se)
+        for x, y in zip(before, after):
+            np.testing.assert_array_equal(x, y)
+        np.testing.assert_array_equal(sim.history(0, 30)[-1], np.bincount(after[0], minlength=4))
+        sim.step(40)
+        tuned = sim.get_state(0)
+        sim.close()
+        ref = fs.Sim.from_model(g, model, heavy_degree=-1)
+        ref.seed(seeds, replica=0)
+        ref.step(70)
+        plain = ref.get_state(0)
+        ref.close()
+    for x, y in zip(tuned, plain):
+        np.testing.assert_array_equal(x, y)
