@@ -12,6 +12,10 @@ Prints one JSON line: GNUPS (node-updates per second / 1e9), the roofline
 record of the step kernel (algorithmic bytes per launch over the measured
 per-launch time against the 8 TB/s HBM peak) and the single-core FP64 oracle
 timed on a bounded sample of the same workload.
+
+--workload selects another named workload of the same kind (the
+Barabasi-Albert graph with autotuned degree bins, or the N = 1e8 8-regular
+graph with compact or FP32 storage); the default line is the one above.
 """
 from __future__ import annotations
 
@@ -29,6 +33,16 @@ sys.path.insert(0, ROOT)
 METRIC = "GNUPS & % HBM roofline; batched-serving scenarios/s + p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "regular10_n1e6"
+GRAPH_TEXT = {
+    "regular10_n1e6": "random 10-regular, N=1e6, configuration model, seed 1",
+    "ba5_n1e6": "Barabasi-Albert m=5, N=1e6, seed 2",
+    "regular8_n1e8": "random 8-regular, N=1e8, union of 8 random perfect matchings, seed 3",
+}
+LAW_TEXT = {
+    "regular10_n1e6": "E~LN(ln3,0.5), I~LN(ln5,0.6)",
+    "ba5_n1e6": "E~Erlang(3, rate 1), I~Weibull(2, 6)",
+    "regular8_n1e8": "E~LN(ln3,0.5), I~LN(ln5,0.6)",
+}
 STEPS_PER_GRAPH = 50
 
 
@@ -62,7 +76,7 @@ def measured_traffic(workload: str):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(rp, ci, model, seeds, budget_s: float):
+def cpu_baseline(rp, ci, model, seeds, budget_s: float, compact: bool):
     """The FP64 oracle (single thread) on the first steps of the same run."""
     import numpy as np
 
@@ -71,24 +85,33 @@ def cpu_baseline(rp, ci, model, seeds, budget_s: float):
 
     n = len(rp) - 1
     st = W.initial_state(n, seeds)
-    age = np.zeros(n, np.float32)
-    oracle.run((rp, ci), model, st, age, 1)  # load + first touch
+    age = np.zeros(n, np.uint16 if compact else np.float32)
+    per_call = max(1, min(5, int(2e7 // n)))
+    st, age, _ = oracle.run((rp, ci), model, st, age, 1, compact=compact)  # load + first touch
     steps, t0 = 0, time.perf_counter()
     while True:
-        st, age, _ = oracle.run((rp, ci), model, st, age, 5, step0=1 + steps)
-        steps += 5
+        st, age, _ = oracle.run((rp, ci), model, st, age, per_call, step0=1 + steps, compact=compact)
+        steps += per_call
         el = time.perf_counter() - t0
         if el >= budget_s:
             break
     return {"value": n * steps / el / 1e9, "unit": "GNUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} steps (steps 1..{steps}) of the same N=1e6 trajectory, "
+            "sample": f"{steps} steps (steps 1..{steps}) of the same N={n:.0e} trajectory, "
                       f"single-threaded FP64 oracle, {el:.1f} s"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--workload", choices=["regular10_n1e6", "ba5_n1e6", "regular8_n1e8"],
+                    default=WORKLOAD)
+    ap.add_argument("--storage", choices=["fp32", "compact"], default=None,
+                    help="state/age storage (default: the workload's)")
+    ap.add_argument("--tune", choices=["auto", "on", "off"], default="auto",
+                    help="autotune the degree bins before timing (auto: when the maximum "
+                         "degree exceeds 64)")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: the workload's trajectory length)")
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
@@ -111,13 +134,18 @@ def main():
     import workloads as W
 
     fs.lib()  # fail loudly without the HIP library
-    wl = W.WORKLOADS[WORKLOAD]
+    workload = args.workload
+    wl = W.WORKLOADS[workload]
     model = wl["model"]
+    storage = args.storage or wl["storage"]
+    compact = storage == "compact"
+    if args.steps is None:
+        args.steps = wl["steps"]
     t0 = time.perf_counter()
     rp, ci = W.workload_graph(wl["graph"])
     n = len(rp) - 1
     seeds = W.seed_nodes(n, wl["seeds"], wl["seed_rng"])
-    print(f"[bench] graph {WORKLOAD}: N={n} E={len(ci)} built in {time.perf_counter() - t0:.1f}s",
+    print(f"[bench] graph {workload}: N={n} E={len(ci)} built in {time.perf_counter() - t0:.1f}s",
           file=sys.stderr, flush=True)
 
     dev = torch.device("cuda:0")
@@ -137,9 +165,19 @@ def main():
     variant = {"auto": fs.VARIANT_AUTO, "stream": fs.VARIANT_STREAM,
                "resident": fs.VARIANT_RESIDENT}[args.variant]
     sim = fs.Sim.from_model(g, model, steps_per_graph=STEPS_PER_GRAPH, stream=stream.cuda_stream,
-                            variant=variant)
+                            variant=variant,
+                            storage=fs.FS_STORAGE_COMPACT if compact else fs.FS_STORAGE_FP32)
     init_state = W.initial_state(n, seeds)
-    init_age = np.zeros(n, np.float32)
+    init_age = np.zeros(n, np.uint16 if compact else np.float32)
+    max_deg = int(np.diff(rp).max())
+    tuned = None
+    if args.tune == "on" or (args.tune == "auto" and max_deg > 64):
+        sim.set_state(init_state, init_age, 0, step_index=0)
+        sim.step(100)  # tune on a state with the epidemic under way
+        sim.sync()
+        tuned = sim.tune()
+        print(f"[bench] tuned degree bins (heavy_degree, segment_edges) = {tuned}", file=sys.stderr,
+              flush=True)
 
     # warm-up (graph instantiation, clocks), then restart the trajectory
     sim.set_state(init_state, init_age, 0, step_index=0)
@@ -167,17 +205,17 @@ def main():
     sec = ms / 1e3
     gnups = n * args.steps / sec / 1e9
     d_mean = len(ci) / n
-    b_alg = bytes_per_update(d_mean, "fp32")
+    b_alg = bytes_per_update(d_mean, storage)
     per_launch_s = sec / args.steps
     achieved = b_alg * n / per_launch_s / 1e9
-    traffic = measured_traffic(WORKLOAD)
+    traffic = measured_traffic(workload if storage == wl["storage"] else f"{workload}_{storage}")
     s_frac = float(hist[:, 0].mean() / n)
     print(f"[bench] {args.steps} steps: {ms:.3f} ms (wall {wall * 1e3:.1f} ms), {gnups:.2f} GNUPS, "
           f"final counts {final.tolist()}, mean S fraction {s_frac:.3f}", file=sys.stderr, flush=True)
 
     cpu = None
     if args.cpu_budget > 0:
-        cpu = cpu_baseline(rp, ci, model, seeds, args.cpu_budget)
+        cpu = cpu_baseline(rp, ci, model, seeds, args.cpu_budget, compact)
         print(f"[bench] cpu baseline {cpu['value'] * 1e3:.1f} MNUPS", file=sys.stderr, flush=True)
 
     rec = {
@@ -191,13 +229,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32",  # hazard and pressure arithmetic; compact storage changes only what is stored
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "graph": "random 10-regular, N=1e6, seed 1",
-                   "laws": "E~LN(ln3,0.5), I~LN(ln5,0.6)", "beta": 0.06, "dt": 0.1,
-                   "seeds": wl["seeds"], "replicas": 1, "storage": "fp32",
+        "config": {"workload": workload, "graph": GRAPH_TEXT[workload], "n": n, "edges": int(len(ci)),
+                   "laws": LAW_TEXT[workload], "beta": model["beta"], "dt": model["dt"],
+                   "seeds": wl["seeds"], "replicas": 1, "storage": storage,
                    "steps_per_graph": STEPS_PER_GRAPH, "kernel_variant": args.variant,
-                   "parallelism": "single GPU"},
+                   "degree_bins": list(tuned) if tuned else None, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "bytes_per_update": b_alg,

@@ -85,6 +85,7 @@ struct StepArgs {
     // or HEAVY_ROW for a binned row.
     const uint16_t* ldeg;
     const uint32_t* chunk_base;
+    const uint8_t* chunk_deg; // the shared light degree of a chunk's rows, 255 if mixed
     const int32_t* col_t;
     const float* w_t;
 };

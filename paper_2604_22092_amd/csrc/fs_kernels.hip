@@ -54,120 +54,150 @@ __device__ __forceinline__ uint32_t bit_at(const uint32_t* __restrict__ w, uint3
     return (w[b >> 5] >> (b & 31)) & 1u;
 }
 
-// Chunks of 64 units each wavefront takes per pass; the hazards and draws of
-// a pass are evaluated on compacted lanes.
-constexpr int CU = 4;
-
-// Pressure of the light rows of CU chunks (lam[u] = beta * pressure for S
-// units, 0 otherwise) from the wavefront-transposed column layout: edge slot j
-// of the chunk's rows is one contiguous run, so every slot is one coalesced
-// load.  When all rows of a chunk have the same light degree d (regular
-// graphs), slot j of row q sits at base + j*Q + q; otherwise a row's position
-// in run j is its rank among the rows with more than j edges (ballot prefix
-// count).  Loads are issued JB slots at a time before they are consumed.
-// Binned rows read their segment partials in segment order.
-constexpr int JB = 8;
-
 __device__ __forceinline__ uint32_t lds_bit(const uint32_t* __restrict__ w, uint32_t b)
 {
     return __builtin_amdgcn_ubfe(w[b >> 5], b & 31, 1);
 }
 
-template <bool WEIGHTED, int CU>
-__device__ __forceinline__ void pressure_multi(const StepArgs& a, const uint32_t* chunk, const int* x,
-                                               const uint32_t* node, const uint16_t* deg,
-                                               const uint32_t* __restrict__ bits, const uint32_t* rep,
-                                               uint32_t lane, float* lam)
+// Light-row edge slots loaded ahead for chunks whose rows share one light
+// degree (every chunk of a regular graph): slot j of row q is col_t[base +
+// j*Q + q], so these loads need only the chunk's metadata and are issued with
+// the state and age loads.
+#ifndef FS_UMAX
+#define FS_UMAX 12
+#endif
+constexpr int UMAX = FS_UMAX;
+// Edge slots per batch of the general (mixed-degree) gather.
+constexpr int JB = 8;
+// Chunks of 64 units each wavefront takes per pass; the hazards and draws of
+// a pass are evaluated on compacted lanes.
+#ifndef FS_CU
+#define FS_CU 2
+#endif
+constexpr int CU = FS_CU;
+
+template <class age_t>
+struct Pass {
+    uint32_t chk[CU], unit[CU], node[CU], rep[CU], base[CU], ud[CU];
+    bool valid[CU], live[CU];
+    int x[CU];
+    age_t ag[CU];
+    uint16_t dg[CU];
+    int32_t c[CU][UMAX];
+};
+
+// Issues every load of a pass that does not depend on the state: chunk
+// metadata (scalar), state, age, light degree, and the edge slots of uniform
+// chunks.
+template <int STORAGE, class age_t>
+__device__ __forceinline__ void issue_pass(const StepArgs& a, uint32_t first, uint32_t nwaves, uint32_t nchunks,
+                                           uint32_t total, uint32_t lane, Pass<age_t>& P)
+{
+    using state_t = typename Store<STORAGE>::state_t;
+    const uint32_t R = 1u << a.lgR;
+    const uint32_t q = lane >> a.lgR;
+#pragma unroll
+    for (int u = 0; u < CU; ++u) {
+        const uint32_t c = first + (uint32_t)u * nwaves;
+        P.live[u] = c < nchunks;
+        P.chk[u] = P.live[u] ? c : nchunks - 1; // a real chunk for the uniform layout walk
+        P.unit[u] = (P.chk[u] << 6) + lane;
+        P.valid[u] = P.live[u] && P.unit[u] < total;
+        P.node[u] = P.unit[u] >> a.lgR;
+        P.rep[u] = P.unit[u] & (R - 1);
+        P.base[u] = a.chunk_base[P.chk[u]];
+        P.ud[u] = P.live[u] ? a.chunk_deg[P.chk[u]] : 0u;
+        P.x[u] = ST_R;
+        P.ag[u] = 0;
+        P.dg[u] = 0;
+        if (P.valid[u]) {
+            P.x[u] = (int)((const state_t*)a.state)[P.unit[u]];
+            P.ag[u] = ((const age_t*)a.age)[P.unit[u]];
+            P.dg[u] = a.ldeg[P.node[u]];
+        }
+#pragma unroll
+        for (int j = 0; j < UMAX; ++j) {
+            P.c[u][j] = 0;
+            if ((uint32_t)j < P.ud[u] && P.valid[u]) P.c[u][j] = a.col_t[P.base[u] + (uint32_t)j * (64u >> a.lgR) + q];
+        }
+    }
+}
+
+// Pressure of one chunk's light row for this lane (Eq. (influence) without
+// beta).  Uniform chunks use the preloaded slots; mixed chunks find a row's
+// position in run j as its rank among the rows with more than j edges (ballot
+// prefix count), JB slots at a time.
+template <bool WEIGHTED, class age_t>
+__device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_t>& P, int u, bool want,
+                                              const uint32_t* __restrict__ bits, uint32_t lane)
 {
     const int32_t lgR = a.lgR;
     const uint32_t R = 1u << lgR;
-    const uint32_t q = lane >> lgR; // row of this lane within the chunk
-    // lanes below this lane's row leader (the lane of replica 0 of its node)
-    const unsigned long long below = (1ull << (lane & ~(R - 1))) - 1ull;
+    const uint32_t rep = P.rep[u];
+    const uint32_t d = P.dg[u] == HEAVY_ROW ? 0u : P.dg[u];
+    uint32_t pi = 0;
+    float pw = 0.0f;
+    if (P.ud[u] <= (uint32_t)UMAX) {
+        const uint32_t rows = 64u >> lgR;
+        const uint32_t q = lane >> lgR;
 #pragma unroll
-    for (int u = 0; u < CU; ++u) {
-        lam[u] = 0.0f;
-        const bool heavy = deg[u] == HEAVY_ROW;
-        const uint32_t d = heavy ? 0u : deg[u];
-        const bool want = x[u] == ST_S && !heavy;
-        const uint32_t base = a.chunk_base[chunk[u]];
-        // chunk-wide degree structure (wave-uniform)
-        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-        const bool uniform = __ballot(d != d0) == 0ull;
-        const uint32_t rows = (uint32_t)__popcll(__ballot(rep[u] == 0 && d > 0));
-        uint32_t pi = 0;
-        float pw = 0.0f;
-        if (uniform) {
-            for (uint32_t j0 = 0; j0 < d0; j0 += JB) {
-                int32_t c[JB];
-                float wv[JB];
-#pragma unroll
-                for (int jj = 0; jj < JB; ++jj) {
-                    c[jj] = 0;
-                    wv[jj] = 0.0f;
-                    if (want && j0 + jj < d0) {
-                        const uint32_t idx = base + (j0 + jj) * rows + q;
-                        c[jj] = a.col_t[idx];
-                        if (WEIGHTED) wv[jj] = a.w_t[idx];
-                    }
-                }
-#pragma unroll
-                for (int jj = 0; jj < JB; ++jj) {
-                    if (want && j0 + jj < d0) {
-                        const uint32_t b = lds_bit(bits, ((uint32_t)c[jj] << lgR) + rep[u]);
-                        if (WEIGHTED) pw = __builtin_fmaf(wv[jj], (float)b, pw);
-                        else pi += b;
-                    }
-                }
-            }
-        } else {
-            uint32_t off = base;
-            for (uint32_t j0 = 0;; j0 += JB) {
-                if (__ballot(rep[u] == 0 && d > j0) == 0ull) break;
-                int32_t c[JB];
-                float wv[JB];
-#pragma unroll
-                for (int jj = 0; jj < JB; ++jj) {
-                    const unsigned long long m = __ballot(rep[u] == 0 && d > j0 + jj);
-                    c[jj] = 0;
-                    wv[jj] = 0.0f;
-                    if (want && d > j0 + jj) {
-                        const uint32_t idx = off + (uint32_t)__popcll(m & below);
-                        c[jj] = a.col_t[idx];
-                        if (WEIGHTED) wv[jj] = a.w_t[idx];
-                    }
-                    off += (uint32_t)__popcll(m);
-                }
-#pragma unroll
-                for (int jj = 0; jj < JB; ++jj) {
-                    if (want && d > j0 + jj) {
-                        const uint32_t b = lds_bit(bits, ((uint32_t)c[jj] << lgR) + rep[u]);
-                        if (WEIGHTED) pw = __builtin_fmaf(wv[jj], (float)b, pw);
-                        else pi += b;
-                    }
-                }
+        for (int j = 0; j < UMAX; ++j) {
+            if ((uint32_t)j < P.ud[u] && want) {
+                const uint32_t b = lds_bit(bits, ((uint32_t)P.c[u][j] << lgR) + rep);
+                if (WEIGHTED) pw = __builtin_fmaf(a.w_t[P.base[u] + (uint32_t)j * rows + q], (float)b, pw);
+                else pi += b;
             }
         }
-        if (want) lam[u] = a.beta * (WEIGHTED ? pw : (float)pi);
-        if (heavy && x[u] == ST_S) {
-            // degree-binned row: partials of its segments, summed in segment order
-            const int32_t dg = a.row_ptr[node[u] + 1] - a.row_ptr[node[u]];
-            const int32_t first = a.heavy_first[node[u]];
-            const int32_t nseg = (dg + a.seg_edges - 1) / a.seg_edges;
-            float p;
-            if (WEIGHTED) {
-                const float* sp = (const float*)a.seg_part;
-                p = 0.0f;
-                for (int32_t j = 0; j < nseg; ++j) p += sp[(size_t)(first + j) * R + rep[u]];
-            } else {
-                const uint32_t* sp = (const uint32_t*)a.seg_part;
-                uint32_t q = 0;
-                for (int32_t j = 0; j < nseg; ++j) q += sp[(size_t)(first + j) * R + rep[u]];
-                p = (float)q;
+    } else {
+        const unsigned long long below = (1ull << (lane & ~(R - 1))) - 1ull;
+        uint32_t off = P.base[u];
+        for (uint32_t j0 = 0;; j0 += JB) {
+            if (__ballot(rep == 0 && d > j0) == 0ull) break;
+            int32_t c[JB];
+            float wv[JB];
+#pragma unroll
+            for (int jj = 0; jj < JB; ++jj) {
+                const unsigned long long m = __ballot(rep == 0 && d > j0 + jj);
+                c[jj] = 0;
+                wv[jj] = 0.0f;
+                if (want && d > j0 + jj) {
+                    const uint32_t idx = off + (uint32_t)__popcll(m & below);
+                    c[jj] = a.col_t[idx];
+                    if (WEIGHTED) wv[jj] = a.w_t[idx];
+                }
+                off += (uint32_t)__popcll(m);
             }
-            lam[u] = a.beta * p;
+#pragma unroll
+            for (int jj = 0; jj < JB; ++jj) {
+                if (want && d > j0 + jj) {
+                    const uint32_t b = lds_bit(bits, ((uint32_t)c[jj] << lgR) + rep);
+                    if (WEIGHTED) pw = __builtin_fmaf(wv[jj], (float)b, pw);
+                    else pi += b;
+                }
+            }
         }
     }
+    return WEIGHTED ? pw : (float)pi;
+}
+
+// Pressure of a degree-binned row: its segment partials in segment order.
+template <bool WEIGHTED>
+__device__ __forceinline__ float pressure_heavy(const StepArgs& a, uint32_t node, uint32_t rep)
+{
+    const size_t R = (size_t)1 << a.lgR;
+    const int32_t dg = a.row_ptr[node + 1] - a.row_ptr[node];
+    const int32_t first = a.heavy_first[node];
+    const int32_t nseg = (dg + a.seg_edges - 1) / a.seg_edges;
+    if (WEIGHTED) {
+        const float* sp = (const float*)a.seg_part;
+        float p = 0.0f;
+        for (int32_t j = 0; j < nseg; ++j) p += sp[(size_t)(first + j) * R + rep];
+        return p;
+    }
+    const uint32_t* sp = (const uint32_t*)a.seg_part;
+    uint32_t p = 0;
+    for (int32_t j = 0; j < nseg; ++j) p += sp[(size_t)(first + j) * R + rep];
+    return (float)p;
 }
 
 // Evaluates f on the flagged items of CU chunks with the items packed into
@@ -214,10 +244,10 @@ __device__ __forceinline__ void compact_apply(uint32_t* xch, uint32_t lane, cons
 
 // One fused step.  Units are processed in chunks of 64 (one wavefront, one
 // 64-bit word of the next infectivity bitmap); every wavefront walks its own
-// chunks with no workgroup barrier, so the memory latency of one wavefront
-// overlaps the work of the others.
+// chunks, CU per pass, with no workgroup barrier inside the walk.
 //  RESIDENT: the whole start-of-step bitmap (units <= RESIDENT_BITS) is copied
-//    into LDS once per workgroup and every gather reads LDS; launched with one
+//    into LDS once per workgroup (direct global-to-LDS loads, overlapped with
+//    the first pass's loads) and every gather reads LDS; launched with one
 //    workgroup of RESIDENT_TPB threads per compute unit.
 //  otherwise: gathers read the bitmap through the caches.
 template <int STORAGE, bool WEIGHTED, bool RATES, bool RESIDENT, int TPB>
@@ -229,11 +259,12 @@ __global__ __launch_bounds__(TPB) void step_kernel(StepArgs a)
     constexpr int NW = TPB / 64;
 
     __shared__ uint32_t s_cnt[4 * 64];
-    __shared__ uint32_t s_bits[RESIDENT ? RESIDENT_BITS / 32 : 1];
+    __shared__ __attribute__((aligned(16))) uint32_t s_bits[RESIDENT ? RESIDENT_BITS / 32 : 4];
     __shared__ uint32_t s_xch[NW][64];
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63;
+    const uint32_t wave = tid >> 6;
     const uint32_t R = 1u << a.lgR;
     const unsigned long long k = a.ctl->step + a.step_off;
     const uint32_t* __restrict__ bits_in = (const uint32_t*)((k & 1) ? a.iota1 : a.iota0);
@@ -242,53 +273,47 @@ __global__ __launch_bounds__(TPB) void step_kernel(StepArgs a)
     age_t* __restrict__ age = (age_t*)a.age;
     const uint32_t total = (uint32_t)a.n << a.lgR;
     const uint32_t nchunks = (total + 63) >> 6;
+    const uint32_t wave_id = blockIdx.x * NW + wave;
+    const uint32_t nwaves = gridDim.x * NW;
 
+    // first pass loads, then the bitmap fill, then one wait for both
+    Pass<age_t> P;
+    uint32_t first = wave_id;
+    if (first < nchunks) issue_pass<STORAGE>(a, first, nwaves, nchunks, total, lane, P);
     if (R > 1)
         for (uint32_t i = tid; i < 4 * R; i += TPB) s_cnt[i] = 0;
     if (RESIDENT) {
-        const uint32_t words = (total + 31) >> 5;
+        // 16 bytes per lane straight into LDS: wave w fills the blocks of 64
+        // uint4 it owns; lane l's block element lands at base + 16 l
+        const uint32_t n4 = (((total + 31) >> 5) + 3) >> 2;
         const uint4* src = (const uint4*)bits_in;
-        uint4* dst = (uint4*)s_bits;
-        for (uint32_t i = tid; i < (words + 3) >> 2; i += TPB) dst[i] = src[i];
+        for (uint32_t b0 = wave * 64; b0 < n4; b0 += TPB) {
+            if (b0 + lane < n4)
+                __builtin_amdgcn_global_load_lds((const void*)(src + b0 + lane),
+                                                 (__attribute__((address_space(3))) void*)((uint4*)s_bits + b0), 16, 0, 0);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
     }
     if (R > 1 || RESIDENT) __syncthreads();
     const uint32_t* __restrict__ gbits = RESIDENT ? s_bits : bits_in;
 
     uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0; // per-wave counts (R == 1)
 
-    // Each wavefront takes CU chunks per pass (stride `pass` apart) and runs
-    // every phase for all of them before the next phase, so the loads of the
-    // chunks are in flight together.
-    const uint32_t wave_id = blockIdx.x * NW + (tid >> 6);
-    const uint32_t nwaves = gridDim.x * NW;
-    for (uint32_t base = wave_id; base < nchunks; base += nwaves * CU) {
-        uint32_t chk[CU], unit[CU], node[CU], rep[CU];
-        bool valid[CU];
-        int x[CU];
-        age_t ag[CU];
-        uint16_t dg[CU];
-#pragma unroll
-        for (int u = 0; u < CU; ++u) {
-            chk[u] = base + (uint32_t)u * nwaves;
-            const bool live = chk[u] < nchunks;
-            if (!live) chk[u] = nchunks - 1; // a real chunk for the uniform layout walk
-            unit[u] = (chk[u] << 6) + lane;
-            valid[u] = live && unit[u] < total;
-            node[u] = unit[u] >> a.lgR;
-            rep[u] = unit[u] & (R - 1);
-            x[u] = ST_R;
-            ag[u] = 0;
-            dg[u] = 0;
-            if (valid[u]) {
-                x[u] = (int)state[unit[u]];
-                ag[u] = age[unit[u]];
-                dg[u] = a.ldeg[node[u]];
-            }
-        }
+    for (; first < nchunks; first += nwaves * CU) {
+        if (first != wave_id) issue_pass<STORAGE>(a, first, nwaves, nchunks, total, lane, P);
 
         // 1.-2. rate: beta * pressure for S; hazard at the start-of-step age for E/I; 0 for R
         float lam[CU];
-        pressure_multi<WEIGHTED, CU>(a, chk, x, node, dg, gbits, rep, lane, lam);
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            lam[u] = 0.0f;
+            const bool heavy = P.dg[u] == HEAVY_ROW;
+            const bool want = P.x[u] == ST_S && !heavy;
+            const float p = pressure_row<WEIGHTED>(a, P, u, want, gbits, lane);
+            if (want) lam[u] = a.beta * p;
+            if (heavy && P.x[u] == ST_S) lam[u] = a.beta * pressure_heavy<WEIGHTED>(a, P.node[u], P.rep[u]);
+        }
+
         // hazards of the E/I units of the pass, on compacted lanes; the payload
         // is the age bit pattern with bit 31 marking the I -> R law (ages are
         // non-negative, so bit 31 is free)
@@ -297,11 +322,11 @@ __global__ __launch_bounds__(TPB) void step_kernel(StepArgs a)
             uint32_t pay[CU], res[CU];
 #pragma unroll
             for (int u = 0; u < CU; ++u) {
-                need[u] = x[u] == ST_E || x[u] == ST_I;
-                pay[u] = age_bits(ag[u]) | (x[u] == ST_I ? 0x80000000u : 0u);
+                need[u] = P.x[u] == ST_E || P.x[u] == ST_I;
+                pay[u] = age_bits(P.ag[u]) | (P.x[u] == ST_I ? 0x80000000u : 0u);
                 res[u] = 0;
             }
-            compact_apply<CU>(s_xch[tid >> 6], lane, need, pay, res, [&](uint32_t w) {
+            compact_apply<CU>(s_xch[wave], lane, need, pay, res, [&](uint32_t w) {
                 const bool isI = (w & 0x80000000u) != 0u;
                 const float xa = age_from_bits<age_t>(w & 0x7FFFFFFFu);
                 float h;
@@ -329,11 +354,11 @@ __global__ __launch_bounds__(TPB) void step_kernel(StepArgs a)
 #pragma unroll
             for (int u = 0; u < CU; ++u) {
                 need[u] = lam[u] > 0.0f;
-                pay[u] = unit[u];
+                pay[u] = P.unit[u];
                 res[u] = 0;
             }
             const uint32_t kk = (uint32_t)k;
-            compact_apply<CU>(s_xch[tid >> 6], lane, need, pay, res, [&](uint32_t un) {
+            compact_apply<CU>(s_xch[wave], lane, need, pay, res, [&](uint32_t un) {
                 return fsd::philox4x32_10(make_uint4(un >> a.lgR, kk, un & (R - 1), 0u), a.key0, a.key1).x >> 8;
             });
 #pragma unroll
@@ -341,8 +366,8 @@ __global__ __launch_bounds__(TPB) void step_kernel(StepArgs a)
                 fire[u] = false;
                 if (need[u]) {
                     const float uu = (float)res[u] * 0x1p-24f;
-                    const float q = -expm1f(-lam[u] * a.dt);
-                    fire[u] = uu < q;
+                    const float qq = -expm1f(-lam[u] * a.dt);
+                    fire[u] = uu < qq;
                 }
             }
         }
@@ -350,22 +375,22 @@ __global__ __launch_bounds__(TPB) void step_kernel(StepArgs a)
 #pragma unroll
         for (int u = 0; u < CU; ++u) {
             // 5.-6. advance state and age in place
-            const int xn = x[u] + (fire[u] ? 1 : 0);
-            if (valid[u]) {
-                if (fire[u]) state[unit[u]] = (state_t)xn;
-                age[unit[u]] = fire[u] ? (age_t)0 : age_next(ag[u], a.dt);
-                if (RATES) a.rates[unit[u]] = lam[u];
+            const int xn = P.x[u] + (fire[u] ? 1 : 0);
+            if (P.valid[u]) {
+                if (fire[u]) state[P.unit[u]] = (state_t)xn;
+                age[P.unit[u]] = fire[u] ? (age_t)0 : age_next(P.ag[u], a.dt);
+                if (RATES) a.rates[P.unit[u]] = lam[u];
             }
             // 7. next-step infectivity bits (one 64-bit word per chunk) and 8. counts
-            const unsigned long long mI = __ballot(valid[u] && xn == ST_I);
-            if (lane == 0 && base + (uint32_t)u * nwaves < nchunks) bits_out[chk[u]] = mI;
+            const unsigned long long mI = __ballot(P.valid[u] && xn == ST_I);
+            if (lane == 0 && P.live[u]) bits_out[P.chk[u]] = mI;
             if (R == 1) {
-                c0 += (uint32_t)__popcll(__ballot(valid[u] && xn == ST_S));
-                c1 += (uint32_t)__popcll(__ballot(valid[u] && xn == ST_E));
+                c0 += (uint32_t)__popcll(__ballot(P.valid[u] && xn == ST_S));
+                c1 += (uint32_t)__popcll(__ballot(P.valid[u] && xn == ST_E));
                 c2 += (uint32_t)__popcll(mI);
-                c3 += (uint32_t)__popcll(__ballot(valid[u] && xn == ST_R));
-            } else if (valid[u]) {
-                atomicAdd(&s_cnt[rep[u] * 4 + xn], 1u); // LDS
+                c3 += (uint32_t)__popcll(__ballot(P.valid[u] && xn == ST_R));
+            } else if (P.valid[u]) {
+                atomicAdd(&s_cnt[P.rep[u] * 4 + xn], 1u); // LDS
             }
         }
     }
@@ -374,11 +399,10 @@ __global__ __launch_bounds__(TPB) void step_kernel(StepArgs a)
     uint32_t* out = a.part + ((size_t)a.step_off * gridDim.x + blockIdx.x) * (4 * R);
     if (R == 1) {
         if (lane == 0) {
-            const uint32_t w = tid >> 6;
-            s_cnt[w * 4 + 0] = c0;
-            s_cnt[w * 4 + 1] = c1;
-            s_cnt[w * 4 + 2] = c2;
-            s_cnt[w * 4 + 3] = c3;
+            s_cnt[wave * 4 + 0] = c0;
+            s_cnt[wave * 4 + 1] = c1;
+            s_cnt[wave * 4 + 2] = c2;
+            s_cnt[wave * 4 + 3] = c3;
         }
         __syncthreads();
         if (tid < 4) {

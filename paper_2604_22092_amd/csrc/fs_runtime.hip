@@ -71,6 +71,7 @@ struct fs_sim {
     void* d_seg_part = nullptr;
     uint16_t* d_ldeg = nullptr;       // light degree per node, HEAVY_ROW for binned rows
     uint32_t* d_chunk_base = nullptr; // wavefront-transposed layout of the light rows
+    uint8_t* d_chunk_deg = nullptr;
     int32_t* d_col_t = nullptr;
     float* d_w_t = nullptr;
     const void* hfn = nullptr;
@@ -200,6 +201,7 @@ void release_sim(fs_sim* s)
     dev_free(s->d_seg_part);
     dev_free(s->d_ldeg);
     dev_free(s->d_chunk_base);
+    dev_free(s->d_chunk_deg);
     dev_free(s->d_col_t);
     dev_free(s->d_w_t);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
@@ -275,12 +277,17 @@ fs_status apply_bins(fs_sim* s, int32_t heavy_deg, int32_t seg_edges)
     std::vector<float> wt;
     colt.reserve((size_t)g->nnz);
     const bool weighted = g->d_weights != nullptr;
+    std::vector<uint8_t> cdeg((size_t)nch);
     for (int64_t c = 0; c < nch; ++c) {
         cbase[c] = (uint32_t)colt.size();
         const int64_t n0 = c * Q, n1 = std::min(n, n0 + Q);
         int32_t maxd = 0;
-        for (int64_t i = n0; i < n1; ++i)
+        bool same = n1 - n0 == Q;
+        for (int64_t i = n0; i < n1; ++i) {
             if (ldeg[i] != fsi::HEAVY_ROW) maxd = std::max<int32_t>(maxd, ldeg[i]);
+            same = same && ldeg[i] != fsi::HEAVY_ROW && ldeg[i] == ldeg[n0];
+        }
+        cdeg[c] = (same && ldeg[n0] < 255) ? (uint8_t)ldeg[n0] : (uint8_t)255;
         for (int32_t j = 0; j < maxd; ++j)
             for (int64_t i = n0; i < n1; ++i)
                 if (ldeg[i] != fsi::HEAVY_ROW && ldeg[i] > j) {
@@ -291,8 +298,9 @@ fs_status apply_bins(fs_sim* s, int32_t heavy_deg, int32_t seg_edges)
     cbase[nch] = (uint32_t)colt.size();
     drop_graph_exec(s);
     for (void* p : {(void*)s->d_heavy_first, (void*)s->d_segs, s->d_seg_part, (void*)s->d_ldeg,
-                    (void*)s->d_chunk_base, (void*)s->d_col_t, (void*)s->d_w_t})
+                    (void*)s->d_chunk_base, (void*)s->d_chunk_deg, (void*)s->d_col_t, (void*)s->d_w_t})
         dev_free(p);
+    s->d_chunk_deg = nullptr;
     s->d_heavy_first = nullptr;
     s->d_segs = nullptr;
     s->d_seg_part = nullptr;
@@ -312,6 +320,8 @@ fs_status apply_bins(fs_sim* s, int32_t heavy_deg, int32_t seg_edges)
     }
     FS_HIP(dev_alloc((void**)&s->d_ldeg, ldeg.size() * sizeof(uint16_t)));
     FS_HIP(dev_alloc((void**)&s->d_chunk_base, cbase.size() * sizeof(uint32_t)));
+    FS_HIP(dev_alloc((void**)&s->d_chunk_deg, cdeg.size()));
+    FS_HIP(hipMemcpy(s->d_chunk_deg, cdeg.data(), cdeg.size(), hipMemcpyHostToDevice));
     FS_HIP(dev_alloc((void**)&s->d_col_t, colt.size() * sizeof(int32_t)));
     FS_HIP(hipMemcpy(s->d_ldeg, ldeg.data(), ldeg.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
     FS_HIP(hipMemcpy(s->d_chunk_base, cbase.data(), cbase.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
@@ -327,6 +337,7 @@ fs_status apply_bins(fs_sim* s, int32_t heavy_deg, int32_t seg_edges)
     s->args.seg_edges = seg_edges;
     s->args.ldeg = s->d_ldeg;
     s->args.chunk_base = s->d_chunk_base;
+    s->args.chunk_deg = s->d_chunk_deg;
     s->args.col_t = s->d_col_t;
     s->args.w_t = s->d_w_t;
     return FS_OK;

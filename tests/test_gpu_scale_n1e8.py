@@ -1,0 +1,127 @@
+"""The random 8-regular workload: N = 1e8 sampled parity for compact and FP32
+storage, and the error of compact storage against the FP64 oracle.
+
+Graph: union of 8 random perfect matchings (seed 3), log-normal E ~ LN(ln 3,
+0.5) and I ~ LN(ln 5, 0.6), beta = 0.07, dt = 0.2 d.  At N = 1e8 the oracle
+checks one step on 1e5-node subsamples at steps 0, 50, 100 and 150: half
+drawn uniformly, half from the nodes whose update is not trivial (E/I/R
+nodes and neighbours of I nodes), since most of the graph is still
+susceptible with zero pressure at every checkpoint.  The compact-storage error is measured on an N = 1e5 instance of
+the same family over whole 600-step trajectories (the outbreak peaks near
+step 300 and is over by step 600).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2604_22092_amd as fs
+import workloads as W
+from _parity import check_mismatch_budget, check_rates, guard_band_mismatches
+
+pytestmark = pytest.mark.gpu
+
+BIG = W.WORKLOADS["regular8_n1e8"]
+
+
+@pytest.fixture(scope="module")
+def big_graph():
+    rp, ci = W.workload_graph(BIG["graph"])
+    with fs.Graph(rp, ci) as g:
+        yield rp, ci, g
+
+
+def subsample(rp, ci, st, count, rng):
+    n = len(rp) - 1
+    uni = rng.choice(n, count // 2, replace=False)
+    d = int(rp[1] - rp[0])
+    busy = np.flatnonzero(st != 0)
+    nb = ci.reshape(n, d)[np.flatnonzero(st == 2)].ravel()
+    pool = np.unique(np.concatenate([busy, nb]))
+    hot = rng.choice(pool, min(len(pool), count // 2), replace=False)
+    return np.unique(np.concatenate([uni, hot]))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("compact", [True, False], ids=["compact", "fp32"])
+def test_n1e8_sampled_one_step_parity(big_graph, compact):
+    """One-step parity on 1e5 sampled nodes at steps 0, 50, 100 and 150 of one
+    GPU trajectory (each checkpoint's step is then part of the trajectory)."""
+    rp, ci, g = big_graph
+    n = len(rp) - 1
+    model = BIG["model"]
+    seeds = W.seed_nodes(n, BIG["seeds"], BIG["seed_rng"])
+    storage = fs.FS_STORAGE_COMPACT if compact else fs.FS_STORAGE_FP32
+    label = f"N=1e8 {'compact' if compact else 'fp32'}"
+    rng = np.random.default_rng(7)
+    sim = fs.Sim.from_model(g, model, storage=storage, steps_per_graph=50, record_rates=True)
+    checked, mism, moved = 0, 0, 0
+    try:
+        sim.seed(seeds, replica=0)
+        for k0 in [0, 50, 100, 150]:
+            sim.step(k0 - sim.step_index())
+            st, age, k = sim.get_state(0)
+            assert k == k0
+            if k0:
+                hist = sim.history(0, k0)
+                np.testing.assert_array_equal(hist[-1], np.bincount(st, minlength=4))
+                np.testing.assert_array_equal(hist.sum(1), n)
+            sim.step(1)
+            gst, gage, _ = sim.get_state(0)
+            rates = sim.rates(0)
+            nodes = subsample(rp, ci, st, 100_000, rng)
+            iota = (st == 2).astype(np.float64)
+            ora = oracle.step_nodes((rp, ci), model, st, age, iota, k, nodes, compact=compact)
+            mism += guard_band_mismatches(gst[nodes], ora["state"], ora["u"], ora["q"],
+                                          f"{label} k={k}")
+            same = gst[nodes] == ora["state"]
+            np.testing.assert_array_equal(gage[nodes][same], ora["age"][same])
+            check_rates(rates[nodes], ora["lam"], f"{label} k={k}")
+            checked += len(nodes)
+            moved += int((gst[nodes] != st[nodes]).sum())
+            del st, age, gst, gage, rates, iota
+    finally:
+        sim.close()
+    check_mismatch_budget(mism, checked, label)
+    assert moved > 300, moved  # the samples hold real transitions
+
+
+def test_compact_storage_error_against_fp64_oracle():
+    """Peak prevalence and attack rate of compact storage (integer step ages)
+    against the FP64 oracle with continuous ages, paired by Philox stream on
+    the same graph: 16 replicas, N = 1e5, 600 steps."""
+    n, d, R, steps = 100_000, 8, 16, 600
+    rp, ci = W.random_regular_matchings(n, d, 3)
+    model = BIG["model"]
+    seeds = W.seed_nodes(n, 50, BIG["seed_rng"])
+    with fs.Graph(rp, ci) as g:
+        sims = {}
+        for name, storage in [("compact", fs.FS_STORAGE_COMPACT), ("fp32", fs.FS_STORAGE_FP32)]:
+            sim = fs.Sim.from_model(g, model, storage=storage, steps_per_graph=50, replicas=R)
+            sim.seed(seeds, replica=-1)
+            sim.step(steps)
+            sims[name] = np.stack([sim.history(0, steps, r) for r in range(R)])
+            sim.close()
+    ora = []
+    for r in range(R):
+        _, _, h = oracle.run((rp, ci), model, W.initial_state(n, seeds), np.zeros(n, np.float32),
+                             steps, replica=r)
+        ora.append(h)
+    ora = np.stack(ora)
+
+    def peak_ar(h):
+        return h[:, :, 2].max(1) / n, 1.0 - h[:, -1, 0] / n
+
+    opk, oar = peak_ar(ora)
+    assert oar.mean() > 0.5  # every replica's outbreak takes off
+    for name in ["compact", "fp32"]:
+        gpk, gar = peak_ar(sims[name])
+        np.testing.assert_array_equal(sims[name].sum(2), n)
+        for a, b, what in [(gpk, opk, "peak"), (gar, oar, "attack rate")]:
+            se = math.sqrt(a.var(ddof=1) / R + b.var(ddof=1) / R)
+            assert abs(a.mean() - b.mean()) < 3 * se, (name, what, a.mean(), b.mean(), se)
+            # paired by Philox stream: two runs separate only after a draw
+            # lands between their probabilities, and even fully separated
+            # outbreaks of this size differ by far less than this
+            assert np.abs(a - b).mean() < 0.01, (name, what, np.abs(a - b).mean())

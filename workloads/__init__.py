@@ -19,10 +19,10 @@ import math
 import numpy as np
 
 from .graphs import (barabasi_albert, complete_graph, csr_from_edges, erdos_renyi,
-                     paper_csr_example, random_regular, star_forest)
+                     paper_csr_example, random_regular, random_regular_matchings, star_forest)
 
 __all__ = ["barabasi_albert", "complete_graph", "csr_from_edges", "erdos_renyi",
-           "paper_csr_example", "random_regular", "star_forest", "seed_nodes",
+           "paper_csr_example", "random_regular", "random_regular_matchings", "star_forest", "seed_nodes",
            "initial_state", "WORKLOADS", "workload_graph", "LN_E", "LN_I"]
 
 # Log-normal holding times of the plain SEIR workloads: E ~ LN(ln 3, 0.5),
@@ -67,9 +67,11 @@ WORKLOADS = {
                   "dt": 0.1, "seed": 0},
         "steps": 500, "seeds": 100, "seed_rng": 102, "storage": "fp32",
     },
-    # random 8-regular graph, N = 1e8 (col_ind 3.2 GB), compact vs FP32 storage
+    # random 8-regular graph, N = 1e8 (col_ind 3.2 GB), compact vs FP32 storage;
+    # built as a union of 8 random perfect matchings (the configuration model's
+    # sort-based repair does not scale to 8e8 stubs)
     "regular8_n1e8": {
-        "graph": ("regular", 100_000_000, 8, 3),
+        "graph": ("regular_m", 100_000_000, 8, 3),
         "model": {"ei": LN_E, "ir": LN_I, "beta": 0.07, "dt": 0.2, "seed": 0},
         "steps": 200, "seeds": 1000, "seed_rng": 103, "storage": "compact",
     },
@@ -82,6 +84,9 @@ def workload_graph(spec):
     if fam == "regular":
         _, n, d, s = spec
         return random_regular(n, d, s)
+    if fam == "regular_m":
+        _, n, d, s = spec
+        return random_regular_matchings(n, d, s)
     if fam == "ba":
         _, n, m, s = spec
         return barabasi_albert(n, m, s)

@@ -83,6 +83,93 @@ def random_regular(n: int, d: int, seed: int):
     return csr_from_edges(n, u, v, symmetric=True)
 
 
+def _batcher_pairs(k: int):
+    """Comparators (i, j), i < j, of Batcher's odd-even merge sort for k keys
+    (the network for the next power of two with every comparator that touches
+    a key >= k dropped, which is still a sorting network for k keys)."""
+    pairs = []
+    p = 1
+    while p < k:
+        q = p
+        while q >= 1:
+            r = q % p
+            for jj in range(r, k - q, 2 * q):
+                for i in range(min(q, k - jj - q)):
+                    if (i + jj) // (2 * p) == (i + jj + q) // (2 * p):
+                        pairs.append((i + jj, i + jj + q))
+            q //= 2
+        p *= 2
+    return pairs
+
+
+def random_regular_matchings(n: int, d: int, seed: int):
+    """Random simple d-regular graph as the union of d independent uniform
+    perfect matchings (n even), for sizes where the configuration model's
+    sort-based repair is too slow (N = 1e8).  For d >= 3 this law is contiguous
+    to the uniform random d-regular graph (Molloy, Robalewska, Robinson and
+    Wormald, 1997), so the two agree on every property that holds with high
+    probability.
+
+    Matching m pairs perm_m[2i] with perm_m[2i+1] for a uniform permutation
+    perm_m, and P[m, a] is the partner of a in it.  The row of node a is
+    [P[0, a], ..., P[d-1, a]], so the CSR is written directly (row_ptr = d a).
+    A pair repeated across two matchings (about d(d-1)/4 of them in
+    expectation, independent of n) is removed by a swap inside the later
+    matching: {a,b},{c,e} -> {a,c},{b,e}, which keeps it a perfect matching and
+    every degree at d.  Rows are returned sorted.
+    """
+    if n % 2:
+        raise ValueError("n must be even")
+    if 2 * d > n:
+        raise ValueError("the matching union is for sparse graphs: need 2 d <= n")
+    if n * d >= 2**31:
+        raise ValueError("edge count does not fit int32")
+    rng = np.random.default_rng(seed)
+    P = np.empty((d, n), dtype=np.int32)
+    for m in range(d):
+        perm = rng.permutation(n).astype(np.int32)
+        P[m, perm[0::2]] = perm[1::2]
+        P[m, perm[1::2]] = perm[0::2]
+        del perm
+    for _ in range(200):
+        bad = np.zeros(n, dtype=bool)
+        for m in range(1, d):
+            for m0 in range(m):
+                bad |= P[m] == P[m0]
+        bad = np.flatnonzero(bad)
+        if len(bad) == 0:
+            break
+        done = set()
+        for a in bad.tolist():
+            row = P[:, a].tolist()
+            for m in range(1, d):
+                b = row[m]
+                if b in row[:m] and a not in done and b not in done:
+                    # move the later copy of {a, b}: swap with a random edge {c, e}
+                    # of matching m (a later round retries if no partner is found)
+                    for _try in range(64):
+                        c = int(rng.integers(0, n))
+                        e = int(P[m, c])
+                        if (len({a, b, c, e}) == 4 and c not in P[:, a].tolist()
+                                and e not in P[:, b].tolist()):
+                            P[m, a], P[m, c] = c, a
+                            P[m, b], P[m, e] = e, b
+                            done.update((a, b, c, e))
+                            break
+                    break
+    else:
+        raise RuntimeError("matching repair did not converge")
+    tmp = np.empty(n, dtype=np.int32)
+    for i, j in _batcher_pairs(d):
+        np.minimum(P[i], P[j], out=tmp)
+        np.maximum(P[i], P[j], out=P[j])
+        P[i] = tmp
+    del tmp
+    col = np.ascontiguousarray(P.T).reshape(-1)
+    del P
+    return np.arange(0, (n + 1) * d, d, dtype=np.int32), col
+
+
 def erdos_renyi(n: int, mean_degree: float, seed: int):
     """G(n, p) with p = mean_degree/(n-1): the edge count is Binomial(n(n-1)/2, p)
     and, given the count, the edge set is a uniform set of distinct pairs."""
