@@ -16,6 +16,12 @@ timed on a bounded sample of the same workload.
 --workload selects another named workload of the same kind (the
 Barabasi-Albert graph with autotuned degree bins, or the N = 1e8 8-regular
 graph with compact or FP32 storage); the default line is the one above.
+
+--serving measures the scenario server instead: a seeded Poisson stream of
+scenario solves (16 replicas, 300 steps, graphs of 1e4..2e6 nodes from a
+resident pool, laws and beta drawn per request) through the server, and the
+same stream as sequential plain solves; it prints scenarios/s and p50/p99
+latency (arrival to counts ready) for both.
 """
 from __future__ import annotations
 
@@ -100,6 +106,120 @@ def cpu_baseline(rp, ci, model, seeds, budget_s: float, compact: bool):
                       f"single-threaded FP64 oracle, {el:.1f} s"}
 
 
+def percentile(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
+
+
+def serving_main(args):
+    import threading
+
+    import numpy as np
+
+    import paper_2604_22092_amd as fs
+    import workloads.serving as WS
+
+    fs.lib()  # fail loudly without the HIP library
+    t0 = time.perf_counter()
+    specs = WS.pool_specs(args.serving_pool, seed=404)
+    pool = [WS.build_graph(sp) for sp in specs]
+    sizes = [len(rp) - 1 for rp, _ in pool]
+    print(f"[serving] pool of {len(pool)} graphs (N {min(sizes)}..{max(sizes)}) built in "
+          f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    graphs = [fs.Graph(rp, ci) for rp, ci in pool]
+    reqs = WS.requests(args.serving_requests, args.serving_rate, sizes, seed=405)
+    updates = sum(sizes[r["graph"]] * r["replicas"] * r["steps"] for r in reqs)
+
+    def plain_solve(r, hist_out=True):
+        sim = fs.Sim(graphs[r["graph"]], r["ei"], r["ir"], r["beta"], r["dt"], seed=r["seed"],
+                     replicas=r["replicas"], history_len=max(r["steps"], 2))
+        sim.seed(r["seeds"], replica=-1)
+        sim.step(r["steps"])
+        h = np.stack([sim.history(0, r["steps"], k) for k in range(r["replicas"])], axis=1) \
+            if hist_out else sim.counts(0)
+        sim.close()
+        return h
+
+    # warm-up: every pool graph once (kernels loaded, the graphs' row layouts
+    # for 16 replicas built and cached, as for resident graphs)
+    for gi in range(len(graphs)):
+        r = dict(reqs[0], graph=gi, steps=4, seeds=np.array([0, 1], np.int64))
+        plain_solve(r, hist_out=False)
+    print(f"[serving] {len(reqs)} requests, {updates / 1e9:.1f} G node-updates, "
+          f"offered {updates / reqs[-1]['arrival'] / 1e9:.1f} GNUPS", file=sys.stderr, flush=True)
+
+    # batched: the server, with requests submitted at their arrival times
+    sv = fs.Server(max_active=args.serving_slots, steps_per_round=args.serving_round)
+    ids = [None] * len(reqs)
+    start = fs.fs_server_clock() + 0.05
+
+    def submitter():
+        for i, r in enumerate(reqs):
+            delay = start + r["arrival"] - fs.fs_server_clock()
+            if delay > 0:
+                time.sleep(delay)
+            ids[i] = sv.submit(graphs[r["graph"]], r["ei"], r["ir"], r["beta"], r["dt"], r["seed"],
+                               r["replicas"], r["steps"], r["seeds"])
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    check = set(range(0, len(reqs), max(1, len(reqs) // 8)))
+    b_hist, b_info = {}, []
+    for i, rid in enumerate(ids):
+        sv.wait(rid)
+        h, info = sv.result(rid)
+        b_info.append(info)
+        if i in check:
+            b_hist[i] = h
+    sv.close()
+    b_lat = [x["t_done"] - x["t_submit"] for x in b_info]
+    b_span = max(x["t_done"] for x in b_info) - start
+    print(f"[serving] batched: {len(reqs) / b_span:.1f} scenarios/s, p50 {percentile(b_lat, 50):.3f}s "
+          f"p99 {percentile(b_lat, 99):.3f}s", file=sys.stderr, flush=True)
+
+    # sequential plain solves of the same stream: one at a time, each starting
+    # when it has arrived and the previous one is done
+    s_lat = []
+    same = 0
+    start = time.perf_counter() + 0.05
+    for i, r in enumerate(reqs):
+        delay = start + r["arrival"] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        h = plain_solve(r)
+        s_lat.append(time.perf_counter() - (start + r["arrival"]))
+        if i in b_hist:
+            if not np.array_equal(h, b_hist[i]):
+                raise SystemExit(f"request {i}: batched and sequential counts differ")
+            same += 1
+    s_span = time.perf_counter() - start
+    print(f"[serving] sequential: {len(reqs) / s_span:.1f} scenarios/s, p50 {percentile(s_lat, 50):.3f}s "
+          f"p99 {percentile(s_lat, 99):.3f}s", file=sys.stderr, flush=True)
+    for g in graphs:
+        g.close()
+
+    def rec(n, span, lat):
+        return {"scenarios_per_s": round(n / span, 3), "p50_s": round(percentile(lat, 50), 4),
+                "p99_s": round(percentile(lat, 99), 4), "makespan_s": round(span, 3),
+                "gnups": round(updates / span / 1e9, 3)}
+
+    out = {
+        "metric": "batched-serving scenarios/s + p50/p99 latency",
+        "value": round(len(reqs) / b_span, 3), "unit": "scenarios/s", "n_gpus": 1,
+        "higher_is_better": True, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "serving_mix", "requests": len(reqs), "rate_per_s": args.serving_rate,
+                   "pool_graphs": len(pool), "n_range": [min(sizes), max(sizes)], "replicas": 16,
+                   "steps": 300, "dt": 0.1, "slots": args.serving_slots,
+                   "steps_per_round": args.serving_round, "parallelism": "single GPU"},
+        "serving": {"batched": rec(len(reqs), b_span, b_lat),
+                    "sequential": rec(len(reqs), s_span, s_lat),
+                    "identical_counts_checked": same,
+                    "offered_gnups": round(updates / reqs[-1]["arrival"] / 1e9, 3)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,8 +235,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
-    ap.add_argument("--variant", choices=["auto", "stream", "resident"], default="auto",
-                    help="step kernel variant (auto: LDS-resident bitmap when N*R <= 2^20)")
+    ap.add_argument("--variant", choices=["auto", "stream", "resident", "summary"], default="auto",
+                    help="step kernel variant (auto: LDS-resident bitmap when N*R <= 2^20, "
+                         "else the LDS summary that screens bitmap reads)")
+    ap.add_argument("--serving", action="store_true",
+                    help="measure the scenario server on the seeded request mix instead")
+    ap.add_argument("--serving-requests", type=int, default=400)
+    ap.add_argument("--serving-rate", type=float, default=50.0, help="Poisson arrivals per second")
+    ap.add_argument("--serving-pool", type=int, default=24, help="resident pool graphs")
+    ap.add_argument("--serving-slots", type=int, default=0, help="server slot limit (0 = default)")
+    ap.add_argument("--serving-round", type=int, default=0, help="steps per round (0 = default)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB, so a "
                          "counter profile of the same process can scale HBM byte counters")
@@ -126,6 +254,9 @@ def main():
               "(replicas and scenarios shard across GPUs without exchange; see the design notes)",
               file=sys.stderr)
         sys.exit(2)
+    if args.serving:
+        serving_main(args)
+        return
 
     import numpy as np
     import torch
@@ -163,7 +294,7 @@ def main():
               flush=True)
     g = fs.Graph(rp, ci)
     variant = {"auto": fs.VARIANT_AUTO, "stream": fs.VARIANT_STREAM,
-               "resident": fs.VARIANT_RESIDENT}[args.variant]
+               "resident": fs.VARIANT_RESIDENT, "summary": fs.VARIANT_SUMMARY}[args.variant]
     sim = fs.Sim.from_model(g, model, steps_per_graph=STEPS_PER_GRAPH, stream=stream.cuda_stream,
                             variant=variant,
                             storage=fs.FS_STORAGE_COMPACT if compact else fs.FS_STORAGE_FP32)

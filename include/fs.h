@@ -136,9 +136,12 @@ typedef struct fs_sim_params {
     int32_t steps_per_graph; /* b: steps per captured hipGraph replay; 0 = launch eagerly */
     int32_t history_len;     /* per-step count ring length (>= 2); 0 = 1024 */
     int32_t record_rates;    /* nonzero: keep each unit's rate lambda of the last step */
-    int32_t variant;         /* step kernel: 0 = automatic, 1 = streaming (bitmap read
+    int32_t variant;         /* step kernel: 0 = automatic (resident when n * n_replicas
+                                <= 2^20, else summary), 1 = streaming (bitmap read
                                 through the caches), 2 = resident (bitmap held in LDS;
-                                n * n_replicas <= 2^20).  Results are identical. */
+                                n * n_replicas <= 2^20), 3 = summary (an LDS summary with
+                                one bit per group of units screens the bitmap reads).
+                                Results are identical. */
     int32_t heavy_degree;    /* degree bins: rows with more incoming edges than this get
                                 their pressure from the heavy-row kernel (segments of
                                 segment_edges edges, one wavefront each); 0 = 64,
@@ -259,6 +262,116 @@ fs_status fs_eval_philox(int64_t n, const uint32_t* ctr, uint64_t seed, uint32_t
 
 /* Library version string. */
 const char* fs_version(void);
+
+/* ---------------------------------------------------------------- batches
+ * A batch advances several sims together, one fused step launch per step
+ * for all of them (Algorithm 3's fused step over a table of simulations
+ * instead of one): each member keeps its own graph, laws, beta, dt, seed,
+ * replicas, step index and count history, and gets exactly the results it
+ * gets alone (same draws, same states, same counts).  Small simulations that
+ * cannot fill the GPU alone fill it together.
+ *
+ * Members must be created with variant = 1 (streaming step), the batch's
+ * storage, and agree on weights (all weighted or none) and record_rates.
+ * While a sim belongs to a batch, its device work runs on the batch's stream:
+ * fs_counts, fs_history, fs_get_state, fs_set_state, fs_get_rates and
+ * fs_sim_seed still work on it; fs_step, fs_sim_set_bins, fs_sim_tune and
+ * fs_sim_destroy return FS_ERR_BUSY until it is removed.
+ */
+typedef struct fs_batch fs_batch;
+
+/* Creates an empty batch on the current HIP device.  storage is
+ * FS_STORAGE_FP32 or FS_STORAGE_COMPACT; stream is a hipStream_t to run on,
+ * or NULL for a stream owned by the batch. */
+fs_status fs_batch_create(int32_t storage, void* stream, fs_batch** out);
+/* Waits for queued work, removes every member (they keep their state) and
+ * releases the batch. */
+fs_status fs_batch_destroy(fs_batch* b);
+/* Adds sim s (its queued work is finished first).  FS_ERR_INVALID_ARG when s
+ * does not meet the member rules above, FS_ERR_BUSY when s is already in a
+ * batch. */
+fs_status fs_batch_add(fs_batch* b, fs_sim* s);
+/* Removes sim s after the batch's queued work; s returns to its own stream. */
+fs_status fs_batch_remove(fs_batch* b, fs_sim* s);
+/* Number of members. */
+fs_status fs_batch_size(fs_batch* b, int32_t* members);
+/* Queues n_steps steps of every member (asynchronous, like fs_step). */
+fs_status fs_batch_step(fs_batch* b, int64_t n_steps);
+/* Waits for the batch's queued work. */
+fs_status fs_batch_sync(fs_batch* b);
+
+/* ----------------------------------------------------------------- server
+ * A scenario server: callers submit independent scenario solves (a resident
+ * graph, laws and rates, replicas, seeds, a number of steps) from any
+ * thread; a worker thread admits queued requests in arrival order while the
+ * device-memory budget and the slot limit allow, advances every admitted
+ * request with one batch (see above) a few steps at a time, and retires the
+ * requests that reach their step count, so a request that arrives while
+ * others are on the GPU joins them at the next round.  A request's counts
+ * equal those of the same sim run alone.
+ */
+typedef struct fs_server fs_server;
+
+typedef struct fs_server_params {
+    int64_t memory_budget;   /* device bytes the admitted requests may hold; 0 = 80% of
+                                the free device memory at creation */
+    int32_t max_active;      /* most requests on the device at once; 0 = 64 */
+    int32_t steps_per_round; /* steps run between admission checks; 0 = 25 */
+    int32_t storage;         /* FS_STORAGE_FP32 or FS_STORAGE_COMPACT for every request */
+    int32_t pad;
+    void* stream;            /* hipStream_t to run on; NULL = a stream owned by the server */
+} fs_server_params;
+
+typedef struct fs_request {
+    fs_graph* graph;         /* resident graph; must outlive the request (fs_graph_destroy
+                                returns FS_ERR_BUSY until the request is collected) */
+    fs_sim_params params;    /* laws, beta, dt, seed and n_replicas; storage, variant,
+                                steps_per_graph, history_len, record_rates and stream are
+                                set by the server */
+    int64_t n_steps;         /* steps to run, in [1, 2^20] */
+    int64_t n_seeds;         /* nodes seeded into E at age 0 in every replica */
+    const int64_t* seeds;    /* host array, copied at submission */
+} fs_request;
+
+typedef struct fs_request_info {
+    double t_submit;         /* server clock (fs_server_clock) at submission */
+    double t_admit;          /* ... when the request's sim was created */
+    double t_done;           /* ... when its counts were copied out */
+    int64_t n_steps;
+    int32_t n_replicas;
+    fs_status status;        /* FS_OK, or the failure that ended the request */
+} fs_request_info;
+
+typedef struct fs_server_stats_t {
+    int64_t queued;          /* submitted, not yet admitted */
+    int64_t active;          /* on the device */
+    int64_t memory_in_use;   /* estimated device bytes of the active requests */
+    int64_t memory_budget;
+    int64_t rounds;          /* batch rounds run so far */
+} fs_server_stats_t;
+
+/* Creates a server on the current HIP device and starts its worker thread. */
+fs_status fs_server_create(const fs_server_params* p, fs_server** out);
+/* Queues a request and returns its id (> 0).  FS_ERR_BUDGET when the request
+ * alone needs more memory than the budget; FS_ERR_INVALID_ARG for bad
+ * arguments (laws and rates are validated when the request is admitted: a
+ * bad one ends that request with FS_ERR_INVALID_ARG). */
+fs_status fs_server_submit(fs_server* sv, const fs_request* rq, int64_t* id);
+/* Waits until request id has finished or timeout_s seconds passed (< 0:
+ * no limit); *done = 1 when it has finished. */
+fs_status fs_server_wait(fs_server* sv, int64_t id, double timeout_s, int32_t* done);
+/* Collects a finished request: copies its per-step counts to history
+ * ([n_steps][n_replicas][4] int64, S E I R after each step; may be NULL) and
+ * its timing to info (may be NULL), then forgets the request.  Returns the
+ * request's failure status if it failed, FS_ERR_BUSY if it has not finished. */
+fs_status fs_server_result(fs_server* sv, int64_t id, int64_t* history, fs_request_info* info);
+/* Current queue, device and memory figures. */
+fs_status fs_server_stats(fs_server* sv, fs_server_stats_t* out);
+/* Cancels queued requests, lets admitted ones finish, stops the worker and
+ * releases the server. */
+fs_status fs_server_destroy(fs_server* sv);
+/* The server clock (seconds, monotonic) used by fs_request_info. */
+double fs_server_clock(void);
 
 #ifdef __cplusplus
 }

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "FS_OK", 1: "FS_ERR_INVALID_ARG", 2: "FS_ERR_INVALID_CSR",
 FS_S, FS_E, FS_I, FS_R = 0, 1, 2, 3
 FS_DIST_EXP, FS_DIST_LOGNORMAL, FS_DIST_WEIBULL, FS_DIST_ERLANG = 0, 1, 2, 3
 FS_STORAGE_FP32, FS_STORAGE_COMPACT = 0, 1
-VARIANT_AUTO, VARIANT_STREAM, VARIANT_RESIDENT = 0, 1, 2
+VARIANT_AUTO, VARIANT_STREAM, VARIANT_RESIDENT, VARIANT_SUMMARY = 0, 1, 2, 3
 
 # Every symbol include/fs.h declares.
 EXPORTS = [
@@ -32,6 +32,10 @@ EXPORTS = [
     "fs_sync", "fs_step_index", "fs_counts", "fs_history", "fs_get_state", "fs_set_state",
     "fs_get_rates", "fs_eval_hazard", "fs_eval_philox", "fs_version", "fs_sim_set_bins",
     "fs_sim_get_bins", "fs_sim_tune",
+    "fs_batch_create", "fs_batch_destroy", "fs_batch_add", "fs_batch_remove", "fs_batch_size",
+    "fs_batch_step", "fs_batch_sync",
+    "fs_server_create", "fs_server_submit", "fs_server_wait", "fs_server_result",
+    "fs_server_stats", "fs_server_destroy", "fs_server_clock",
 ]
 
 
@@ -59,6 +63,29 @@ class fs_sim_params(ctypes.Structure):
                 ("record_rates", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("heavy_degree", ctypes.c_int32), ("segment_edges", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
+
+
+class fs_server_params(ctypes.Structure):
+    _fields_ = [("memory_budget", ctypes.c_int64), ("max_active", ctypes.c_int32),
+                ("steps_per_round", ctypes.c_int32), ("storage", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class fs_request(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_void_p), ("params", fs_sim_params), ("n_steps", ctypes.c_int64),
+                ("n_seeds", ctypes.c_int64), ("seeds", ctypes.c_void_p)]
+
+
+class fs_request_info(ctypes.Structure):
+    _fields_ = [("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("n_steps", ctypes.c_int64),
+                ("n_replicas", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
+class fs_server_stats_t(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int64), ("active", ctypes.c_int64),
+                ("memory_in_use", ctypes.c_int64), ("memory_budget", ctypes.c_int64),
+                ("rounds", ctypes.c_int64)]
 
 
 _lib = None
@@ -104,6 +131,20 @@ def _declare(L):
         "fs_sim_get_bins": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                              ctypes.POINTER(ctypes.c_int64)], I32),
         "fs_sim_tune": ([P, I32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], I32),
+        "fs_batch_create": ([I32, P, PP], I32),
+        "fs_batch_destroy": ([P], I32),
+        "fs_batch_add": ([P, P], I32),
+        "fs_batch_remove": ([P, P], I32),
+        "fs_batch_size": ([P, ctypes.POINTER(ctypes.c_int32)], I32),
+        "fs_batch_step": ([P, I64], I32),
+        "fs_batch_sync": ([P], I32),
+        "fs_server_create": ([ctypes.POINTER(fs_server_params), PP], I32),
+        "fs_server_submit": ([P, ctypes.POINTER(fs_request), ctypes.POINTER(ctypes.c_int64)], I32),
+        "fs_server_wait": ([P, I64, ctypes.c_double, ctypes.POINTER(ctypes.c_int32)], I32),
+        "fs_server_result": ([P, I64, P, ctypes.POINTER(fs_request_info)], I32),
+        "fs_server_stats": ([P, ctypes.POINTER(fs_server_stats_t)], I32),
+        "fs_server_destroy": ([P], I32),
+        "fs_server_clock": ([], ctypes.c_double),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -284,6 +325,28 @@ class Graph:
         self.close()
 
 
+def make_params(ei, ir, beta: float, dt: float, seed: int = 0, replicas: int = 1,
+                storage: int = FS_STORAGE_FP32, steps_per_graph: int = 0, history_len: int = 0,
+                record_rates: bool = False, variant: int = 0, heavy_degree: int = 0,
+                segment_edges: int = 0, stream=None) -> fs_sim_params:
+    p = fs_sim_params()
+    p.ei = make_dist(ei)
+    p.ir = make_dist(ir)
+    p.beta = float(beta)
+    p.dt = float(dt)
+    p.seed = int(seed) & (2**64 - 1)
+    p.n_replicas = int(replicas)
+    p.storage = int(storage)
+    p.steps_per_graph = int(steps_per_graph)
+    p.history_len = int(history_len)
+    p.record_rates = 1 if record_rates else 0
+    p.variant = int(variant)
+    p.heavy_degree = int(heavy_degree)
+    p.segment_edges = int(segment_edges)
+    p.stream = None if stream is None else ctypes.c_void_p(int(stream))
+    return p
+
+
 class Sim:
     """R replicas of the SEIR renewal process on one Graph."""
 
@@ -291,21 +354,8 @@ class Sim:
                  replicas: int = 1, storage: int = FS_STORAGE_FP32, steps_per_graph: int = 0,
                  history_len: int = 0, record_rates: bool = False, variant: int = 0,
                  heavy_degree: int = 0, segment_edges: int = 0, stream=None):
-        p = fs_sim_params()
-        p.ei = make_dist(ei)
-        p.ir = make_dist(ir)
-        p.beta = float(beta)
-        p.dt = float(dt)
-        p.seed = int(seed) & (2**64 - 1)
-        p.n_replicas = int(replicas)
-        p.storage = int(storage)
-        p.steps_per_graph = int(steps_per_graph)
-        p.history_len = int(history_len)
-        p.record_rates = 1 if record_rates else 0
-        p.variant = int(variant)
-        p.heavy_degree = int(heavy_degree)
-        p.segment_edges = int(segment_edges)
-        p.stream = None if stream is None else ctypes.c_void_p(int(stream))
+        p = make_params(ei, ir, beta, dt, seed, replicas, storage, steps_per_graph, history_len,
+                        record_rates, variant, heavy_degree, segment_edges, stream)
         self.graph = graph
         self.n = graph.n
         self.replicas = int(replicas)
@@ -364,3 +414,162 @@ class Sim:
 
     def __exit__(self, *exc):
         self.close()
+
+
+# ------------------------------------------------------------- batches, server
+
+def fs_batch_create(storage: int = FS_STORAGE_FP32, stream=None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    st = None if stream is None else ctypes.c_void_p(int(stream))
+    _check(lib().fs_batch_create(int(storage), st, ctypes.byref(h)), "fs_batch_create")
+    return h
+
+
+def fs_batch_destroy(h):
+    _check(lib().fs_batch_destroy(h), "fs_batch_destroy")
+
+
+def fs_batch_add(h, sim):
+    _check(lib().fs_batch_add(h, sim), "fs_batch_add")
+
+
+def fs_batch_remove(h, sim):
+    _check(lib().fs_batch_remove(h, sim), "fs_batch_remove")
+
+
+def fs_batch_size(h) -> int:
+    v = ctypes.c_int32()
+    _check(lib().fs_batch_size(h, ctypes.byref(v)), "fs_batch_size")
+    return v.value
+
+
+def fs_batch_step(h, n_steps: int):
+    _check(lib().fs_batch_step(h, int(n_steps)), "fs_batch_step")
+
+
+def fs_batch_sync(h):
+    _check(lib().fs_batch_sync(h), "fs_batch_sync")
+
+
+def fs_server_create(memory_budget: int = 0, max_active: int = 0, steps_per_round: int = 0,
+                     storage: int = FS_STORAGE_FP32, stream=None) -> ctypes.c_void_p:
+    p = fs_server_params(int(memory_budget), int(max_active), int(steps_per_round), int(storage), 0,
+                         None if stream is None else ctypes.c_void_p(int(stream)))
+    h = ctypes.c_void_p()
+    _check(lib().fs_server_create(ctypes.byref(p), ctypes.byref(h)), "fs_server_create")
+    return h
+
+
+def fs_server_submit(h, graph, params: fs_sim_params, n_steps: int, seeds) -> int:
+    sd = np.ascontiguousarray(seeds, dtype=np.int64)
+    rq = fs_request(graph, params, int(n_steps), len(sd), _ptr(sd))
+    rid = ctypes.c_int64()
+    _check(lib().fs_server_submit(h, ctypes.byref(rq), ctypes.byref(rid)), "fs_server_submit")
+    return rid.value
+
+
+def fs_server_wait(h, rid: int, timeout_s: float = -1.0) -> bool:
+    done = ctypes.c_int32()
+    _check(lib().fs_server_wait(h, int(rid), float(timeout_s), ctypes.byref(done)), "fs_server_wait")
+    return bool(done.value)
+
+
+def fs_server_result(h, rid: int, n_steps: int, replicas: int):
+    hist = np.zeros((n_steps, replicas, 4), dtype=np.int64)
+    info = fs_request_info()
+    _check(lib().fs_server_result(h, int(rid), _ptr(hist), ctypes.byref(info)), "fs_server_result")
+    return hist, {f: getattr(info, f) for f, _ in fs_request_info._fields_}
+
+
+def fs_server_stats(h) -> dict:
+    st = fs_server_stats_t()
+    _check(lib().fs_server_stats(h, ctypes.byref(st)), "fs_server_stats")
+    return {f: getattr(st, f) for f, _ in fs_server_stats_t._fields_}
+
+
+def fs_server_destroy(h):
+    _check(lib().fs_server_destroy(h), "fs_server_destroy")
+
+
+def fs_server_clock() -> float:
+    return lib().fs_server_clock()
+
+
+class Batch:
+    """Several Sims advanced by one fused launch per step (members must be
+    created with variant=VARIANT_STREAM and share storage)."""
+
+    def __init__(self, storage: int = FS_STORAGE_FP32, stream=None):
+        self.handle = fs_batch_create(storage, stream)
+        self.members = []
+
+    def add(self, sim: Sim):
+        fs_batch_add(self.handle, sim.handle)
+        self.members.append(sim)
+
+    def remove(self, sim: Sim):
+        fs_batch_remove(self.handle, sim.handle)
+        self.members.remove(sim)
+
+    def size(self) -> int:
+        return fs_batch_size(self.handle)
+
+    def step(self, n_steps: int = 1):
+        fs_batch_step(self.handle, n_steps)
+
+    def sync(self):
+        fs_batch_sync(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            fs_batch_destroy(self.handle)
+            self.handle = None
+            self.members = []
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Server:
+    """The scenario server: submit(...) from any thread, result(...) when done."""
+
+    def __init__(self, memory_budget: int = 0, max_active: int = 0, steps_per_round: int = 0,
+                 storage: int = FS_STORAGE_FP32, stream=None):
+        self.handle = fs_server_create(memory_budget, max_active, steps_per_round, storage, stream)
+        self._shape = {}
+
+    def submit(self, graph: Graph, ei, ir, beta: float, dt: float, seed: int, replicas: int,
+               n_steps: int, seeds) -> int:
+        p = make_params(ei, ir, beta, dt, seed, replicas)
+        rid = fs_server_submit(self.handle, graph.handle, p, n_steps, seeds)
+        self._shape[rid] = (int(n_steps), int(replicas))
+        return rid
+
+    def wait(self, rid: int, timeout_s: float = -1.0) -> bool:
+        return fs_server_wait(self.handle, rid, timeout_s)
+
+    def result(self, rid: int):
+        """(history [n_steps][replicas][4], info dict); forgets the request."""
+        n_steps, replicas = self._shape.pop(rid)
+        return fs_server_result(self.handle, rid, n_steps, replicas)
+
+    def stats(self) -> dict:
+        return fs_server_stats(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            fs_server_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+__all__ = [n for n, v in list(globals().items())
+           if not n.startswith("_") and not isinstance(v, type(os)) and n not in ("annotations",)]

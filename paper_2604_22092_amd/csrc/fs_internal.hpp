@@ -10,13 +10,18 @@ enum : int32_t { K_EXP = 0, K_LN = 1, K_WB = 2, K_ERL = 3 };
 
 // Workgroup size of the helper kernels (four wave64 wavefronts).
 constexpr int WG = 256;
-// Step kernel variants: the streaming variant (bitmap read through the
-// caches) runs STREAM_TPB threads per workgroup; the resident variant (bitmap
-// held in LDS, one workgroup per compute unit) runs RESIDENT_TPB threads and
-// holds up to RESIDENT_BITS units.  Both walk 64-unit chunks per wavefront.
+// Step kernel variants, all walking 64-unit chunks per wavefront:
+//  MODE_STREAM   bitmap read through the caches; STREAM_TPB threads per workgroup;
+//  MODE_RESIDENT the whole bitmap (up to RESIDENT_BITS units) held in LDS;
+//  MODE_SUMMARY  an LDS summary with one bit per 2^lg_gran units (set when any
+//                unit of the group is infectious; at most SUMMARY_BITS bits)
+//                screens the reads of the bitmap, which stays in global memory.
+// The two LDS variants run one RESIDENT_TPB-thread workgroup per compute unit.
+enum : int32_t { MODE_STREAM = 0, MODE_RESIDENT = 1, MODE_SUMMARY = 2 };
 constexpr int STREAM_TPB = 256;
 constexpr int RESIDENT_TPB = 1024;
 constexpr uint32_t RESIDENT_BITS = 1u << 20;
+constexpr uint32_t SUMMARY_BITS = 1u << 20;
 // Bitmaps are allocated in whole 512-unit tiles (8 words of 64 bits).
 constexpr uint32_t BITMAP_TILE = 512;
 
@@ -64,7 +69,7 @@ struct StepArgs {
     int32_t n;
     int32_t lgR;          // R = 1 << lgR replicas
     uint32_t step_off;    // j: this launch runs step ctl->step + j, partial slot j
-    uint32_t ntiles;      // unused (kept for layout stability)
+    int32_t lg_gran;      // MODE_SUMMARY: units per summary bit = 1 << lg_gran (>= 6)
     int32_t same_kind;    // E and I laws share a kind: one hazard call per lane
     int32_t pad0;
     HazardDev hz[2];      // [0] E -> I, [1] I -> R
@@ -88,6 +93,25 @@ struct StepArgs {
     const uint8_t* chunk_deg; // the shared light degree of a chunk's rows, 255 if mixed
     const int32_t* col_t;
     const float* w_t;
+    // MODE_SUMMARY: summary of the step's input bitmap, sum_bits bits
+    const uint32_t* summary;
+    uint32_t sum_bits;
+    uint32_t pad1;
+};
+
+// Arguments of the summary launch that follows a step launch (or a bitmap
+// rebuild): it summarises bitmap iota[(ctl->step + step_off + after) & 1].
+struct SumArgs {
+    const unsigned long long* iota0;
+    const unsigned long long* iota1;
+    const Ctl* ctl;
+    unsigned long long* summary;
+    uint32_t words;     // 64-bit words per bitmap
+    uint32_t sum_words; // 64-bit words of the summary
+    int32_t lg_gran;
+    uint32_t step_off;
+    uint32_t after;     // 1: the bitmap written by step ctl->step + step_off
+    uint32_t pad;
 };
 
 constexpr uint16_t HEAVY_ROW = 0xFFFF;
@@ -110,6 +134,15 @@ struct HeavyArgs {
     int32_t lgR;
     uint32_t step_off;
     uint32_t pad;
+};
+
+// One member's count reduction in a batch: per-workgroup partials of G
+// workgroups, C = 4R counters each, summed into the H-slot history ring.
+struct RedArgs {
+    const Ctl* ctl;
+    const uint32_t* part;
+    uint32_t* hist;
+    uint32_t G, C, H, pad;
 };
 
 // Upper bound on step workgroups (they loop over tiles beyond it), chosen so

@@ -59,6 +59,20 @@ __device__ __forceinline__ uint32_t lds_bit(const uint32_t* __restrict__ w, uint
     return __builtin_amdgcn_ubfe(w[b >> 5], b & 31, 1);
 }
 
+// Infectivity bit b of the step's input: from the LDS copy (MODE_RESIDENT),
+// from global memory (MODE_STREAM), or from global memory only when the LDS
+// summary says its group holds an infectious unit (MODE_SUMMARY).
+template <int MODE>
+__device__ __forceinline__ uint32_t fetch_bit(const uint32_t* __restrict__ lds, const uint32_t* __restrict__ gbits,
+                                              uint32_t b, int32_t lg_gran)
+{
+    if (MODE == MODE_RESIDENT) return lds_bit(lds, b);
+    if (MODE == MODE_STREAM) return bit_at(gbits, b);
+    uint32_t r = 0;
+    if (lds_bit(lds, b >> lg_gran)) r = bit_at(gbits, b);
+    return r;
+}
+
 // Light-row edge slots loaded ahead for chunks whose rows share one light
 // degree (every chunk of a regular graph): slot j of row q is col_t[base +
 // j*Q + q], so these loads need only the chunk's metadata and are issued with
@@ -72,7 +86,7 @@ constexpr int JB = 8;
 // Chunks of 64 units each wavefront takes per pass; the hazards and draws of
 // a pass are evaluated on compacted lanes.
 #ifndef FS_CU
-#define FS_CU 2
+#define FS_CU 1
 #endif
 constexpr int CU = FS_CU;
 
@@ -127,9 +141,10 @@ __device__ __forceinline__ void issue_pass(const StepArgs& a, uint32_t first, ui
 // beta).  Uniform chunks use the preloaded slots; mixed chunks find a row's
 // position in run j as its rank among the rows with more than j edges (ballot
 // prefix count), JB slots at a time.
-template <bool WEIGHTED, class age_t>
+template <int MODE, bool WEIGHTED, class age_t>
 __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_t>& P, int u, bool want,
-                                              const uint32_t* __restrict__ bits, uint32_t lane)
+                                              const uint32_t* __restrict__ lds, const uint32_t* __restrict__ gbits,
+                                              uint32_t lane)
 {
     const int32_t lgR = a.lgR;
     const uint32_t R = 1u << lgR;
@@ -143,7 +158,7 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
 #pragma unroll
         for (int j = 0; j < UMAX; ++j) {
             if ((uint32_t)j < P.ud[u] && want) {
-                const uint32_t b = lds_bit(bits, ((uint32_t)P.c[u][j] << lgR) + rep);
+                const uint32_t b = fetch_bit<MODE>(lds, gbits, ((uint32_t)P.c[u][j] << lgR) + rep, a.lg_gran);
                 if (WEIGHTED) pw = __builtin_fmaf(a.w_t[P.base[u] + (uint32_t)j * rows + q], (float)b, pw);
                 else pi += b;
             }
@@ -170,7 +185,7 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
 #pragma unroll
             for (int jj = 0; jj < JB; ++jj) {
                 if (want && d > j0 + jj) {
-                    const uint32_t b = lds_bit(bits, ((uint32_t)c[jj] << lgR) + rep);
+                    const uint32_t b = fetch_bit<MODE>(lds, gbits, ((uint32_t)c[jj] << lgR) + rep, a.lg_gran);
                     if (WEIGHTED) pw = __builtin_fmaf(wv[jj], (float)b, pw);
                     else pi += b;
                 }
@@ -245,21 +260,26 @@ __device__ __forceinline__ void compact_apply(uint32_t* xch, uint32_t lane, cons
 // One fused step.  Units are processed in chunks of 64 (one wavefront, one
 // 64-bit word of the next infectivity bitmap); every wavefront walks its own
 // chunks, CU per pass, with no workgroup barrier inside the walk.
-//  RESIDENT: the whole start-of-step bitmap (units <= RESIDENT_BITS) is copied
-//    into LDS once per workgroup (direct global-to-LDS loads, overlapped with
-//    the first pass's loads) and every gather reads LDS; launched with one
-//    workgroup of RESIDENT_TPB threads per compute unit.
-//  otherwise: gathers read the bitmap through the caches.
-template <int STORAGE, bool WEIGHTED, bool RATES, bool RESIDENT, int TPB>
-__global__ __launch_bounds__(TPB) void step_kernel(StepArgs a)
+//  MODE_RESIDENT: the whole start-of-step bitmap (units <= RESIDENT_BITS) is
+//    copied into LDS once per workgroup (direct global-to-LDS loads, overlapped
+//    with the first pass's loads) and every gather reads LDS;
+//  MODE_SUMMARY: the bitmap's summary is copied into LDS the same way, and a
+//    gather reads the global bitmap only where the summary bit is set (when
+//    infection is sparse most neighbours fall in empty groups);
+//  MODE_STREAM: gathers read the bitmap through the caches.
+// The LDS variants run one workgroup of RESIDENT_TPB threads per compute unit.
+template <int STORAGE, bool WEIGHTED, bool RATES, int MODE, int TPB>
+__device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uint32_t nblocks)
 {
+    constexpr bool USE_LDS = MODE != MODE_STREAM;
     using S = Store<STORAGE>;
     using state_t = typename S::state_t;
     using age_t = typename S::age_t;
     constexpr int NW = TPB / 64;
 
     __shared__ uint32_t s_cnt[4 * 64];
-    __shared__ __attribute__((aligned(16))) uint32_t s_bits[RESIDENT ? RESIDENT_BITS / 32 : 4];
+    __shared__ __attribute__((aligned(16))) uint32_t s_bits[USE_LDS ? RESIDENT_BITS / 32 : 4];
+    static_assert(SUMMARY_BITS <= RESIDENT_BITS, "the summary shares the LDS bitmap array");
     __shared__ uint32_t s_xch[NW][64];
 
     const uint32_t tid = threadIdx.x;
@@ -273,8 +293,8 @@ __global__ __launch_bounds__(TPB) void step_kernel(StepArgs a)
     age_t* __restrict__ age = (age_t*)a.age;
     const uint32_t total = (uint32_t)a.n << a.lgR;
     const uint32_t nchunks = (total + 63) >> 6;
-    const uint32_t wave_id = blockIdx.x * NW + wave;
-    const uint32_t nwaves = gridDim.x * NW;
+    const uint32_t wave_id = block * NW + wave;
+    const uint32_t nwaves = nblocks * NW;
 
     // first pass loads, then the bitmap fill, then one wait for both
     Pass<age_t> P;
@@ -282,11 +302,12 @@ __global__ __launch_bounds__(TPB) void step_kernel(StepArgs a)
     if (first < nchunks) issue_pass<STORAGE>(a, first, nwaves, nchunks, total, lane, P);
     if (R > 1)
         for (uint32_t i = tid; i < 4 * R; i += TPB) s_cnt[i] = 0;
-    if (RESIDENT) {
+    if (USE_LDS) {
         // 16 bytes per lane straight into LDS: wave w fills the blocks of 64
         // uint4 it owns; lane l's block element lands at base + 16 l
-        const uint32_t n4 = (((total + 31) >> 5) + 3) >> 2;
-        const uint4* src = (const uint4*)bits_in;
+        const uint32_t nbits = MODE == MODE_RESIDENT ? total : a.sum_bits;
+        const uint32_t n4 = (((nbits + 31) >> 5) + 3) >> 2;
+        const uint4* src = (const uint4*)(MODE == MODE_RESIDENT ? bits_in : a.summary);
         for (uint32_t b0 = wave * 64; b0 < n4; b0 += TPB) {
             if (b0 + lane < n4)
                 __builtin_amdgcn_global_load_lds((const void*)(src + b0 + lane),
@@ -294,8 +315,7 @@ __global__ __launch_bounds__(TPB) void step_kernel(StepArgs a)
         }
         __builtin_amdgcn_s_waitcnt(0);
     }
-    if (R > 1 || RESIDENT) __syncthreads();
-    const uint32_t* __restrict__ gbits = RESIDENT ? s_bits : bits_in;
+    if (R > 1 || USE_LDS) __syncthreads();
 
     uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0; // per-wave counts (R == 1)
 
@@ -309,7 +329,7 @@ __global__ __launch_bounds__(TPB) void step_kernel(StepArgs a)
             lam[u] = 0.0f;
             const bool heavy = P.dg[u] == HEAVY_ROW;
             const bool want = P.x[u] == ST_S && !heavy;
-            const float p = pressure_row<WEIGHTED>(a, P, u, want, gbits, lane);
+            const float p = pressure_row<MODE, WEIGHTED>(a, P, u, want, s_bits, bits_in, lane);
             if (want) lam[u] = a.beta * p;
             if (heavy && P.x[u] == ST_S) lam[u] = a.beta * pressure_heavy<WEIGHTED>(a, P.node[u], P.rep[u]);
         }
@@ -396,7 +416,7 @@ __global__ __launch_bounds__(TPB) void step_kernel(StepArgs a)
     }
 
     // one plain store of this workgroup's counts; the reduce kernel sums them
-    uint32_t* out = a.part + ((size_t)a.step_off * gridDim.x + blockIdx.x) * (4 * R);
+    uint32_t* out = a.part + ((size_t)a.step_off * nblocks + block) * (4 * R);
     if (R == 1) {
         if (lane == 0) {
             s_cnt[wave * 4 + 0] = c0;
@@ -417,19 +437,53 @@ __global__ __launch_bounds__(TPB) void step_kernel(StepArgs a)
     }
 }
 
+template <int STORAGE, bool WEIGHTED, bool RATES, int MODE, int TPB>
+__global__ __launch_bounds__(TPB) void step_kernel(StepArgs a)
+{
+    step_body<STORAGE, WEIGHTED, RATES, MODE, TPB>(a, blockIdx.x, gridDim.x);
+}
+
+// Index of the table entry that owns workgroup b: first[m] <= b < first[m + 1]
+// (a uniform binary search over the members' block ranges).
+__device__ __forceinline__ uint32_t owner_of(const uint32_t* __restrict__ first, uint32_t members, uint32_t b)
+{
+    uint32_t lo = 0, hi = members;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (first[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// One fused step for every member of a batch of simulations (each with its
+// own graph, laws, replicas and step index): member m owns the workgroups
+// [first[m], first[m + 1]) and runs exactly the streaming step on them, so
+// its results are those it gets alone.  step_off is the launch's position in
+// its sequence (member m runs step table[m].ctl->step + step_off).
+template <int STORAGE, bool WEIGHTED, bool RATES>
+__global__ __launch_bounds__(STREAM_TPB) void step_batch_kernel(const StepArgs* __restrict__ table,
+                                                                const uint32_t* __restrict__ first,
+                                                                uint32_t members, uint32_t step_off)
+{
+    const uint32_t m = owner_of(first, members, blockIdx.x);
+    StepArgs a = table[m];
+    a.step_off = step_off;
+    step_body<STORAGE, WEIGHTED, RATES, MODE_STREAM, STREAM_TPB>(a, blockIdx.x - first[m], first[m + 1] - first[m]);
+}
+
 // Sums per-workgroup count partials.  Block j handles slot j: rows of C
 // counters from G workgroups, part[j][g][c]; the totals go to
 // out[((base + j) mod H)][c] where base = ctl->step (0 without ctl).
 // Requires C <= WG and WG % C == 0 (C = 4R with R a power of two <= 64).
-__global__ __launch_bounds__(WG) void reduce_kernel(const Ctl* ctl, const uint32_t* part, uint32_t G,
-                                                     uint32_t C, uint32_t* out, uint32_t H)
+__device__ __forceinline__ void reduce_body(const Ctl* ctl, const uint32_t* part, uint32_t G, uint32_t C,
+                                            uint32_t* out, uint32_t H, uint32_t j, uint32_t r)
 {
     __shared__ uint32_t s[WG];
     const uint32_t t = threadIdx.x;
-    const uint32_t j = blockIdx.x;
     // of a sequence longer than the ring only the last H steps are kept, so
     // no two blocks write one slot
-    if ((size_t)j + H < (size_t)gridDim.x) return;
+    if ((size_t)j + H < (size_t)r) return;
     const uint32_t groups = WG / C;
     const uint32_t c = t % C;
     const uint32_t* p = part + (size_t)j * G * C;
@@ -445,9 +499,46 @@ __global__ __launch_bounds__(WG) void reduce_kernel(const Ctl* ctl, const uint32
     }
 }
 
+__global__ __launch_bounds__(WG) void reduce_kernel(const Ctl* ctl, const uint32_t* part, uint32_t G,
+                                                     uint32_t C, uint32_t* out, uint32_t H)
+{
+    reduce_body(ctl, part, G, C, out, H, blockIdx.x, gridDim.x);
+}
+
+// Batched reduce: block (j, m) sums slot j of member m (grid r x members).
+__global__ __launch_bounds__(WG) void reduce_batch_kernel(const RedArgs* __restrict__ table)
+{
+    const RedArgs q = table[blockIdx.y];
+    reduce_body(q.ctl, q.part, q.G, q.C, q.hist, q.H, blockIdx.x, gridDim.x);
+}
+
 __global__ void advance_kernel(Ctl* ctl, uint32_t r)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) ctl->step = ctl->step + r;
+}
+
+// Batched advance: thread m adds r to member m's step index.
+__global__ void advance_batch_kernel(Ctl* const* __restrict__ ctls, uint32_t members, uint32_t r)
+{
+    const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < members) ctls[m]->step = ctls[m]->step + r;
+}
+
+// Summary of an infectivity bitmap: bit s is set when any of the 2^lg_gran
+// units of group s is infectious, i.e. when one of its 2^(lg_gran - 6) bitmap
+// words is nonzero.  One thread per summary bit, one summary word per wave.
+__global__ __launch_bounds__(WG) void summary_kernel(SumArgs q)
+{
+    const unsigned long long k = q.ctl->step + q.step_off + q.after;
+    const unsigned long long* __restrict__ bits = (k & 1) ? q.iota1 : q.iota0;
+    const uint32_t s = blockIdx.x * WG + threadIdx.x;
+    const uint32_t gw = 1u << (q.lg_gran - 6);
+    const uint64_t w0 = (uint64_t)s * gw;
+    bool any = false;
+    for (uint32_t i = 0; i < gw; ++i)
+        if (w0 + i < q.words && bits[w0 + i] != 0ull) any = true;
+    const unsigned long long m = __ballot(any);
+    if ((threadIdx.x & 63) == 0 && (s >> 6) < q.sum_words) q.summary[s >> 6] = m;
 }
 
 // Pressure partials of heavy-row segments (degree-binned dispatch).  One
@@ -456,7 +547,7 @@ __global__ void advance_kernel(Ctl* ctl, uint32_t r)
 // folded with a fixed shuffle tree (deterministic) and lanes 0..R-1 store
 // them.  Reads the same start-of-step bitmap as the step launch that follows.
 template <bool WEIGHTED>
-__global__ __launch_bounds__(WG) void heavy_pressure_kernel(HeavyArgs h)
+__device__ __forceinline__ void heavy_body(const HeavyArgs& h, uint32_t block, uint32_t nblocks)
 {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t R = 1u << h.lgR;
@@ -465,8 +556,8 @@ __global__ __launch_bounds__(WG) void heavy_pressure_kernel(HeavyArgs h)
     const uint32_t rep = lane & (R - 1);
     const unsigned long long k = h.ctl->step + h.step_off;
     const uint32_t* __restrict__ bits = (const uint32_t*)((k & 1) ? h.iota1 : h.iota0);
-    const uint32_t nwaves = gridDim.x * (WG / 64);
-    for (uint32_t s = blockIdx.x * (WG / 64) + (threadIdx.x >> 6); s < h.nseg; s += nwaves) {
+    const uint32_t nwaves = nblocks * (WG / 64);
+    for (uint32_t s = block * (WG / 64) + (threadIdx.x >> 6); s < h.nseg; s += nwaves) {
         const Segment sg = h.segs[s];
         uint32_t ci = 0;
         float cw = 0.0f;
@@ -484,6 +575,24 @@ __global__ __launch_bounds__(WG) void heavy_pressure_kernel(HeavyArgs h)
             else ((uint32_t*)h.seg_part)[(size_t)s * R + lane] = ci;
         }
     }
+}
+
+template <bool WEIGHTED>
+__global__ __launch_bounds__(WG) void heavy_pressure_kernel(HeavyArgs h)
+{
+    heavy_body<WEIGHTED>(h, blockIdx.x, gridDim.x);
+}
+
+// Batched heavy-row partials: member m owns workgroups [first[m], first[m + 1]).
+template <bool WEIGHTED>
+__global__ __launch_bounds__(WG) void heavy_batch_kernel(const HeavyArgs* __restrict__ table,
+                                                         const uint32_t* __restrict__ first, uint32_t members,
+                                                         uint32_t step_off)
+{
+    const uint32_t m = owner_of(first, members, blockIdx.x);
+    HeavyArgs h = table[m];
+    h.step_off = step_off;
+    heavy_body<WEIGHTED>(h, blockIdx.x - first[m], first[m + 1] - first[m]);
 }
 
 template <int STORAGE>
@@ -603,12 +712,14 @@ __global__ void eval_philox_kernel(const uint4* ctr, uint32_t k0, uint32_t k1, u
 
 // ---------------------------------------------------------------- launchers
 
-const void* step_kernel_fn(int storage, bool weighted, bool rates, bool resident)
+const void* step_kernel_fn(int storage, bool weighted, bool rates, int mode)
 {
 #define FS_SEL(S, W, RT)                                                                         \
-    if (storage == S && weighted == W && rates == RT)                                            \
-        return resident ? (const void*)&step_kernel<S, W, RT, true, RESIDENT_TPB>                \
-                        : (const void*)&step_kernel<S, W, RT, false, STREAM_TPB>;
+    if (storage == S && weighted == W && rates == RT) {                                          \
+        if (mode == MODE_RESIDENT) return (const void*)&step_kernel<S, W, RT, MODE_RESIDENT, RESIDENT_TPB>; \
+        if (mode == MODE_SUMMARY) return (const void*)&step_kernel<S, W, RT, MODE_SUMMARY, RESIDENT_TPB>;   \
+        return (const void*)&step_kernel<S, W, RT, MODE_STREAM, STREAM_TPB>;                     \
+    }
     FS_SEL(0, false, false) FS_SEL(0, false, true) FS_SEL(0, true, false) FS_SEL(0, true, true)
     FS_SEL(1, false, false) FS_SEL(1, false, true) FS_SEL(1, true, false) FS_SEL(1, true, true)
 #undef FS_SEL
@@ -638,6 +749,23 @@ const void* heavy_kernel_fn(bool weighted)
     return weighted ? (const void*)&heavy_pressure_kernel<true> : (const void*)&heavy_pressure_kernel<false>;
 }
 const void* advance_kernel_fn() { return (const void*)&advance_kernel; }
+const void* summary_kernel_fn() { return (const void*)&summary_kernel; }
+
+const void* step_batch_kernel_fn(int storage, bool weighted, bool rates)
+{
+#define FS_SEL(S, W, RT)                                                                         \
+    if (storage == S && weighted == W && rates == RT) return (const void*)&step_batch_kernel<S, W, RT>;
+    FS_SEL(0, false, false) FS_SEL(0, false, true) FS_SEL(0, true, false) FS_SEL(0, true, true)
+    FS_SEL(1, false, false) FS_SEL(1, false, true) FS_SEL(1, true, false) FS_SEL(1, true, true)
+#undef FS_SEL
+    return nullptr;
+}
+const void* heavy_batch_kernel_fn(bool weighted)
+{
+    return weighted ? (const void*)&heavy_batch_kernel<true> : (const void*)&heavy_batch_kernel<false>;
+}
+const void* reduce_batch_kernel_fn() { return (const void*)&reduce_batch_kernel; }
+const void* advance_batch_kernel_fn() { return (const void*)&advance_batch_kernel; }
 
 hipError_t launch_put_replica(int storage, void* state, void* age, const int32_t* src_state, const void* src_age,
                               int32_t n, int32_t lgR, int32_t replica, hipStream_t s)

@@ -9,10 +9,10 @@
 namespace fsk {
 
 // Address of the fused step kernel for a storage/weights/rates combination
-// (launched with one StepArgs argument); resident selects the LDS-bitmap
-// variant (RESIDENT_TPB threads, one workgroup per compute unit), otherwise
-// STREAM_TPB threads per workgroup.
-const void* step_kernel_fn(int storage, bool weighted, bool rates, bool resident);
+// (launched with one StepArgs argument); mode is fsi::MODE_*: the LDS
+// variants run RESIDENT_TPB threads, one workgroup per compute unit, the
+// streaming variant STREAM_TPB threads per workgroup.
+const void* step_kernel_fn(int storage, bool weighted, bool rates, int mode);
 
 // Exact counts of one replica: per-workgroup partials (at most max_grid rows
 // of 4 in `part`) reduced into out4.
@@ -25,6 +25,21 @@ const void* reduce_kernel_fn();
 const void* heavy_kernel_fn(bool weighted);
 // advance_kernel(Ctl*, uint32_t r): adds r to the step index; one thread.
 const void* advance_kernel_fn();
+// summary_kernel(SumArgs): one thread per summary bit (sum_words * 64 threads
+// in WG-thread workgroups).
+const void* summary_kernel_fn();
+
+// Batched launches over the members of an fs_batch (see the kernels for the
+// block-to-member mapping):
+// step_batch_kernel(const StepArgs* table, const uint32_t* first, uint32_t members, uint32_t step_off),
+//   STREAM_TPB threads, first[members] workgroups;
+const void* step_batch_kernel_fn(int storage, bool weighted, bool rates);
+// heavy_batch_kernel(const HeavyArgs* table, const uint32_t* first, uint32_t members, uint32_t step_off), WG threads;
+const void* heavy_batch_kernel_fn(bool weighted);
+// reduce_batch_kernel(const RedArgs* table): grid (r, members), WG threads;
+const void* reduce_batch_kernel_fn();
+// advance_batch_kernel(Ctl* const* ctls, uint32_t members, uint32_t r): one thread per member.
+const void* advance_batch_kernel_fn();
 hipError_t launch_put_replica(int storage, void* state, void* age, const int32_t* src_state, const void* src_age,
                               int32_t n, int32_t lgR, int32_t replica, hipStream_t s);
 hipError_t launch_rebuild_bits(int storage, const void* state, uint32_t total, unsigned long long* bits,

@@ -13,73 +13,9 @@
 #include <string>
 #include <vector>
 
-#include "fs.h"
-#include "fs_internal.hpp"
-#include "fs_kernels.hpp"
+#include "fs_runtime.hpp"
 
-using fsi::HazardDev;
-using fsi::StepArgs;
-using fsi::WG;
-
-struct fs_graph {
-    int device = 0;
-    int64_t n = 0, nnz = 0;
-    int32_t* d_row_ptr = nullptr;
-    int32_t* d_col_ind = nullptr;
-    float* d_weights = nullptr;
-    int32_t max_degree = 0;
-    double mean_degree = 0.0;
-    std::vector<int32_t> h_row_ptr; // host copies for degree binning and layouts
-    std::vector<int32_t> h_col_ind;
-    std::vector<float> h_weights;
-    std::atomic<int> users{0};
-};
-
-struct fs_sim {
-    fs_graph* g = nullptr;
-    fs_sim_params p{};
-    int device = 0;
-    int lgR = 0, R = 1;
-    int storage = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    void* d_state = nullptr;
-    void* d_age = nullptr;
-    void* d_iota[2] = {nullptr, nullptr};
-    float* d_rates = nullptr;
-    fsi::Ctl* d_ctl = nullptr;
-    uint32_t* d_hist = nullptr;    // [H][R][4] counts after each step
-    uint32_t* d_part = nullptr;    // [chunk][G][R][4] per-workgroup partials
-    uint32_t* d_rc_part = nullptr; // recount partials [RC_GRID][4]
-    uint32_t* d_cnt4 = nullptr;
-    int H = 1024;
-    uint32_t G = 0;                // step workgroups
-    uint32_t tpb = 0;              // threads (units) per step workgroup / tile
-    bool resident = false;         // bitmap held in LDS
-    uint32_t bit_words = 0;        // 64-bit words per infectivity bitmap
-    uint32_t chunk = 0;            // steps per launch sequence (partial slots)
-    int64_t step = 0;      // index of the next step (host mirror of ctl->step)
-    int64_t hist_from = 0; // first step whose count row is recorded
-    StepArgs args{};
-    const void* kfn = nullptr;
-    // degree bins
-    int32_t heavy_deg = 0;         // rows with degree > heavy_deg are binned; < 0: none
-    int32_t seg_edges = 512;
-    uint32_t nseg = 0;
-    int32_t* d_heavy_first = nullptr;
-    fsi::Segment* d_segs = nullptr;
-    void* d_seg_part = nullptr;
-    uint16_t* d_ldeg = nullptr;       // light degree per node, HEAVY_ROW for binned rows
-    uint32_t* d_chunk_base = nullptr; // wavefront-transposed layout of the light rows
-    uint8_t* d_chunk_deg = nullptr;
-    int32_t* d_col_t = nullptr;
-    float* d_w_t = nullptr;
-    const void* hfn = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-};
-
-namespace {
+namespace fsr {
 
 thread_local std::string g_err;
 
@@ -89,30 +25,6 @@ fs_status fail(fs_status s, const std::string& msg)
     return s;
 }
 
-#define FS_HIP(call)                                                                           \
-    do {                                                                                       \
-        hipError_t e_ = (call);                                                                \
-        if (e_ != hipSuccess)                                                                  \
-            return fail(e_ == hipErrorOutOfMemory ? FS_ERR_OUT_OF_MEMORY : FS_ERR_DEVICE,      \
-                        std::string(#call) + ": " + hipGetErrorString(e_));                    \
-    } while (0)
-
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int d)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != d) (void)hipSetDevice(d);
-    }
-    ~DeviceGuard()
-    {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-
-// Device allocations go through hipMalloc; a failed allocation reports
-// FS_ERR_OUT_OF_MEMORY and the caller releases what it already holds.
 hipError_t dev_alloc(void** p, size_t bytes)
 {
     *p = nullptr;
@@ -125,11 +37,6 @@ void dev_free(void* p)
     if (p) (void)hipFree(p);
 }
 
-// RAII device buffer for call-local temporaries.
-struct DevBuf {
-    void* p = nullptr;
-    ~DevBuf() { dev_free(p); }
-};
 
 void split(double v, float& hi, float& lo)
 {
@@ -196,14 +103,9 @@ void release_sim(fs_sim* s)
     dev_free(s->d_part);
     dev_free(s->d_rc_part);
     dev_free(s->d_cnt4);
-    dev_free(s->d_heavy_first);
-    dev_free(s->d_segs);
+    dev_free(s->d_summary);
     dev_free(s->d_seg_part);
-    dev_free(s->d_ldeg);
-    dev_free(s->d_chunk_base);
-    dev_free(s->d_chunk_deg);
-    dev_free(s->d_col_t);
-    dev_free(s->d_w_t);
+    s->layout.reset();
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     if (s->g) s->g->users.fetch_sub(1);
     delete s;
@@ -222,6 +124,7 @@ constexpr uint32_t RC_GRID = 1024;
 struct SeqArgs {
     std::vector<StepArgs> step;
     std::vector<fsi::HeavyArgs> heavy;
+    std::vector<fsi::SumArgs> sum;
     const fsi::Ctl* ctl_c;
     fsi::Ctl* ctl;
     const uint32_t* part;
@@ -247,12 +150,23 @@ void drop_graph_exec(fs_sim* s)
 // 65535 or more edges) are cut into segments of at most seg_edges edges for
 // the heavy-row kernel; the other rows are laid out wavefront-transposed for
 // the step kernel (see StepArgs::col_t).
-fs_status apply_bins(fs_sim* s, int32_t heavy_deg, int32_t seg_edges)
+Layout::~Layout()
 {
-    const fs_graph* g = s->g;
-    if (seg_edges < 64 || seg_edges > (1 << 20)) return fail(FS_ERR_INVALID_ARG, "segment_edges must be in [64, 2^20]");
-    const int32_t cap = 65534; // largest light degree a uint16 entry holds
-    const int32_t limit = heavy_deg < 0 ? cap : std::min(heavy_deg, cap);
+    dev_free(d_heavy_first);
+    dev_free(d_segs);
+    dev_free(d_ldeg);
+    dev_free(d_chunk_base);
+    dev_free(d_chunk_deg);
+    dev_free(d_col_t);
+    dev_free(d_w_t);
+}
+
+// Builds the layout of graph g for R replicas (Q = 64/R nodes per chunk).
+fs_status build_layout(const fs_graph* g, int32_t R, int32_t limit, int32_t seg_edges, std::shared_ptr<Layout>& out)
+{
+    auto L = std::make_shared<Layout>();
+    L->limit = limit;
+    L->seg_edges = seg_edges;
     const int64_t n = g->n;
     const std::vector<int32_t>& rp = g->h_row_ptr;
     std::vector<int32_t> first;
@@ -270,7 +184,7 @@ fs_status apply_bins(fs_sim* s, int32_t heavy_deg, int32_t seg_edges)
         for (int32_t x = b; x < e; x += seg_edges) segs.push_back({(int32_t)i, x, std::min(e, x + seg_edges), 0});
     }
     // wavefront-transposed light layout: Q nodes per 64-unit chunk
-    const int64_t Q = 64 / s->R;
+    const int64_t Q = 64 / R;
     const int64_t nch = (n + Q - 1) / Q;
     std::vector<uint32_t> cbase((size_t)nch + 1);
     std::vector<int32_t> colt;
@@ -288,6 +202,16 @@ fs_status apply_bins(fs_sim* s, int32_t heavy_deg, int32_t seg_edges)
             same = same && ldeg[i] != fsi::HEAVY_ROW && ldeg[i] == ldeg[n0];
         }
         cdeg[c] = (same && ldeg[n0] < 255) ? (uint8_t)ldeg[n0] : (uint8_t)255;
+        if (same) {
+            // every row has the same light degree: slot j of row q at j*Q + q
+            const int32_t d = ldeg[n0];
+            for (int32_t j = 0; j < d; ++j)
+                for (int64_t i = n0; i < n1; ++i) colt.push_back(g->h_col_ind[rp[i] + j]);
+            if (weighted)
+                for (int32_t j = 0; j < d; ++j)
+                    for (int64_t i = n0; i < n1; ++i) wt.push_back(g->h_weights[rp[i] + j]);
+            continue;
+        }
         for (int32_t j = 0; j < maxd; ++j)
             for (int64_t i = n0; i < n1; ++i)
                 if (ldeg[i] != fsi::HEAVY_ROW && ldeg[i] > j) {
@@ -296,52 +220,157 @@ fs_status apply_bins(fs_sim* s, int32_t heavy_deg, int32_t seg_edges)
                 }
     }
     cbase[nch] = (uint32_t)colt.size();
+    L->nseg = (uint32_t)segs.size();
+    if (L->nseg) {
+        FS_HIP(dev_alloc((void**)&L->d_heavy_first, first.size() * sizeof(int32_t)));
+        FS_HIP(dev_alloc((void**)&L->d_segs, segs.size() * sizeof(fsi::Segment)));
+        FS_HIP(hipMemcpy(L->d_heavy_first, first.data(), first.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        FS_HIP(hipMemcpy(L->d_segs, segs.data(), segs.size() * sizeof(fsi::Segment), hipMemcpyHostToDevice));
+    }
+    FS_HIP(dev_alloc((void**)&L->d_ldeg, ldeg.size() * sizeof(uint16_t)));
+    FS_HIP(dev_alloc((void**)&L->d_chunk_base, cbase.size() * sizeof(uint32_t)));
+    FS_HIP(dev_alloc((void**)&L->d_chunk_deg, cdeg.size()));
+    FS_HIP(dev_alloc((void**)&L->d_col_t, colt.size() * sizeof(int32_t)));
+    FS_HIP(hipMemcpy(L->d_chunk_deg, cdeg.data(), cdeg.size(), hipMemcpyHostToDevice));
+    FS_HIP(hipMemcpy(L->d_ldeg, ldeg.data(), ldeg.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+    FS_HIP(hipMemcpy(L->d_chunk_base, cbase.data(), cbase.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    if (!colt.empty())
+        FS_HIP(hipMemcpy(L->d_col_t, colt.data(), colt.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (weighted) {
+        FS_HIP(dev_alloc((void**)&L->d_w_t, wt.size() * sizeof(float)));
+        if (!wt.empty()) FS_HIP(hipMemcpy(L->d_w_t, wt.data(), wt.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    L->bytes = first.size() * 4 + segs.size() * sizeof(fsi::Segment) + ldeg.size() * 2 + cbase.size() * 4 +
+               cdeg.size() + colt.size() * 4 + wt.size() * 4;
+    out = std::move(L);
+    return FS_OK;
+}
+
+int32_t light_limit(int32_t heavy_deg)
+{
+    const int32_t cap = 65534; // largest light degree a uint16 entry holds
+    return heavy_deg < 0 ? cap : std::min(heavy_deg, cap);
+}
+
+bool layout_cached(fs_graph* g, int32_t R, int32_t heavy_deg, int32_t seg_edges)
+{
+    std::lock_guard<std::mutex> lk(g->layout_mu);
+    return g->layouts.count(LayoutKey(R, light_limit(heavy_deg), seg_edges)) != 0;
+}
+
+size_t sim_footprint(fs_graph* g, const fs_sim_params* p)
+{
+    const size_t R = (size_t)std::max(p->n_replicas, 1);
+    const size_t units = (size_t)g->n * R;
+    const size_t H = p->history_len ? (size_t)p->history_len : 1024;
+    const size_t chunk = (size_t)std::max(p->steps_per_graph, 64);
+    const size_t grid = std::min<size_t>((units + 255) / 256, fsi::max_step_grid((int)R));
+    size_t b = units * (state_bytes(p->storage) + age_bytes(p->storage));
+    b += 2 * bitmap_words(units) * 8;                   // infectivity ping-pong
+    b += H * R * 16 + chunk * grid * R * 16;            // history ring, count partials
+    const int32_t hd = p->heavy_degree == 0 ? 64 : p->heavy_degree;
+    const int32_t se = p->segment_edges == 0 ? 512 : p->segment_edges;
+    if (!layout_cached(g, (int32_t)R, hd, se)) {
+        b += (size_t)g->nnz * 4 * (g->d_weights ? 2 : 1);   // transposed light rows (+ weights)
+        b += (size_t)g->n * 2 + ((size_t)g->n * R / 64 + 1) * 5; // degrees, chunk metadata
+        b += (size_t)g->nnz / 64 * 16 + (size_t)g->n * 4;   // heavy segments (upper bound)
+    }
+    b += (size_t)g->nnz / 64 * 4 * R;                       // heavy-segment partials (upper bound)
+    if (p->record_rates) b += units * 4;
+    return b + ((size_t)1 << 20);
+}
+
+// Points sim s at the layout of its graph for (R, heavy_deg, seg_edges),
+// building it on first use, and gives s its own heavy-segment partials.
+// Cached layouts no sim uses any more, other than this one, are released.
+fs_status apply_bins(fs_sim* s, int32_t heavy_deg, int32_t seg_edges)
+{
+    fs_graph* g = s->g;
+    if (seg_edges < 64 || seg_edges > (1 << 20)) return fail(FS_ERR_INVALID_ARG, "segment_edges must be in [64, 2^20]");
+    const int32_t limit = light_limit(heavy_deg);
+    const LayoutKey key(s->R, limit, seg_edges);
+    std::shared_ptr<Layout> L;
+    {
+        std::lock_guard<std::mutex> lk(g->layout_mu);
+        auto it = g->layouts.find(key);
+        if (it != g->layouts.end()) {
+            L = it->second;
+        } else {
+            fs_status st = build_layout(g, s->R, limit, seg_edges, L);
+            if (st != FS_OK) return st;
+            g->layouts[key] = L;
+        }
+    }
     drop_graph_exec(s);
-    for (void* p : {(void*)s->d_heavy_first, (void*)s->d_segs, s->d_seg_part, (void*)s->d_ldeg,
-                    (void*)s->d_chunk_base, (void*)s->d_chunk_deg, (void*)s->d_col_t, (void*)s->d_w_t})
-        dev_free(p);
-    s->d_chunk_deg = nullptr;
-    s->d_heavy_first = nullptr;
-    s->d_segs = nullptr;
+    dev_free(s->d_seg_part);
     s->d_seg_part = nullptr;
-    s->d_ldeg = nullptr;
-    s->d_chunk_base = nullptr;
-    s->d_col_t = nullptr;
-    s->d_w_t = nullptr;
-    s->nseg = (uint32_t)segs.size();
+    s->layout = L;
+    {
+        std::lock_guard<std::mutex> lk(g->layout_mu);
+        for (auto it = g->layouts.begin(); it != g->layouts.end();) {
+            if (it->first != key && it->second.use_count() == 1) it = g->layouts.erase(it);
+            else ++it;
+        }
+    }
+    s->nseg = L->nseg;
+    s->d_segs = L->d_segs;
     s->heavy_deg = heavy_deg;
     s->seg_edges = seg_edges;
-    if (s->nseg) {
-        FS_HIP(dev_alloc((void**)&s->d_heavy_first, first.size() * sizeof(int32_t)));
-        FS_HIP(dev_alloc((void**)&s->d_segs, segs.size() * sizeof(fsi::Segment)));
-        FS_HIP(dev_alloc(&s->d_seg_part, segs.size() * (size_t)s->R * sizeof(uint32_t)));
-        FS_HIP(hipMemcpy(s->d_heavy_first, first.data(), first.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-        FS_HIP(hipMemcpy(s->d_segs, segs.data(), segs.size() * sizeof(fsi::Segment), hipMemcpyHostToDevice));
-    }
-    FS_HIP(dev_alloc((void**)&s->d_ldeg, ldeg.size() * sizeof(uint16_t)));
-    FS_HIP(dev_alloc((void**)&s->d_chunk_base, cbase.size() * sizeof(uint32_t)));
-    FS_HIP(dev_alloc((void**)&s->d_chunk_deg, cdeg.size()));
-    FS_HIP(hipMemcpy(s->d_chunk_deg, cdeg.data(), cdeg.size(), hipMemcpyHostToDevice));
-    FS_HIP(dev_alloc((void**)&s->d_col_t, colt.size() * sizeof(int32_t)));
-    FS_HIP(hipMemcpy(s->d_ldeg, ldeg.data(), ldeg.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
-    FS_HIP(hipMemcpy(s->d_chunk_base, cbase.data(), cbase.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
-    if (!colt.empty())
-        FS_HIP(hipMemcpy(s->d_col_t, colt.data(), colt.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    if (weighted) {
-        FS_HIP(dev_alloc((void**)&s->d_w_t, wt.size() * sizeof(float)));
-        if (!wt.empty()) FS_HIP(hipMemcpy(s->d_w_t, wt.data(), wt.size() * sizeof(float), hipMemcpyHostToDevice));
-    }
-    s->args.heavy_first = s->d_heavy_first;
+    if (s->nseg) FS_HIP(dev_alloc(&s->d_seg_part, (size_t)s->nseg * (size_t)s->R * sizeof(uint32_t)));
+    s->args.heavy_first = L->d_heavy_first;
     s->args.seg_part = s->d_seg_part;
     s->args.heavy_deg = limit;
     s->args.seg_edges = seg_edges;
-    s->args.ldeg = s->d_ldeg;
-    s->args.chunk_base = s->d_chunk_base;
-    s->args.chunk_deg = s->d_chunk_deg;
-    s->args.col_t = s->d_col_t;
-    s->args.w_t = s->d_w_t;
+    s->args.ldeg = L->d_ldeg;
+    s->args.chunk_base = L->d_chunk_base;
+    s->args.chunk_deg = L->d_chunk_deg;
+    s->args.col_t = L->d_col_t;
+    s->args.w_t = L->d_w_t;
     return FS_OK;
 }
+
+fsi::SumArgs summary_args(const fs_sim* s, uint32_t after)
+{
+    fsi::SumArgs a{};
+    a.iota0 = (const unsigned long long*)s->d_iota[0];
+    a.iota1 = (const unsigned long long*)s->d_iota[1];
+    a.ctl = s->d_ctl;
+    a.summary = s->d_summary;
+    a.words = s->bit_words;
+    a.sum_words = s->sum_words;
+    a.lg_gran = s->lg_gran;
+    a.step_off = 0;
+    a.after = after;
+    return a;
+}
+
+uint32_t summary_grid(const fs_sim* s) { return (s->sum_words * 64u + WG - 1) / WG; }
+
+// Rebuilds the summary of the current bitmap (after seeding or a state load;
+// ctl->step must already hold the sim's step index).
+hipError_t refresh_summary(fs_sim* s)
+{
+    if (s->mode != fsi::MODE_SUMMARY) return hipSuccess;
+    fsi::SumArgs a = summary_args(s, 0);
+    void* argv[] = {&a};
+    return hipLaunchKernel(fsk::summary_kernel_fn(), dim3(summary_grid(s)), dim3(WG), argv, 0, s->stream);
+}
+
+fsi::HeavyArgs heavy_args(const fs_sim* s)
+{
+    fsi::HeavyArgs h{};
+    h.col_ind = s->g->d_col_ind;
+    h.weights = s->g->d_weights;
+    h.segs = s->d_segs;
+    h.seg_part = s->d_seg_part;
+    h.iota0 = s->d_iota[0];
+    h.iota1 = s->d_iota[1];
+    h.ctl = s->d_ctl;
+    h.nseg = s->nseg;
+    h.lgR = s->lgR;
+    return h;
+}
+
 
 void make_seq(fs_sim* s, uint32_t r, SeqArgs& q)
 {
@@ -349,18 +378,13 @@ void make_seq(fs_sim* s, uint32_t r, SeqArgs& q)
     for (uint32_t j = 0; j < r; ++j) q.step[j].step_off = j;
     q.heavy.clear();
     if (s->nseg) {
-        fsi::HeavyArgs h{};
-        h.col_ind = s->g->d_col_ind;
-        h.weights = s->g->d_weights;
-        h.segs = s->d_segs;
-        h.seg_part = s->d_seg_part;
-        h.iota0 = s->d_iota[0];
-        h.iota1 = s->d_iota[1];
-        h.ctl = s->d_ctl;
-        h.nseg = s->nseg;
-        h.lgR = s->lgR;
-        q.heavy.assign(r, h);
+        q.heavy.assign(r, heavy_args(s));
         for (uint32_t j = 0; j < r; ++j) q.heavy[j].step_off = j;
+    }
+    q.sum.clear();
+    if (s->mode == fsi::MODE_SUMMARY) {
+        q.sum.assign(r, summary_args(s, 1));
+        for (uint32_t j = 0; j < r; ++j) q.sum[j].step_off = j;
     }
     q.ctl_c = s->d_ctl;
     q.ctl = s->d_ctl;
@@ -399,6 +423,10 @@ fs_status build_graph_exec(fs_sim* s, int b)
         }
         void* argv[] = {&q.step[j]};
         if ((st = add(s->kfn, dim3(s->G), dim3(s->tpb), argv)) != FS_OK) return st;
+        if (!q.sum.empty()) {
+            void* sargv[] = {&q.sum[j]};
+            if ((st = add(fsk::summary_kernel_fn(), dim3(summary_grid(s)), dim3(WG), sargv)) != FS_OK) return st;
+        }
     }
     void* rargv[] = {&q.ctl_c, &q.part, &q.G, &q.C, &q.hist, &q.H};
     if ((st = add(fsk::reduce_kernel_fn(), dim3(q.r), dim3(WG), rargv)) != FS_OK) return st;
@@ -419,6 +447,10 @@ fs_status launch_sequence(fs_sim* s, uint32_t r)
         }
         void* argv[] = {&q.step[j]};
         FS_HIP(hipLaunchKernel(s->kfn, dim3(s->G), dim3(s->tpb), argv, 0, s->stream));
+        if (!q.sum.empty()) {
+            void* sargv[] = {&q.sum[j]};
+            FS_HIP(hipLaunchKernel(fsk::summary_kernel_fn(), dim3(summary_grid(s)), dim3(WG), sargv, 0, s->stream));
+        }
     }
     void* rargv[] = {&q.ctl_c, &q.part, &q.G, &q.C, &q.hist, &q.H};
     FS_HIP(hipLaunchKernel(fsk::reduce_kernel_fn(), dim3(r), dim3(WG), rargv, 0, s->stream));
@@ -427,7 +459,9 @@ fs_status launch_sequence(fs_sim* s, uint32_t r)
     return FS_OK;
 }
 
-} // namespace
+} // namespace fsr
+
+using namespace fsr;
 
 #define FS_GUARD_BEGIN try {
 #define FS_GUARD_END                                                        \
@@ -585,20 +619,27 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
             return bad(e, "stream");
         s->own_stream = true;
     }
-    if (p->variant < 0 || p->variant > 2) {
+    if (p->variant < 0 || p->variant > 3) {
         release_sim(s);
-        return fail(FS_ERR_INVALID_ARG, "variant must be 0 (auto), 1 (stream) or 2 (resident)");
+        return fail(FS_ERR_INVALID_ARG, "variant must be 0 (auto), 1 (stream), 2 (resident) or 3 (summary)");
     }
     const bool fits_lds = units <= fsi::RESIDENT_BITS;
     if (p->variant == 2 && !fits_lds) {
         release_sim(s);
         return fail(FS_ERR_INVALID_ARG, "the resident variant holds at most 2^20 units (n * n_replicas)");
     }
-    s->resident = p->variant == 2 || (p->variant == 0 && fits_lds);
-    s->tpb = s->resident ? fsi::RESIDENT_TPB : fsi::STREAM_TPB;
+    s->mode = p->variant == 1 ? fsi::MODE_STREAM
+            : p->variant == 2 ? fsi::MODE_RESIDENT
+            : p->variant == 3 ? fsi::MODE_SUMMARY
+            : (fits_lds ? fsi::MODE_RESIDENT : fsi::MODE_SUMMARY);
+    s->lg_gran = 6;
+    while (((units + ((size_t)1 << s->lg_gran) - 1) >> s->lg_gran) > fsi::SUMMARY_BITS) ++s->lg_gran;
+    s->sum_bits = (uint32_t)((units + ((size_t)1 << s->lg_gran) - 1) >> s->lg_gran);
+    s->sum_words = (s->sum_bits + 63) / 64;
+    s->tpb = s->mode == fsi::MODE_STREAM ? fsi::STREAM_TPB : fsi::RESIDENT_TPB;
     const size_t chunks = (units + 63) / 64;
     const size_t tiles = (chunks + s->tpb / 64 - 1) / (s->tpb / 64); // workgroups with work
-    if (s->resident) {
+    if (s->mode != fsi::MODE_STREAM) {
         int cus = 0;
         if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device)) != hipSuccess)
             return bad(e, "device attribute");
@@ -619,7 +660,9 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
         (e = dev_alloc((void**)&s->d_hist, hist_words * sizeof(uint32_t))) != hipSuccess ||
         (e = dev_alloc((void**)&s->d_part, part_words * sizeof(uint32_t))) != hipSuccess ||
         (e = dev_alloc((void**)&s->d_rc_part, RC_GRID * 4 * sizeof(uint32_t))) != hipSuccess ||
-        (e = dev_alloc((void**)&s->d_cnt4, 4 * sizeof(uint32_t))) != hipSuccess)
+        (e = dev_alloc((void**)&s->d_cnt4, 4 * sizeof(uint32_t))) != hipSuccess ||
+        (s->mode == fsi::MODE_SUMMARY &&
+         (e = dev_alloc((void**)&s->d_summary, ((size_t)s->sum_bits + 511) / 512 * 64)) != hipSuccess))
         return bad(e, "device allocation");
     if ((e = hipMemsetAsync(s->d_state, 0, units * state_bytes(s->storage), s->stream)) != hipSuccess ||
         (e = hipMemsetAsync(s->d_age, 0, units * age_bytes(s->storage), s->stream)) != hipSuccess ||
@@ -628,6 +671,8 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
         (s->d_rates && (e = hipMemsetAsync(s->d_rates, 0, units * sizeof(float), s->stream)) != hipSuccess) ||
         (e = hipMemsetAsync(s->d_ctl, 0, sizeof(fsi::Ctl), s->stream)) != hipSuccess ||
         (e = hipMemsetAsync(s->d_hist, 0, hist_words * sizeof(uint32_t), s->stream)) != hipSuccess ||
+        (s->d_summary &&
+         (e = hipMemsetAsync(s->d_summary, 0, ((size_t)s->sum_bits + 511) / 512 * 64, s->stream)) != hipSuccess) ||
         (e = hipStreamSynchronize(s->stream)) != hipSuccess)
         return bad(e, "initialisation");
 
@@ -645,7 +690,9 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
     a.n = (int32_t)g->n;
     a.lgR = s->lgR;
     a.step_off = 0;
-    a.ntiles = 0;
+    a.lg_gran = s->lg_gran;
+    a.summary = (const uint32_t*)s->d_summary;
+    a.sum_bits = s->sum_bits;
     a.same_kind = hz[0].kind == hz[1].kind;
     a.hz[0] = hz[0];
     a.hz[1] = hz[1];
@@ -653,7 +700,7 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
     a.dt = (float)p->dt;
     a.key0 = (uint32_t)p->seed;
     a.key1 = (uint32_t)(p->seed >> 32);
-    s->kfn = fsk::step_kernel_fn(s->storage, g->d_weights != nullptr, p->record_rates != 0, s->resident);
+    s->kfn = fsk::step_kernel_fn(s->storage, g->d_weights != nullptr, p->record_rates != 0, s->mode);
     s->hfn = fsk::heavy_kernel_fn(g->d_weights != nullptr);
     if (!s->kfn || !s->hfn) {
         release_sim(s);
@@ -678,6 +725,7 @@ fs_status fs_sim_destroy(fs_sim* s)
 {
     FS_GUARD_BEGIN
     if (!s) return fail(FS_ERR_INVALID_ARG, "sim is NULL");
+    if (s->batch) return fail(FS_ERR_BUSY, "sim belongs to a batch: remove it first");
     DeviceGuard dg(s->device);
     hipError_t e = hipStreamSynchronize(s->stream);
     release_sim(s);
@@ -706,6 +754,7 @@ fs_status fs_sim_seed(fs_sim* s, int32_t replica, int64_t count, const int64_t* 
                             compartment, s->stream));
     FS_HIP(fsk::launch_rebuild_bits(s->storage, s->d_state, (uint32_t)(s->g->n * s->R),
                                     (unsigned long long*)s->d_iota[s->step & 1], s->bit_words, s->stream));
+    FS_HIP(refresh_summary(s));
     FS_HIP(hipStreamSynchronize(s->stream));
     return FS_OK;
     FS_GUARD_END
@@ -715,6 +764,7 @@ fs_status fs_step(fs_sim* s, int64_t n_steps)
 {
     FS_GUARD_BEGIN
     if (!s) return fail(FS_ERR_INVALID_ARG, "sim is NULL");
+    if (s->batch) return fail(FS_ERR_BUSY, "sim belongs to a batch: step it with fs_batch_step");
     if (n_steps < 0) return fail(FS_ERR_INVALID_ARG, "n_steps < 0");
     if (n_steps == 0) return FS_OK;
     DeviceGuard dg(s->device);
@@ -852,6 +902,7 @@ fs_status fs_set_state(fs_sim* s, int32_t replica, const int32_t* state, const f
     FS_HIP(fsk::launch_rebuild_bits(s->storage, s->d_state, (uint32_t)units,
                                     (unsigned long long*)s->d_iota[new_step & 1], s->bit_words, s->stream));
     if (step_index >= 0) FS_HIP(fsk::launch_set_ctl(s->d_ctl, (unsigned long long)step_index, s->stream));
+    FS_HIP(refresh_summary(s));
     FS_HIP(hipStreamSynchronize(s->stream));
     if (step_index >= 0) {
         s->step = step_index;
@@ -883,6 +934,7 @@ fs_status fs_sim_set_bins(fs_sim* s, int32_t heavy_degree, int32_t segment_edges
 {
     FS_GUARD_BEGIN
     if (!s) return fail(FS_ERR_INVALID_ARG, "sim is NULL");
+    if (s->batch) return fail(FS_ERR_BUSY, "sim belongs to a batch");
     if (heavy_degree < -1) return fail(FS_ERR_INVALID_ARG, "heavy_degree must be >= -1");
     DeviceGuard dg(s->device);
     FS_HIP(hipStreamSynchronize(s->stream));
@@ -903,6 +955,7 @@ fs_status fs_sim_tune(fs_sim* s, int32_t trial_steps, int32_t* heavy_degree, int
 {
     FS_GUARD_BEGIN
     if (!s) return fail(FS_ERR_INVALID_ARG, "sim is NULL");
+    if (s->batch) return fail(FS_ERR_BUSY, "sim belongs to a batch");
     if (trial_steps < 1 || trial_steps > 4096) return fail(FS_ERR_INVALID_ARG, "trial_steps must be in [1, 4096]");
     DeviceGuard dg(s->device);
     FS_HIP(hipStreamSynchronize(s->stream));
@@ -918,8 +971,10 @@ fs_status fs_sim_tune(fs_sim* s, int32_t trial_steps, int32_t* heavy_degree, int
                   {s->d_iota[0], (size_t)s->bit_words * 8, {}},
                   {s->d_iota[1], (size_t)s->bit_words * 8, {}},
                   {s->d_ctl, sizeof(fsi::Ctl), {}},
-                  {s->d_hist, (size_t)s->H * s->R * 4 * sizeof(uint32_t), {}}};
+                  {s->d_hist, (size_t)s->H * s->R * 4 * sizeof(uint32_t), {}},
+                  {s->d_summary, s->d_summary ? ((size_t)s->sum_bits + 511) / 512 * 64 : 0, {}}};
     for (auto& b : bufs) {
+        if (!b.live) continue;
         FS_HIP(dev_alloc(&b.copy.p, b.bytes));
         FS_HIP(hipMemcpyAsync(b.copy.p, b.live, b.bytes, hipMemcpyDeviceToDevice, s->stream));
     }
@@ -957,14 +1012,15 @@ fs_status fs_sim_tune(fs_sim* s, int32_t trial_steps, int32_t* heavy_degree, int
             best = c;
         }
         for (auto& b : bufs)
-            if (hipMemcpyAsync(b.live, b.copy.p, b.bytes, hipMemcpyDeviceToDevice, s->stream) != hipSuccess) {
+            if (b.live && hipMemcpyAsync(b.live, b.copy.p, b.bytes, hipMemcpyDeviceToDevice, s->stream) != hipSuccess) {
                 st = fail(FS_ERR_DEVICE, "restore");
                 break;
             }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    for (auto& b : bufs) (void)hipMemcpyAsync(b.live, b.copy.p, b.bytes, hipMemcpyDeviceToDevice, s->stream);
+    for (auto& b : bufs)
+        if (b.live) (void)hipMemcpyAsync(b.live, b.copy.p, b.bytes, hipMemcpyDeviceToDevice, s->stream);
     FS_HIP(hipStreamSynchronize(s->stream));
     if (st != FS_OK) return st;
     if ((st = apply_bins(s, best.first, best.second)) != FS_OK) return st;

@@ -1,0 +1,154 @@
+// Private runtime structures of the library: the graph and simulation
+// handles behind the C ABI and the helpers shared by the runtime sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "fs.h"
+#include "fs_internal.hpp"
+#include "fs_kernels.hpp"
+
+using fsi::HazardDev;
+using fsi::StepArgs;
+using fsi::WG;
+
+struct fs_batch;
+
+namespace fsr {
+// The degree-binned, wavefront-transposed layout of a graph's rows for one
+// replica count and one pair of bin thresholds (light-degree limit, heavy
+// segment length).  It depends on nothing else, so every sim of the graph
+// with these parameters shares one copy (the graph caches it).
+struct Layout {
+    int32_t limit = 0;           // rows with more edges than this are heavy
+    int32_t seg_edges = 0;
+    uint32_t nseg = 0;           // heavy-row segments
+    int32_t* d_heavy_first = nullptr;
+    fsi::Segment* d_segs = nullptr;
+    uint16_t* d_ldeg = nullptr;       // light degree per node, HEAVY_ROW for binned rows
+    uint32_t* d_chunk_base = nullptr; // wavefront-transposed layout of the light rows
+    uint8_t* d_chunk_deg = nullptr;
+    int32_t* d_col_t = nullptr;
+    float* d_w_t = nullptr;
+    size_t bytes = 0;
+    ~Layout();
+};
+using LayoutKey = std::tuple<int32_t, int32_t, int32_t>; // (replicas, limit, seg_edges)
+} // namespace fsr
+
+struct fs_graph {
+    int device = 0;
+    int64_t n = 0, nnz = 0;
+    int32_t* d_row_ptr = nullptr;
+    int32_t* d_col_ind = nullptr;
+    float* d_weights = nullptr;
+    int32_t max_degree = 0;
+    double mean_degree = 0.0;
+    std::vector<int32_t> h_row_ptr; // host copies for degree binning and layouts
+    std::vector<int32_t> h_col_ind;
+    std::vector<float> h_weights;
+    std::atomic<int> users{0};
+    std::mutex layout_mu;        // guards layouts (sims of one graph may live on several threads)
+    std::map<fsr::LayoutKey, std::shared_ptr<fsr::Layout>> layouts;
+};
+
+struct fs_sim {
+    fs_graph* g = nullptr;
+    fs_sim_params p{};
+    int device = 0;
+    int lgR = 0, R = 1;
+    int storage = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void* d_state = nullptr;
+    void* d_age = nullptr;
+    void* d_iota[2] = {nullptr, nullptr};
+    float* d_rates = nullptr;
+    fsi::Ctl* d_ctl = nullptr;
+    uint32_t* d_hist = nullptr;    // [H][R][4] counts after each step
+    uint32_t* d_part = nullptr;    // [chunk][G][R][4] per-workgroup partials
+    uint32_t* d_rc_part = nullptr; // recount partials [RC_GRID][4]
+    uint32_t* d_cnt4 = nullptr;
+    int H = 1024;
+    uint32_t G = 0;                // step workgroups
+    uint32_t tpb = 0;              // threads (units) per step workgroup / tile
+    int mode = fsi::MODE_STREAM;   // step kernel variant
+    unsigned long long* d_summary = nullptr; // MODE_SUMMARY: summary of the current bitmap
+    uint32_t sum_bits = 0, sum_words = 0;
+    int32_t lg_gran = 6;
+    uint32_t bit_words = 0;        // 64-bit words per infectivity bitmap
+    uint32_t chunk = 0;            // steps per launch sequence (partial slots)
+    int64_t step = 0;      // index of the next step (host mirror of ctl->step)
+    int64_t hist_from = 0; // first step whose count row is recorded
+    StepArgs args{};
+    const void* kfn = nullptr;
+    // degree bins
+    int32_t heavy_deg = 0;         // rows with degree > heavy_deg are binned; < 0: none
+    int32_t seg_edges = 512;
+    uint32_t nseg = 0;
+    std::shared_ptr<fsr::Layout> layout; // shared with the graph's other sims
+    void* d_seg_part = nullptr;          // this sim's heavy-segment partials [segment][R]
+    fsi::Segment* d_segs = nullptr;      // = layout->d_segs
+    const void* hfn = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    fs_batch* batch = nullptr;     // the batch the sim belongs to, if any
+    hipStream_t saved_stream = nullptr; // the sim's own stream while it runs on a batch's
+};
+
+namespace fsr {
+
+// Records the detail message of a failure (read by fs_last_error) and returns s.
+fs_status fail(fs_status s, const std::string& msg);
+extern thread_local std::string g_err;
+
+#define FS_HIP(call)                                                                           \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fsr::fail(e_ == hipErrorOutOfMemory ? FS_ERR_OUT_OF_MEMORY : FS_ERR_DEVICE, \
+                             std::string(#call) + ": " + hipGetErrorString(e_));               \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int d)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != d) (void)hipSetDevice(d);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// Device allocations go through hipMalloc; a failed allocation reports
+// FS_ERR_OUT_OF_MEMORY and the caller releases what it already holds.
+hipError_t dev_alloc(void** p, size_t bytes);
+void dev_free(void* p);
+
+// RAII device buffer for call-local temporaries.
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() { dev_free(p); }
+};
+
+size_t state_bytes(int storage);
+size_t age_bytes(int storage);
+uint32_t heavy_grid(const fs_sim* s);
+fsi::HeavyArgs heavy_args(const fs_sim* s);
+// Device bytes a sim of this graph and these parameters holds (an estimate
+// used for admission by memory budget).
+size_t sim_footprint(fs_graph* g, const fs_sim_params* p);
+
+} // namespace fsr

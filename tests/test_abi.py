@@ -86,3 +86,21 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(_capi, "LIB_PATH", str(tmp_path / "absent.so"))
     with pytest.raises(RuntimeError, match="not built"):
         _capi.lib()
+
+
+def test_batch_and_server_host_validation():
+    import ctypes
+    L = fs.lib()
+    h = ctypes.c_void_p()
+    assert L.fs_batch_create(7, None, ctypes.byref(h)) == 1 and h.value is None
+    for bad in [fs.fs_server_params(0, 0, 0, 9, 0, None),     # unknown storage
+                fs.fs_server_params(-1, 0, 0, 0, 0, None),    # negative budget
+                fs.fs_server_params(0, -2, 0, 0, 0, None)]:   # negative slot limit
+        assert L.fs_server_create(ctypes.byref(bad), ctypes.byref(h)) == 1 and h.value is None
+    assert L.fs_server_create(None, ctypes.byref(h)) == 1
+    assert L.fs_batch_step(None, 1) == 1
+    assert L.fs_batch_add(None, None) == 1
+    rid = ctypes.c_int64()
+    assert L.fs_server_submit(None, None, ctypes.byref(rid)) == 1
+    assert L.fs_server_stats(None, None) == 1
+    assert b"NULL" in L.fs_last_error()

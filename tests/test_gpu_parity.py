@@ -131,7 +131,8 @@ def test_one_step_parity_at_checkpoints(small_graph, compact):
 
 # ------------------------------------------------------- whole trajectories
 
-VARIANTS = {"stream": fs.VARIANT_STREAM, "resident": fs.VARIANT_RESIDENT}
+VARIANTS = {"stream": fs.VARIANT_STREAM, "resident": fs.VARIANT_RESIDENT,
+            "summary": fs.VARIANT_SUMMARY}
 
 
 def run_gpu(g, model, seeds, steps, n, compact=False, b=0, replicas=1, variant=0):
@@ -177,7 +178,7 @@ def test_graph_replay_equals_eager(small_graph):
 
 
 @pytest.mark.parametrize("compact", [False, True], ids=["fp32", "compact"])
-def test_stream_and_resident_variants_identical(compact):
+def test_all_variants_identical(compact):
     # a scale-free graph (hub rows take the degree-binned path)
     n = 20_000
     rp, ci = W.barabasi_albert(n, 4, 6)
@@ -185,16 +186,58 @@ def test_stream_and_resident_variants_identical(compact):
              "seed": 21}
     seeds = W.seed_nodes(n, 30, 1)
     with fs.Graph(rp, ci) as g:
-        a = run_gpu(g, model, seeds, 150, n, compact, b=25, replicas=2, variant=fs.VARIANT_STREAM)
-        b = run_gpu(g, model, seeds, 150, n, compact, b=25, replicas=2, variant=fs.VARIANT_RESIDENT)
-    for ra, rb in zip(a, b):
-        for x, y in zip(ra, rb):
-            np.testing.assert_array_equal(x, y)
+        runs = {name: run_gpu(g, model, seeds, 150, n, compact, b=25, replicas=2, variant=v)
+                for name, v in VARIANTS.items()}
+    for name in ["resident", "summary"]:
+        for ra, rb in zip(runs["stream"], runs[name]):
+            for x, y in zip(ra, rb):
+                np.testing.assert_array_equal(x, y)
+
+
+def test_summary_variant_with_coarse_groups():
+    """N*R just above 2^26 units makes each summary bit cover 128 units (two
+    bitmap words).  Contacts form a random 8-regular graph on 200k nodes spread
+    over the whole id range; every other node is isolated.  The summary and
+    streaming variants agree exactly and one step matches the oracle."""
+    n, R = (1 << 25) + 1000, 2
+    rng = np.random.default_rng(11)
+    sub = np.sort(rng.choice(n, 200_000, replace=False))
+    srp, sci = W.random_regular_matchings(len(sub), 8, 4)
+    deg = np.zeros(n, np.int64)
+    deg[sub] = 8
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(deg, out=rp[1:])
+    rp = rp.astype(np.int32)
+    ci = sub[sci].astype(np.int32)  # rows of sub[i] keep their order
+    model = dict(SMALL["model"], beta=0.2, seed=5)
+    seeds = sub[rng.choice(len(sub), 300, replace=False)]
+    with fs.Graph(rp, ci) as g:
+        out = {}
+        for name in ["summary", "stream"]:
+            sim = fs.Sim.from_model(g, model, steps_per_graph=20, replicas=R, variant=VARIANTS[name],
+                                    record_rates=True)
+            sim.seed(seeds, replica=-1, compartment=fs.FS_E)
+            sim.step(80)
+            st, age, k = sim.get_state(1)
+            sim.step(1)
+            out[name] = (st, age, *sim.get_state(1)[:2], sim.history(0, 81, 1), sim.rates(1))
+            sim.close()
+    for x, y in zip(out["summary"], out["stream"]):
+        np.testing.assert_array_equal(x, y)
+    st, age, gst, gage, hist, rates = out["summary"]
+    assert hist[-2, 2] > 50  # infection spread along the contacts
+    nodes = np.concatenate([sub[rng.choice(len(sub), 50_000, replace=False)],
+                            rng.choice(n, 10_000, replace=False)])
+    ora = oracle.step_nodes((rp, ci), model, st, age, (st == 2).astype(np.float64), 80, nodes,
+                            replica=1)
+    nm = guard_band_mismatches(gst[nodes], ora["state"], ora["u"], ora["q"], "coarse summary")
+    check_mismatch_budget(nm, len(nodes), "coarse summary")
+    check_rates(rates[nodes], ora["lam"], "coarse summary")
 
 
 def test_resident_variant_size_limit():
     # the LDS-resident bitmap holds at most 2^20 units; larger sims take the
-    # streaming variant automatically and refuse an explicit resident request
+    # summary variant automatically and refuse an explicit resident request
     n = (1 << 20) + 1
     rp = np.zeros(n + 1, np.int32)
     with fs.Graph(rp, np.zeros(0, np.int32)) as g:
