@@ -552,9 +552,17 @@ class Server:
         return fs_server_wait(self.handle, rid, timeout_s)
 
     def result(self, rid: int):
-        """(history [n_steps][replicas][4], info dict); forgets the request."""
-        n_steps, replicas = self._shape.pop(rid)
-        return fs_server_result(self.handle, rid, n_steps, replicas)
+        """(history [n_steps][replicas][4], info dict); forgets the request.
+        Raises FsError for an unknown, unfinished or failed request."""
+        n_steps, replicas = self._shape.get(rid, (0, 1))
+        try:
+            out = fs_server_result(self.handle, rid, n_steps, replicas)
+        except FsError as e:
+            if e.status != 5:  # anything but "not finished" forgets the request
+                self._shape.pop(rid, None)
+            raise
+        self._shape.pop(rid, None)
+        return out
 
     def stats(self) -> dict:
         return fs_server_stats(self.handle)

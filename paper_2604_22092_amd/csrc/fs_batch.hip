@@ -311,6 +311,7 @@ struct Request {
     std::vector<int64_t> seeds;
     size_t bytes = 0;
     fs_sim* sim = nullptr;
+    bool solo = false;             // runs its own step kernels instead of joining the batch
     int64_t done_steps = 0;
     fs_request_info info{};
     std::vector<int64_t> history; // [n_steps][R][4]
@@ -323,7 +324,8 @@ struct Request {
 struct fs_server {
     fs_server_params p{};
     int device = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;       // rounds: every admitted request's steps
+    hipStream_t admit_stream = nullptr; // creation and seeding of new requests
     bool own_stream = false;
     fs_batch* batch = nullptr;
     size_t budget = 0, in_use = 0;
@@ -341,28 +343,55 @@ struct fs_server {
 
 namespace {
 
-// Creates and seeds the sim of an admitted request (worker thread).
+// Requests with at least this many units give every wavefront of the GPU a
+// chunk by themselves: they run their own step kernels (the variant that
+// suits their size) on the server stream.  Smaller ones share the batch's
+// fused launches.
+constexpr size_t SOLO_UNITS = (size_t)1 << 18;
+
+// Creates and seeds the sim of an admitted request on the admission stream,
+// while the current round runs (worker thread).  The sim joins the rounds
+// later (join_request).
 fs_status start_request(fs_server* sv, Request& q)
 {
+    q.solo = (size_t)q.g->n * (size_t)q.p.n_replicas >= SOLO_UNITS;
     fs_sim_params p = q.p;
     p.storage = sv->p.storage;
-    p.variant = 1;
+    p.variant = q.solo ? 0 : 1;
     p.steps_per_graph = 0;
     p.history_len = (int32_t)std::max<int64_t>(q.n_steps, 2);
-    p.stream = sv->stream;
+    p.stream = sv->admit_stream;
     p.record_rates = 0;
     fs_status st = fs_sim_create(q.g, &p, &q.sim);
     if (st != FS_OK) return st;
     if (!q.seeds.empty() && (st = fs_sim_seed(q.sim, -1, (int64_t)q.seeds.size(), q.seeds.data(), FS_E)) != FS_OK)
         return st;
-    return fs_batch_add(sv->batch, q.sim);
+    return FS_OK;
 }
 
-// Copies a finished request's counts and releases its sim (worker thread).
+// Moves a created sim onto the server stream (its setup on the admission
+// stream is complete: fs_sim_seed synchronised it) and, unless it runs solo,
+// into the batch.  Called between rounds.
+fs_status join_request(fs_server* sv, Request& q)
+{
+    q.sim->stream = sv->stream;
+    return q.solo ? FS_OK : fs_batch_add(sv->batch, q.sim);
+}
+
+void drop_sim(fs_server* sv, Request& q)
+{
+    if (!q.sim) return;
+    if (q.sim->batch) (void)fs_batch_remove(sv->batch, q.sim);
+    (void)fs_sim_destroy(q.sim);
+    q.sim = nullptr;
+}
+
+// Copies a finished request's counts and releases its sim (worker thread,
+// between rounds).
 fs_status finish_request(fs_server* sv, Request& q)
 {
     const int R = q.p.n_replicas;
-    fs_status st = fs_batch_remove(sv->batch, q.sim);
+    fs_status st = q.sim->batch ? fs_batch_remove(sv->batch, q.sim) : FS_OK;
     if (st == FS_OK) {
         q.history.assign((size_t)q.n_steps * R * 4, 0);
         std::vector<int64_t> one((size_t)q.n_steps * 4);
@@ -372,94 +401,131 @@ fs_status finish_request(fs_server* sv, Request& q)
                 for (int c = 0; c < 4; ++c) q.history[((size_t)k * R + r) * 4 + c] = one[(size_t)k * 4 + c];
         }
     }
-    (void)fs_sim_destroy(q.sim);
-    q.sim = nullptr;
+    drop_sim(sv, q);
     return st;
 }
 
+
+// Ends request q with status st (the lock is held).
+void end_request(fs_server* sv, Request& q, fs_status st, const std::string& err)
+{
+    q.info.status = st;
+    if (st != FS_OK) q.error = err;
+    if (q.info.t_done == 0.0) q.info.t_done = now_s();
+    q.finished = true;
+    q.g->users.fetch_sub(1);
+}
+
+// The worker: each iteration launches one round of steps for the active
+// requests, admits queued requests while that round runs, waits for it,
+// retires the requests that are done and lets the new ones join.
 void worker_loop(fs_server* sv)
 {
     (void)hipSetDevice(sv->device);
     std::unique_lock<std::mutex> lk(sv->mu);
+    std::vector<std::shared_ptr<Request>> joining;
     while (true) {
-        // admission: FIFO while the slot limit and the memory budget allow
-        while (!sv->queue.empty() && (int)sv->active.size() < sv->p.max_active &&
-               (sv->active.empty() || sv->in_use + sv->queue.front()->bytes <= sv->budget)) {
+        if (sv->active.empty() && joining.empty()) {
+            if (sv->stop && sv->queue.empty()) break;
+            sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
+            if (sv->queue.empty()) continue;
+        }
+        // 1. launch one round: every active request advances by r steps,
+        //    r bounded by the request closest to its end
+        int64_t r = sv->p.steps_per_round;
+        for (auto& q : sv->active) r = std::min(r, q->n_steps - q->done_steps);
+        std::vector<std::shared_ptr<Request>> act = sv->active;
+        lk.unlock();
+        fs_status st = FS_OK;
+        std::string err;
+        if (!act.empty()) {
+            st = fs_batch_step(sv->batch, r);
+            for (auto& q : act)
+                if (st == FS_OK && q->solo) st = fs_step(q->sim, r);
+            if (st != FS_OK) err = g_err;
+        }
+        // 2. admissions (FIFO while the slot limit and the memory budget
+        //    allow), overlapped with the round on the device
+        lk.lock();
+        while (st == FS_OK && !sv->queue.empty() &&
+               (int)(sv->active.size() + joining.size()) < sv->p.max_active &&
+               (sv->active.empty() && joining.empty() ? true : sv->in_use + sv->queue.front()->bytes <= sv->budget)) {
             std::shared_ptr<Request> q = sv->queue.front();
             sv->queue.pop_front();
             sv->in_use += q->bytes;
             lk.unlock();
             q->info.t_admit = now_s();
-            fs_status st = start_request(sv, *q);
-            const std::string err = st == FS_OK ? std::string() : g_err;
+            const fs_status ast = start_request(sv, *q);
+            const std::string aerr = ast == FS_OK ? std::string() : g_err;
+            if (ast != FS_OK) drop_sim(sv, *q);
             lk.lock();
-            if (st != FS_OK) {
-                if (q->sim) {
-                    if (q->sim->batch) (void)fs_batch_remove(sv->batch, q->sim);
-                    (void)fs_sim_destroy(q->sim);
-                    q->sim = nullptr;
-                }
+            if (ast != FS_OK) {
                 sv->in_use -= q->bytes;
-                q->info.status = st;
-                q->error = err;
-                q->info.t_done = now_s();
-                q->finished = true;
-                q->g->users.fetch_sub(1);
+                end_request(sv, *q, ast, aerr);
                 sv->cv_done.notify_all();
                 continue;
             }
-            sv->active.push_back(q);
+            joining.push_back(q);
         }
-        if (sv->active.empty()) {
-            if (sv->stop) break;
-            sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
-            continue;
-        }
-        // one round: the batch advances every active request by the same
-        // number of steps, bounded by the request closest to its end
-        int64_t r = sv->p.steps_per_round;
-        for (auto& q : sv->active) r = std::min(r, q->n_steps - q->done_steps);
-        std::vector<std::shared_ptr<Request>> act = sv->active;
         lk.unlock();
-        fs_status st = fs_batch_step(sv->batch, r);
-        if (st == FS_OK) st = fs_batch_sync(sv->batch);
-        const std::string err = st == FS_OK ? std::string() : g_err;
+        // 3. wait for the round
+        if (!act.empty() && st == FS_OK) {
+            st = fs_batch_sync(sv->batch);
+            if (st != FS_OK) err = g_err;
+        }
+        // 4. retire the requests that are done; 5. the new ones join
         std::vector<std::shared_ptr<Request>> ended;
         for (auto& q : act) {
             q->done_steps += r;
             if (st != FS_OK || q->done_steps >= q->n_steps) ended.push_back(q);
         }
-        for (auto& q : ended) {
-            fs_status fst = st;
+        std::vector<fs_status> fst(ended.size(), st);
+        std::vector<std::string> ferr(ended.size(), err);
+        for (size_t i = 0; i < ended.size(); ++i) {
             if (st == FS_OK) {
-                fst = finish_request(sv, *q);
-            } else if (q->sim) {
-                (void)fs_batch_remove(sv->batch, q->sim);
-                (void)fs_sim_destroy(q->sim);
-                q->sim = nullptr;
+                fst[i] = finish_request(sv, *ended[i]);
+                if (fst[i] != FS_OK) ferr[i] = g_err;
+            } else {
+                drop_sim(sv, *ended[i]);
             }
-            q->info.status = fst;
-            if (fst != FS_OK) q->error = st != FS_OK ? err : g_err;
-            q->info.t_done = now_s();
+            ended[i]->info.t_done = now_s();
         }
+        std::vector<std::shared_ptr<Request>> joined, failed;
+        std::vector<std::string> jerr;
+        for (auto& q : joining) {
+            const fs_status jst = st == FS_OK ? join_request(sv, *q) : st;
+            if (jst == FS_OK) {
+                joined.push_back(q);
+            } else {
+                jerr.push_back(st == FS_OK ? g_err : err);
+                drop_sim(sv, *q);
+                failed.push_back(q);
+            }
+        }
+        joining.clear();
         lk.lock();
         ++sv->rounds;
-        for (auto& q : ended) {
-            sv->active.erase(std::remove(sv->active.begin(), sv->active.end(), q), sv->active.end());
-            sv->in_use -= q->bytes;
-            q->finished = true;
-            q->g->users.fetch_sub(1);
+        for (size_t i = 0; i < ended.size(); ++i) {
+            sv->active.erase(std::remove(sv->active.begin(), sv->active.end(), ended[i]), sv->active.end());
+            sv->in_use -= ended[i]->bytes;
+            end_request(sv, *ended[i], fst[i], ferr[i]);
         }
-        if (!ended.empty()) sv->cv_done.notify_all();
+        for (size_t i = 0; i < failed.size(); ++i) {
+            sv->in_use -= failed[i]->bytes;
+            end_request(sv, *failed[i], st == FS_OK ? FS_ERR_DEVICE : st, jerr[i]);
+        }
+        for (auto& q : joined) sv->active.push_back(q);
+        if (!ended.empty() || !failed.empty()) sv->cv_done.notify_all();
         if (st != FS_OK) {
             // a device failure ends every request and the server
             sv->worker_error = err;
-            for (auto& q : sv->queue) {
-                q->info.status = st;
-                q->error = err;
-                q->finished = true;
-                q->g->users.fetch_sub(1);
+            for (auto& q : sv->active) {
+                drop_sim(sv, *q);
+                sv->in_use -= q->bytes;
+                end_request(sv, *q, st, err);
             }
+            sv->active.clear();
+            for (auto& q : sv->queue) end_request(sv, *q, st, err);
             sv->queue.clear();
             sv->stop = true;
             sv->cv_done.notify_all();
@@ -500,8 +566,13 @@ fs_status fs_server_create(const fs_server_params* p, fs_server** out)
         FS_HIP(hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking));
         sv->own_stream = true;
     }
+    if (hipStreamCreateWithFlags(&sv->admit_stream, hipStreamNonBlocking) != hipSuccess) {
+        if (sv->own_stream) (void)hipStreamDestroy(sv->stream);
+        return fail(FS_ERR_DEVICE, "admission stream");
+    }
     fs_status st = fs_batch_create(p->storage, sv->stream, &sv->batch);
     if (st != FS_OK) {
+        (void)hipStreamDestroy(sv->admit_stream);
         if (sv->own_stream) (void)hipStreamDestroy(sv->stream);
         return st;
     }
@@ -617,6 +688,7 @@ fs_status fs_server_destroy(fs_server* sv)
     {
         DeviceGuard dg(sv->device);
         (void)fs_batch_destroy(sv->batch);
+        (void)hipStreamDestroy(sv->admit_stream);
         if (sv->own_stream) (void)hipStreamDestroy(sv->stream);
     }
     delete sv;

@@ -1,6 +1,7 @@
 // Layouts shared by the step kernels and the host runtime of the library.
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace fsi {
@@ -22,6 +23,9 @@ constexpr int STREAM_TPB = 256;
 constexpr int RESIDENT_TPB = 1024;
 constexpr uint32_t RESIDENT_BITS = 1u << 20;
 constexpr uint32_t SUMMARY_BITS = 1u << 20;
+// Light rows of a chunk whose rows all have the same degree d <= UNIFORM_MAX_DEG
+// have their edge slots loaded ahead with the chunk's state (the preload depth).
+constexpr int UNIFORM_MAX_DEG = 12;
 // Bitmaps are allocated in whole 512-unit tiles (8 words of 64 bits).
 constexpr uint32_t BITMAP_TILE = 512;
 
@@ -85,12 +89,16 @@ struct StepArgs {
     int32_t seg_edges;
     // light rows in wavefront-transposed order: for the Q = 64/R nodes of chunk
     // c, edge j of every row with more than j light edges is stored at
-    // chunk_base[c] + (edges j' < j of the chunk) + (rank of the row among the
-    // chunk's rows with more than j edges).  ldeg[node] is the row's degree,
-    // or HEAVY_ROW for a binned row.
+    // chunk_meta[c].x + (edges j' < j of the chunk) + (rank of the row among
+    // the chunk's rows with more than j edges); chunk_meta[c].y is the light
+    // degree all the chunk's rows share (full chunks only), or 255.  ldeg[node]
+    // is the row's degree, or HEAVY_ROW for a binned row.
     const uint16_t* ldeg;
-    const uint32_t* chunk_base;
-    const uint8_t* chunk_deg; // the shared light degree of a chunk's rows, 255 if mixed
+    const uint2* chunk_meta;
+    // every chunk uniform with this degree (<= UNIFORM_MAX_DEG) and no heavy
+    // rows: chunk c starts at slot c * (64 / R) * udeg; else -1
+    int32_t udeg;
+    int32_t pad2;
     const int32_t* col_t;
     const float* w_t;
     // MODE_SUMMARY: summary of the step's input bitmap, sum_bits bits

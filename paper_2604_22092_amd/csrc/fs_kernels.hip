@@ -46,6 +46,14 @@ __device__ __forceinline__ float age_units(float a) { return a; }
 __device__ __forceinline__ float age_units(uint16_t a) { return (float)a; }
 __device__ __forceinline__ float age_next(float a, float dt) { return a + dt; }
 __device__ __forceinline__ uint16_t age_next(uint16_t a, float) { return a == 65535 ? a : (uint16_t)(a + 1); }
+template <class T>
+__device__ __forceinline__ T age_from_raw(uint32_t w);
+template <>
+__device__ __forceinline__ float age_from_raw<float>(uint32_t w) { return __uint_as_float(w); }
+template <>
+__device__ __forceinline__ uint16_t age_from_raw<uint16_t>(uint32_t w) { return (uint16_t)w; }
+__device__ __forceinline__ uint32_t age_to_raw(float a) { return __float_as_uint(a); }
+__device__ __forceinline__ uint32_t age_to_raw(uint16_t a) { return a; }
 
 // Infectivity is held as one bit per unit (bit u = 1{X_u = I}); with constant
 // shedding s = 1 this is the exact value of Eq. (infectivity) without beta.
@@ -59,28 +67,80 @@ __device__ __forceinline__ uint32_t lds_bit(const uint32_t* __restrict__ w, uint
     return __builtin_amdgcn_ubfe(w[b >> 5], b & 31, 1);
 }
 
-// Infectivity bit b of the step's input: from the LDS copy (MODE_RESIDENT),
-// from global memory (MODE_STREAM), or from global memory only when the LDS
-// summary says its group holds an infectious unit (MODE_SUMMARY).
-template <int MODE>
-__device__ __forceinline__ uint32_t fetch_bit(const uint32_t* __restrict__ lds, const uint32_t* __restrict__ gbits,
-                                              uint32_t b, int32_t lg_gran)
+// Raw buffer accesses.  Word 3 of the descriptor (0x00020000) is the gfx9
+// raw-buffer format: 32-bit data, no swizzle, range checked against the byte
+// count in word 2.  An access whose offset is outside that range reads 0 and
+// writes nothing, with no memory request.  The step uses this instead of
+// branches: lanes and slots that must not touch memory get offset OOB, and
+// every path issues the same memory instructions, so the compiler can wait
+// for exactly the loads it needs while later loads are still in flight.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int BUF_WORD3 = 0x00020000;
+constexpr uint32_t OOB = 0x80000000u; // beyond every byte range used here (< 2^31)
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes)
 {
-    if (MODE == MODE_RESIDENT) return lds_bit(lds, b);
-    if (MODE == MODE_STREAM) return bit_at(gbits, b);
-    uint32_t r = 0;
-    if (lds_bit(lds, b >> lg_gran)) r = bit_at(gbits, b);
-    return r;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, BUF_WORD3);
+}
+__device__ __forceinline__ uint32_t ld32(rsrc_t r, uint32_t off) { return __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0); }
+__device__ __forceinline__ void st32(rsrc_t r, uint32_t off, uint32_t v) { __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)off, 0, 0); }
+
+// Element access of the storage types through a buffer descriptor.
+template <class T>
+struct BufIO;
+template <>
+struct BufIO<int32_t> {
+    __device__ static uint32_t ld(rsrc_t r, uint32_t i) { return ld32(r, i << 2); }
+    __device__ static void st(rsrc_t r, uint32_t i, uint32_t v) { st32(r, i << 2, v); }
+};
+template <>
+struct BufIO<float> {
+    __device__ static uint32_t ld(rsrc_t r, uint32_t i) { return ld32(r, i << 2); }
+    __device__ static void st(rsrc_t r, uint32_t i, uint32_t v) { st32(r, i << 2, v); }
+};
+template <>
+struct BufIO<uint8_t> {
+    __device__ static uint32_t ld(rsrc_t r, uint32_t i) { return __builtin_amdgcn_raw_buffer_load_b8(r, (int)i, 0, 0); }
+    __device__ static void st(rsrc_t r, uint32_t i, uint32_t v)
+    {
+        __builtin_amdgcn_raw_buffer_store_b8((uint8_t)v, r, (int)i, 0, 0);
+    }
+};
+template <>
+struct BufIO<uint16_t> {
+    __device__ static uint32_t ld(rsrc_t r, uint32_t i)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, (int)(i << 1), 0, 0);
+    }
+    __device__ static void st(rsrc_t r, uint32_t i, uint32_t v)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)v, r, (int)(i << 1), 0, 0);
+    }
+};
+// Element index that is out of range for every descriptor built here.
+constexpr uint32_t OOB_ELEM = OOB >> 2;
+
+// Infectivity bit b of the step's input for a lane that wants it (use):
+// from the LDS copy (MODE_RESIDENT), from global memory (MODE_STREAM), or
+// from global memory only when the LDS summary says its group holds an
+// infectious unit (MODE_SUMMARY).  Lanes that do not want it read nothing
+// from global memory and get 0.  b must be a valid unit index.
+template <int MODE>
+__device__ __forceinline__ uint32_t fetch_bit(const uint32_t* __restrict__ lds, rsrc_t gbits, uint32_t b,
+                                              int32_t lg_gran, bool use)
+{
+    if (MODE == MODE_RESIDENT) return use ? lds_bit(lds, b) : 0u;
+    bool go = use;
+    if (MODE == MODE_SUMMARY) go = go && lds_bit(lds, b >> lg_gran) != 0u;
+    const uint32_t w = ld32(gbits, go ? (b >> 5) << 2 : OOB);
+    return (w >> (b & 31)) & 1u;
 }
 
 // Light-row edge slots loaded ahead for chunks whose rows share one light
 // degree (every chunk of a regular graph): slot j of row q is col_t[base +
 // j*Q + q], so these loads need only the chunk's metadata and are issued with
 // the state and age loads.
-#ifndef FS_UMAX
-#define FS_UMAX 12
-#endif
-constexpr int UMAX = FS_UMAX;
+constexpr int UMAX = UNIFORM_MAX_DEG;
 // Edge slots per batch of the general (mixed-degree) gather.
 constexpr int JB = 8;
 // Chunks of 64 units each wavefront takes per pass; the hazards and draws of
@@ -89,51 +149,60 @@ constexpr int JB = 8;
 #define FS_CU 1
 #endif
 constexpr int CU = FS_CU;
+// Issue the next pass's loads before processing the current one.
+#ifndef FS_PREFETCH
+#define FS_PREFETCH 1
+#endif
+constexpr bool PREFETCH = FS_PREFETCH != 0;
 
+// The loads of one pass, as issued: chunk numbers and metadata are
+// wave-uniform; xr, agw and dgr are the raw state, age and degree words
+// (0 for lanes past the chunk's valid units), used only after the pass's
+// wait.
 template <class age_t>
 struct Pass {
-    uint32_t chk[CU], unit[CU], node[CU], rep[CU], base[CU], ud[CU];
-    bool valid[CU], live[CU];
-    int x[CU];
-    age_t ag[CU];
-    uint16_t dg[CU];
+    uint32_t chk[CU], base[CU], ud[CU], nvalid[CU];
+    bool live[CU];
+    uint32_t xr[CU], agw[CU], dgr[CU];
     int32_t c[CU][UMAX];
 };
 
 // Issues every load of a pass that does not depend on the state: chunk
-// metadata (scalar), state, age, light degree, and the edge slots of uniform
-// chunks.
-template <int STORAGE, class age_t>
+// metadata (one scalar load), state, age and light degree, and the edge
+// slots of uniform chunks (whose rows are all present).  Each array is read
+// through a descriptor covering only this chunk's valid entries, so no lane
+// branches and a pass past the last chunk reads nothing.
+template <int STORAGE, bool UNIFORM, class age_t>
 __device__ __forceinline__ void issue_pass(const StepArgs& a, uint32_t first, uint32_t nwaves, uint32_t nchunks,
                                            uint32_t total, uint32_t lane, Pass<age_t>& P)
 {
     using state_t = typename Store<STORAGE>::state_t;
-    const uint32_t R = 1u << a.lgR;
+    const uint32_t rows = 64u >> a.lgR;
     const uint32_t q = lane >> a.lgR;
 #pragma unroll
     for (int u = 0; u < CU; ++u) {
-        const uint32_t c = first + (uint32_t)u * nwaves;
+        const uint32_t c = __builtin_amdgcn_readfirstlane(first + (uint32_t)u * nwaves);
         P.live[u] = c < nchunks;
-        P.chk[u] = P.live[u] ? c : nchunks - 1; // a real chunk for the uniform layout walk
-        P.unit[u] = (P.chk[u] << 6) + lane;
-        P.valid[u] = P.live[u] && P.unit[u] < total;
-        P.node[u] = P.unit[u] >> a.lgR;
-        P.rep[u] = P.unit[u] & (R - 1);
-        P.base[u] = a.chunk_base[P.chk[u]];
-        P.ud[u] = P.live[u] ? a.chunk_deg[P.chk[u]] : 0u;
-        P.x[u] = ST_R;
-        P.ag[u] = 0;
-        P.dg[u] = 0;
-        if (P.valid[u]) {
-            P.x[u] = (int)((const state_t*)a.state)[P.unit[u]];
-            P.ag[u] = ((const age_t*)a.age)[P.unit[u]];
-            P.dg[u] = a.ldeg[P.node[u]];
+        P.chk[u] = P.live[u] ? c : nchunks - 1;
+        if (UNIFORM) {
+            P.base[u] = P.chk[u] * rows * (uint32_t)a.udeg;
+            P.ud[u] = P.live[u] ? (uint32_t)a.udeg : 0u;
+        } else {
+            const uint2 meta = a.chunk_meta[P.chk[u]];
+            P.base[u] = meta.x;
+            P.ud[u] = P.live[u] ? meta.y : 0u;
         }
+        const uint32_t u0 = P.chk[u] << 6;
+        P.nvalid[u] = P.live[u] ? min(64u, total - u0) : 0u;
+        const uint32_t n0 = u0 >> a.lgR;
+        const uint32_t nrows = P.live[u] ? min(rows, (uint32_t)a.n - n0) : 0u;
+        P.xr[u] = BufIO<state_t>::ld(make_rsrc((const state_t*)a.state + u0, P.nvalid[u] * sizeof(state_t)), lane);
+        P.agw[u] = BufIO<age_t>::ld(make_rsrc((const age_t*)a.age + u0, P.nvalid[u] * sizeof(age_t)), lane);
+        P.dgr[u] = BufIO<uint16_t>::ld(make_rsrc(a.ldeg + n0, nrows * 2u), q);
+        const bool pre = P.ud[u] <= (uint32_t)UMAX;
+        const rsrc_t cr = make_rsrc(a.col_t + P.base[u], pre ? P.ud[u] * rows * 4u : 0u);
 #pragma unroll
-        for (int j = 0; j < UMAX; ++j) {
-            P.c[u][j] = 0;
-            if ((uint32_t)j < P.ud[u] && P.valid[u]) P.c[u][j] = a.col_t[P.base[u] + (uint32_t)j * (64u >> a.lgR) + q];
-        }
+        for (int j = 0; j < UMAX; ++j) P.c[u][j] = (int32_t)ld32(cr, ((uint32_t)j * rows + q) << 2);
     }
 }
 
@@ -141,26 +210,33 @@ __device__ __forceinline__ void issue_pass(const StepArgs& a, uint32_t first, ui
 // beta).  Uniform chunks use the preloaded slots; mixed chunks find a row's
 // position in run j as its rank among the rows with more than j edges (ballot
 // prefix count), JB slots at a time.
-template <int MODE, bool WEIGHTED, class age_t>
+template <int MODE, bool WEIGHTED, bool UNIFORM, class age_t>
 __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_t>& P, int u, bool want,
-                                              const uint32_t* __restrict__ lds, const uint32_t* __restrict__ gbits,
+                                              uint32_t dg, const uint32_t* __restrict__ lds, rsrc_t gbits,
                                               uint32_t lane)
 {
     const int32_t lgR = a.lgR;
     const uint32_t R = 1u << lgR;
-    const uint32_t rep = P.rep[u];
-    const uint32_t d = P.dg[u] == HEAVY_ROW ? 0u : P.dg[u];
+    const uint32_t rep = lane & (R - 1);
+    const uint32_t d = dg == HEAVY_ROW ? 0u : dg;
     uint32_t pi = 0;
     float pw = 0.0f;
-    if (P.ud[u] <= (uint32_t)UMAX) {
+    if (UNIFORM || P.ud[u] <= (uint32_t)UMAX) {
+        // uniform chunk: slots past the degree hold 0 (a valid node) and are
+        // not used; weights come through the same per-chunk range
         const uint32_t rows = 64u >> lgR;
         const uint32_t q = lane >> lgR;
+        const rsrc_t wr = make_rsrc(WEIGHTED ? (const void*)(a.w_t + P.base[u]) : (const void*)a.w_t,
+                                    WEIGHTED ? P.ud[u] * rows * 4u : 0u);
 #pragma unroll
         for (int j = 0; j < UMAX; ++j) {
-            if ((uint32_t)j < P.ud[u] && want) {
-                const uint32_t b = fetch_bit<MODE>(lds, gbits, ((uint32_t)P.c[u][j] << lgR) + rep, a.lg_gran);
-                if (WEIGHTED) pw = __builtin_fmaf(a.w_t[P.base[u] + (uint32_t)j * rows + q], (float)b, pw);
-                else pi += b;
+            const bool use = (uint32_t)j < P.ud[u] && want;
+            const uint32_t b = fetch_bit<MODE>(lds, gbits, ((uint32_t)P.c[u][j] << lgR) + rep, a.lg_gran, use);
+            if (WEIGHTED) {
+                const float w = __uint_as_float(ld32(wr, use ? ((uint32_t)j * rows + q) << 2 : OOB));
+                pw = __builtin_fmaf(w, (float)b, pw);
+            } else {
+                pi += b;
             }
         }
     } else {
@@ -185,7 +261,7 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
 #pragma unroll
             for (int jj = 0; jj < JB; ++jj) {
                 if (want && d > j0 + jj) {
-                    const uint32_t b = fetch_bit<MODE>(lds, gbits, ((uint32_t)c[jj] << lgR) + rep, a.lg_gran);
+                    const uint32_t b = fetch_bit<MODE>(lds, gbits, ((uint32_t)c[jj] << lgR) + rep, a.lg_gran, true);
                     if (WEIGHTED) pw = __builtin_fmaf(wv[jj], (float)b, pw);
                     else pi += b;
                 }
@@ -257,6 +333,130 @@ __device__ __forceinline__ void compact_apply(uint32_t* xch, uint32_t lane, cons
     }
 }
 
+// Everything of one pass after its loads were issued: rates (gather,
+// hazards), draws, stores, next-infectivity words and counts.
+template <int STORAGE, bool WEIGHTED, bool RATES, int MODE, bool UNIFORM, class age_t>
+__device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t>& P, uint32_t lane,
+                                             const uint32_t* __restrict__ s_bits, rsrc_t gbits, uint32_t* xch,
+                                             unsigned long long k, unsigned long long* __restrict__ bits_out,
+                                             uint32_t* s_cnt, uint32_t& c0, uint32_t& c1, uint32_t& c2,
+                                             uint32_t& c3)
+{
+    using state_t = typename Store<STORAGE>::state_t;
+    const uint32_t R = 1u << a.lgR;
+
+    // the pass's loaded words; lanes past the chunk's valid units act as R
+    bool valid[CU];
+    int x[CU];
+    age_t ag[CU];
+    uint32_t dg[CU], unit[CU];
+#pragma unroll
+    for (int u = 0; u < CU; ++u) {
+        valid[u] = lane < P.nvalid[u];
+        unit[u] = (P.chk[u] << 6) + lane;
+        x[u] = valid[u] ? (int)P.xr[u] : ST_R;
+        ag[u] = valid[u] ? age_from_raw<age_t>(P.agw[u]) : (age_t)0;
+        dg[u] = valid[u] ? P.dgr[u] : 0u;
+    }
+
+    // 1.-2. rate: beta * pressure for S; hazard at the start-of-step age for E/I; 0 for R
+    float lam[CU];
+#pragma unroll
+    for (int u = 0; u < CU; ++u) {
+        lam[u] = 0.0f;
+        const bool heavy = !UNIFORM && dg[u] == HEAVY_ROW;
+        const bool want = x[u] == ST_S && !heavy;
+        const float p = pressure_row<MODE, WEIGHTED, UNIFORM>(a, P, u, want, dg[u], s_bits, gbits, lane);
+        if (want) lam[u] = a.beta * p;
+        if (!UNIFORM && heavy && x[u] == ST_S)
+            lam[u] = a.beta * pressure_heavy<WEIGHTED>(a, unit[u] >> a.lgR, unit[u] & (R - 1));
+    }
+
+    // hazards of the E/I units of the pass, on compacted lanes; the payload
+    // is the age bit pattern with bit 31 marking the I -> R law (ages are
+    // non-negative, so bit 31 is free)
+    {
+        bool need[CU];
+        uint32_t pay[CU], res[CU];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            need[u] = x[u] == ST_E || x[u] == ST_I;
+            pay[u] = age_bits(ag[u]) | (x[u] == ST_I ? 0x80000000u : 0u);
+            res[u] = 0;
+        }
+        compact_apply<CU>(xch, lane, need, pay, res, [&](uint32_t w) {
+            const bool isI = (w & 0x80000000u) != 0u;
+            const float xa = age_from_bits<age_t>(w & 0x7FFFFFFFu);
+            float h;
+            if (a.same_kind) {
+                HazardDev hd = a.hz[0];
+                if (isI) hd = a.hz[1];
+                hd.kind = a.hz[0].kind;
+                h = fsd::hazard(hd, xa);
+            } else {
+                h = isI ? fsd::hazard(a.hz[1], xa) : fsd::hazard(a.hz[0], xa);
+            }
+            return __float_as_uint(h);
+        });
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+            if (need[u]) lam[u] = __uint_as_float(res[u]);
+    }
+
+    // 3.-4. Bernoulli tau-leap: fire when u < 1 - exp(-lambda dt); no draw at
+    // lambda = 0.  The Philox draws of the pass run on compacted lanes.
+    bool fire[CU];
+    {
+        bool need[CU];
+        uint32_t pay[CU], res[CU];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            need[u] = lam[u] > 0.0f;
+            pay[u] = unit[u];
+            res[u] = 0;
+        }
+        const uint32_t kk = (uint32_t)k;
+        compact_apply<CU>(xch, lane, need, pay, res, [&](uint32_t un) {
+            return fsd::philox4x32_10(make_uint4(un >> a.lgR, kk, un & (R - 1), 0u), a.key0, a.key1).x >> 8;
+        });
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            fire[u] = false;
+            if (need[u]) {
+                const float uu = (float)res[u] * 0x1p-24f;
+                const float qq = -expm1f(-lam[u] * a.dt);
+                fire[u] = uu < qq;
+            }
+        }
+    }
+
+#pragma unroll
+    for (int u = 0; u < CU; ++u) {
+        // 5.-6. advance state and age in place (the chunk's descriptors drop
+        // the lanes past its valid units; the state only changes on a firing)
+        const int xn = x[u] + (fire[u] ? 1 : 0);
+        const uint32_t u0 = P.chk[u] << 6;
+        BufIO<state_t>::st(make_rsrc((state_t*)a.state + u0, P.nvalid[u] * sizeof(state_t)),
+                           fire[u] ? lane : OOB_ELEM, (uint32_t)xn);
+        BufIO<age_t>::st(make_rsrc((age_t*)a.age + u0, P.nvalid[u] * sizeof(age_t)), lane,
+                         age_to_raw(fire[u] ? (age_t)0 : age_next(ag[u], a.dt)));
+        if (RATES) st32(make_rsrc(a.rates + u0, P.nvalid[u] * 4u), lane << 2, __float_as_uint(lam[u]));
+        // 7. next-step infectivity bits (one 64-bit word per chunk, written by
+        // lanes 0 and 1) and 8. counts
+        const unsigned long long mI = __ballot(valid[u] && xn == ST_I);
+        st32(make_rsrc(bits_out + P.chk[u], P.live[u] ? 8u : 0u), lane < 2 ? lane << 2 : OOB,
+             lane == 0 ? (uint32_t)mI : (uint32_t)(mI >> 32));
+        if (R == 1) {
+            c0 += (uint32_t)__popcll(__ballot(valid[u] && xn == ST_S));
+            c1 += (uint32_t)__popcll(__ballot(valid[u] && xn == ST_E));
+            c2 += (uint32_t)__popcll(mI);
+            c3 += (uint32_t)__popcll(__ballot(valid[u] && xn == ST_R));
+        } else if (valid[u]) {
+            atomicAdd(&s_cnt[(unit[u] & (R - 1)) * 4 + xn], 1u); // LDS
+        }
+    }
+}
+
 // One fused step.  Units are processed in chunks of 64 (one wavefront, one
 // 64-bit word of the next infectivity bitmap); every wavefront walks its own
 // chunks, CU per pass, with no workgroup barrier inside the walk.
@@ -268,13 +468,11 @@ __device__ __forceinline__ void compact_apply(uint32_t* xch, uint32_t lane, cons
 //    infection is sparse most neighbours fall in empty groups);
 //  MODE_STREAM: gathers read the bitmap through the caches.
 // The LDS variants run one workgroup of RESIDENT_TPB threads per compute unit.
-template <int STORAGE, bool WEIGHTED, bool RATES, int MODE, int TPB>
+template <int STORAGE, bool WEIGHTED, bool RATES, int MODE, bool UNIFORM, int TPB>
 __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uint32_t nblocks)
 {
     constexpr bool USE_LDS = MODE != MODE_STREAM;
-    using S = Store<STORAGE>;
-    using state_t = typename S::state_t;
-    using age_t = typename S::age_t;
+    using age_t = typename Store<STORAGE>::age_t;
     constexpr int NW = TPB / 64;
 
     __shared__ uint32_t s_cnt[4 * 64];
@@ -284,22 +482,22 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63;
-    const uint32_t wave = tid >> 6;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6); // wave-uniform, in a scalar register
     const uint32_t R = 1u << a.lgR;
     const unsigned long long k = a.ctl->step + a.step_off;
     const uint32_t* __restrict__ bits_in = (const uint32_t*)((k & 1) ? a.iota1 : a.iota0);
     unsigned long long* __restrict__ bits_out = (unsigned long long*)((k & 1) ? a.iota0 : a.iota1);
-    state_t* __restrict__ state = (state_t*)a.state;
-    age_t* __restrict__ age = (age_t*)a.age;
     const uint32_t total = (uint32_t)a.n << a.lgR;
     const uint32_t nchunks = (total + 63) >> 6;
+    // the input bitmap: whole 512-unit tiles of 64 bytes
+    const rsrc_t gbits = make_rsrc(bits_in, ((total + 511u) >> 9) << 6);
     const uint32_t wave_id = block * NW + wave;
     const uint32_t nwaves = nblocks * NW;
 
     // first pass loads, then the bitmap fill, then one wait for both
     Pass<age_t> P;
     uint32_t first = wave_id;
-    if (first < nchunks) issue_pass<STORAGE>(a, first, nwaves, nchunks, total, lane, P);
+    issue_pass<STORAGE, UNIFORM>(a, first, nwaves, nchunks, total, lane, P);
     if (R > 1)
         for (uint32_t i = tid; i < 4 * R; i += TPB) s_cnt[i] = 0;
     if (USE_LDS) {
@@ -319,100 +517,24 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
 
     uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0; // per-wave counts (R == 1)
 
-    for (; first < nchunks; first += nwaves * CU) {
-        if (first != wave_id) issue_pass<STORAGE>(a, first, nwaves, nchunks, total, lane, P);
-
-        // 1.-2. rate: beta * pressure for S; hazard at the start-of-step age for E/I; 0 for R
-        float lam[CU];
-#pragma unroll
-        for (int u = 0; u < CU; ++u) {
-            lam[u] = 0.0f;
-            const bool heavy = P.dg[u] == HEAVY_ROW;
-            const bool want = P.x[u] == ST_S && !heavy;
-            const float p = pressure_row<MODE, WEIGHTED>(a, P, u, want, s_bits, bits_in, lane);
-            if (want) lam[u] = a.beta * p;
-            if (heavy && P.x[u] == ST_S) lam[u] = a.beta * pressure_heavy<WEIGHTED>(a, P.node[u], P.rep[u]);
-        }
-
-        // hazards of the E/I units of the pass, on compacted lanes; the payload
-        // is the age bit pattern with bit 31 marking the I -> R law (ages are
-        // non-negative, so bit 31 is free)
-        {
-            bool need[CU];
-            uint32_t pay[CU], res[CU];
-#pragma unroll
-            for (int u = 0; u < CU; ++u) {
-                need[u] = P.x[u] == ST_E || P.x[u] == ST_I;
-                pay[u] = age_bits(P.ag[u]) | (P.x[u] == ST_I ? 0x80000000u : 0u);
-                res[u] = 0;
-            }
-            compact_apply<CU>(s_xch[wave], lane, need, pay, res, [&](uint32_t w) {
-                const bool isI = (w & 0x80000000u) != 0u;
-                const float xa = age_from_bits<age_t>(w & 0x7FFFFFFFu);
-                float h;
-                if (a.same_kind) {
-                    HazardDev hd = a.hz[0];
-                    if (isI) hd = a.hz[1];
-                    hd.kind = a.hz[0].kind;
-                    h = fsd::hazard(hd, xa);
-                } else {
-                    h = isI ? fsd::hazard(a.hz[1], xa) : fsd::hazard(a.hz[0], xa);
-                }
-                return __float_as_uint(h);
-            });
-#pragma unroll
-            for (int u = 0; u < CU; ++u)
-                if (need[u]) lam[u] = __uint_as_float(res[u]);
-        }
-
-        // 3.-4. Bernoulli tau-leap: fire when u < 1 - exp(-lambda dt); no draw at
-        // lambda = 0.  The Philox draws of the pass run on compacted lanes.
-        bool fire[CU];
-        {
-            bool need[CU];
-            uint32_t pay[CU], res[CU];
-#pragma unroll
-            for (int u = 0; u < CU; ++u) {
-                need[u] = lam[u] > 0.0f;
-                pay[u] = P.unit[u];
-                res[u] = 0;
-            }
-            const uint32_t kk = (uint32_t)k;
-            compact_apply<CU>(s_xch[wave], lane, need, pay, res, [&](uint32_t un) {
-                return fsd::philox4x32_10(make_uint4(un >> a.lgR, kk, un & (R - 1), 0u), a.key0, a.key1).x >> 8;
-            });
-#pragma unroll
-            for (int u = 0; u < CU; ++u) {
-                fire[u] = false;
-                if (need[u]) {
-                    const float uu = (float)res[u] * 0x1p-24f;
-                    const float qq = -expm1f(-lam[u] * a.dt);
-                    fire[u] = uu < qq;
-                }
-            }
-        }
-
-#pragma unroll
-        for (int u = 0; u < CU; ++u) {
-            // 5.-6. advance state and age in place
-            const int xn = P.x[u] + (fire[u] ? 1 : 0);
-            if (P.valid[u]) {
-                if (fire[u]) state[P.unit[u]] = (state_t)xn;
-                age[P.unit[u]] = fire[u] ? (age_t)0 : age_next(P.ag[u], a.dt);
-                if (RATES) a.rates[P.unit[u]] = lam[u];
-            }
-            // 7. next-step infectivity bits (one 64-bit word per chunk) and 8. counts
-            const unsigned long long mI = __ballot(P.valid[u] && xn == ST_I);
-            if (lane == 0 && P.live[u]) bits_out[P.chk[u]] = mI;
-            if (R == 1) {
-                c0 += (uint32_t)__popcll(__ballot(P.valid[u] && xn == ST_S));
-                c1 += (uint32_t)__popcll(__ballot(P.valid[u] && xn == ST_E));
-                c2 += (uint32_t)__popcll(mI);
-                c3 += (uint32_t)__popcll(__ballot(P.valid[u] && xn == ST_R));
-            } else if (P.valid[u]) {
-                atomicAdd(&s_cnt[P.rep[u] * 4 + xn], 1u); // LDS
-            }
-        }
+    // passes: the loads of the next pass are issued (always: a pass past the
+    // end reads nothing) before the current pass is processed; two register
+    // sets, unrolled by two
+    Pass<age_t> P1;
+    const uint32_t stride = nwaves * CU;
+    for (;;) {
+        if (first >= nchunks) break;
+        if (PREFETCH) issue_pass<STORAGE, UNIFORM>(a, first + stride, nwaves, nchunks, total, lane, P1);
+        process_pass<STORAGE, WEIGHTED, RATES, MODE, UNIFORM>(a, P, lane, s_bits, gbits, s_xch[wave], k, bits_out,
+                                                              s_cnt, c0, c1, c2, c3);
+        first += stride;
+        if (first >= nchunks) break;
+        if (!PREFETCH) issue_pass<STORAGE, UNIFORM>(a, first, nwaves, nchunks, total, lane, P1);
+        if (PREFETCH) issue_pass<STORAGE, UNIFORM>(a, first + stride, nwaves, nchunks, total, lane, P);
+        process_pass<STORAGE, WEIGHTED, RATES, MODE, UNIFORM>(a, P1, lane, s_bits, gbits, s_xch[wave], k, bits_out,
+                                                              s_cnt, c0, c1, c2, c3);
+        first += stride;
+        if (!PREFETCH && first < nchunks) issue_pass<STORAGE, UNIFORM>(a, first, nwaves, nchunks, total, lane, P);
     }
 
     // one plain store of this workgroup's counts; the reduce kernel sums them
@@ -437,10 +559,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
     }
 }
 
-template <int STORAGE, bool WEIGHTED, bool RATES, int MODE, int TPB>
+template <int STORAGE, bool WEIGHTED, bool RATES, int MODE, bool UNIFORM, int TPB>
 __global__ __launch_bounds__(TPB) void step_kernel(StepArgs a)
 {
-    step_body<STORAGE, WEIGHTED, RATES, MODE, TPB>(a, blockIdx.x, gridDim.x);
+    step_body<STORAGE, WEIGHTED, RATES, MODE, UNIFORM, TPB>(a, blockIdx.x, gridDim.x);
 }
 
 // Index of the table entry that owns workgroup b: first[m] <= b < first[m + 1]
@@ -469,7 +591,8 @@ __global__ __launch_bounds__(STREAM_TPB) void step_batch_kernel(const StepArgs* 
     const uint32_t m = owner_of(first, members, blockIdx.x);
     StepArgs a = table[m];
     a.step_off = step_off;
-    step_body<STORAGE, WEIGHTED, RATES, MODE_STREAM, STREAM_TPB>(a, blockIdx.x - first[m], first[m + 1] - first[m]);
+    step_body<STORAGE, WEIGHTED, RATES, MODE_STREAM, false, STREAM_TPB>(a, blockIdx.x - first[m],
+                                                                        first[m + 1] - first[m]);
 }
 
 // Sums per-workgroup count partials.  Block j handles slot j: rows of C
@@ -712,14 +835,19 @@ __global__ void eval_philox_kernel(const uint4* ctr, uint32_t k0, uint32_t k1, u
 
 // ---------------------------------------------------------------- launchers
 
-const void* step_kernel_fn(int storage, bool weighted, bool rates, int mode)
+template <int S, bool W, bool RT, bool U>
+const void* step_kernel_sel(int mode)
+{
+    if (mode == MODE_RESIDENT) return (const void*)&step_kernel<S, W, RT, MODE_RESIDENT, U, RESIDENT_TPB>;
+    if (mode == MODE_SUMMARY) return (const void*)&step_kernel<S, W, RT, MODE_SUMMARY, U, RESIDENT_TPB>;
+    return (const void*)&step_kernel<S, W, RT, MODE_STREAM, U, STREAM_TPB>;
+}
+
+const void* step_kernel_fn(int storage, bool weighted, bool rates, int mode, bool uniform)
 {
 #define FS_SEL(S, W, RT)                                                                         \
-    if (storage == S && weighted == W && rates == RT) {                                          \
-        if (mode == MODE_RESIDENT) return (const void*)&step_kernel<S, W, RT, MODE_RESIDENT, RESIDENT_TPB>; \
-        if (mode == MODE_SUMMARY) return (const void*)&step_kernel<S, W, RT, MODE_SUMMARY, RESIDENT_TPB>;   \
-        return (const void*)&step_kernel<S, W, RT, MODE_STREAM, STREAM_TPB>;                     \
-    }
+    if (storage == S && weighted == W && rates == RT)                                            \
+        return uniform ? step_kernel_sel<S, W, RT, true>(mode) : step_kernel_sel<S, W, RT, false>(mode);
     FS_SEL(0, false, false) FS_SEL(0, false, true) FS_SEL(0, true, false) FS_SEL(0, true, true)
     FS_SEL(1, false, false) FS_SEL(1, false, true) FS_SEL(1, true, false) FS_SEL(1, true, true)
 #undef FS_SEL

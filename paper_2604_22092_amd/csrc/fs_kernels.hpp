@@ -12,7 +12,8 @@ namespace fsk {
 // (launched with one StepArgs argument); mode is fsi::MODE_*: the LDS
 // variants run RESIDENT_TPB threads, one workgroup per compute unit, the
 // streaming variant STREAM_TPB threads per workgroup.
-const void* step_kernel_fn(int storage, bool weighted, bool rates, int mode);
+// uniform selects the instantiation for layouts with StepArgs::udeg >= 0.
+const void* step_kernel_fn(int storage, bool weighted, bool rates, int mode, bool uniform);
 
 // Exact counts of one replica: per-workgroup partials (at most max_grid rows
 // of 4 in `part`) reduced into out4.

@@ -155,8 +155,7 @@ Layout::~Layout()
     dev_free(d_heavy_first);
     dev_free(d_segs);
     dev_free(d_ldeg);
-    dev_free(d_chunk_base);
-    dev_free(d_chunk_deg);
+    dev_free(d_chunk_meta);
     dev_free(d_col_t);
     dev_free(d_w_t);
 }
@@ -186,6 +185,14 @@ fs_status build_layout(const fs_graph* g, int32_t R, int32_t limit, int32_t seg_
     // wavefront-transposed light layout: Q nodes per 64-unit chunk
     const int64_t Q = 64 / R;
     const int64_t nch = (n + Q - 1) / Q;
+    // uniform graph: no heavy row and one light degree <= UNIFORM_MAX_DEG; the
+    // last chunk's missing rows are then padded with column 0 (their lanes
+    // are past the last unit and never use them)
+    int32_t ud_all = segs.empty() && n > 0 ? (int32_t)ldeg[0] : -1;
+    for (int64_t i = 0; i < n && ud_all >= 0; ++i)
+        if ((int32_t)ldeg[i] != ud_all) ud_all = -1;
+    if (ud_all > fsi::UNIFORM_MAX_DEG) ud_all = -1;
+    L->udeg = ud_all;
     std::vector<uint32_t> cbase((size_t)nch + 1);
     std::vector<int32_t> colt;
     std::vector<float> wt;
@@ -202,6 +209,15 @@ fs_status build_layout(const fs_graph* g, int32_t R, int32_t limit, int32_t seg_
             same = same && ldeg[i] != fsi::HEAVY_ROW && ldeg[i] == ldeg[n0];
         }
         cdeg[c] = (same && ldeg[n0] < 255) ? (uint8_t)ldeg[n0] : (uint8_t)255;
+        if (ud_all >= 0 && n1 - n0 < Q) {
+            cdeg[c] = (uint8_t)ud_all;
+            for (int32_t j = 0; j < ud_all; ++j)
+                for (int64_t i = n0; i < n0 + Q; ++i) colt.push_back(i < n1 ? g->h_col_ind[rp[i] + j] : 0);
+            if (weighted)
+                for (int32_t j = 0; j < ud_all; ++j)
+                    for (int64_t i = n0; i < n0 + Q; ++i) wt.push_back(i < n1 ? g->h_weights[rp[i] + j] : 0.0f);
+            continue;
+        }
         if (same) {
             // every row has the same light degree: slot j of row q at j*Q + q
             const int32_t d = ldeg[n0];
@@ -228,12 +244,12 @@ fs_status build_layout(const fs_graph* g, int32_t R, int32_t limit, int32_t seg_
         FS_HIP(hipMemcpy(L->d_segs, segs.data(), segs.size() * sizeof(fsi::Segment), hipMemcpyHostToDevice));
     }
     FS_HIP(dev_alloc((void**)&L->d_ldeg, ldeg.size() * sizeof(uint16_t)));
-    FS_HIP(dev_alloc((void**)&L->d_chunk_base, cbase.size() * sizeof(uint32_t)));
-    FS_HIP(dev_alloc((void**)&L->d_chunk_deg, cdeg.size()));
+    std::vector<uint2> meta(cbase.size());
+    for (size_t c = 0; c < cbase.size(); ++c) meta[c] = make_uint2(cbase[c], c < cdeg.size() ? cdeg[c] : 255u);
+    FS_HIP(dev_alloc((void**)&L->d_chunk_meta, meta.size() * sizeof(uint2)));
     FS_HIP(dev_alloc((void**)&L->d_col_t, colt.size() * sizeof(int32_t)));
-    FS_HIP(hipMemcpy(L->d_chunk_deg, cdeg.data(), cdeg.size(), hipMemcpyHostToDevice));
+    FS_HIP(hipMemcpy(L->d_chunk_meta, meta.data(), meta.size() * sizeof(uint2), hipMemcpyHostToDevice));
     FS_HIP(hipMemcpy(L->d_ldeg, ldeg.data(), ldeg.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
-    FS_HIP(hipMemcpy(L->d_chunk_base, cbase.data(), cbase.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     if (!colt.empty())
         FS_HIP(hipMemcpy(L->d_col_t, colt.data(), colt.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     if (weighted) {
@@ -322,8 +338,9 @@ fs_status apply_bins(fs_sim* s, int32_t heavy_deg, int32_t seg_edges)
     s->args.heavy_deg = limit;
     s->args.seg_edges = seg_edges;
     s->args.ldeg = L->d_ldeg;
-    s->args.chunk_base = L->d_chunk_base;
-    s->args.chunk_deg = L->d_chunk_deg;
+    s->args.chunk_meta = L->d_chunk_meta;
+    s->args.udeg = L->udeg;
+    s->kfn = fsk::step_kernel_fn(s->storage, g->d_weights != nullptr, s->d_rates != nullptr, s->mode, L->udeg >= 0);
     s->args.col_t = L->d_col_t;
     s->args.w_t = L->d_w_t;
     return FS_OK;
@@ -700,7 +717,7 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
     a.dt = (float)p->dt;
     a.key0 = (uint32_t)p->seed;
     a.key1 = (uint32_t)(p->seed >> 32);
-    s->kfn = fsk::step_kernel_fn(s->storage, g->d_weights != nullptr, p->record_rates != 0, s->mode);
+    s->kfn = fsk::step_kernel_fn(s->storage, g->d_weights != nullptr, p->record_rates != 0, s->mode, false);
     s->hfn = fsk::heavy_kernel_fn(g->d_weights != nullptr);
     if (!s->kfn || !s->hfn) {
         release_sim(s);
@@ -747,8 +764,10 @@ fs_status fs_sim_seed(fs_sim* s, int32_t replica, int64_t count, const int64_t* 
     for (int64_t j = 0; j < count; ++j)
         if (nodes[j] < 0 || nodes[j] >= s->g->n) return fail(FS_ERR_INVALID_ARG, "seed node out of range");
     DeviceGuard dg(s->device);
-    DevBuf tmp;
-    FS_HIP(dev_alloc(&tmp.p, sizeof(int64_t) * (size_t)count));
+    // stream-ordered staging buffer: allocating and freeing it does not wait
+    // for work queued on other streams
+    StreamBuf tmp(s->stream);
+    FS_HIP(hipMallocAsync(&tmp.p, sizeof(int64_t) * (size_t)count, s->stream));
     FS_HIP(hipMemcpyAsync(tmp.p, nodes, sizeof(int64_t) * (size_t)count, hipMemcpyHostToDevice, s->stream));
     FS_HIP(fsk::launch_seed(s->storage, s->d_state, s->d_age, (const int64_t*)tmp.p, count, s->lgR, replica,
                             compartment, s->stream));

@@ -31,11 +31,11 @@ struct Layout {
     int32_t limit = 0;           // rows with more edges than this are heavy
     int32_t seg_edges = 0;
     uint32_t nseg = 0;           // heavy-row segments
+    int32_t udeg = -1;           // the uniform light degree of every chunk, or -1
     int32_t* d_heavy_first = nullptr;
     fsi::Segment* d_segs = nullptr;
     uint16_t* d_ldeg = nullptr;       // light degree per node, HEAVY_ROW for binned rows
-    uint32_t* d_chunk_base = nullptr; // wavefront-transposed layout of the light rows
-    uint8_t* d_chunk_deg = nullptr;
+    uint2* d_chunk_meta = nullptr;    // per chunk: (first slot in col_t, shared degree or 255)
     int32_t* d_col_t = nullptr;
     float* d_w_t = nullptr;
     size_t bytes = 0;
@@ -141,6 +141,17 @@ void dev_free(void* p);
 struct DevBuf {
     void* p = nullptr;
     ~DevBuf() { dev_free(p); }
+};
+
+// RAII stream-ordered temporary (hipMallocAsync on `s`), freed in stream order.
+struct StreamBuf {
+    void* p = nullptr;
+    hipStream_t s;
+    explicit StreamBuf(hipStream_t st) : s(st) {}
+    ~StreamBuf()
+    {
+        if (p) (void)hipFreeAsync(p, s);
+    }
 };
 
 size_t state_bytes(int storage);
