@@ -136,18 +136,29 @@ typedef struct fs_sim_params {
     int32_t steps_per_graph; /* b: steps per captured hipGraph replay; 0 = launch eagerly */
     int32_t history_len;     /* per-step count ring length (>= 2); 0 = 1024 */
     int32_t record_rates;    /* nonzero: keep each unit's rate lambda of the last step */
-    int32_t variant;         /* step kernel: 0 = automatic (resident when n * n_replicas
-                                <= 2^20, else summary), 1 = streaming (bitmap read
-                                through the caches), 2 = resident (bitmap held in LDS;
-                                n * n_replicas <= 2^20), 3 = summary (an LDS summary with
-                                one bit per group of units screens the bitmap reads).
-                                Results are identical. */
+    int32_t variant;         /* step kernel: 1 = streaming (bitmap read through the
+                                caches), 2 = resident (bitmap held in LDS; n * n_replicas
+                                <= 2^20), 3 = summary (an LDS summary with one bit per
+                                group of units screens the bitmap reads), 0 = automatic:
+                                resident when it fits, else summary for adaptive steps,
+                                bitmaps over 8 MB, or uniform-degree graphs with at most
+                                4 replicas, else streaming.  Results are identical. */
     int32_t heavy_degree;    /* degree bins: rows with more incoming edges than this get
                                 their pressure from the heavy-row kernel (segments of
                                 segment_edges edges, one wavefront each); 0 = 64,
                                 -1 = no bins.  Results are identical for unit weights. */
     int32_t segment_edges;   /* edges per heavy-row segment, in [64, 2^20]; 0 = 512 */
     void* stream;            /* hipStream_t to run on; NULL = a stream owned by the sim */
+    int32_t adaptive;        /* nonzero: adaptive step size (Section "Bernoulli tau-leaping",
+                                adaptive step selection; the tau update of Algorithm 3):
+                                step k+1 uses min(dt, epsilon / (max_i lambda_i + delta))
+                                with the maximum over step k's rates of all units of all
+                                replicas; dt is the cap, used by the first step after
+                                creation or a state load.  FP32 storage only, variants
+                                0/2/3 only, not in batches. */
+    int32_t pad;
+    double epsilon;          /* adaptive: bound on lambda * dt per step, > 0 */
+    double delta;            /* adaptive: added to the largest rate, >= 0 */
 } fs_sim_params;
 
 /*
@@ -201,6 +212,12 @@ fs_status fs_counts(fs_sim* s, int32_t replica, int64_t out[4]);
  *   out: n x 4 int64, row-major.  Synchronises.
  */
 fs_status fs_history(fs_sim* s, int32_t replica, int64_t first_step, int64_t n, int64_t* out);
+
+/* Step sizes (days) of steps first_step .. first_step + n - 1, into out[n]
+ * (host).  Fixed-step sims return dt for every step; adaptive ones the step
+ * each step used, within the same window of recorded steps as fs_history
+ * (FS_ERR_INVALID_ARG outside it).  Synchronises the sim's stream. */
+fs_status fs_step_sizes(fs_sim* s, int64_t first_step, int64_t n, double* out);
 
 /*
  * Copies one replica's state out (synchronises).

@@ -110,6 +110,11 @@ def _declare(L):
                                 _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P]
     L.or_run.argtypes = [_I64, _P, _P, _P, ctypes.POINTER(Params), _U64, _I64, _U32, _P, _P,
                          _P, _P, _P]
+    L.or_next_dt.argtypes = [ctypes.c_double] * 4
+    L.or_next_dt.restype = ctypes.c_double
+    L.or_run_adaptive.argtypes = [_I64, _P, _P, _P, ctypes.POINTER(Params), ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, _U64, _I64, _U32, _P, _P, _P,
+                                  _P, _P]
     L.gx_run.argtypes = [_I64, _P, _P, _P, ctypes.POINTER(Dist), ctypes.POINTER(Dist),
                          ctypes.c_double, ctypes.c_double, _P, _U64, _P, _P, _I64, _P, _P]
     L.gx_run.restype = _I64
@@ -249,6 +254,29 @@ def run(graph, model: dict, state, age, n_steps: int, step0: int = 0, replica: i
     lib().or_run(n, _ptr(rp), _ptr(ci), _ptr(w), ctypes.byref(p), int(step0), int(n_steps),
                  int(replica), _ptr(st), _ptr(ad), _ptr(ag), _ptr(scratch), _ptr(hist))
     return st, (ag if compact else ad), hist
+
+
+def next_dt(lam_max: float, eps: float, dt_max: float, delta: float = 0.0) -> float:
+    """The adaptive step after a step whose largest rate was lam_max."""
+    return lib().or_next_dt(float(lam_max), float(eps), float(dt_max), float(delta))
+
+
+def run_adaptive(graph, model: dict, state, age, n_steps: int, eps: float, dt_max: float,
+                 delta: float = 0.0, step0: int = 0, replica: int = 0):
+    """An adaptive-step trajectory (ages in days; model["dt"] is ignored):
+    returns (state, age, history[n_steps, 4], dts[n_steps])."""
+    rp, ci, w = _graph(graph)
+    n = len(rp) - 1
+    st = np.array(state, dtype=np.int32, copy=True)
+    p = make_params(dict(model, dt=dt_max), AGE_DAYS_F32)
+    ad = np.array(age, dtype=np.float32, copy=True)
+    scratch = np.empty(3 * n, dtype=np.float64)
+    hist = np.zeros((n_steps, 4), dtype=np.int64)
+    dts = np.zeros(n_steps, dtype=np.float64)
+    lib().or_run_adaptive(n, _ptr(rp), _ptr(ci), _ptr(w), ctypes.byref(p), float(eps), float(dt_max),
+                          float(delta), int(step0), int(n_steps), int(replica), _ptr(st), _ptr(ad),
+                          _ptr(scratch), _ptr(hist), _ptr(dts))
+    return st, ad, hist, dts
 
 
 # ----------------------------------------------------------- exact simulation

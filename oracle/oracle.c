@@ -371,3 +371,50 @@ void or_run(int64_t n, const int32_t* row_ptr, const int32_t* col_ind, const flo
         double* t = cur; cur = nxt; nxt = t;
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Adaptive step size (Section "Bernoulli tau-leaping", adaptive step        */
+/* selection; the tau update that closes each fused step of Algorithm 3).    */
+/* ------------------------------------------------------------------------ */
+
+/* The step that follows a step whose largest rate over all nodes was
+ * lam_max: min(dt_max, eps / (lam_max + delta)).  With lam_max + delta = 0
+ * the quotient is +inf and the cap applies. */
+double or_next_dt(double lam_max, double eps, double dt_max, double delta)
+{
+    double d = eps / (lam_max + delta);
+    return d < dt_max ? d : dt_max;
+}
+
+/*
+ * An adaptive trajectory of n_steps steps for one replica (ages in days):
+ * the first step uses dt_max; every later step uses or_next_dt of the
+ * largest rate lambda_i of the step before it, over all nodes.  dts
+ * (n_steps, may be NULL) receives the step sizes used, history (n_steps x 4,
+ * may be NULL) the counts.  scratch must hold 3*n doubles.  p->dt is ignored.
+ */
+void or_run_adaptive(int64_t n, const int32_t* row_ptr, const int32_t* col_ind, const float* weights,
+                     const or_params* p, double eps, double dt_max, double delta, uint64_t step0,
+                     int64_t n_steps, uint32_t replica, int32_t* state, float* age_days, double* scratch,
+                     int64_t* history, double* dts)
+{
+    double* cur = scratch;
+    double* nxt = scratch + n;
+    double* lam = scratch + 2 * n;
+    or_params q = *p;
+    q.age_mode = OR_AGE_DAYS_F32;
+    q.dt = dt_max;
+    for (int64_t i = 0; i < n; ++i) cur[i] = (state[i] == OR_I) ? 1.0 : 0.0;
+    int64_t counts[4];
+    for (int64_t s = 0; s < n_steps; ++s) {
+        or_step(n, row_ptr, col_ind, weights, &q, step0 + (uint64_t)s, replica, state, age_days, NULL,
+                cur, nxt, counts, lam, NULL, NULL);
+        if (history) memcpy(history + 4 * s, counts, sizeof counts);
+        if (dts) dts[s] = q.dt;
+        double lam_max = 0.0;
+        for (int64_t i = 0; i < n; ++i)
+            if (lam[i] > lam_max) lam_max = lam[i];
+        q.dt = or_next_dt(lam_max, eps, dt_max, delta);
+        double* t = cur; cur = nxt; nxt = t;
+    }
+}

@@ -31,7 +31,7 @@ EXPORTS = [
     "fs_graph_get_info", "fs_sim_create", "fs_sim_destroy", "fs_sim_seed", "fs_step",
     "fs_sync", "fs_step_index", "fs_counts", "fs_history", "fs_get_state", "fs_set_state",
     "fs_get_rates", "fs_eval_hazard", "fs_eval_philox", "fs_version", "fs_sim_set_bins",
-    "fs_sim_get_bins", "fs_sim_tune",
+    "fs_sim_get_bins", "fs_sim_tune", "fs_step_sizes",
     "fs_batch_create", "fs_batch_destroy", "fs_batch_add", "fs_batch_remove", "fs_batch_size",
     "fs_batch_step", "fs_batch_sync",
     "fs_server_create", "fs_server_submit", "fs_server_wait", "fs_server_result",
@@ -62,7 +62,8 @@ class fs_sim_params(ctypes.Structure):
                 ("steps_per_graph", ctypes.c_int32), ("history_len", ctypes.c_int32),
                 ("record_rates", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("heavy_degree", ctypes.c_int32), ("segment_edges", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("adaptive", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("epsilon", ctypes.c_double), ("delta", ctypes.c_double)]
 
 
 class fs_server_params(ctypes.Structure):
@@ -122,6 +123,7 @@ def _declare(L):
         "fs_step_index": ([P, ctypes.POINTER(ctypes.c_int64)], I32),
         "fs_counts": ([P, I32, P], I32),
         "fs_history": ([P, I32, I64, I64, P], I32),
+        "fs_step_sizes": ([P, I64, I64, P], I32),
         "fs_get_state": ([P, I32, P, P, P, ctypes.POINTER(ctypes.c_int64)], I32),
         "fs_set_state": ([P, I32, P, P, P, I64], I32),
         "fs_get_rates": ([P, I32, P], I32),
@@ -243,6 +245,12 @@ def fs_history(h, replica: int, first_step: int, n: int) -> np.ndarray:
     return out
 
 
+def fs_step_sizes(h, first_step: int, n: int) -> np.ndarray:
+    out = np.zeros(n, dtype=np.float64)
+    _check(lib().fs_step_sizes(h, int(first_step), int(n), _ptr(out)), "fs_step_sizes")
+    return out
+
+
 def fs_get_state(h, replica: int, n: int, storage: int):
     st = np.empty(n, dtype=np.int32)
     ad = np.empty(n, dtype=np.float32) if storage == FS_STORAGE_FP32 else None
@@ -328,7 +336,8 @@ class Graph:
 def make_params(ei, ir, beta: float, dt: float, seed: int = 0, replicas: int = 1,
                 storage: int = FS_STORAGE_FP32, steps_per_graph: int = 0, history_len: int = 0,
                 record_rates: bool = False, variant: int = 0, heavy_degree: int = 0,
-                segment_edges: int = 0, stream=None) -> fs_sim_params:
+                segment_edges: int = 0, stream=None, adaptive: bool = False,
+                epsilon: float = 0.03, delta: float = 0.0) -> fs_sim_params:
     p = fs_sim_params()
     p.ei = make_dist(ei)
     p.ir = make_dist(ir)
@@ -344,6 +353,9 @@ def make_params(ei, ir, beta: float, dt: float, seed: int = 0, replicas: int = 1
     p.heavy_degree = int(heavy_degree)
     p.segment_edges = int(segment_edges)
     p.stream = None if stream is None else ctypes.c_void_p(int(stream))
+    p.adaptive = 1 if adaptive else 0
+    p.epsilon = float(epsilon)
+    p.delta = float(delta)
     return p
 
 
@@ -353,9 +365,11 @@ class Sim:
     def __init__(self, graph: Graph, ei, ir, beta: float, dt: float, seed: int = 0,
                  replicas: int = 1, storage: int = FS_STORAGE_FP32, steps_per_graph: int = 0,
                  history_len: int = 0, record_rates: bool = False, variant: int = 0,
-                 heavy_degree: int = 0, segment_edges: int = 0, stream=None):
+                 heavy_degree: int = 0, segment_edges: int = 0, stream=None,
+                 adaptive: bool = False, epsilon: float = 0.03, delta: float = 0.0):
         p = make_params(ei, ir, beta, dt, seed, replicas, storage, steps_per_graph, history_len,
-                        record_rates, variant, heavy_degree, segment_edges, stream)
+                        record_rates, variant, heavy_degree, segment_edges, stream, adaptive,
+                        epsilon, delta)
         self.graph = graph
         self.n = graph.n
         self.replicas = int(replicas)
@@ -384,6 +398,9 @@ class Sim:
 
     def history(self, first_step: int, n: int, replica: int = 0) -> np.ndarray:
         return fs_history(self.handle, replica, first_step, n)
+
+    def step_sizes(self, first_step: int, n: int) -> np.ndarray:
+        return fs_step_sizes(self.handle, first_step, n)
 
     def get_state(self, replica: int = 0):
         return fs_get_state(self.handle, replica, self.n, self.storage)

@@ -7,15 +7,18 @@
 // launch per sequence.  Each member runs exactly the streaming step it would
 // run alone, so its results are the same alone and in the batch.
 //
-// The server keeps a queue of scenario requests and one batch.  A worker
-// thread admits queued requests while the memory budget and the slot limit
-// allow, runs the batch a few steps at a time, and retires the requests that
-// are done, so requests that arrive while others run join the next launch.
+// The server keeps a queue of scenario requests.  A worker thread runs
+// rounds of steps on one stream: large requests step alone with the kernel
+// variant that suits them, small ones share a batch.  While one round runs on
+// the device the worker admits queued requests (creating and seeding their
+// sims on a second stream) and retires the requests the previous round
+// finished, so the device always has the next round queued.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstring>
 #include <deque>
 #include <exception>
 #include <map>
@@ -30,6 +33,54 @@
 
 using namespace fsr;
 
+namespace {
+
+// Pinned host staging for asynchronous uploads: two buffers used in turn,
+// each reused only after the event of its last upload has completed.
+struct Staging {
+    void* host[2] = {nullptr, nullptr};
+    size_t cap[2] = {0, 0};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool used[2] = {false, false};
+    int cur = 0;
+    ~Staging()
+    {
+        for (int i = 0; i < 2; ++i) {
+            if (ev[i]) {
+                (void)hipEventSynchronize(ev[i]);
+                (void)hipEventDestroy(ev[i]);
+            }
+            if (host[i]) (void)hipHostFree(host[i]);
+        }
+    }
+    // A buffer of at least `bytes` whose previous upload has finished.
+    fs_status take(size_t bytes, void** out, int* slot)
+    {
+        const int i = cur;
+        cur ^= 1;
+        if (!ev[i]) FS_HIP(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+        if (used[i]) FS_HIP(hipEventSynchronize(ev[i]));
+        if (cap[i] < bytes) {
+            if (host[i]) (void)hipHostFree(host[i]);
+            host[i] = nullptr;
+            cap[i] = 0;
+            FS_HIP(hipHostMalloc(&host[i], std::max<size_t>(bytes, 4096), hipHostMallocDefault));
+            cap[i] = std::max<size_t>(bytes, 4096);
+        }
+        *out = host[i];
+        *slot = i;
+        return FS_OK;
+    }
+    fs_status mark(int slot, hipStream_t s)
+    {
+        FS_HIP(hipEventRecord(ev[slot], s));
+        used[slot] = true;
+        return FS_OK;
+    }
+};
+
+} // namespace
+
 struct fs_batch {
     int device = 0;
     int storage = 0;
@@ -39,22 +90,18 @@ struct fs_batch {
     bool own_stream = false;
     std::vector<fs_sim*> members;
     bool dirty = true;
-    // device tables, rebuilt when the membership changes
+    // device tables (one stream-ordered block), rebuilt when the membership changes
+    void* d_tables = nullptr;
+    size_t d_cap = 0;
     StepArgs* d_table = nullptr;
     uint32_t* d_first = nullptr;
     fsi::HeavyArgs* d_htable = nullptr;
     uint32_t* d_hfirst = nullptr;
     fsi::RedArgs* d_red = nullptr;
     fsi::Ctl** d_ctls = nullptr;
-    size_t cap = 0;
     uint32_t blocks = 0, hblocks = 0, hmembers = 0;
     uint32_t chunk = 0; // longest launch sequence (partial slots of the members)
-    // host copies of the tables (kept alive for the asynchronous uploads)
-    std::vector<StepArgs> h_table;
-    std::vector<uint32_t> h_first, h_hfirst;
-    std::vector<fsi::HeavyArgs> h_htable;
-    std::vector<fsi::RedArgs> h_red;
-    std::vector<fsi::Ctl*> h_ctls;
+    Staging staging;
 };
 
 namespace {
@@ -66,52 +113,28 @@ namespace {
     catch (const std::exception& e) { return fail(FS_ERR_DEVICE, e.what()); }                   \
     catch (...) { return fail(FS_ERR_DEVICE, "unknown exception"); }
 
-void free_tables(fs_batch* b)
-{
-    dev_free(b->d_table);
-    dev_free(b->d_first);
-    dev_free(b->d_htable);
-    dev_free(b->d_hfirst);
-    dev_free(b->d_red);
-    dev_free(b->d_ctls);
-    b->d_table = nullptr;
-    b->d_first = nullptr;
-    b->d_htable = nullptr;
-    b->d_hfirst = nullptr;
-    b->d_red = nullptr;
-    b->d_ctls = nullptr;
-    b->cap = 0;
-}
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Rebuilds the device tables from the current members: one staging buffer
+// holds every table and one asynchronous copy uploads it.  Work already
+// queued on the batch stream reads the tables it was launched with: the copy
+// is ordered after it, and a grown table block is a new allocation while the
+// old one is freed in stream order.
 fs_status rebuild_tables(fs_batch* b)
 {
     const size_t M = b->members.size();
-    // the previous uploads read the host copies: let them finish first
-    FS_HIP(hipStreamSynchronize(b->stream));
-    if (M > b->cap) {
-        free_tables(b);
-        const size_t cap = std::max<size_t>(M, 16);
-        FS_HIP(dev_alloc((void**)&b->d_table, cap * sizeof(StepArgs)));
-        FS_HIP(dev_alloc((void**)&b->d_first, (cap + 1) * sizeof(uint32_t)));
-        FS_HIP(dev_alloc((void**)&b->d_htable, cap * sizeof(fsi::HeavyArgs)));
-        FS_HIP(dev_alloc((void**)&b->d_hfirst, (cap + 1) * sizeof(uint32_t)));
-        FS_HIP(dev_alloc((void**)&b->d_red, cap * sizeof(fsi::RedArgs)));
-        FS_HIP(dev_alloc((void**)&b->d_ctls, cap * sizeof(fsi::Ctl*)));
-        b->cap = cap;
-    }
-    b->h_table.clear();
-    b->h_first.assign(1, 0u);
-    b->h_htable.clear();
-    b->h_hfirst.assign(1, 0u);
-    b->h_red.clear();
-    b->h_ctls.clear();
+    std::vector<StepArgs> table;
+    std::vector<uint32_t> first(1, 0u), hfirst(1, 0u);
+    std::vector<fsi::HeavyArgs> htable;
+    std::vector<fsi::RedArgs> red;
+    std::vector<fsi::Ctl*> ctls;
     b->chunk = 1u << 30;
     for (fs_sim* s : b->members) {
-        b->h_table.push_back(s->args);
-        b->h_first.push_back(b->h_first.back() + s->G);
+        table.push_back(s->args);
+        first.push_back(first.back() + s->G);
         if (s->nseg) {
-            b->h_htable.push_back(heavy_args(s));
-            b->h_hfirst.push_back(b->h_hfirst.back() + heavy_grid(s));
+            htable.push_back(heavy_args(s));
+            hfirst.push_back(hfirst.back() + heavy_grid(s));
         }
         fsi::RedArgs r{};
         r.ctl = s->d_ctl;
@@ -120,28 +143,64 @@ fs_status rebuild_tables(fs_batch* b)
         r.G = s->G;
         r.C = 4u * (uint32_t)s->R;
         r.H = (uint32_t)s->H;
-        b->h_red.push_back(r);
-        b->h_ctls.push_back(s->d_ctl);
+        red.push_back(r);
+        ctls.push_back(s->d_ctl);
         b->chunk = std::min(b->chunk, s->chunk);
     }
-    b->blocks = b->h_first.back();
-    b->hblocks = b->h_hfirst.back();
-    b->hmembers = (uint32_t)b->h_htable.size();
-    if (M) {
-        FS_HIP(hipMemcpyAsync(b->d_table, b->h_table.data(), M * sizeof(StepArgs), hipMemcpyHostToDevice, b->stream));
-        FS_HIP(hipMemcpyAsync(b->d_first, b->h_first.data(), (M + 1) * sizeof(uint32_t), hipMemcpyHostToDevice,
-                              b->stream));
-        FS_HIP(hipMemcpyAsync(b->d_red, b->h_red.data(), M * sizeof(fsi::RedArgs), hipMemcpyHostToDevice, b->stream));
-        FS_HIP(hipMemcpyAsync(b->d_ctls, b->h_ctls.data(), M * sizeof(fsi::Ctl*), hipMemcpyHostToDevice, b->stream));
-        if (b->hmembers) {
-            FS_HIP(hipMemcpyAsync(b->d_htable, b->h_htable.data(), b->hmembers * sizeof(fsi::HeavyArgs),
-                                  hipMemcpyHostToDevice, b->stream));
-            FS_HIP(hipMemcpyAsync(b->d_hfirst, b->h_hfirst.data(), (b->hmembers + 1) * sizeof(uint32_t),
-                                  hipMemcpyHostToDevice, b->stream));
-        }
-    }
+    b->blocks = first.back();
+    b->hblocks = hfirst.back();
+    b->hmembers = (uint32_t)htable.size();
     b->dirty = false;
+    if (M == 0) return FS_OK;
+    const size_t o_table = 0;
+    const size_t o_first = align_up(o_table + M * sizeof(StepArgs));
+    const size_t o_htable = align_up(o_first + (M + 1) * sizeof(uint32_t));
+    const size_t o_hfirst = align_up(o_htable + std::max<size_t>(htable.size(), 1) * sizeof(fsi::HeavyArgs));
+    const size_t o_red = align_up(o_hfirst + hfirst.size() * sizeof(uint32_t));
+    const size_t o_ctls = align_up(o_red + M * sizeof(fsi::RedArgs));
+    const size_t bytes = align_up(o_ctls + M * sizeof(fsi::Ctl*));
+    void* host = nullptr;
+    int slot = 0;
+    fs_status st = b->staging.take(bytes, &host, &slot);
+    if (st != FS_OK) return st;
+    char* h = (char*)host;
+    std::memcpy(h + o_table, table.data(), M * sizeof(StepArgs));
+    std::memcpy(h + o_first, first.data(), first.size() * sizeof(uint32_t));
+    if (!htable.empty()) std::memcpy(h + o_htable, htable.data(), htable.size() * sizeof(fsi::HeavyArgs));
+    std::memcpy(h + o_hfirst, hfirst.data(), hfirst.size() * sizeof(uint32_t));
+    std::memcpy(h + o_red, red.data(), M * sizeof(fsi::RedArgs));
+    std::memcpy(h + o_ctls, ctls.data(), M * sizeof(fsi::Ctl*));
+    if (bytes > b->d_cap) {
+        if (b->d_tables) (void)hipFreeAsync(b->d_tables, b->stream);
+        b->d_tables = nullptr;
+        b->d_cap = 0;
+        FS_HIP(hipMallocAsync(&b->d_tables, bytes * 2, b->stream));
+        b->d_cap = bytes * 2;
+    }
+    char* d = (char*)b->d_tables;
+    FS_HIP(hipMemcpyAsync(d, host, bytes, hipMemcpyHostToDevice, b->stream));
+    if ((st = b->staging.mark(slot, b->stream)) != FS_OK) return st;
+    b->d_table = (StepArgs*)(d + o_table);
+    b->d_first = (uint32_t*)(d + o_first);
+    b->d_htable = (fsi::HeavyArgs*)(d + o_htable);
+    b->d_hfirst = (uint32_t*)(d + o_hfirst);
+    b->d_red = (fsi::RedArgs*)(d + o_red);
+    b->d_ctls = (fsi::Ctl**)(d + o_ctls);
     return FS_OK;
+}
+
+// Membership changes without waiting: the caller guarantees that queued
+// batch work never touches a sim after it leaves (the next launch uses
+// rebuilt tables) and that an added sim's own queued work is finished.
+void attach(fs_batch* b, fs_sim* s)
+{
+    b->weighted = s->g->d_weights != nullptr;
+    b->rates = s->d_rates != nullptr;
+    s->saved_stream = s->stream;
+    s->stream = b->stream;
+    s->batch = b;
+    b->members.push_back(s);
+    b->dirty = true;
 }
 
 void detach(fs_batch* b, fs_sim* s)
@@ -177,6 +236,25 @@ fs_status batch_sequence(fs_batch* b, uint32_t r)
     return FS_OK;
 }
 
+// Queues n_steps steps of every member (no host wait).
+fs_status batch_step(fs_batch* b, int64_t n_steps)
+{
+    if (n_steps <= 0 || b->members.empty()) return FS_OK;
+    if (b->dirty) {
+        fs_status st = rebuild_tables(b);
+        if (st != FS_OK) return st;
+    }
+    int64_t rem = n_steps;
+    while (rem > 0) {
+        const uint32_t r = (uint32_t)std::min<int64_t>(rem, b->chunk);
+        fs_status st = batch_sequence(b, r);
+        if (st != FS_OK) return st;
+        rem -= r;
+    }
+    for (fs_sim* s : b->members) s->step += n_steps;
+    return FS_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -208,9 +286,12 @@ fs_status fs_batch_destroy(fs_batch* b)
     DeviceGuard dg(b->device);
     const hipError_t e = hipStreamSynchronize(b->stream);
     while (!b->members.empty()) detach(b, b->members.back());
-    free_tables(b);
-    if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    if (b->d_tables) (void)hipFreeAsync(b->d_tables, b->stream);
+    (void)hipStreamSynchronize(b->stream);
+    const bool own = b->own_stream;
+    hipStream_t s = b->stream;
     delete b;
+    if (own) (void)hipStreamDestroy(s);
     if (e != hipSuccess) return fail(FS_ERR_DEVICE, std::string("pending work failed: ") + hipGetErrorString(e));
     return FS_OK;
     FS_GUARD_END
@@ -225,18 +306,13 @@ fs_status fs_batch_add(fs_batch* b, fs_sim* s)
     if (s->mode != fsi::MODE_STREAM)
         return fail(FS_ERR_INVALID_ARG, "batch members run the streaming step: create the sim with variant = 1");
     if (s->storage != b->storage) return fail(FS_ERR_INVALID_ARG, "sim storage differs from the batch's");
+    if (s->p.adaptive) return fail(FS_ERR_INVALID_ARG, "adaptive-step sims cannot join a batch");
     const int w = s->g->d_weights != nullptr, rt = s->d_rates != nullptr;
     if (!b->members.empty() && (w != b->weighted || rt != b->rates))
         return fail(FS_ERR_INVALID_ARG, "batch members must agree on weights and record_rates");
     DeviceGuard dg(b->device);
     FS_HIP(hipStreamSynchronize(s->stream));
-    b->weighted = w;
-    b->rates = rt;
-    s->saved_stream = s->stream;
-    s->stream = b->stream;
-    s->batch = b;
-    b->members.push_back(s);
-    b->dirty = true;
+    attach(b, s);
     return FS_OK;
     FS_GUARD_END
 }
@@ -265,21 +341,8 @@ fs_status fs_batch_step(fs_batch* b, int64_t n_steps)
     FS_GUARD_BEGIN
     if (!b) return fail(FS_ERR_INVALID_ARG, "batch is NULL");
     if (n_steps < 0) return fail(FS_ERR_INVALID_ARG, "n_steps < 0");
-    if (n_steps == 0 || b->members.empty()) return FS_OK;
     DeviceGuard dg(b->device);
-    if (b->dirty) {
-        fs_status st = rebuild_tables(b);
-        if (st != FS_OK) return st;
-    }
-    int64_t rem = n_steps;
-    while (rem > 0) {
-        const uint32_t r = (uint32_t)std::min<int64_t>(rem, b->chunk);
-        fs_status st = batch_sequence(b, r);
-        if (st != FS_OK) return st;
-        rem -= r;
-    }
-    for (fs_sim* s : b->members) s->step += n_steps;
-    return FS_OK;
+    return batch_step(b, n_steps);
     FS_GUARD_END
 }
 
@@ -303,6 +366,34 @@ double now_s()
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
+// Pinned host buffers for count histories, reused across requests (worker
+// thread only).
+struct PinnedPool {
+    std::vector<std::pair<void*, size_t>> free_list;
+    std::map<void*, size_t> size_of;
+    ~PinnedPool()
+    {
+        for (auto& f : size_of) (void)hipHostFree(f.first);
+    }
+    void* take(size_t bytes)
+    {
+        for (size_t i = 0; i < free_list.size(); ++i)
+            if (free_list[i].second >= bytes) {
+                void* p = free_list[i].first;
+                free_list.erase(free_list.begin() + (long)i);
+                return p;
+            }
+        void* p = nullptr;
+        if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+        size_of[p] = bytes;
+        return p;
+    }
+    void give(void* p)
+    {
+        if (p) free_list.push_back({p, size_of[p]});
+    }
+};
+
 struct Request {
     int64_t id = 0;
     fs_graph* g = nullptr;
@@ -311,10 +402,11 @@ struct Request {
     std::vector<int64_t> seeds;
     size_t bytes = 0;
     fs_sim* sim = nullptr;
-    bool solo = false;             // runs its own step kernels instead of joining the batch
-    int64_t done_steps = 0;
+    bool solo = false;               // runs its own step kernels instead of joining the batch
+    int64_t done_steps = 0;          // steps queued so far
+    uint32_t* pinned_hist = nullptr; // [n_steps][R][4] counts, copied after the last round
     fs_request_info info{};
-    std::vector<int64_t> history; // [n_steps][R][4]
+    std::vector<int64_t> history;    // [n_steps][R][4]
     std::string error;
     bool finished = false;
 };
@@ -332,13 +424,14 @@ struct fs_server {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<std::shared_ptr<Request>> queue;             // submitted, not admitted
-    std::vector<std::shared_ptr<Request>> active;           // on the device
+    std::vector<std::shared_ptr<Request>> active;           // stepping in the next round
     std::map<int64_t, std::shared_ptr<Request>> requests;   // every request not yet collected
     int64_t next_id = 1;
     bool stop = false;
     std::thread worker;
     std::string worker_error;
     uint64_t rounds = 0;
+    PinnedPool pinned;
 };
 
 namespace {
@@ -346,15 +439,15 @@ namespace {
 // Requests with at least this many units give every wavefront of the GPU a
 // chunk by themselves: they run their own step kernels (the variant that
 // suits their size) on the server stream.  Smaller ones share the batch's
-// fused launches.
+// fused launches.  At most MAX_SOLO large requests step at once (sharing the
+// GPU between more of them only lengthens each one's latency).
 constexpr size_t SOLO_UNITS = (size_t)1 << 18;
+constexpr int MAX_SOLO = 2;
 
 // Creates and seeds the sim of an admitted request on the admission stream,
-// while the current round runs (worker thread).  The sim joins the rounds
-// later (join_request).
+// while a round runs (worker thread, lock not held).
 fs_status start_request(fs_server* sv, Request& q)
 {
-    q.solo = (size_t)q.g->n * (size_t)q.p.n_replicas >= SOLO_UNITS;
     fs_sim_params p = q.p;
     p.storage = sv->p.storage;
     p.variant = q.solo ? 0 : 1;
@@ -366,48 +459,27 @@ fs_status start_request(fs_server* sv, Request& q)
     if (st != FS_OK) return st;
     if (!q.seeds.empty() && (st = fs_sim_seed(q.sim, -1, (int64_t)q.seeds.size(), q.seeds.data(), FS_E)) != FS_OK)
         return st;
+    q.pinned_hist = (uint32_t*)sv->pinned.take((size_t)q.n_steps * q.p.n_replicas * 4 * sizeof(uint32_t));
+    if (!q.pinned_hist) return fail(FS_ERR_OUT_OF_MEMORY, "pinned host buffer");
     return FS_OK;
 }
 
-// Moves a created sim onto the server stream (its setup on the admission
-// stream is complete: fs_sim_seed synchronised it) and, unless it runs solo,
-// into the batch.  Called between rounds.
-fs_status join_request(fs_server* sv, Request& q)
-{
-    q.sim->stream = sv->stream;
-    return q.solo ? FS_OK : fs_batch_add(sv->batch, q.sim);
-}
-
+// Releases a request's sim in stream order (no wait) and its pinned buffer.
 void drop_sim(fs_server* sv, Request& q)
 {
-    if (!q.sim) return;
-    if (q.sim->batch) (void)fs_batch_remove(sv->batch, q.sim);
-    (void)fs_sim_destroy(q.sim);
-    q.sim = nullptr;
-}
-
-// Copies a finished request's counts and releases its sim (worker thread,
-// between rounds).
-fs_status finish_request(fs_server* sv, Request& q)
-{
-    const int R = q.p.n_replicas;
-    fs_status st = q.sim->batch ? fs_batch_remove(sv->batch, q.sim) : FS_OK;
-    if (st == FS_OK) {
-        q.history.assign((size_t)q.n_steps * R * 4, 0);
-        std::vector<int64_t> one((size_t)q.n_steps * 4);
-        for (int r = 0; r < R && st == FS_OK; ++r) {
-            st = fs_history(q.sim, r, 0, q.n_steps, one.data());
-            for (int64_t k = 0; k < q.n_steps && st == FS_OK; ++k)
-                for (int c = 0; c < 4; ++c) q.history[((size_t)k * R + r) * 4 + c] = one[(size_t)k * 4 + c];
-        }
+    if (q.sim) {
+        if (q.sim->batch) detach(sv->batch, q.sim);
+        release_sim(q.sim);
+        q.sim = nullptr;
     }
-    drop_sim(sv, q);
-    return st;
+    if (q.pinned_hist) {
+        sv->pinned.give(q.pinned_hist);
+        q.pinned_hist = nullptr;
+    }
 }
-
 
 // Ends request q with status st (the lock is held).
-void end_request(fs_server* sv, Request& q, fs_status st, const std::string& err)
+void end_request(Request& q, fs_status st, const std::string& err)
 {
     q.info.status = st;
     if (st != FS_OK) q.error = err;
@@ -416,43 +488,96 @@ void end_request(fs_server* sv, Request& q, fs_status st, const std::string& err
     q.g->users.fetch_sub(1);
 }
 
-// The worker: each iteration launches one round of steps for the active
-// requests, admits queued requests while that round runs, waits for it,
-// retires the requests that are done and lets the new ones join.
+struct Round {
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+    std::vector<std::shared_ptr<Request>> ending; // requests whose last steps it holds
+};
+
+// The worker.  Each iteration: (1) requests admitted last time join the
+// active set; (2) one round of steps is queued for the active set, and the
+// count histories of the requests it finishes are queued for copying right
+// after it; (3) queued requests are admitted while that round runs; (4) the
+// previous round is waited for and its finished requests are retired.  The
+// device thus has a round queued while the host works.
 void worker_loop(fs_server* sv)
 {
     (void)hipSetDevice(sv->device);
-    std::unique_lock<std::mutex> lk(sv->mu);
+    Round rounds[2];
+    fs_status st = FS_OK;
+    std::string err;
+    for (auto& r : rounds)
+        if (hipEventCreateWithFlags(&r.ev, hipEventDisableTiming) != hipSuccess) {
+            r.ev = nullptr;
+            st = FS_ERR_DEVICE;
+            err = "event creation failed";
+        }
+    int cur = 0;
     std::vector<std::shared_ptr<Request>> joining;
-    while (true) {
-        if (sv->active.empty() && joining.empty()) {
+    std::unique_lock<std::mutex> lk(sv->mu);
+    while (st == FS_OK) {
+        Round& prev = rounds[cur ^ 1];
+        Round& now = rounds[cur];
+        if (sv->active.empty() && joining.empty() && !prev.pending) {
             if (sv->stop && sv->queue.empty()) break;
             sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
-            if (sv->queue.empty()) continue;
         }
-        // 1. launch one round: every active request advances by r steps,
-        //    r bounded by the request closest to its end
-        int64_t r = sv->p.steps_per_round;
-        for (auto& q : sv->active) r = std::min(r, q->n_steps - q->done_steps);
-        std::vector<std::shared_ptr<Request>> act = sv->active;
-        lk.unlock();
-        fs_status st = FS_OK;
-        std::string err;
-        if (!act.empty()) {
-            st = fs_batch_step(sv->batch, r);
+        // 1. join: admitted sims (their setup stream is synchronised) move to
+        //    the server stream, small ones into the batch
+        for (auto& q : joining) {
+            q->sim->stream = sv->stream;
+            if (!q->solo) attach(sv->batch, q->sim);
+            sv->active.push_back(q);
+        }
+        joining.clear();
+        // 2. queue one round
+        now.ending.clear();
+        now.pending = false;
+        if (!sv->active.empty()) {
+            int64_t r = sv->p.steps_per_round;
+            for (auto& q : sv->active) r = std::min(r, q->n_steps - q->done_steps);
+            std::vector<std::shared_ptr<Request>> act = sv->active;
+            lk.unlock();
+            st = batch_step(sv->batch, r);
             for (auto& q : act)
                 if (st == FS_OK && q->solo) st = fs_step(q->sim, r);
+            for (auto& q : act) {
+                if (st != FS_OK) break;
+                q->done_steps += r;
+                if (q->done_steps < q->n_steps) continue;
+                now.ending.push_back(q);
+                const size_t bytes = (size_t)q->n_steps * q->p.n_replicas * 4 * sizeof(uint32_t);
+                if (hipMemcpyAsync(q->pinned_hist, q->sim->d_hist, bytes, hipMemcpyDeviceToHost, sv->stream) !=
+                    hipSuccess)
+                    st = fail(FS_ERR_DEVICE, "history copy");
+                if (q->sim->batch) detach(sv->batch, q->sim); // the next round's tables leave it out
+            }
+            if (st == FS_OK && hipEventRecord(now.ev, sv->stream) != hipSuccess) st = fail(FS_ERR_DEVICE, "event record");
             if (st != FS_OK) err = g_err;
+            now.pending = st == FS_OK;
+            lk.lock();
+            for (auto& q : now.ending)
+                sv->active.erase(std::remove(sv->active.begin(), sv->active.end(), q), sv->active.end());
+            if (st != FS_OK) break;
         }
-        // 2. admissions (FIFO while the slot limit and the memory budget
-        //    allow), overlapped with the round on the device
-        lk.lock();
-        while (st == FS_OK && !sv->queue.empty() &&
-               (int)(sv->active.size() + joining.size()) < sv->p.max_active &&
-               (sv->active.empty() && joining.empty() ? true : sv->in_use + sv->queue.front()->bytes <= sv->budget)) {
-            std::shared_ptr<Request> q = sv->queue.front();
-            sv->queue.pop_front();
+        // 3. admissions while the round runs: arrival order, except that a
+        //    large request waiting for a solo slot does not hold back smaller
+        //    ones; within the slot limit and the memory budget
+        int solos = 0;
+        for (auto& q : sv->active) solos += q->solo ? 1 : 0;
+        for (auto it = sv->queue.begin(); it != sv->queue.end();) {
+            std::shared_ptr<Request> q = *it;
+            q->solo = (size_t)q->g->n * (size_t)q->p.n_replicas >= SOLO_UNITS;
+            const bool idle = sv->active.empty() && joining.empty() && !now.pending && !prev.pending;
+            if ((int)(sv->active.size() + joining.size()) >= sv->p.max_active) break;
+            if (!idle && sv->in_use + q->bytes > sv->budget) break;
+            if (q->solo && solos >= MAX_SOLO) {
+                ++it;
+                continue;
+            }
+            sv->queue.erase(it);
             sv->in_use += q->bytes;
+            solos += q->solo ? 1 : 0;
             lk.unlock();
             q->info.t_admit = now_s();
             const fs_status ast = start_request(sv, *q);
@@ -461,77 +586,73 @@ void worker_loop(fs_server* sv)
             lk.lock();
             if (ast != FS_OK) {
                 sv->in_use -= q->bytes;
-                end_request(sv, *q, ast, aerr);
+                solos -= q->solo ? 1 : 0;
+                end_request(*q, ast, aerr);
                 sv->cv_done.notify_all();
-                continue;
-            }
-            joining.push_back(q);
-        }
-        lk.unlock();
-        // 3. wait for the round
-        if (!act.empty() && st == FS_OK) {
-            st = fs_batch_sync(sv->batch);
-            if (st != FS_OK) err = g_err;
-        }
-        // 4. retire the requests that are done; 5. the new ones join
-        std::vector<std::shared_ptr<Request>> ended;
-        for (auto& q : act) {
-            q->done_steps += r;
-            if (st != FS_OK || q->done_steps >= q->n_steps) ended.push_back(q);
-        }
-        std::vector<fs_status> fst(ended.size(), st);
-        std::vector<std::string> ferr(ended.size(), err);
-        for (size_t i = 0; i < ended.size(); ++i) {
-            if (st == FS_OK) {
-                fst[i] = finish_request(sv, *ended[i]);
-                if (fst[i] != FS_OK) ferr[i] = g_err;
             } else {
-                drop_sim(sv, *ended[i]);
+                joining.push_back(q);
             }
-            ended[i]->info.t_done = now_s();
+            it = sv->queue.begin(); // the queue may have grown while unlocked
         }
-        std::vector<std::shared_ptr<Request>> joined, failed;
-        std::vector<std::string> jerr;
-        for (auto& q : joining) {
-            const fs_status jst = st == FS_OK ? join_request(sv, *q) : st;
-            if (jst == FS_OK) {
-                joined.push_back(q);
-            } else {
-                jerr.push_back(st == FS_OK ? g_err : err);
+        // 4. retire the previous round's finished requests
+        if (prev.pending) {
+            lk.unlock();
+            if (hipEventSynchronize(prev.ev) != hipSuccess) {
+                st = fail(FS_ERR_DEVICE, "round failed");
+                err = g_err;
+            }
+            for (auto& q : prev.ending) {
+                if (st == FS_OK) {
+                    const int R = q->p.n_replicas;
+                    q->history.assign((size_t)q->n_steps * R * 4, 0);
+                    for (size_t i = 0; i < q->history.size(); ++i) q->history[i] = q->pinned_hist[i];
+                }
                 drop_sim(sv, *q);
-                failed.push_back(q);
+                q->info.t_done = now_s();
             }
+            lk.lock();
+            ++sv->rounds;
+            for (auto& q : prev.ending) {
+                sv->in_use -= q->bytes;
+                end_request(*q, st, err);
+            }
+            if (!prev.ending.empty()) sv->cv_done.notify_all();
+            prev.ending.clear();
+            prev.pending = false;
         }
-        joining.clear();
+        cur ^= 1;
+    }
+    if (st != FS_OK) {
+        // a device failure ends every request and the server
+        sv->worker_error = err;
+        lk.unlock();
+        (void)hipStreamSynchronize(sv->stream);
         lk.lock();
-        ++sv->rounds;
-        for (size_t i = 0; i < ended.size(); ++i) {
-            sv->active.erase(std::remove(sv->active.begin(), sv->active.end(), ended[i]), sv->active.end());
-            sv->in_use -= ended[i]->bytes;
-            end_request(sv, *ended[i], fst[i], ferr[i]);
-        }
-        for (size_t i = 0; i < failed.size(); ++i) {
-            sv->in_use -= failed[i]->bytes;
-            end_request(sv, *failed[i], st == FS_OK ? FS_ERR_DEVICE : st, jerr[i]);
-        }
-        for (auto& q : joined) sv->active.push_back(q);
-        if (!ended.empty() || !failed.empty()) sv->cv_done.notify_all();
-        if (st != FS_OK) {
-            // a device failure ends every request and the server
-            sv->worker_error = err;
-            for (auto& q : sv->active) {
+        for (auto& r : rounds) {
+            for (auto& q : r.ending) {
                 drop_sim(sv, *q);
                 sv->in_use -= q->bytes;
-                end_request(sv, *q, st, err);
+                end_request(*q, st, err);
             }
-            sv->active.clear();
-            for (auto& q : sv->queue) end_request(sv, *q, st, err);
-            sv->queue.clear();
-            sv->stop = true;
-            sv->cv_done.notify_all();
-            break;
+            r.ending.clear();
         }
+        for (auto* list : {&sv->active, &joining}) {
+            for (auto& q : *list) {
+                drop_sim(sv, *q);
+                sv->in_use -= q->bytes;
+                end_request(*q, st, err);
+            }
+            list->clear();
+        }
+        for (auto& q : sv->queue) end_request(*q, st, err);
+        sv->queue.clear();
+        sv->stop = true;
+        sv->cv_done.notify_all();
     }
+    lk.unlock();
+    (void)hipStreamSynchronize(sv->stream);
+    for (auto& r : rounds)
+        if (r.ev) (void)hipEventDestroy(r.ev);
 }
 
 } // namespace
@@ -592,6 +713,8 @@ fs_status fs_server_submit(fs_server* sv, const fs_request* rq, int64_t* id)
     if (rq->n_steps < 1 || rq->n_steps > (1 << 20)) return fail(FS_ERR_INVALID_ARG, "n_steps must be in [1, 2^20]");
     if (rq->n_seeds < 0 || (rq->n_seeds > 0 && !rq->seeds)) return fail(FS_ERR_INVALID_ARG, "bad seed list");
     if (rq->graph->device != sv->device) return fail(FS_ERR_INVALID_ARG, "graph is on another device");
+    if (rq->params.n_replicas < 1 || rq->params.n_replicas > 64) return fail(FS_ERR_INVALID_ARG, "n_replicas out of range");
+    if (rq->params.adaptive) return fail(FS_ERR_INVALID_ARG, "the server runs fixed-step requests only");
     for (int64_t j = 0; j < rq->n_seeds; ++j)
         if (rq->seeds[j] < 0 || rq->seeds[j] >= rq->graph->n) return fail(FS_ERR_INVALID_ARG, "seed node out of range");
     auto q = std::make_shared<Request>();
@@ -672,7 +795,7 @@ fs_status fs_server_destroy(fs_server* sv)
     if (!sv) return fail(FS_ERR_INVALID_ARG, "server is NULL");
     {
         std::lock_guard<std::mutex> lk(sv->mu);
-        // queued requests are cancelled; active ones run to completion
+        // queued requests are cancelled; admitted ones run to completion
         for (auto& q : sv->queue) {
             q->info.status = FS_ERR_BUSY;
             q->error = "cancelled: server destroyed";
@@ -688,6 +811,7 @@ fs_status fs_server_destroy(fs_server* sv)
     {
         DeviceGuard dg(sv->device);
         (void)fs_batch_destroy(sv->batch);
+        (void)hipStreamSynchronize(sv->admit_stream);
         (void)hipStreamDestroy(sv->admit_stream);
         if (sv->own_stream) (void)hipStreamDestroy(sv->stream);
     }

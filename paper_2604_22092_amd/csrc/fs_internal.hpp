@@ -55,7 +55,7 @@ struct HazardDev {
 // arguments and no step kernel touches a shared counter.
 struct Ctl {
     unsigned long long step;
-    unsigned long long pad;
+    unsigned long long adapt_from; // adaptive step: the step that uses the cap (creation, state load)
 };
 
 // Kernel arguments of one fused step launch.
@@ -104,6 +104,15 @@ struct StepArgs {
     // MODE_SUMMARY: summary of the step's input bitmap, sum_bits bits
     const uint32_t* summary;
     uint32_t sum_bits;
+    // adaptive step size: dt is the cap; step k reads the per-workgroup rate
+    // maxima of step k-1 from lam_part[((k-1) & 1) * grid ..] and writes its
+    // own to lam_part[(k & 1) * grid ..]; block 0 records the step in
+    // dt_hist[k % hist_len]
+    int32_t adaptive;
+    float* lam_part;
+    float* dt_hist;
+    float eps, delta;
+    uint32_t hist_len;
     uint32_t pad1;
 };
 

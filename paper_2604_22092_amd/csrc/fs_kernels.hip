@@ -340,7 +340,7 @@ __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t
                                              const uint32_t* __restrict__ s_bits, rsrc_t gbits, uint32_t* xch,
                                              unsigned long long k, unsigned long long* __restrict__ bits_out,
                                              uint32_t* s_cnt, uint32_t& c0, uint32_t& c1, uint32_t& c2,
-                                             uint32_t& c3)
+                                             uint32_t& c3, float dt, float& lmax)
 {
     using state_t = typename Store<STORAGE>::state_t;
     const uint32_t R = 1u << a.lgR;
@@ -424,7 +424,7 @@ __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t
             fire[u] = false;
             if (need[u]) {
                 const float uu = (float)res[u] * 0x1p-24f;
-                const float qq = -expm1f(-lam[u] * a.dt);
+                const float qq = -expm1f(-lam[u] * dt);
                 fire[u] = uu < qq;
             }
         }
@@ -439,7 +439,8 @@ __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t
         BufIO<state_t>::st(make_rsrc((state_t*)a.state + u0, P.nvalid[u] * sizeof(state_t)),
                            fire[u] ? lane : OOB_ELEM, (uint32_t)xn);
         BufIO<age_t>::st(make_rsrc((age_t*)a.age + u0, P.nvalid[u] * sizeof(age_t)), lane,
-                         age_to_raw(fire[u] ? (age_t)0 : age_next(ag[u], a.dt)));
+                         age_to_raw(fire[u] ? (age_t)0 : age_next(ag[u], dt)));
+        lmax = fmaxf(lmax, lam[u]);
         if (RATES) st32(make_rsrc(a.rates + u0, P.nvalid[u] * 4u), lane << 2, __float_as_uint(lam[u]));
         // 7. next-step infectivity bits (one 64-bit word per chunk, written by
         // lanes 0 and 1) and 8. counts
@@ -491,6 +492,17 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
     const uint32_t nchunks = (total + 63) >> 6;
     // the input bitmap: whole 512-unit tiles of 64 bytes
     const rsrc_t gbits = make_rsrc(bits_in, ((total + 511u) >> 9) << 6);
+    // this step's size: fixed, or (adaptive) from the largest rate of the
+    // previous step, folded by every wave from the per-workgroup maxima
+    float dt = a.dt;
+    if (a.adaptive && k != a.ctl->adapt_from) {
+        const float* prev = a.lam_part + (size_t)((k - 1) & 1) * nblocks;
+        float m = 0.0f;
+        for (uint32_t i = lane; i < nblocks; i += 64) m = fmaxf(m, prev[i]);
+        for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+        dt = fminf(a.dt, a.eps / (m + a.delta));
+    }
+    float lmax = 0.0f;
     const uint32_t wave_id = block * NW + wave;
     const uint32_t nwaves = nblocks * NW;
 
@@ -526,13 +538,13 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
         if (first >= nchunks) break;
         if (PREFETCH) issue_pass<STORAGE, UNIFORM>(a, first + stride, nwaves, nchunks, total, lane, P1);
         process_pass<STORAGE, WEIGHTED, RATES, MODE, UNIFORM>(a, P, lane, s_bits, gbits, s_xch[wave], k, bits_out,
-                                                              s_cnt, c0, c1, c2, c3);
+                                                              s_cnt, c0, c1, c2, c3, dt, lmax);
         first += stride;
         if (first >= nchunks) break;
         if (!PREFETCH) issue_pass<STORAGE, UNIFORM>(a, first, nwaves, nchunks, total, lane, P1);
         if (PREFETCH) issue_pass<STORAGE, UNIFORM>(a, first + stride, nwaves, nchunks, total, lane, P);
         process_pass<STORAGE, WEIGHTED, RATES, MODE, UNIFORM>(a, P1, lane, s_bits, gbits, s_xch[wave], k, bits_out,
-                                                              s_cnt, c0, c1, c2, c3);
+                                                              s_cnt, c0, c1, c2, c3, dt, lmax);
         first += stride;
         if (!PREFETCH && first < nchunks) issue_pass<STORAGE, UNIFORM>(a, first, nwaves, nchunks, total, lane, P);
     }
@@ -556,6 +568,21 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
     } else {
         __syncthreads();
         for (uint32_t i = tid; i < 4 * R; i += TPB) out[i] = s_cnt[i];
+    }
+    if (a.adaptive) {
+        // the workgroup's largest rate, for the next step's size; block 0
+        // records this step's size
+        __shared__ float s_lmax[NW];
+        for (int off = 32; off > 0; off >>= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, off, 64));
+        if (lane == 0) s_lmax[wave] = lmax;
+        __syncthreads();
+        if (tid == 0) {
+            float m = 0.0f;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) m = fmaxf(m, s_lmax[w]);
+            a.lam_part[(size_t)(k & 1) * nblocks + block] = m;
+            if (block == 0) a.dt_hist[k % a.hist_len] = dt;
+        }
     }
 }
 
@@ -815,7 +842,10 @@ __global__ void clear_u32_kernel(uint32_t* p, size_t n)
 
 __global__ void set_ctl_kernel(Ctl* ctl, unsigned long long step)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) ctl->step = step;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctl->step = step;
+        ctl->adapt_from = step;
+    }
 }
 
 __global__ void eval_hazard_kernel(HazardDev h, int32_t storage, const void* ages, float* out, int64_t n)

@@ -37,6 +37,35 @@ void dev_free(void* p)
     if (p) (void)hipFree(p);
 }
 
+// Per-sim buffers are stream-ordered allocations on the sim's stream: making
+// and releasing a sim never waits for work queued on other streams.  The
+// device's default pool keeps freed memory for reuse.
+void keep_pool(int device)
+{
+    static std::mutex mu;
+    static std::vector<int> done;
+    std::lock_guard<std::mutex> lk(mu);
+    if (std::find(done.begin(), done.end(), device) != done.end()) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    done.push_back(device);
+}
+
+hipError_t sim_alloc(fs_sim* s, void** p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    return hipMallocAsync(p, bytes, s->stream);
+}
+
+void sim_free(fs_sim* s, void* p)
+{
+    if (p) (void)hipFreeAsync(p, s->stream);
+}
+
 
 void split(double v, float& hi, float& lo)
 {
@@ -93,18 +122,12 @@ void release_sim(fs_sim* s)
     if (s->graph) (void)hipGraphDestroy(s->graph);
     s->exec = nullptr;
     s->graph = nullptr;
-    dev_free(s->d_state);
-    dev_free(s->d_age);
-    dev_free(s->d_iota[0]);
-    dev_free(s->d_iota[1]);
-    dev_free(s->d_rates);
-    dev_free(s->d_ctl);
-    dev_free(s->d_hist);
-    dev_free(s->d_part);
-    dev_free(s->d_rc_part);
-    dev_free(s->d_cnt4);
-    dev_free(s->d_summary);
-    dev_free(s->d_seg_part);
+    if (s->stream) {
+        for (void* p : {s->d_state, s->d_age, s->d_iota[0], s->d_iota[1], (void*)s->d_rates, (void*)s->d_ctl,
+                        (void*)s->d_hist, (void*)s->d_part, (void*)s->d_rc_part, (void*)s->d_cnt4,
+                        (void*)s->d_summary, s->d_seg_part, (void*)s->d_lam_part, (void*)s->d_dt_hist})
+            sim_free(s, p);
+    }
     s->layout.reset();
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     if (s->g) s->g->users.fetch_sub(1);
@@ -318,7 +341,7 @@ fs_status apply_bins(fs_sim* s, int32_t heavy_deg, int32_t seg_edges)
         }
     }
     drop_graph_exec(s);
-    dev_free(s->d_seg_part);
+    sim_free(s, s->d_seg_part);
     s->d_seg_part = nullptr;
     s->layout = L;
     {
@@ -332,7 +355,7 @@ fs_status apply_bins(fs_sim* s, int32_t heavy_deg, int32_t seg_edges)
     s->d_segs = L->d_segs;
     s->heavy_deg = heavy_deg;
     s->seg_edges = seg_edges;
-    if (s->nseg) FS_HIP(dev_alloc(&s->d_seg_part, (size_t)s->nseg * (size_t)s->R * sizeof(uint32_t)));
+    if (s->nseg) FS_HIP(sim_alloc(s, &s->d_seg_part, (size_t)s->nseg * (size_t)s->R * sizeof(uint32_t)));
     s->args.heavy_first = L->d_heavy_first;
     s->args.seg_part = s->d_seg_part;
     s->args.heavy_deg = limit;
@@ -516,12 +539,13 @@ fs_status fs_graph_create(int64_t n, const int32_t* row_ptr, const int32_t* col_
     if (n < 1 || n >= (int64_t)1 << 31) return fail(FS_ERR_INVALID_ARG, "n must satisfy 1 <= n < 2^31");
     if (!row_ptr) return fail(FS_ERR_INVALID_ARG, "row_ptr is NULL");
     if (row_ptr[0] != 0) return fail(FS_ERR_INVALID_CSR, "row_ptr[0] must be 0");
-    int32_t maxd = 0;
+    int32_t maxd = 0, mind = INT32_MAX;
     for (int64_t i = 0; i < n; ++i) {
         const int64_t d = (int64_t)row_ptr[i + 1] - (int64_t)row_ptr[i];
         if (d < 0)
             return fail(FS_ERR_INVALID_CSR, "row_ptr decreases at row " + std::to_string(i));
         if (d > maxd) maxd = (int32_t)d;
+        if (d < mind) mind = (int32_t)d;
     }
     const int64_t nnz = row_ptr[n];
     if (nnz > 0 && !col_ind) return fail(FS_ERR_INVALID_ARG, "col_ind is NULL");
@@ -535,6 +559,7 @@ fs_status fs_graph_create(int64_t n, const int32_t* row_ptr, const int32_t* col_
     g->n = n;
     g->nnz = nnz;
     g->max_degree = maxd;
+    g->min_degree = mind;
     g->mean_degree = (double)nnz / (double)n;
     g->h_row_ptr.assign(row_ptr, row_ptr + n + 1);
     if (nnz) g->h_col_ind.assign(col_ind, col_ind + nnz);
@@ -607,6 +632,15 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
     if (p->heavy_degree < -1) return fail(FS_ERR_INVALID_ARG, "heavy_degree must be -1, 0 or positive");
     if (p->segment_edges != 0 && (p->segment_edges < 64 || p->segment_edges > (1 << 20)))
         return fail(FS_ERR_INVALID_ARG, "segment_edges must be 0 or in [64, 2^20]");
+    if (p->adaptive) {
+        if (p->storage != FS_STORAGE_FP32)
+            return fail(FS_ERR_INVALID_ARG, "adaptive steps need FP32 storage (ages in days)");
+        if (p->variant == 1) return fail(FS_ERR_INVALID_ARG, "adaptive steps need variant 0, 2 or 3");
+        if (!(p->epsilon > 0.0) || !std::isfinite(p->epsilon))
+            return fail(FS_ERR_INVALID_ARG, "epsilon must be finite and > 0");
+        if (!(p->delta >= 0.0) || !std::isfinite(p->delta))
+            return fail(FS_ERR_INVALID_ARG, "delta must be finite and >= 0");
+    }
     HazardDev hz[2];
     fs_status st;
     if ((st = prep_hazard(p->ei, p->storage, p->dt, &hz[0], "ei")) != FS_OK) return st;
@@ -645,10 +679,18 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
         release_sim(s);
         return fail(FS_ERR_INVALID_ARG, "the resident variant holds at most 2^20 units (n * n_replicas)");
     }
+    // automatic choice (measured on MI355X): the LDS bitmap when it fits; else
+    // the LDS summary for adaptive steps, for bitmaps beyond 8 MB (the
+    // summary screens random reads that would miss the L2), and for
+    // uniform-degree graphs with at most 4 replicas; else the streaming
+    // variant, whose higher occupancy wins once replicas share bitmap words
+    const bool uniform = g->min_degree == g->max_degree && g->max_degree <= fsi::UNIFORM_MAX_DEG;
+    const bool summary_auto = p->adaptive || bitmap_words(units) * 8 > ((size_t)8 << 20) || (uniform && R <= 4);
     s->mode = p->variant == 1 ? fsi::MODE_STREAM
             : p->variant == 2 ? fsi::MODE_RESIDENT
             : p->variant == 3 ? fsi::MODE_SUMMARY
-            : (fits_lds ? fsi::MODE_RESIDENT : fsi::MODE_SUMMARY);
+            : fits_lds ? fsi::MODE_RESIDENT
+            : summary_auto ? fsi::MODE_SUMMARY : fsi::MODE_STREAM;
     s->lg_gran = 6;
     while (((units + ((size_t)1 << s->lg_gran) - 1) >> s->lg_gran) > fsi::SUMMARY_BITS) ++s->lg_gran;
     s->sum_bits = (uint32_t)((units + ((size_t)1 << s->lg_gran) - 1) >> s->lg_gran);
@@ -668,18 +710,21 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
     s->chunk = (uint32_t)std::max(p->steps_per_graph, 64);
     const size_t hist_words = (size_t)s->H * R * 4;
     const size_t part_words = (size_t)s->chunk * s->G * R * 4;
-    if ((e = dev_alloc(&s->d_state, units * state_bytes(s->storage))) != hipSuccess ||
-        (e = dev_alloc(&s->d_age, units * age_bytes(s->storage))) != hipSuccess ||
-        (e = dev_alloc(&s->d_iota[0], (size_t)s->bit_words * 8)) != hipSuccess ||
-        (e = dev_alloc(&s->d_iota[1], (size_t)s->bit_words * 8)) != hipSuccess ||
-        (p->record_rates && (e = dev_alloc((void**)&s->d_rates, units * sizeof(float))) != hipSuccess) ||
-        (e = dev_alloc((void**)&s->d_ctl, sizeof(fsi::Ctl))) != hipSuccess ||
-        (e = dev_alloc((void**)&s->d_hist, hist_words * sizeof(uint32_t))) != hipSuccess ||
-        (e = dev_alloc((void**)&s->d_part, part_words * sizeof(uint32_t))) != hipSuccess ||
-        (e = dev_alloc((void**)&s->d_rc_part, RC_GRID * 4 * sizeof(uint32_t))) != hipSuccess ||
-        (e = dev_alloc((void**)&s->d_cnt4, 4 * sizeof(uint32_t))) != hipSuccess ||
+    keep_pool(s->device);
+    if ((e = sim_alloc(s, &s->d_state, units * state_bytes(s->storage))) != hipSuccess ||
+        (e = sim_alloc(s, &s->d_age, units * age_bytes(s->storage))) != hipSuccess ||
+        (e = sim_alloc(s, &s->d_iota[0], (size_t)s->bit_words * 8)) != hipSuccess ||
+        (e = sim_alloc(s, &s->d_iota[1], (size_t)s->bit_words * 8)) != hipSuccess ||
+        (p->record_rates && (e = sim_alloc(s, (void**)&s->d_rates, units * sizeof(float))) != hipSuccess) ||
+        (e = sim_alloc(s, (void**)&s->d_ctl, sizeof(fsi::Ctl))) != hipSuccess ||
+        (e = sim_alloc(s, (void**)&s->d_hist, hist_words * sizeof(uint32_t))) != hipSuccess ||
+        (e = sim_alloc(s, (void**)&s->d_part, part_words * sizeof(uint32_t))) != hipSuccess ||
+        (e = sim_alloc(s, (void**)&s->d_rc_part, RC_GRID * 4 * sizeof(uint32_t))) != hipSuccess ||
+        (e = sim_alloc(s, (void**)&s->d_cnt4, 4 * sizeof(uint32_t))) != hipSuccess ||
         (s->mode == fsi::MODE_SUMMARY &&
-         (e = dev_alloc((void**)&s->d_summary, ((size_t)s->sum_bits + 511) / 512 * 64)) != hipSuccess))
+         (e = sim_alloc(s, (void**)&s->d_summary, ((size_t)s->sum_bits + 511) / 512 * 64)) != hipSuccess) ||
+        (p->adaptive && ((e = sim_alloc(s, (void**)&s->d_lam_part, 2 * (size_t)s->G * sizeof(float))) != hipSuccess ||
+                         (e = sim_alloc(s, (void**)&s->d_dt_hist, (size_t)s->H * sizeof(float))) != hipSuccess)))
         return bad(e, "device allocation");
     if ((e = hipMemsetAsync(s->d_state, 0, units * state_bytes(s->storage), s->stream)) != hipSuccess ||
         (e = hipMemsetAsync(s->d_age, 0, units * age_bytes(s->storage), s->stream)) != hipSuccess ||
@@ -708,6 +753,12 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
     a.lgR = s->lgR;
     a.step_off = 0;
     a.lg_gran = s->lg_gran;
+    a.adaptive = p->adaptive ? 1 : 0;
+    a.lam_part = s->d_lam_part;
+    a.dt_hist = s->d_dt_hist;
+    a.eps = (float)p->epsilon;
+    a.delta = (float)p->delta;
+    a.hist_len = (uint32_t)s->H;
     a.summary = (const uint32_t*)s->d_summary;
     a.sum_bits = s->sum_bits;
     a.same_kind = hz[0].kind == hz[1].kind;
@@ -865,6 +916,29 @@ fs_status fs_history(fs_sim* s, int32_t replica, int64_t first_step, int64_t n, 
     FS_GUARD_END
 }
 
+fs_status fs_step_sizes(fs_sim* s, int64_t first_step, int64_t n, double* out)
+{
+    FS_GUARD_BEGIN
+    if (!s || (n > 0 && !out)) return fail(FS_ERR_INVALID_ARG, "NULL argument");
+    if (n < 0) return fail(FS_ERR_INVALID_ARG, "n < 0");
+    if (n == 0) return FS_OK;
+    const int64_t lo = std::max(s->hist_from, s->step - (int64_t)s->H);
+    if (first_step < lo || first_step + n > s->step)
+        return fail(FS_ERR_INVALID_ARG, "requested steps are not in the kept history [" + std::to_string(lo) +
+                                            ", " + std::to_string(s->step) + ")");
+    if (!s->d_dt_hist) {
+        for (int64_t j = 0; j < n; ++j) out[j] = (double)(float)s->p.dt;
+        return FS_OK;
+    }
+    DeviceGuard dg(s->device);
+    std::vector<float> h((size_t)s->H);
+    FS_HIP(hipMemcpyAsync(h.data(), s->d_dt_hist, h.size() * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+    FS_HIP(hipStreamSynchronize(s->stream));
+    for (int64_t j = 0; j < n; ++j) out[j] = (double)h[(size_t)((first_step + j) % s->H)];
+    return FS_OK;
+    FS_GUARD_END
+}
+
 fs_status fs_get_state(fs_sim* s, int32_t replica, int32_t* state, float* age_days, uint16_t* age_steps,
                        int64_t* step_index)
 {
@@ -877,9 +951,9 @@ fs_status fs_get_state(fs_sim* s, int32_t replica, int32_t* state, float* age_da
         return fail(FS_ERR_INVALID_ARG, "pass exactly the age array of the sim's storage");
     DeviceGuard dg(s->device);
     const size_t n = (size_t)s->g->n;
-    DevBuf ds, da;
-    FS_HIP(dev_alloc(&ds.p, n * sizeof(int32_t)));
-    FS_HIP(dev_alloc(&da.p, n * age_bytes(s->storage)));
+    StreamBuf ds(s->stream); StreamBuf da(s->stream);
+    FS_HIP(hipMallocAsync(&ds.p, n * sizeof(int32_t), s->stream));
+    FS_HIP(hipMallocAsync(&da.p, n * age_bytes(s->storage), s->stream));
     FS_HIP(fsk::launch_get_replica(s->storage, s->d_state, s->d_age, (int32_t*)ds.p, da.p, (int32_t)n, s->lgR,
                                    replica, s->stream));
     FS_HIP(hipMemcpyAsync(state, ds.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s->stream));
@@ -911,16 +985,17 @@ fs_status fs_set_state(fs_sim* s, int32_t replica, const int32_t* state, const f
     DeviceGuard dg(s->device);
     const int64_t new_step = step_index >= 0 ? step_index : s->step;
     const size_t units = n * (size_t)s->R;
-    DevBuf ds, da;
-    FS_HIP(dev_alloc(&ds.p, n * sizeof(int32_t)));
-    FS_HIP(dev_alloc(&da.p, n * age_bytes(s->storage)));
+    StreamBuf ds(s->stream); StreamBuf da(s->stream);
+    FS_HIP(hipMallocAsync(&ds.p, n * sizeof(int32_t), s->stream));
+    FS_HIP(hipMallocAsync(&da.p, n * age_bytes(s->storage), s->stream));
     FS_HIP(hipMemcpyAsync(ds.p, state, n * sizeof(int32_t), hipMemcpyHostToDevice, s->stream));
     FS_HIP(hipMemcpyAsync(da.p, age_in, n * age_bytes(s->storage), hipMemcpyHostToDevice, s->stream));
     FS_HIP(fsk::launch_put_replica(s->storage, s->d_state, s->d_age, (const int32_t*)ds.p, da.p, (int32_t)n, s->lgR,
                                    replica, s->stream));
     FS_HIP(fsk::launch_rebuild_bits(s->storage, s->d_state, (uint32_t)units,
                                     (unsigned long long*)s->d_iota[new_step & 1], s->bit_words, s->stream));
-    if (step_index >= 0) FS_HIP(fsk::launch_set_ctl(s->d_ctl, (unsigned long long)step_index, s->stream));
+    // the step index, and (adaptive steps) a restart of the step-size rule at the cap
+    FS_HIP(fsk::launch_set_ctl(s->d_ctl, (unsigned long long)new_step, s->stream));
     FS_HIP(refresh_summary(s));
     FS_HIP(hipStreamSynchronize(s->stream));
     if (step_index >= 0) {
@@ -940,8 +1015,8 @@ fs_status fs_get_rates(fs_sim* s, int32_t replica, float* out)
     if (!s->d_rates) return fail(FS_ERR_INVALID_ARG, "sim was created without record_rates");
     DeviceGuard dg(s->device);
     const size_t n = (size_t)s->g->n;
-    DevBuf d;
-    FS_HIP(dev_alloc(&d.p, n * sizeof(float)));
+    StreamBuf d(s->stream);
+    FS_HIP(hipMallocAsync(&d.p, n * sizeof(float), s->stream));
     FS_HIP(fsk::launch_get_rates(s->d_rates, (float*)d.p, (int32_t)n, s->lgR, replica, s->stream));
     FS_HIP(hipMemcpyAsync(out, d.p, n * sizeof(float), hipMemcpyDeviceToHost, s->stream));
     FS_HIP(hipStreamSynchronize(s->stream));
@@ -991,7 +1066,9 @@ fs_status fs_sim_tune(fs_sim* s, int32_t trial_steps, int32_t* heavy_degree, int
                   {s->d_iota[1], (size_t)s->bit_words * 8, {}},
                   {s->d_ctl, sizeof(fsi::Ctl), {}},
                   {s->d_hist, (size_t)s->H * s->R * 4 * sizeof(uint32_t), {}},
-                  {s->d_summary, s->d_summary ? ((size_t)s->sum_bits + 511) / 512 * 64 : 0, {}}};
+                  {s->d_summary, s->d_summary ? ((size_t)s->sum_bits + 511) / 512 * 64 : 0, {}},
+                  {s->d_lam_part, 2 * (size_t)s->G * sizeof(float), {}},
+                  {s->d_dt_hist, (size_t)s->H * sizeof(float), {}}};
     for (auto& b : bufs) {
         if (!b.live) continue;
         FS_HIP(dev_alloc(&b.copy.p, b.bytes));

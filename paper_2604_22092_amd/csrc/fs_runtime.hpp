@@ -51,6 +51,7 @@ struct fs_graph {
     int32_t* d_col_ind = nullptr;
     float* d_weights = nullptr;
     int32_t max_degree = 0;
+    int32_t min_degree = 0;
     double mean_degree = 0.0;
     std::vector<int32_t> h_row_ptr; // host copies for degree binning and layouts
     std::vector<int32_t> h_col_ind;
@@ -77,6 +78,8 @@ struct fs_sim {
     uint32_t* d_part = nullptr;    // [chunk][G][R][4] per-workgroup partials
     uint32_t* d_rc_part = nullptr; // recount partials [RC_GRID][4]
     uint32_t* d_cnt4 = nullptr;
+    float* d_lam_part = nullptr;   // adaptive step: per-workgroup rate maxima [2][G]
+    float* d_dt_hist = nullptr;    // adaptive step: step size of each step, ring of H
     int H = 1024;
     uint32_t G = 0;                // step workgroups
     uint32_t tpb = 0;              // threads (units) per step workgroup / tile
@@ -154,6 +157,9 @@ struct StreamBuf {
     }
 };
 
+// Releases a sim without waiting for its stream: its buffers are freed in
+// stream order (callers guarantee no later work on other streams uses them).
+void release_sim(fs_sim* s);
 size_t state_bytes(int storage);
 size_t age_bytes(int storage);
 uint32_t heavy_grid(const fs_sim* s);
