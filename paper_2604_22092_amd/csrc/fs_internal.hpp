@@ -25,7 +25,10 @@ constexpr uint32_t RESIDENT_BITS = 1u << 20;
 constexpr uint32_t SUMMARY_BITS = 1u << 20;
 // Light rows of a chunk whose rows all have the same degree d <= UNIFORM_MAX_DEG
 // have their edge slots loaded ahead with the chunk's state (the preload depth).
-constexpr int UNIFORM_MAX_DEG = 12;
+#ifndef FS_UMAX
+#define FS_UMAX 12
+#endif
+constexpr int UNIFORM_MAX_DEG = FS_UMAX;
 // Bitmaps are allocated in whole 512-unit tiles (8 words of 64 bits).
 constexpr uint32_t BITMAP_TILE = 512;
 
@@ -95,6 +98,8 @@ struct StepArgs {
     // is the row's degree, or HEAVY_ROW for a binned row.
     const uint16_t* ldeg;
     const uint2* chunk_meta;
+    // the caller's id of each (internal) node: the draws are keyed by it
+    const int32_t* orig_id;
     // every chunk uniform with this degree (<= UNIFORM_MAX_DEG) and no heavy
     // rows: chunk c starts at slot c * (64 / R) * udeg; else -1
     int32_t udeg;

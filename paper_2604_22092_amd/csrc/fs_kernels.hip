@@ -163,7 +163,7 @@ template <class age_t>
 struct Pass {
     uint32_t chk[CU], base[CU], ud[CU], nvalid[CU];
     bool live[CU];
-    uint32_t xr[CU], agw[CU], dgr[CU];
+    uint32_t xr[CU], agw[CU], dgr[CU], org[CU];
     int32_t c[CU][UMAX];
 };
 
@@ -199,6 +199,9 @@ __device__ __forceinline__ void issue_pass(const StepArgs& a, uint32_t first, ui
         P.xr[u] = BufIO<state_t>::ld(make_rsrc((const state_t*)a.state + u0, P.nvalid[u] * sizeof(state_t)), lane);
         P.agw[u] = BufIO<age_t>::ld(make_rsrc((const age_t*)a.age + u0, P.nvalid[u] * sizeof(age_t)), lane);
         P.dgr[u] = BufIO<uint16_t>::ld(make_rsrc(a.ldeg + n0, nrows * 2u), q);
+        // graphs in a degree-sorted order (never uniform ones) key the draws
+        // by the caller's node id
+        P.org[u] = UNIFORM ? n0 + q : ld32(make_rsrc(a.orig_id + n0, nrows * 4u), q << 2);
         const bool pre = P.ud[u] <= (uint32_t)UMAX;
         const rsrc_t cr = make_rsrc(a.col_t + P.base[u], pre ? P.ud[u] * rows * 4u : 0u);
 #pragma unroll
@@ -412,7 +415,7 @@ __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t
 #pragma unroll
         for (int u = 0; u < CU; ++u) {
             need[u] = lam[u] > 0.0f;
-            pay[u] = unit[u];
+            pay[u] = (P.org[u] << a.lgR) | (lane & (R - 1)); // the caller's node id and the replica
             res[u] = 0;
         }
         const uint32_t kk = (uint32_t)k;

@@ -66,6 +66,23 @@ void sim_free(fs_sim* s, void* p)
     if (p) (void)hipFreeAsync(p, s->stream);
 }
 
+// Per-node arrays between the caller's node order and a graph's internal
+// order (no copy when the graph keeps the caller's order).
+template <class T>
+const T* to_internal(const fs_graph* g, const T* in, std::vector<T>& tmp)
+{
+    if (g->h_orig.empty()) return in;
+    tmp.resize(g->h_orig.size());
+    for (size_t j = 0; j < tmp.size(); ++j) tmp[j] = in[g->h_orig[j]];
+    return tmp.data();
+}
+
+template <class T>
+void to_caller(const fs_graph* g, const T* in, T* out)
+{
+    for (size_t j = 0; j < g->h_orig.size(); ++j) out[g->h_orig[j]] = in[j];
+}
+
 
 void split(double v, float& hi, float& lo)
 {
@@ -362,6 +379,7 @@ fs_status apply_bins(fs_sim* s, int32_t heavy_deg, int32_t seg_edges)
     s->args.seg_edges = seg_edges;
     s->args.ldeg = L->d_ldeg;
     s->args.chunk_meta = L->d_chunk_meta;
+    s->args.orig_id = g->d_orig;
     s->args.udeg = L->udeg;
     s->kfn = fsk::step_kernel_fn(s->storage, g->d_weights != nullptr, s->d_rates != nullptr, s->mode, L->udeg >= 0);
     s->args.col_t = L->d_col_t;
@@ -561,27 +579,64 @@ fs_status fs_graph_create(int64_t n, const int32_t* row_ptr, const int32_t* col_
     g->max_degree = maxd;
     g->min_degree = mind;
     g->mean_degree = (double)nnz / (double)n;
-    g->h_row_ptr.assign(row_ptr, row_ptr + n + 1);
-    if (nnz) g->h_col_ind.assign(col_ind, col_ind + nnz);
-    if (weights && nnz) g->h_weights.assign(weights, weights + nnz);
+    if (mind == maxd) {
+        g->h_row_ptr.assign(row_ptr, row_ptr + n + 1);
+        if (nnz) g->h_col_ind.assign(col_ind, col_ind + nnz);
+        if (weights && nnz) g->h_weights.assign(weights, weights + nnz);
+    } else {
+        // degree-sorted internal order (counting sort, stable): rows keep
+        // their edges in the caller's order, columns are relabelled
+        std::vector<int64_t> cnt((size_t)maxd + 2, 0);
+        for (int64_t i = 0; i < n; ++i) ++cnt[(size_t)(row_ptr[i + 1] - row_ptr[i]) + 1];
+        for (size_t d = 1; d < cnt.size(); ++d) cnt[d] += cnt[d - 1];
+        g->h_orig.resize((size_t)n);
+        g->h_inv.resize((size_t)n);
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t pos = cnt[(size_t)(row_ptr[i + 1] - row_ptr[i])]++;
+            g->h_orig[(size_t)pos] = (int32_t)i;
+            g->h_inv[(size_t)i] = (int32_t)pos;
+        }
+        g->h_row_ptr.resize((size_t)n + 1);
+        g->h_row_ptr[0] = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            const int32_t i = g->h_orig[(size_t)j];
+            g->h_row_ptr[(size_t)j + 1] = g->h_row_ptr[(size_t)j] + (row_ptr[i + 1] - row_ptr[i]);
+        }
+        g->h_col_ind.resize((size_t)nnz);
+        if (weights) g->h_weights.resize((size_t)nnz);
+        for (int64_t j = 0; j < n; ++j) {
+            const int32_t i = g->h_orig[(size_t)j];
+            int32_t o = g->h_row_ptr[(size_t)j];
+            for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e, ++o) {
+                g->h_col_ind[(size_t)o] = g->h_inv[(size_t)col_ind[e]];
+                if (weights) g->h_weights[(size_t)o] = weights[e];
+            }
+        }
+    }
+    std::vector<int32_t> orig_dev((size_t)n);
+    for (int64_t j = 0; j < n; ++j) orig_dev[(size_t)j] = g->h_orig.empty() ? (int32_t)j : g->h_orig[(size_t)j];
     auto cleanup = [&](fs_status st) {
         dev_free(g->d_row_ptr);
         dev_free(g->d_col_ind);
         dev_free(g->d_weights);
+        dev_free(g->d_orig);
         delete g;
         return st;
     };
     hipError_t e;
     if ((e = dev_alloc((void**)&g->d_row_ptr, sizeof(int32_t) * (size_t)(n + 1))) != hipSuccess ||
         (e = dev_alloc((void**)&g->d_col_ind, sizeof(int32_t) * (size_t)nnz)) != hipSuccess ||
+        (e = dev_alloc((void**)&g->d_orig, sizeof(int32_t) * (size_t)n)) != hipSuccess ||
         (weights && (e = dev_alloc((void**)&g->d_weights, sizeof(float) * (size_t)nnz)) != hipSuccess))
         return cleanup(fail(FS_ERR_OUT_OF_MEMORY, std::string("device allocation: ") + hipGetErrorString(e)));
-    if ((e = hipMemcpy(g->d_row_ptr, row_ptr, sizeof(int32_t) * (size_t)(n + 1), hipMemcpyHostToDevice)) !=
+    if ((e = hipMemcpy(g->d_row_ptr, g->h_row_ptr.data(), sizeof(int32_t) * (size_t)(n + 1), hipMemcpyHostToDevice)) !=
             hipSuccess ||
-        (nnz && (e = hipMemcpy(g->d_col_ind, col_ind, sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice)) !=
-                    hipSuccess) ||
+        (nnz && (e = hipMemcpy(g->d_col_ind, g->h_col_ind.data(), sizeof(int32_t) * (size_t)nnz,
+                               hipMemcpyHostToDevice)) != hipSuccess) ||
+        (e = hipMemcpy(g->d_orig, orig_dev.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice)) != hipSuccess ||
         (weights && nnz &&
-         (e = hipMemcpy(g->d_weights, weights, sizeof(float) * (size_t)nnz, hipMemcpyHostToDevice)) != hipSuccess))
+         (e = hipMemcpy(g->d_weights, g->h_weights.data(), sizeof(float) * (size_t)nnz, hipMemcpyHostToDevice)) !=
+             hipSuccess))
         return cleanup(fail(FS_ERR_DEVICE, std::string("upload: ") + hipGetErrorString(e)));
     *out = g;
     return FS_OK;
@@ -597,6 +652,7 @@ fs_status fs_graph_destroy(fs_graph* g)
     dev_free(g->d_row_ptr);
     dev_free(g->d_col_ind);
     dev_free(g->d_weights);
+    dev_free(g->d_orig);
     delete g;
     return FS_OK;
     FS_GUARD_END
@@ -817,6 +873,12 @@ fs_status fs_sim_seed(fs_sim* s, int32_t replica, int64_t count, const int64_t* 
     DeviceGuard dg(s->device);
     // stream-ordered staging buffer: allocating and freeing it does not wait
     // for work queued on other streams
+    std::vector<int64_t> internal;
+    if (!s->g->h_inv.empty()) {
+        internal.resize((size_t)count);
+        for (int64_t j = 0; j < count; ++j) internal[(size_t)j] = s->g->h_inv[(size_t)nodes[j]];
+        nodes = internal.data();
+    }
     StreamBuf tmp(s->stream);
     FS_HIP(hipMallocAsync(&tmp.p, sizeof(int64_t) * (size_t)count, s->stream));
     FS_HIP(hipMemcpyAsync(tmp.p, nodes, sizeof(int64_t) * (size_t)count, hipMemcpyHostToDevice, s->stream));
@@ -956,9 +1018,19 @@ fs_status fs_get_state(fs_sim* s, int32_t replica, int32_t* state, float* age_da
     FS_HIP(hipMallocAsync(&da.p, n * age_bytes(s->storage), s->stream));
     FS_HIP(fsk::launch_get_replica(s->storage, s->d_state, s->d_age, (int32_t*)ds.p, da.p, (int32_t)n, s->lgR,
                                    replica, s->stream));
-    FS_HIP(hipMemcpyAsync(state, ds.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s->stream));
-    FS_HIP(hipMemcpyAsync(age_out, da.p, n * age_bytes(s->storage), hipMemcpyDeviceToHost, s->stream));
+    const bool reorder = !s->g->h_orig.empty();
+    std::vector<int32_t> st_int(reorder ? n : 0);
+    std::vector<uint8_t> age_int(reorder ? n * age_bytes(s->storage) : 0);
+    FS_HIP(hipMemcpyAsync(reorder ? (void*)st_int.data() : (void*)state, ds.p, n * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s->stream));
+    FS_HIP(hipMemcpyAsync(reorder ? (void*)age_int.data() : age_out, da.p, n * age_bytes(s->storage),
+                          hipMemcpyDeviceToHost, s->stream));
     FS_HIP(hipStreamSynchronize(s->stream));
+    if (reorder) {
+        to_caller(s->g, st_int.data(), state);
+        if (s->storage == FS_STORAGE_FP32) to_caller(s->g, (const float*)age_int.data(), age_days);
+        else to_caller(s->g, (const uint16_t*)age_int.data(), age_steps);
+    }
     if (step_index) *step_index = s->step;
     return FS_OK;
     FS_GUARD_END
@@ -985,6 +1057,12 @@ fs_status fs_set_state(fs_sim* s, int32_t replica, const int32_t* state, const f
     DeviceGuard dg(s->device);
     const int64_t new_step = step_index >= 0 ? step_index : s->step;
     const size_t units = n * (size_t)s->R;
+    std::vector<int32_t> st_tmp;
+    std::vector<float> ad_tmp;
+    std::vector<uint16_t> as_tmp;
+    state = to_internal(s->g, state, st_tmp);
+    age_in = s->storage == FS_STORAGE_FP32 ? (const void*)to_internal(s->g, age_days, ad_tmp)
+                                           : (const void*)to_internal(s->g, age_steps, as_tmp);
     StreamBuf ds(s->stream); StreamBuf da(s->stream);
     FS_HIP(hipMallocAsync(&ds.p, n * sizeof(int32_t), s->stream));
     FS_HIP(hipMallocAsync(&da.p, n * age_bytes(s->storage), s->stream));
@@ -1018,8 +1096,11 @@ fs_status fs_get_rates(fs_sim* s, int32_t replica, float* out)
     StreamBuf d(s->stream);
     FS_HIP(hipMallocAsync(&d.p, n * sizeof(float), s->stream));
     FS_HIP(fsk::launch_get_rates(s->d_rates, (float*)d.p, (int32_t)n, s->lgR, replica, s->stream));
-    FS_HIP(hipMemcpyAsync(out, d.p, n * sizeof(float), hipMemcpyDeviceToHost, s->stream));
+    const bool reorder = !s->g->h_orig.empty();
+    std::vector<float> r_int(reorder ? n : 0);
+    FS_HIP(hipMemcpyAsync(reorder ? r_int.data() : out, d.p, n * sizeof(float), hipMemcpyDeviceToHost, s->stream));
     FS_HIP(hipStreamSynchronize(s->stream));
+    if (reorder) to_caller(s->g, r_int.data(), out);
     return FS_OK;
     FS_GUARD_END
 }

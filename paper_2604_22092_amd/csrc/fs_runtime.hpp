@@ -53,7 +53,15 @@ struct fs_graph {
     int32_t max_degree = 0;
     int32_t min_degree = 0;
     double mean_degree = 0.0;
-    std::vector<int32_t> h_row_ptr; // host copies for degree binning and layouts
+    // Graphs whose rows do not all have one degree are kept with their nodes
+    // in a degree-sorted internal order, so the 64-unit chunks of the step
+    // are (almost all) uniform in degree.  h_orig[internal] is the caller's
+    // node id and h_inv its inverse (both empty for the identity order); the
+    // CSR copies below and every per-node device array are in internal order,
+    // and the C ABI converts node ids and per-node arrays at its boundary.
+    std::vector<int32_t> h_orig, h_inv;
+    int32_t* d_orig = nullptr;      // internal -> caller's id on the device (identity when not reordered)
+    std::vector<int32_t> h_row_ptr; // host copies (internal order) for degree binning and layouts
     std::vector<int32_t> h_col_ind;
     std::vector<float> h_weights;
     std::atomic<int> users{0};
