@@ -17,6 +17,11 @@ descriptions use:
     ("weibull", shape, scale)
     ("erlang", k, rate)      integer shape k
 
+A model may name a shedding profile s(tau) of Eq. (infectivity) under the key
+"shed": ("density", law, A) for s = A f(tau), ("hazard", law, A) for
+s = A h(tau), with `law` one of the tuples above; absent or ("constant",)
+means s == 1.
+
 Parity: every function here is pinned by a CPU test against something other
 than itself (numpy and rocRAND for Philox, scipy/mpmath for the hazards,
 closed forms, brute force and an exact event-driven simulation for the step).
@@ -70,7 +75,11 @@ class Dist(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("ei", Dist), ("ir", Dist), ("beta", ctypes.c_double),
                 ("dt", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("age_mode", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("age_mode", ctypes.c_int32), ("shed_mode", ctypes.c_int32),
+                ("shed", Dist), ("shed_scale", ctypes.c_double)]
+
+
+SHED_MODES = {"constant": 0, "density": 1, "hazard": 2}
 
 
 def make_dist(spec) -> Dist:
@@ -87,8 +96,13 @@ def make_dist(spec) -> Dist:
 
 
 def make_params(model: dict, age_mode: int = AGE_DAYS_F32) -> Params:
+    shed = model.get("shed") or ("constant",)
+    mode = SHED_MODES[shed[0]]
+    law = make_dist(shed[1]) if mode else Dist(0, 0, 0.0, 0.0)
+    scale = float(shed[2]) if mode else 1.0
     return Params(make_dist(model["ei"]), make_dist(model["ir"]), float(model["beta"]),
-                  float(model["dt"]), int(model.get("seed", 0)) & (2**64 - 1), int(age_mode), 0)
+                  float(model["dt"]), int(model.get("seed", 0)) & (2**64 - 1), int(age_mode),
+                  mode, law, scale)
 
 
 _P = ctypes.c_void_p
@@ -104,6 +118,8 @@ def _declare(L):
     L.or_uniform.restype = ctypes.c_double
     L.or_erfcx_many.argtypes = [_I64, _P, _P]
     L.or_hazard_many.argtypes = [ctypes.POINTER(Dist), _I64, _P, _P]
+    L.or_density_many.argtypes = [ctypes.POINTER(Dist), _I64, _P, _P]
+    L.or_infectivity.argtypes = [_I64, ctypes.POINTER(Params), _P, _P, _P, _P]
     L.or_step.argtypes = [_I64, _P, _P, _P, ctypes.POINTER(Params), _U64, _U32, _P, _P, _P,
                           _P, _P, _P, _P, _P, _P]
     L.or_step_nodes.argtypes = [_I64, _P, _P, _P, ctypes.POINTER(Params), _U64, _U32, _P, _P,
@@ -180,6 +196,27 @@ def hazard(spec, tau) -> np.ndarray:
     return out
 
 
+def density(spec, tau) -> np.ndarray:
+    """Density f(tau) of a holding-time law (shedding profiles s = A f)."""
+    tau = _c(np.atleast_1d(tau), np.float64)
+    out = np.empty_like(tau)
+    d = make_dist(spec)
+    lib().or_density_many(ctypes.byref(d), len(tau), _ptr(tau), _ptr(out))
+    return out
+
+
+def infectivity(model: dict, state, age, compact: bool = False) -> np.ndarray:
+    """iota_i = s(tau_i) 1{X_i = I} of Eq. (infectivity), from a state and age."""
+    st = _c(state, np.int32)
+    n = len(st)
+    p = make_params(model, AGE_STEPS_U16 if compact else AGE_DAYS_F32)
+    ad = None if compact else _c(age, np.float32)
+    ag = _c(age, np.uint16) if compact else None
+    out = np.empty(n, dtype=np.float64)
+    lib().or_infectivity(n, ctypes.byref(p), _ptr(st), _ptr(ad), _ptr(ag), _ptr(out))
+    return out
+
+
 # -------------------------------------------------------------------------- step
 
 def _graph(graph):
@@ -193,7 +230,7 @@ def step(graph, model: dict, state, age, iota, step_index: int, replica: int = 0
     """One step from (state, age, iota); returns the new arrays plus logs.
 
     age is float32 days (compact=False) or uint16 step counts (compact=True).
-    iota is the start-of-step infectivity (0/1 values, any float dtype).
+    iota is the start-of-step infectivity s(tau) 1{X = I} (see infectivity()).
     """
     rp, ci, w = _graph(graph)
     n = len(rp) - 1

@@ -21,13 +21,21 @@
  *                fire = (u < q_i); no draw when lambda_i == 0
  *   5. state     X' = successor(X) when fire (S->E->I->R, R absorbing)
  *   6. age       reset to 0 on a transition, else advanced by dt (renewal property)
- *   7. infectivity for the next step  iota'_i = 1{X'_i = I}  (shedding s == 1)
+ *   7. infectivity for the next step  iota'_i = s(tau'_i) * 1{X'_i = I}, with the
+ *      shedding profile s of Eq. (infectivity): s == 1 (constant shedding,
+ *      Markovian edges), a scaled density A*f(tau) of a holding-time law, or a
+ *      scaled hazard A*h(tau) (the in-kernel age-dependent form of the
+ *      overhead study, Table "agedep_overhead")
  *   8. exact integer counts of S, E, I, R after the step
  *
  * Readings taken where the paper leaves a choice (each also listed in the
  * design notes of the repository):
- *   - beta is applied to the pressure, not folded into iota; iota is the
- *     0/1 indicator (mathematically the same product, Eq. (infectivity)).
+ *   - beta is applied to the pressure, not folded into iota; iota is
+ *     s(tau) 1{X = I} (mathematically the same product, Eq. (infectivity)).
+ *   - the infectivity read by step k is that of the state and age at the
+ *     start of step k (the pre-pass of Algorithm 3); writing it at the end of
+ *     step k-1 from the new state and age, as the fused kernel does, is the
+ *     same value.
  *   - the hazard is evaluated at the age at the start of the step.
  *   - the step size is fixed (the adaptive rule is not on this path).
  *   - FP32-storage ages advance as (float)((float)tau + (float)dt), mirroring
@@ -224,11 +232,62 @@ void or_hazard_many(const or_dist* d, int64_t n, const double* tau, double* out)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Densities f(tau) of the same laws, for shedding profiles s = A*f          */
+/* (Eq. (infectivity): a log-normal density is the paper's example).          */
+/* At tau = 0 they take their right limit (0 except for the exponential law,  */
+/* Weibull shape 1 and Erlang k = 1, whose density starts at the rate).       */
+/* ------------------------------------------------------------------------ */
+
+/* log-normal: f = exp(-(ln tau - mu)^2 / (2 sigma^2)) / (tau sigma sqrt(2 pi)) */
+double or_density_lognormal(double tau, double mu, double sigma)
+{
+    if (!(tau > 0.0)) return 0.0;
+    double z = (log(tau) - mu) / sigma;
+    return exp(-0.5 * z * z) / (tau * sigma * sqrt(2.0 * M_PI));
+}
+
+/* Weibull(shape kk, scale lam): f = (kk/lam) (tau/lam)^(kk-1) exp(-(tau/lam)^kk) */
+double or_density_weibull(double tau, double shape, double scale)
+{
+    if (tau < 0.0) return 0.0;
+    if (tau == 0.0) return shape == 1.0 ? 1.0 / scale : 0.0;
+    double x = tau / scale;
+    return (shape / scale) * pow(x, shape - 1.0) * exp(-pow(x, shape));
+}
+
+/* Erlang(k, rate theta): f = theta (theta tau)^(k-1) exp(-theta tau) / (k-1)! */
+double or_density_erlang(double tau, int32_t k, double rate)
+{
+    if (tau < 0.0) return 0.0;
+    if (tau == 0.0) return k == 1 ? rate : 0.0;
+    double x = rate * tau;
+    return rate * exp((double)(k - 1) * log(x) - x - lgamma((double)k));
+}
+
+double or_density(const or_dist* d, double tau)
+{
+    switch (d->kind) {
+    case OR_DIST_EXP: return tau < 0.0 ? 0.0 : d->a * exp(-d->a * tau);
+    case OR_DIST_LOGNORMAL: return or_density_lognormal(tau, d->a, d->b);
+    case OR_DIST_WEIBULL: return or_density_weibull(tau, d->a, d->b);
+    case OR_DIST_ERLANG: return or_density_erlang(tau, d->k, d->a);
+    default: return NAN;
+    }
+}
+
+void or_density_many(const or_dist* d, int64_t n, const double* tau, double* out)
+{
+    for (int64_t j = 0; j < n; ++j) out[j] = or_density(d, tau[j]);
+}
+
+/* ------------------------------------------------------------------------ */
 /* One tau-leap step (Algorithm 3), FP64 arithmetic, node by node.           */
 /* ------------------------------------------------------------------------ */
 
 enum { OR_S = 0, OR_E = 1, OR_I = 2, OR_R = 3 };
 enum { OR_AGE_DAYS_F32 = 0, OR_AGE_STEPS_U16 = 1 };
+
+enum { OR_SHED_CONST = 0, OR_SHED_DENSITY = 1, OR_SHED_HAZARD = 2 };
 
 typedef struct {
     or_dist ei, ir;
@@ -236,8 +295,31 @@ typedef struct {
     double dt;   /* step size (days) */
     uint64_t seed;
     int32_t age_mode; /* OR_AGE_* */
-    int32_t pad;
+    int32_t shed_mode; /* OR_SHED_*: s == 1, s = shed_scale*f, s = shed_scale*h of law `shed` */
+    or_dist shed;
+    double shed_scale;
 } or_params;
+
+/* Shedding profile s(tau) of an infectious node of age tau (Eq. (infectivity)). */
+double or_shed(const or_params* p, double tau)
+{
+    switch (p->shed_mode) {
+    case OR_SHED_CONST: return 1.0;
+    case OR_SHED_DENSITY: return p->shed_scale * or_density(&p->shed, tau);
+    case OR_SHED_HAZARD: return p->shed_scale * or_hazard(&p->shed, tau);
+    default: return NAN;
+    }
+}
+
+/* Infectivity of every node from its state and age: s(tau_i) 1{X_i = I}. */
+void or_infectivity(int64_t n, const or_params* p, const int32_t* state, const float* age_days,
+                    const uint16_t* age_steps, double* out)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double tau = (p->age_mode == OR_AGE_DAYS_F32) ? (double)age_days[i] : (double)age_steps[i] * p->dt;
+        out[i] = state[i] == OR_I ? or_shed(p, tau) : 0.0;
+    }
+}
 
 /* Per-node outcome, used both by the full step and by the sampled-node form. */
 typedef struct {
@@ -314,8 +396,9 @@ void or_step(int64_t n, const int32_t* row_ptr, const int32_t* col_ind, const fl
         state[i] = o.state;
         if (age_days) age_days[i] = o.age_days;
         if (age_steps) age_steps[i] = o.age_steps;
-        /* 7. next-step infectivity (Eq. (infectivity) with s == 1) */
-        iota_out[i] = (o.state == OR_I) ? 1.0 : 0.0;
+        /* 7. next-step infectivity (Eq. (infectivity)) from the new state and age */
+        double tau_new = (p->age_mode == OR_AGE_DAYS_F32) ? (double)o.age_days : (double)o.age_steps * p->dt;
+        iota_out[i] = (o.state == OR_I) ? or_shed(p, tau_new) : 0.0;
         counts[o.state] += 1;
         if (log_lambda) log_lambda[i] = o.lambda;
         if (log_q) log_q[i] = o.q;
@@ -351,7 +434,7 @@ void or_step_nodes(int64_t n, const int32_t* row_ptr, const int32_t* col_ind, co
 
 /*
  * A whole trajectory of n_steps steps for one replica, starting at step index
- * step0 with the given state/age (iota is rebuilt from the state, as s == 1).
+ * step0 with the given state/age (iota is built from the state and age).
  * history (n_steps x 4, may be NULL) receives the counts after every step.
  * scratch must hold 2*n doubles (the two infectivity buffers).
  */
@@ -362,7 +445,7 @@ void or_run(int64_t n, const int32_t* row_ptr, const int32_t* col_ind, const flo
 {
     double* cur = scratch;
     double* nxt = scratch + n;
-    for (int64_t i = 0; i < n; ++i) cur[i] = (state[i] == OR_I) ? 1.0 : 0.0;
+    or_infectivity(n, p, state, age_days, age_steps, cur);
     int64_t counts[4];
     for (int64_t s = 0; s < n_steps; ++s) {
         or_step(n, row_ptr, col_ind, weights, p, step0 + (uint64_t)s, replica, state, age_days,
@@ -404,7 +487,7 @@ void or_run_adaptive(int64_t n, const int32_t* row_ptr, const int32_t* col_ind, 
     or_params q = *p;
     q.age_mode = OR_AGE_DAYS_F32;
     q.dt = dt_max;
-    for (int64_t i = 0; i < n; ++i) cur[i] = (state[i] == OR_I) ? 1.0 : 0.0;
+    or_infectivity(n, &q, state, age_days, NULL, cur);
     int64_t counts[4];
     for (int64_t s = 0; s < n_steps; ++s) {
         or_step(n, row_ptr, col_ind, weights, &q, step0 + (uint64_t)s, replica, state, age_days, NULL,
