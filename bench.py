@@ -17,6 +17,15 @@ timed on a bounded sample of the same workload.
 Barabasi-Albert graph with autotuned degree bins, or the N = 1e8 8-regular
 graph with compact or FP32 storage); the default line is the one above.
 
+--shed runs the same workload with an age-dependent shedding profile s(tau)
+(Eq. (infectivity)): "hazard" is s = h_IR(tau), the form the paper's overhead
+study writes in-kernel; "density" a log-normal shedding curve (median 2.5 d,
+sigma 0.5) scaled to 5 infectious days; "unit" the profile s = 1 through the
+shedding kernels (the constant run's trajectory, so its time against the
+default line is the cost of the shedding path itself).  --compaction turns on active-node
+compaction; --beta overrides the transmission rate (a saturating epidemic is
+where compaction pays).
+
 --serving measures the scenario server instead: a seeded Poisson stream of
 scenario solves (16 replicas, 300 steps, graphs of 1e4..2e6 nodes from a
 resident pool, laws and beta drawn per request) through the server, and the
@@ -50,6 +59,11 @@ LAW_TEXT = {
     "regular8_n1e8": "E~LN(ln3,0.5), I~LN(ln5,0.6)",
 }
 STEPS_PER_GRAPH = 50
+SHEDS = {
+    "none": None,
+    "density": ("density", ("lognormal", 0.9162907318741551, 0.5), 5.0),   # median 2.5 d
+    "unit": ("hazard", ("exp", 1.0), 1.0),
+}
 
 
 def bytes_per_update(d_mean: float, storage: str) -> float:
@@ -238,6 +252,11 @@ def main():
     ap.add_argument("--variant", choices=["auto", "stream", "resident", "summary"], default="auto",
                     help="step kernel variant (auto: LDS-resident bitmap when N*R <= 2^20, "
                          "else the LDS summary that screens bitmap reads)")
+    ap.add_argument("--shed", choices=["none", "hazard", "density", "unit"], default="none",
+                    help="shedding profile s(tau): none (s = 1), hazard (h_IR), density (log-normal), "
+                         "unit (s = 1 through the shedding kernels)")
+    ap.add_argument("--compaction", action="store_true", help="active-node compaction")
+    ap.add_argument("--beta", type=float, default=None, help="override the workload's beta")
     ap.add_argument("--serving", action="store_true",
                     help="measure the scenario server on the seeded request mix instead")
     ap.add_argument("--serving-requests", type=int, default=400)
@@ -267,7 +286,11 @@ def main():
     fs.lib()  # fail loudly without the HIP library
     workload = args.workload
     wl = W.WORKLOADS[workload]
-    model = wl["model"]
+    model = dict(wl["model"])
+    if args.beta is not None:
+        model["beta"] = args.beta
+    shed = ("hazard", model["ir"], 1.0) if args.shed == "hazard" else SHEDS[args.shed]
+    model["shed"] = shed
     storage = args.storage or wl["storage"]
     compact = storage == "compact"
     if args.steps is None:
@@ -296,7 +319,7 @@ def main():
     variant = {"auto": fs.VARIANT_AUTO, "stream": fs.VARIANT_STREAM,
                "resident": fs.VARIANT_RESIDENT, "summary": fs.VARIANT_SUMMARY}[args.variant]
     sim = fs.Sim.from_model(g, model, steps_per_graph=STEPS_PER_GRAPH, stream=stream.cuda_stream,
-                            variant=variant,
+                            variant=variant, compaction=args.compaction,
                             storage=fs.FS_STORAGE_COMPACT if compact else fs.FS_STORAGE_FP32)
     init_state = W.initial_state(n, seeds)
     init_age = np.zeros(n, np.uint16 if compact else np.float32)
@@ -339,7 +362,8 @@ def main():
     b_alg = bytes_per_update(d_mean, storage)
     per_launch_s = sec / args.steps
     achieved = b_alg * n / per_launch_s / 1e9
-    traffic = measured_traffic(workload if storage == wl["storage"] else f"{workload}_{storage}")
+    plain = args.shed == "none" and not args.compaction
+    traffic = measured_traffic(workload if storage == wl["storage"] else f"{workload}_{storage}") if plain else None
     s_frac = float(hist[:, 0].mean() / n)
     print(f"[bench] {args.steps} steps: {ms:.3f} ms (wall {wall * 1e3:.1f} ms), {gnups:.2f} GNUPS, "
           f"final counts {final.tolist()}, mean S fraction {s_frac:.3f}", file=sys.stderr, flush=True)
@@ -366,6 +390,8 @@ def main():
                    "laws": LAW_TEXT[workload], "beta": model["beta"], "dt": model["dt"],
                    "seeds": wl["seeds"], "replicas": 1, "storage": storage,
                    "steps_per_graph": STEPS_PER_GRAPH, "kernel_variant": args.variant,
+                   "shedding": args.shed if shed is None else [shed[0], list(shed[1]), shed[2]],
+                   "compaction": args.compaction,
                    "degree_bins": list(tuned) if tuned else None, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

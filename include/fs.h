@@ -79,6 +79,20 @@ typedef struct fs_dist {
     double b;
 } fs_dist;
 
+/* Shedding profile s(tau) of an infectious node of age tau (Eq. (infectivity):
+ * the infectivity of source j is beta * s(tau_j) * 1{X_j = I}).
+ *   FS_SHED_CONSTANT: s = 1 (Markovian edges; the infectivity is one bit)
+ *   FS_SHED_DENSITY:  s = shed_scale * f(tau), f the density of shed_law
+ *                     (the paper's example: a log-normal viral-load curve)
+ *   FS_SHED_HAZARD:   s = shed_scale * h(tau), h the hazard of shed_law (the
+ *                     in-kernel form of the overhead study, Table
+ *                     "agedep_overhead", uses h_IR)
+ * The value a node sheds during step k is s of its age at the start of step
+ * k; a node that has just become infectious has age 0. */
+#define FS_SHED_CONSTANT 0
+#define FS_SHED_DENSITY 1
+#define FS_SHED_HAZARD 2
+
 /* Storage of the per-unit state (mixed-precision storage, Section
  * "Mixed-precision storage with an fp32 accumulator"); arithmetic is FP32 in
  * both.
@@ -87,7 +101,8 @@ typedef struct fs_dist {
  *                       saturating at 65535)
  * In both, the next-step infectivity of Eq. (infectivity) is kept as one bit
  * per unit, 1{X = I}: with constant shedding s = 1 that bit is its exact value
- * (beta multiplies the pressure instead). */
+ * (beta multiplies the pressure instead).  Age-dependent shedding adds a
+ * float32 s(tau) per unit, read only where the bit is set. */
 #define FS_STORAGE_FP32 0
 #define FS_STORAGE_COMPACT 1
 
@@ -159,6 +174,20 @@ typedef struct fs_sim_params {
     int32_t pad;
     double epsilon;          /* adaptive: bound on lambda * dt per step, > 0 */
     double delta;            /* adaptive: added to the largest rate, >= 0 */
+    int32_t shedding;        /* FS_SHED_*; age-dependent forms need n * n_replicas < 2^29
+                                and are not available in batches or the server */
+    int32_t compaction;      /* nonzero: active-node compaction (Section "Epidemic-aware
+                                compute sparsity"): at the start of every launch sequence
+                                (each captured replay of steps_per_graph steps, or each
+                                eager run of at most max(steps_per_graph, 64) steps) the
+                                64-unit chunks whose units are all R are dropped from the
+                                launches until the next state load or seeding.  R is
+                                absorbing, so states, non-R ages and counts are identical
+                                to the uncompacted run; the ages of R units in dropped
+                                chunks stop advancing, and their recorded rates are 0.
+                                Not available in batches or the server. */
+    fs_dist shed_law;        /* the law of s(tau) (FS_SHED_DENSITY, FS_SHED_HAZARD) */
+    double shed_scale;       /* A >= 0, finite */
 } fs_sim_params;
 
 /*
@@ -270,6 +299,14 @@ fs_status fs_sim_tune(fs_sim* s, int32_t trial_steps, int32_t* heavy_degree, int
  */
 fs_status fs_eval_hazard(const fs_dist* law, int32_t storage, double dt, int64_t n,
                          const void* ages, float* out);
+
+/*
+ * Evaluates a shedding profile (form FS_SHED_DENSITY or FS_SHED_HAZARD, law,
+ * scale A) at n ages with the same device arithmetic the step kernels use.
+ * ages and out as for fs_eval_hazard.  Synchronises.
+ */
+fs_status fs_eval_shedding(const fs_dist* law, int32_t form, double scale, int32_t storage, double dt, int64_t n,
+                           const void* ages, float* out);
 
 /*
  * Evaluates Philox4x32-10 on the device for n counters (n x 4 uint32, host)

@@ -23,6 +23,8 @@ STATUS_NAMES = {0: "FS_OK", 1: "FS_ERR_INVALID_ARG", 2: "FS_ERR_INVALID_CSR",
 FS_S, FS_E, FS_I, FS_R = 0, 1, 2, 3
 FS_DIST_EXP, FS_DIST_LOGNORMAL, FS_DIST_WEIBULL, FS_DIST_ERLANG = 0, 1, 2, 3
 FS_STORAGE_FP32, FS_STORAGE_COMPACT = 0, 1
+FS_SHED_CONSTANT, FS_SHED_DENSITY, FS_SHED_HAZARD = 0, 1, 2
+SHED_FORMS = {"constant": FS_SHED_CONSTANT, "density": FS_SHED_DENSITY, "hazard": FS_SHED_HAZARD}
 VARIANT_AUTO, VARIANT_STREAM, VARIANT_RESIDENT, VARIANT_SUMMARY = 0, 1, 2, 3
 
 # Every symbol include/fs.h declares.
@@ -30,7 +32,7 @@ EXPORTS = [
     "fs_status_string", "fs_last_error", "fs_graph_create", "fs_graph_destroy",
     "fs_graph_get_info", "fs_sim_create", "fs_sim_destroy", "fs_sim_seed", "fs_step",
     "fs_sync", "fs_step_index", "fs_counts", "fs_history", "fs_get_state", "fs_set_state",
-    "fs_get_rates", "fs_eval_hazard", "fs_eval_philox", "fs_version", "fs_sim_set_bins",
+    "fs_get_rates", "fs_eval_hazard", "fs_eval_shedding", "fs_eval_philox", "fs_version", "fs_sim_set_bins",
     "fs_sim_get_bins", "fs_sim_tune", "fs_step_sizes",
     "fs_batch_create", "fs_batch_destroy", "fs_batch_add", "fs_batch_remove", "fs_batch_size",
     "fs_batch_step", "fs_batch_sync",
@@ -63,7 +65,9 @@ class fs_sim_params(ctypes.Structure):
                 ("record_rates", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("heavy_degree", ctypes.c_int32), ("segment_edges", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("adaptive", ctypes.c_int32), ("pad", ctypes.c_int32),
-                ("epsilon", ctypes.c_double), ("delta", ctypes.c_double)]
+                ("epsilon", ctypes.c_double), ("delta", ctypes.c_double),
+                ("shedding", ctypes.c_int32), ("compaction", ctypes.c_int32),
+                ("shed_law", fs_dist), ("shed_scale", ctypes.c_double)]
 
 
 class fs_server_params(ctypes.Structure):
@@ -128,6 +132,8 @@ def _declare(L):
         "fs_set_state": ([P, I32, P, P, P, I64], I32),
         "fs_get_rates": ([P, I32, P], I32),
         "fs_eval_hazard": ([ctypes.POINTER(fs_dist), I32, ctypes.c_double, I64, P, P], I32),
+        "fs_eval_shedding": ([ctypes.POINTER(fs_dist), I32, ctypes.c_double, I32, ctypes.c_double, I64, P, P],
+                             I32),
         "fs_eval_philox": ([I64, P, U64, P], I32),
         "fs_sim_set_bins": ([P, I32, I32], I32),
         "fs_sim_get_bins": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
@@ -301,6 +307,16 @@ def fs_eval_hazard(spec, ages, storage: int = FS_STORAGE_FP32, dt: float = 1.0) 
     return out
 
 
+def fs_eval_shedding(shed, ages, storage: int = FS_STORAGE_FP32, dt: float = 1.0) -> np.ndarray:
+    """Device values of a shedding profile ("density" | "hazard", law, scale) at ages."""
+    a = np.ascontiguousarray(ages, dtype=np.float32 if storage == FS_STORAGE_FP32 else np.uint16)
+    out = np.empty(len(a), dtype=np.float32)
+    d = make_dist(shed[1])
+    _check(lib().fs_eval_shedding(ctypes.byref(d), SHED_FORMS[shed[0]], float(shed[2]), int(storage),
+                                  float(dt), len(a), _ptr(a), _ptr(out)), "fs_eval_shedding")
+    return out
+
+
 def fs_eval_philox(ctr, seed: int) -> np.ndarray:
     c = np.ascontiguousarray(np.atleast_2d(ctr), dtype=np.uint32)
     out = np.empty_like(c)
@@ -337,7 +353,9 @@ def make_params(ei, ir, beta: float, dt: float, seed: int = 0, replicas: int = 1
                 storage: int = FS_STORAGE_FP32, steps_per_graph: int = 0, history_len: int = 0,
                 record_rates: bool = False, variant: int = 0, heavy_degree: int = 0,
                 segment_edges: int = 0, stream=None, adaptive: bool = False,
-                epsilon: float = 0.03, delta: float = 0.0) -> fs_sim_params:
+                epsilon: float = 0.03, delta: float = 0.0, shed=None,
+                compaction: bool = False) -> fs_sim_params:
+    """shed: None or ("constant",) for s = 1, else ("density" | "hazard", law, scale)."""
     p = fs_sim_params()
     p.ei = make_dist(ei)
     p.ir = make_dist(ir)
@@ -356,6 +374,12 @@ def make_params(ei, ir, beta: float, dt: float, seed: int = 0, replicas: int = 1
     p.adaptive = 1 if adaptive else 0
     p.epsilon = float(epsilon)
     p.delta = float(delta)
+    shed = shed or ("constant",)
+    p.shedding = SHED_FORMS[shed[0]]
+    if p.shedding != FS_SHED_CONSTANT:
+        p.shed_law = make_dist(shed[1])
+        p.shed_scale = float(shed[2])
+    p.compaction = 1 if compaction else 0
     return p
 
 
@@ -366,10 +390,11 @@ class Sim:
                  replicas: int = 1, storage: int = FS_STORAGE_FP32, steps_per_graph: int = 0,
                  history_len: int = 0, record_rates: bool = False, variant: int = 0,
                  heavy_degree: int = 0, segment_edges: int = 0, stream=None,
-                 adaptive: bool = False, epsilon: float = 0.03, delta: float = 0.0):
+                 adaptive: bool = False, epsilon: float = 0.03, delta: float = 0.0, shed=None,
+                 compaction: bool = False):
         p = make_params(ei, ir, beta, dt, seed, replicas, storage, steps_per_graph, history_len,
                         record_rates, variant, heavy_degree, segment_edges, stream, adaptive,
-                        epsilon, delta)
+                        epsilon, delta, shed, compaction)
         self.graph = graph
         self.n = graph.n
         self.replicas = int(replicas)
@@ -378,6 +403,9 @@ class Sim:
 
     @classmethod
     def from_model(cls, graph: Graph, model: dict, **kw):
+        """A sim of a model dict (laws "ei", "ir", "beta", "dt", optional "seed"
+        and shedding profile "shed")."""
+        kw.setdefault("shed", model.get("shed"))
         return cls(graph, model["ei"], model["ir"], model["beta"], model["dt"],
                    seed=model.get("seed", 0), **kw)
 

@@ -1,18 +1,22 @@
-"""Builds libflashspread.so (HIP for gfx950) in the package directory."""
+"""Builds libflashspread.so (HIP for gfx950) in the package directory: every
+source compiles to an object in _build/ (in parallel), then one link."""
 from __future__ import annotations
 
 import glob
 import os
 import shutil
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libflashspread.so")
 SOURCES = sorted(glob.glob(os.path.join(PKG, "csrc", "*.hip")))
 
+BUILD_DIR = os.path.join(PKG, "_build")
+
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
@@ -23,19 +27,27 @@ def hipcc() -> str:
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source into libflashspread.so (always rebuilds)."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(PKG, "csrc"), "-o", tmp, *SOURCES]
+def _run(cmd, verbose):
     res = subprocess.run(cmd, capture_output=True, text=True)
-    if verbose or res.returncode != 0:
-        noise = "packed-fp32-ops"
-        msg = "\n".join(l for l in (res.stdout + res.stderr).splitlines() if noise not in l)
-        if msg.strip():
-            print(msg)
+    noise = "packed-fp32-ops"
+    msg = "\n".join(l for l in (res.stdout + res.stderr).splitlines() if noise not in l)
+    if (verbose or res.returncode != 0) and msg.strip():
+        print(msg)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed ({res.returncode}): {' '.join(cmd)}")
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every HIP source and link libflashspread.so (always rebuilds)."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc")]
+    objs = [os.path.join(BUILD_DIR, os.path.basename(src)[:-4] + ".o") for src in SOURCES]
+    jobs = [[hipcc(), *HIPCC_FLAGS, *inc, "-c", "-o", o, src] for src, o in zip(SOURCES, objs)]
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", "8"))))
+    with ThreadPoolExecutor(workers) as ex:
+        list(ex.map(lambda c: _run(c, verbose), jobs))
+    tmp = LIB + ".tmp"
+    _run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs], verbose)
     os.replace(tmp, LIB)
     return LIB
 

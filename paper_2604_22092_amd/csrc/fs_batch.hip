@@ -85,7 +85,6 @@ struct fs_batch {
     int device = 0;
     int storage = 0;
     int weighted = -1; // fixed by the first member
-    int rates = -1;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::vector<fs_sim*> members;
@@ -195,7 +194,6 @@ fs_status rebuild_tables(fs_batch* b)
 void attach(fs_batch* b, fs_sim* s)
 {
     b->weighted = s->g->d_weights != nullptr;
-    b->rates = s->d_rates != nullptr;
     s->saved_stream = s->stream;
     s->stream = b->stream;
     s->batch = b;
@@ -215,7 +213,10 @@ void detach(fs_batch* b, fs_sim* s)
 fs_status batch_sequence(fs_batch* b, uint32_t r)
 {
     const uint32_t M = (uint32_t)b->members.size();
-    const void* kfn = fsk::step_batch_kernel_fn(b->storage, b->weighted == 1, b->rates == 1);
+    // the instantiation with rate recording only when a member records them
+    bool rates = false;
+    for (const fs_sim* s : b->members) rates = rates || s->d_rates != nullptr;
+    const void* kfn = fsk::step_batch_kernel_fn(b->storage, b->weighted == 1, rates);
     const void* hfn = fsk::heavy_batch_kernel_fn(b->weighted == 1);
     if (!kfn || !hfn) return fail(FS_ERR_DEVICE, "no batch kernel for this configuration");
     for (uint32_t j = 0; j < r; ++j) {
@@ -307,9 +308,11 @@ fs_status fs_batch_add(fs_batch* b, fs_sim* s)
         return fail(FS_ERR_INVALID_ARG, "batch members run the streaming step: create the sim with variant = 1");
     if (s->storage != b->storage) return fail(FS_ERR_INVALID_ARG, "sim storage differs from the batch's");
     if (s->p.adaptive) return fail(FS_ERR_INVALID_ARG, "adaptive-step sims cannot join a batch");
-    const int w = s->g->d_weights != nullptr, rt = s->d_rates != nullptr;
-    if (!b->members.empty() && (w != b->weighted || rt != b->rates))
-        return fail(FS_ERR_INVALID_ARG, "batch members must agree on weights and record_rates");
+    if (s->p.shedding != FS_SHED_CONSTANT) return fail(FS_ERR_INVALID_ARG, "sims with age-dependent shedding cannot join a batch");
+    if (s->p.compaction) return fail(FS_ERR_INVALID_ARG, "sims with compaction cannot join a batch");
+    const int w = s->g->d_weights != nullptr;
+    if (!b->members.empty() && w != b->weighted)
+        return fail(FS_ERR_INVALID_ARG, "batch members must agree on weights");
     DeviceGuard dg(b->device);
     FS_HIP(hipStreamSynchronize(s->stream));
     attach(b, s);
@@ -715,6 +718,8 @@ fs_status fs_server_submit(fs_server* sv, const fs_request* rq, int64_t* id)
     if (rq->graph->device != sv->device) return fail(FS_ERR_INVALID_ARG, "graph is on another device");
     if (rq->params.n_replicas < 1 || rq->params.n_replicas > 64) return fail(FS_ERR_INVALID_ARG, "n_replicas out of range");
     if (rq->params.adaptive) return fail(FS_ERR_INVALID_ARG, "the server runs fixed-step requests only");
+    if (rq->params.shedding != FS_SHED_CONSTANT || rq->params.compaction)
+        return fail(FS_ERR_INVALID_ARG, "the server runs constant-shedding requests without compaction only");
     for (int64_t j = 0; j < rq->n_seeds; ++j)
         if (rq->seeds[j] < 0 || rq->seeds[j] >= rq->graph->n) return fail(FS_ERR_INVALID_ARG, "seed node out of range");
     auto q = std::make_shared<Request>();

@@ -161,6 +161,58 @@ __device__ __forceinline__ float hazard(const HazardDev& h, float x)
 }
 
 // ---------------------------------------------------------------------------
+// Shedding profiles s(x) (Eq. (infectivity)); parameters as in ShedDev.
+// Exponents are formed in float-float and exp(e_hi + e_lo) is taken as
+// exp(e_hi) (1 + e_lo).
+// ---------------------------------------------------------------------------
+using fsi::ShedDev;
+
+__device__ __forceinline__ float exp_ff(ff e)
+{
+    const float E = expf(e.hi);
+    return __builtin_isinf(E) ? E : __builtin_fmaf(E, e.lo, E);
+}
+
+__device__ __forceinline__ float shed_density(const ShedDev& s, float x)
+{
+    if (!(x > 0.0f)) return s.s0;
+    const HazardDev& h = s.hz;
+    switch (h.kind) {
+    case fsi::K_LN: {
+        const ff t = ff_add(log_ff(x), ff{h.c_hi, h.c_lo});
+        const ff z = ff_mul(t, ff{h.g_hi, h.g_lo});
+        const ff sq = two_prod(z.hi, z.hi);
+        const float lo = __builtin_fmaf(2.0f * z.hi, z.lo, sq.lo);
+        return h.K * exp_ff(ff{-sq.hi, -lo}) / x;
+    }
+    case fsi::K_WB: {
+        const ff t = ff_add(log_ff(x), ff{h.c_hi, h.c_lo});
+        const ff a = ff_mul(t, ff{h.g_hi, h.g_lo});
+        const float w = exp_ff(ff_mul(t, ff{s.m_hi, s.m_lo})); // (tau / scale)^shape
+        return h.K * exp_ff(ff_add(a, ff{-w, 0.0f}));
+    }
+    case fsi::K_ERL: {
+        const ff p = two_prod(h.x_hi, x);
+        const ff y = quick_two_sum(p.hi, __builtin_fmaf(h.x_lo, x, p.lo));
+        const ff L = ff_add(log_ff(y.hi), ff{y.lo / y.hi, 0.0f});
+        ff e = ff_mul(L, ff{(float)(h.k - 1), 0.0f});
+        e = ff_add(e, ff{-y.hi, -y.lo});
+        e = ff_add(e, ff{-s.lf_hi, -s.lf_lo});
+        return h.K * exp_ff(e);
+    }
+    default: {
+        const ff p = two_prod(h.x_hi, x);
+        return h.K * exp_ff(ff{-p.hi, -__builtin_fmaf(h.x_lo, x, p.lo)});
+    }
+    }
+}
+
+__device__ __forceinline__ float shed(const ShedDev& s, float x)
+{
+    return s.density ? shed_density(s, x) : hazard(s.hz, x);
+}
+
+// ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of
 //   (c0,c1,c2,c3) <- (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0))
 // with the key advanced by the Weyl increments between rounds.

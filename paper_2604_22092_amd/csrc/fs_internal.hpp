@@ -31,6 +31,11 @@ constexpr uint32_t SUMMARY_BITS = 1u << 20;
 constexpr int UNIFORM_MAX_DEG = FS_UMAX;
 // Bitmaps are allocated in whole 512-unit tiles (8 words of 64 bits).
 constexpr uint32_t BITMAP_TILE = 512;
+// Active-chunk compaction: the refresh runs one workgroup of WG_REFRESH
+// threads, each taking 16 flags per tile, so flag arrays are padded to whole
+// tiles of LIVE_TILE chunks.
+constexpr int WG_REFRESH = 1024;
+constexpr uint32_t LIVE_TILE = 16 * WG_REFRESH;
 
 // Hazard parameters, prepared on the host in double precision and rounded
 // once.  Ages reach the device in a unit u: days (FP32 storage) or steps of
@@ -49,6 +54,25 @@ struct HazardDev {
     float c_hi, c_lo;
     float g_hi, g_lo;
     float x_hi, x_lo;
+};
+
+// Shedding profile s(x) of an infectious unit of age x (Eq. (infectivity)),
+// in the age unit u of the storage, prepared on the host in double precision
+// with the scale A folded in:
+//   hazard form (density == 0): s = A h(x), the hazard of `hz` with K scaled by A;
+//   density form (density != 0), s = A f(x) by hz.kind:
+//     log-normal:  s = K exp(-z^2) / x,  z = (ln x + c) g,  K = A / (sigma sqrt(2 pi) u)
+//     Weibull:     s = K exp(g t - exp(m t)),  t = ln x + c,  K = A shape / scale,
+//                  g = shape - 1, m = shape
+//     Erlang:      s = K exp((k - 1) ln y - y - lf),  y = xr x,  K = A rate, lf = ln (k - 1)!
+//     exponential: s = K exp(-y),  y = xr x,  K = A rate
+//   with c, g and xr = rate u as in HazardDev; x = 0 gives s0 (the right limit).
+struct ShedDev {
+    HazardDev hz;
+    int32_t density;
+    float s0;
+    float m_hi, m_lo;
+    float lf_hi, lf_lo;
 };
 
 // Device-resident control block of a simulation.  `step` is the index of the
@@ -70,7 +94,7 @@ struct StepArgs {
     void* age;            // float days or uint16 steps, [n][R]
     void* iota0;          // infectivity bitmaps, bit u = 1{X_u = I}; step k reads
     void* iota1;          // iota[k & 1] and writes iota[(k + 1) & 1]
-    float* rates;         // optional per-unit lambda (debug), [n][R]
+    float* rates;         // optional per-unit lambda (debug), [n][R]; nullptr: none
     const Ctl* ctl;
     uint32_t* part;       // per-workgroup counts [chunk slot][grid][R][4]
     int32_t n;
@@ -119,6 +143,21 @@ struct StepArgs {
     float eps, delta;
     uint32_t hist_len;
     uint32_t pad1;
+    // age-dependent shedding (shedding kernels only): float s(tau) of every
+    // unit that is infectious, [n][R], ping-pong like the bitmaps (only units
+    // whose bit is set are ever read)
+    float* shed0;
+    float* shed1;
+    ShedDev shed;
+    // active-chunk compaction (nullptr act: off): the launch walks the chunks
+    // act[2 .. 2 + act[0]) (ascending); every other chunk holds only R units
+    // and is skipped, and act[1] R units per replica are added to the counts
+    // of workgroup 0.  When live is set (the last step of a launch sequence,
+    // whose flags the next sequence's refresh reads), every processed chunk
+    // stores 1 in live[chunk] when it held a unit that is not R at the start
+    // of the step, else 0.
+    const uint32_t* act;
+    uint8_t* live;
 };
 
 // Arguments of the summary launch that follows a step launch (or a bitmap
@@ -156,6 +195,11 @@ struct HeavyArgs {
     int32_t lgR;
     uint32_t step_off;
     uint32_t pad;
+    const float* shed0; // shedding kernels: the s(tau) buffers of StepArgs
+    const float* shed1;
+    const void* state;  // start-of-step states: segments of rows that are not S
+    int32_t storage;    // in any replica are skipped (0: int32 states, 1: uint8)
+    int32_t pad2;
 };
 
 // One member's count reduction in a batch: per-workgroup partials of G

@@ -8,12 +8,20 @@
 
 namespace fsk {
 
-// Address of the fused step kernel for a storage/weights/rates combination
+// Address of the fused step kernel for a storage/weights combination
 // (launched with one StepArgs argument); mode is fsi::MODE_*: the LDS
 // variants run RESIDENT_TPB threads, one workgroup per compute unit, the
 // streaming variant STREAM_TPB threads per workgroup.
-// uniform selects the instantiation for layouts with StepArgs::udeg >= 0.
-const void* step_kernel_fn(int storage, bool weighted, bool rates, int mode, bool uniform);
+// uniform selects the instantiation for layouts with StepArgs::udeg >= 0;
+// shed the one for age-dependent shedding (StepArgs::shed0/shed1/shed);
+// extra the one that records rates (StepArgs::rates) and walks the
+// active-chunk list of compaction (StepArgs::act, live).
+const void* step_kernel_fn(int storage, bool weighted, int mode, bool uniform, bool shed, bool extra);
+// (the other (shed, extra) instantiations, each defined by a source of its own)
+const void* step_kernel_fn_extra(int storage, bool weighted, int mode, bool uniform);
+const void* step_kernel_fn_shed(int storage, bool weighted, int mode, bool uniform);
+const void* step_kernel_fn_shed_extra(int storage, bool weighted, int mode, bool uniform);
+const void* heavy_kernel_fn_shed(bool weighted);
 
 // Exact counts of one replica: per-workgroup partials (at most max_grid rows
 // of 4 in `part`) reduced into out4.
@@ -23,7 +31,7 @@ hipError_t launch_recount(int storage, const void* state, int32_t n, int32_t lgR
 // one block per slot, WG threads.
 const void* reduce_kernel_fn();
 // heavy_pressure_kernel(HeavyArgs): segment partials of degree-binned rows; WG threads.
-const void* heavy_kernel_fn(bool weighted);
+const void* heavy_kernel_fn(bool weighted, bool shed);
 // advance_kernel(Ctl*, uint32_t r): adds r to the step index; one thread.
 const void* advance_kernel_fn();
 // summary_kernel(SumArgs): one thread per summary bit (sum_words * 64 threads
@@ -34,7 +42,7 @@ const void* summary_kernel_fn();
 // block-to-member mapping):
 // step_batch_kernel(const StepArgs* table, const uint32_t* first, uint32_t members, uint32_t step_off),
 //   STREAM_TPB threads, first[members] workgroups;
-const void* step_batch_kernel_fn(int storage, bool weighted, bool rates);
+const void* step_batch_kernel_fn(int storage, bool weighted, bool extra);
 // heavy_batch_kernel(const HeavyArgs* table, const uint32_t* first, uint32_t members, uint32_t step_off), WG threads;
 const void* heavy_batch_kernel_fn(bool weighted);
 // reduce_batch_kernel(const RedArgs* table): grid (r, members), WG threads;
@@ -55,6 +63,19 @@ hipError_t launch_clear_u32(uint32_t* p, size_t n, hipStream_t s);
 hipError_t launch_set_ctl(fsi::Ctl* ctl, unsigned long long step, hipStream_t s);
 hipError_t launch_eval_hazard(const fsi::HazardDev& h, int32_t storage, const void* ages, float* out, int64_t n,
                               hipStream_t s);
+hipError_t launch_eval_shed(const fsi::ShedDev& sd, int32_t storage, const void* ages, float* out, int64_t n,
+                            hipStream_t s);
+// s(tau) of the infectious units into out (others untouched).
+hipError_t launch_rebuild_shed(int storage, const void* state, const void* age, uint32_t total,
+                               const fsi::ShedDev& sd, float* out, hipStream_t s);
+// Live flags of all nchunks chunks from the state.
+hipError_t launch_chunk_live(int storage, const void* state, uint32_t total, uint8_t* live, uint32_t nchunks,
+                             hipStream_t s);
+// compact_refresh_kernel(const uint8_t* live, uint32_t nchunks, uint32_t rows, uint32_t n, uint32_t* act):
+// one workgroup of WG_REFRESH threads; live padded with zeros to whole tiles of LIVE_TILE flags.
+const void* compact_refresh_kernel_fn();
+// clear_u32_kernel(uint32_t* p, size_t n): grid-stride zero fill, 256 threads.
+const void* clear_u32_kernel_fn();
 hipError_t launch_eval_philox(const uint4* ctr, uint32_t k0, uint32_t k1, uint4* out, int64_t n, hipStream_t s);
 
 } // namespace fsk

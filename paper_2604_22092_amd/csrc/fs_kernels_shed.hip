@@ -1,0 +1,22 @@
+// Step kernels with age-dependent shedding (Eq. (infectivity) with a
+// profile s(tau) other than 1; Table "agedep_overhead" measures its cost),
+// without rate recording and compaction; compiled apart from the other
+// step kernels so they all build in parallel.
+#include <hip/hip_runtime.h>
+
+#include "fs_kernels.hpp"
+#include "fs_step.hpp"
+
+namespace fsk {
+
+const void* step_kernel_fn_shed(int storage, bool weighted, int mode, bool uniform)
+{
+    return step_kernel_pick<true, false>(storage, weighted, mode, uniform);
+}
+
+const void* heavy_kernel_fn_shed(bool weighted)
+{
+    return weighted ? (const void*)&heavy_pressure_kernel<true, true> : (const void*)&heavy_pressure_kernel<false, true>;
+}
+
+} // namespace fsk

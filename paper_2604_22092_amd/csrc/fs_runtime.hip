@@ -127,6 +127,52 @@ fs_status prep_hazard(const fs_dist& d, int storage, double dt, HazardDev* h, co
     }
 }
 
+// Shedding profile of Eq. (infectivity) for the device (see fsi::ShedDev):
+// the law's hazard parameters, then the constant K and the extra terms of
+// the chosen form, in double precision, rounded once.
+fs_status prep_shed(int32_t form, const fs_dist& d, double A, int storage, double dt, fsi::ShedDev* sd)
+{
+    std::memset(sd, 0, sizeof *sd);
+    if (form == FS_SHED_CONSTANT) return FS_OK;
+    if (form != FS_SHED_DENSITY && form != FS_SHED_HAZARD)
+        return fail(FS_ERR_INVALID_ARG, "shedding must be FS_SHED_CONSTANT, FS_SHED_DENSITY or FS_SHED_HAZARD");
+    if (!(A >= 0.0) || !std::isfinite(A)) return fail(FS_ERR_INVALID_ARG, "shed_scale must be finite and >= 0");
+    fs_status st = prep_hazard(d, storage, dt, &sd->hz, "shed_law");
+    if (st != FS_OK) return st;
+    const double unit = storage == FS_STORAGE_COMPACT ? dt : 1.0;
+    const double sq2pi = std::sqrt(2.0 * M_PI);
+    if (form == FS_SHED_HAZARD) {
+        double K = d.a; // exponential, Erlang: the rate
+        if (d.kind == FS_DIST_LOGNORMAL) K = std::sqrt(2.0 / M_PI) / (d.b * unit);
+        if (d.kind == FS_DIST_WEIBULL) K = d.a / d.b;
+        sd->hz.K = (float)(A * K);
+        return FS_OK;
+    }
+    sd->density = 1;
+    switch (d.kind) {
+    case FS_DIST_LOGNORMAL:
+        sd->hz.K = (float)(A / (d.b * sq2pi * unit));
+        sd->s0 = 0.0f;
+        break;
+    case FS_DIST_WEIBULL:
+        sd->hz.K = (float)(A * d.a / d.b);
+        split(d.a, sd->m_hi, sd->m_lo);
+        sd->s0 = d.a == 1.0 ? (float)(A / d.b) : 0.0f;
+        break;
+    case FS_DIST_ERLANG:
+        sd->hz.K = (float)(A * d.a);
+        split(std::lgamma((double)d.k), sd->lf_hi, sd->lf_lo);
+        sd->s0 = d.k == 1 ? (float)(A * d.a) : 0.0f;
+        break;
+    default: // exponential
+        sd->hz.K = (float)(A * d.a);
+        split(d.a * unit, sd->hz.x_hi, sd->hz.x_lo);
+        sd->s0 = (float)(A * d.a);
+        break;
+    }
+    return FS_OK;
+}
+
 size_t state_bytes(int storage) { return storage == FS_STORAGE_FP32 ? 4 : 1; }
 size_t age_bytes(int storage) { return storage == FS_STORAGE_FP32 ? 4 : 2; }
 // 64-bit words of an infectivity bitmap of `units` bits, in whole tiles.
@@ -142,7 +188,8 @@ void release_sim(fs_sim* s)
     if (s->stream) {
         for (void* p : {s->d_state, s->d_age, s->d_iota[0], s->d_iota[1], (void*)s->d_rates, (void*)s->d_ctl,
                         (void*)s->d_hist, (void*)s->d_part, (void*)s->d_rc_part, (void*)s->d_cnt4,
-                        (void*)s->d_summary, s->d_seg_part, (void*)s->d_lam_part, (void*)s->d_dt_hist})
+                        (void*)s->d_summary, s->d_seg_part, (void*)s->d_lam_part, (void*)s->d_dt_hist,
+                        (void*)s->d_shed[0], (void*)s->d_shed[1], (void*)s->d_live, (void*)s->d_act})
             sim_free(s, p);
     }
     s->layout.reset();
@@ -160,7 +207,9 @@ fs_status check_replica(const fs_sim* s, int32_t replica, bool allow_all)
 
 constexpr uint32_t RC_GRID = 1024;
 
-// Launch sequence of r steps: r step launches, one reduce, one advance.
+// Launch sequence of r steps: (with compaction: a rates clear when rates are
+// recorded, and the active-list refresh) r step launches, one reduce, one
+// advance.
 struct SeqArgs {
     std::vector<StepArgs> step;
     std::vector<fsi::HeavyArgs> heavy;
@@ -170,7 +219,15 @@ struct SeqArgs {
     const uint32_t* part;
     uint32_t G, C, H, r;
     uint32_t* hist;
+    // compaction refresh
+    const uint8_t* live;
+    uint32_t nchunks, rows, n;
+    uint32_t* act;
+    uint32_t* rates;
+    size_t rates_words;
 };
+
+uint32_t clear_grid(size_t words) { return (uint32_t)std::max<size_t>(1, std::min<size_t>((words + 255) / 256, 4096)); }
 
 uint32_t heavy_grid(const fs_sim* s)
 {
@@ -333,6 +390,8 @@ size_t sim_footprint(fs_graph* g, const fs_sim_params* p)
     }
     b += (size_t)g->nnz / 64 * 4 * R;                       // heavy-segment partials (upper bound)
     if (p->record_rates) b += units * 4;
+    if (p->shedding != FS_SHED_CONSTANT) b += units * 8;
+    if (p->compaction) b += (units / 64 + 1) * 5 + fsi::LIVE_TILE;
     return b + ((size_t)1 << 20);
 }
 
@@ -381,7 +440,8 @@ fs_status apply_bins(fs_sim* s, int32_t heavy_deg, int32_t seg_edges)
     s->args.chunk_meta = L->d_chunk_meta;
     s->args.orig_id = g->d_orig;
     s->args.udeg = L->udeg;
-    s->kfn = fsk::step_kernel_fn(s->storage, g->d_weights != nullptr, s->d_rates != nullptr, s->mode, L->udeg >= 0);
+    s->kfn = fsk::step_kernel_fn(s->storage, g->d_weights != nullptr, s->mode, L->udeg >= 0, s->d_shed[0] != nullptr,
+                                 s->d_rates != nullptr || s->d_act != nullptr);
     s->args.col_t = L->d_col_t;
     s->args.w_t = L->d_w_t;
     return FS_OK;
@@ -414,6 +474,27 @@ hipError_t refresh_summary(fs_sim* s)
     return hipLaunchKernel(fsk::summary_kernel_fn(), dim3(summary_grid(s)), dim3(WG), argv, 0, s->stream);
 }
 
+// After a change of states from the host (seeding, a state load): the
+// shedding values s(tau) of the infectious units, read by step `step`, and
+// the live flags of every chunk for compaction.
+hipError_t refresh_derived(fs_sim* s, int64_t step)
+{
+    const uint32_t total = (uint32_t)(s->g->n * s->R);
+    hipError_t e = hipSuccess;
+    // compaction: a chunk the next refresh drops is never written again, so
+    // the other bitmap must hold its (all-R, zero) words too
+    if (s->d_live &&
+        (e = fsk::launch_rebuild_bits(s->storage, s->d_state, total, (unsigned long long*)s->d_iota[(step + 1) & 1],
+                                      s->bit_words, s->stream)) != hipSuccess)
+        return e;
+    if (s->d_shed[0] &&
+        (e = fsk::launch_rebuild_shed(s->storage, s->d_state, s->d_age, total, s->shed, s->d_shed[step & 1],
+                                      s->stream)) != hipSuccess)
+        return e;
+    if (s->d_live) e = fsk::launch_chunk_live(s->storage, s->d_state, total, s->d_live, s->nchunks, s->stream);
+    return e;
+}
+
 fsi::HeavyArgs heavy_args(const fs_sim* s)
 {
     fsi::HeavyArgs h{};
@@ -426,6 +507,10 @@ fsi::HeavyArgs heavy_args(const fs_sim* s)
     h.ctl = s->d_ctl;
     h.nseg = s->nseg;
     h.lgR = s->lgR;
+    h.shed0 = s->d_shed[0];
+    h.shed1 = s->d_shed[1];
+    h.state = s->d_state;
+    h.storage = s->storage;
     return h;
 }
 
@@ -434,6 +519,9 @@ void make_seq(fs_sim* s, uint32_t r, SeqArgs& q)
 {
     q.step.assign(r, s->args);
     for (uint32_t j = 0; j < r; ++j) q.step[j].step_off = j;
+    // compaction: only the sequence's last step records the live flags the
+    // next refresh reads
+    for (uint32_t j = 0; j + 1 < r; ++j) q.step[j].live = nullptr;
     q.heavy.clear();
     if (s->nseg) {
         q.heavy.assign(r, heavy_args(s));
@@ -452,6 +540,13 @@ void make_seq(fs_sim* s, uint32_t r, SeqArgs& q)
     q.H = (uint32_t)s->H;
     q.r = r;
     q.hist = s->d_hist;
+    q.live = s->d_live;
+    q.nchunks = s->nchunks;
+    q.rows = 64u >> s->lgR;
+    q.n = (uint32_t)s->g->n;
+    q.act = s->d_act;
+    q.rates = (uint32_t*)s->d_rates;
+    q.rates_words = (size_t)s->g->n * (size_t)s->R;
 }
 
 fs_status build_graph_exec(fs_sim* s, int b)
@@ -474,6 +569,15 @@ fs_status build_graph_exec(fs_sim* s, int b)
         return FS_OK;
     };
     fs_status st;
+    if (s->d_act) {
+        if (q.rates) {
+            void* cargv[] = {&q.rates, &q.rates_words};
+            if ((st = add(fsk::clear_u32_kernel_fn(), dim3(clear_grid(q.rates_words)), dim3(256), cargv)) != FS_OK)
+                return st;
+        }
+        void* fargv[] = {&q.live, &q.nchunks, &q.rows, &q.n, &q.act};
+        if ((st = add(fsk::compact_refresh_kernel_fn(), dim3(1), dim3(fsi::WG_REFRESH), fargv)) != FS_OK) return st;
+    }
     for (int j = 0; j < b; ++j) {
         if (s->nseg) {
             void* hargv[] = {&q.heavy[j]};
@@ -498,6 +602,15 @@ fs_status launch_sequence(fs_sim* s, uint32_t r)
 {
     SeqArgs q;
     make_seq(s, r, q);
+    if (s->d_act) {
+        if (q.rates) {
+            void* cargv[] = {&q.rates, &q.rates_words};
+            FS_HIP(hipLaunchKernel(fsk::clear_u32_kernel_fn(), dim3(clear_grid(q.rates_words)), dim3(256), cargv, 0,
+                                   s->stream));
+        }
+        void* fargv[] = {&q.live, &q.nchunks, &q.rows, &q.n, &q.act};
+        FS_HIP(hipLaunchKernel(fsk::compact_refresh_kernel_fn(), dim3(1), dim3(fsi::WG_REFRESH), fargv, 0, s->stream));
+    }
     for (uint32_t j = 0; j < r; ++j) {
         if (s->nseg) {
             void* hargv[] = {&q.heavy[j]};
@@ -701,6 +814,11 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
     fs_status st;
     if ((st = prep_hazard(p->ei, p->storage, p->dt, &hz[0], "ei")) != FS_OK) return st;
     if ((st = prep_hazard(p->ir, p->storage, p->dt, &hz[1], "ir")) != FS_OK) return st;
+    fsi::ShedDev shed;
+    if ((st = prep_shed(p->shedding, p->shed_law, p->shed_scale, p->storage, p->dt, &shed)) != FS_OK) return st;
+    const bool shedding = p->shedding != FS_SHED_CONSTANT;
+    if (shedding && (int64_t)g->n * R >= (int64_t)1 << 29)
+        return fail(FS_ERR_INVALID_ARG, "age-dependent shedding needs n * n_replicas below 2^29");
 
     DeviceGuard dg(g->device);
     fs_sim* s = new fs_sim();
@@ -763,6 +881,9 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
         s->G = (uint32_t)std::min<size_t>(tiles, fsi::max_step_grid(R));
     }
     s->bit_words = (uint32_t)bitmap_words(units);
+    s->nchunks = (uint32_t)chunks;
+    s->live_bytes = (chunks + fsi::LIVE_TILE - 1) / fsi::LIVE_TILE * fsi::LIVE_TILE;
+    s->shed = shed;
     s->chunk = (uint32_t)std::max(p->steps_per_graph, 64);
     const size_t hist_words = (size_t)s->H * R * 4;
     const size_t part_words = (size_t)s->chunk * s->G * R * 4;
@@ -780,7 +901,11 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
         (s->mode == fsi::MODE_SUMMARY &&
          (e = sim_alloc(s, (void**)&s->d_summary, ((size_t)s->sum_bits + 511) / 512 * 64)) != hipSuccess) ||
         (p->adaptive && ((e = sim_alloc(s, (void**)&s->d_lam_part, 2 * (size_t)s->G * sizeof(float))) != hipSuccess ||
-                         (e = sim_alloc(s, (void**)&s->d_dt_hist, (size_t)s->H * sizeof(float))) != hipSuccess)))
+                         (e = sim_alloc(s, (void**)&s->d_dt_hist, (size_t)s->H * sizeof(float))) != hipSuccess)) ||
+        (shedding && ((e = sim_alloc(s, (void**)&s->d_shed[0], units * sizeof(float))) != hipSuccess ||
+                      (e = sim_alloc(s, (void**)&s->d_shed[1], units * sizeof(float))) != hipSuccess)) ||
+        (p->compaction && ((e = sim_alloc(s, (void**)&s->d_live, s->live_bytes)) != hipSuccess ||
+                           (e = sim_alloc(s, (void**)&s->d_act, (2 + chunks) * sizeof(uint32_t))) != hipSuccess)))
         return bad(e, "device allocation");
     if ((e = hipMemsetAsync(s->d_state, 0, units * state_bytes(s->storage), s->stream)) != hipSuccess ||
         (e = hipMemsetAsync(s->d_age, 0, units * age_bytes(s->storage), s->stream)) != hipSuccess ||
@@ -791,6 +916,12 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
         (e = hipMemsetAsync(s->d_hist, 0, hist_words * sizeof(uint32_t), s->stream)) != hipSuccess ||
         (s->d_summary &&
          (e = hipMemsetAsync(s->d_summary, 0, ((size_t)s->sum_bits + 511) / 512 * 64, s->stream)) != hipSuccess) ||
+        (s->d_shed[0] && (e = hipMemsetAsync(s->d_shed[0], 0, units * sizeof(float), s->stream)) != hipSuccess) ||
+        (s->d_shed[1] && (e = hipMemsetAsync(s->d_shed[1], 0, units * sizeof(float), s->stream)) != hipSuccess) ||
+        // every unit starts in S: every chunk is live; the padding never is
+        (s->d_live && (e = hipMemsetAsync(s->d_live, 0, s->live_bytes, s->stream)) != hipSuccess) ||
+        (s->d_live && (e = hipMemsetAsync(s->d_live, 1, chunks, s->stream)) != hipSuccess) ||
+        (s->d_act && (e = hipMemsetAsync(s->d_act, 0, (2 + chunks) * sizeof(uint32_t), s->stream)) != hipSuccess) ||
         (e = hipStreamSynchronize(s->stream)) != hipSuccess)
         return bad(e, "initialisation");
 
@@ -824,8 +955,14 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
     a.dt = (float)p->dt;
     a.key0 = (uint32_t)p->seed;
     a.key1 = (uint32_t)(p->seed >> 32);
-    s->kfn = fsk::step_kernel_fn(s->storage, g->d_weights != nullptr, p->record_rates != 0, s->mode, false);
-    s->hfn = fsk::heavy_kernel_fn(g->d_weights != nullptr);
+    a.shed0 = s->d_shed[0];
+    a.shed1 = s->d_shed[1];
+    a.shed = shed;
+    a.act = s->d_act;
+    a.live = s->d_live;
+    s->kfn = fsk::step_kernel_fn(s->storage, g->d_weights != nullptr, s->mode, false, shedding,
+                                 s->d_rates != nullptr || s->d_act != nullptr);
+    s->hfn = fsk::heavy_kernel_fn(g->d_weights != nullptr, shedding);
     if (!s->kfn || !s->hfn) {
         release_sim(s);
         return fail(FS_ERR_DEVICE, "no step kernel for this configuration");
@@ -886,6 +1023,7 @@ fs_status fs_sim_seed(fs_sim* s, int32_t replica, int64_t count, const int64_t* 
                             compartment, s->stream));
     FS_HIP(fsk::launch_rebuild_bits(s->storage, s->d_state, (uint32_t)(s->g->n * s->R),
                                     (unsigned long long*)s->d_iota[s->step & 1], s->bit_words, s->stream));
+    FS_HIP(refresh_derived(s, s->step));
     FS_HIP(refresh_summary(s));
     FS_HIP(hipStreamSynchronize(s->stream));
     return FS_OK;
@@ -1072,6 +1210,7 @@ fs_status fs_set_state(fs_sim* s, int32_t replica, const int32_t* state, const f
                                    replica, s->stream));
     FS_HIP(fsk::launch_rebuild_bits(s->storage, s->d_state, (uint32_t)units,
                                     (unsigned long long*)s->d_iota[new_step & 1], s->bit_words, s->stream));
+    FS_HIP(refresh_derived(s, new_step));
     // the step index, and (adaptive steps) a restart of the step-size rule at the cap
     FS_HIP(fsk::launch_set_ctl(s->d_ctl, (unsigned long long)new_step, s->stream));
     FS_HIP(refresh_summary(s));
@@ -1149,6 +1288,10 @@ fs_status fs_sim_tune(fs_sim* s, int32_t trial_steps, int32_t* heavy_degree, int
                   {s->d_hist, (size_t)s->H * s->R * 4 * sizeof(uint32_t), {}},
                   {s->d_summary, s->d_summary ? ((size_t)s->sum_bits + 511) / 512 * 64 : 0, {}},
                   {s->d_lam_part, 2 * (size_t)s->G * sizeof(float), {}},
+                  {s->d_shed[0], (size_t)s->g->n * s->R * sizeof(float), {}},
+                  {s->d_shed[1], (size_t)s->g->n * s->R * sizeof(float), {}},
+                  {s->d_live, s->live_bytes, {}},
+                  {s->d_act, (2 + (size_t)s->nchunks) * sizeof(uint32_t), {}},
                   {s->d_dt_hist, (size_t)s->H * sizeof(float), {}}};
     for (auto& b : bufs) {
         if (!b.live) continue;
@@ -1224,6 +1367,32 @@ fs_status fs_eval_hazard(const fs_dist* law, int32_t storage, double dt, int64_t
     FS_HIP(dev_alloc(&dout.p, (size_t)n * sizeof(float)));
     FS_HIP(hipMemcpy(da.p, ages, (size_t)n * ab, hipMemcpyHostToDevice));
     FS_HIP(fsk::launch_eval_hazard(h, storage, da.p, (float*)dout.p, n, nullptr));
+    FS_HIP(hipMemcpy(out, dout.p, (size_t)n * sizeof(float), hipMemcpyDeviceToHost));
+    FS_HIP(hipDeviceSynchronize());
+    return FS_OK;
+    FS_GUARD_END
+}
+
+fs_status fs_eval_shedding(const fs_dist* law, int32_t form, double scale, int32_t storage, double dt, int64_t n,
+                           const void* ages, float* out)
+{
+    FS_GUARD_BEGIN
+    if (!law || (n > 0 && (!ages || !out))) return fail(FS_ERR_INVALID_ARG, "NULL argument");
+    if (storage != FS_STORAGE_FP32 && storage != FS_STORAGE_COMPACT) return fail(FS_ERR_INVALID_ARG, "unknown storage");
+    if (!(dt > 0.0)) return fail(FS_ERR_INVALID_ARG, "dt must be > 0");
+    if (n < 0) return fail(FS_ERR_INVALID_ARG, "n < 0");
+    if (form != FS_SHED_DENSITY && form != FS_SHED_HAZARD)
+        return fail(FS_ERR_INVALID_ARG, "form must be FS_SHED_DENSITY or FS_SHED_HAZARD");
+    fsi::ShedDev sd;
+    fs_status st = prep_shed(form, *law, scale, storage, dt, &sd);
+    if (st != FS_OK) return st;
+    if (n == 0) return FS_OK;
+    const size_t ab = storage == FS_STORAGE_FP32 ? 4 : 2;
+    DevBuf da, dout;
+    FS_HIP(dev_alloc(&da.p, (size_t)n * ab));
+    FS_HIP(dev_alloc(&dout.p, (size_t)n * sizeof(float)));
+    FS_HIP(hipMemcpy(da.p, ages, (size_t)n * ab, hipMemcpyHostToDevice));
+    FS_HIP(fsk::launch_eval_shed(sd, storage, da.p, (float*)dout.p, n, nullptr));
     FS_HIP(hipMemcpy(out, dout.p, (size_t)n * sizeof(float), hipMemcpyDeviceToHost));
     FS_HIP(hipDeviceSynchronize());
     return FS_OK;

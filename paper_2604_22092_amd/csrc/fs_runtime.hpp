@@ -88,6 +88,12 @@ struct fs_sim {
     uint32_t* d_cnt4 = nullptr;
     float* d_lam_part = nullptr;   // adaptive step: per-workgroup rate maxima [2][G]
     float* d_dt_hist = nullptr;    // adaptive step: step size of each step, ring of H
+    float* d_shed[2] = {nullptr, nullptr}; // age-dependent shedding: s(tau) per unit, ping-pong
+    uint8_t* d_live = nullptr;     // compaction: live flag per chunk, zero-padded to LIVE_TILE
+    uint32_t* d_act = nullptr;     // compaction: [2 + nchunks] active-chunk list
+    uint32_t nchunks = 0;          // 64-unit chunks
+    size_t live_bytes = 0;
+    fsi::ShedDev shed{};
     int H = 1024;
     uint32_t G = 0;                // step workgroups
     uint32_t tpb = 0;              // threads (units) per step workgroup / tile

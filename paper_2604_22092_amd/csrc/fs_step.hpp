@@ -1,0 +1,850 @@
+// The fused step of the renewal tau-leap (FlashSpread, arXiv 2604.22092,
+// Algorithm 3 with Eq. (influence), Eq. (infectivity), Proposition 1 and the
+// Bernoulli tau-leap rule) as templates, instantiated by the kernel sources
+// of the library (constant shedding in one, age-dependent shedding in the
+// other, so the two compile in parallel).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fs_device.hpp"
+#include "fs_internal.hpp"
+
+namespace fsk {
+
+using namespace fsi;
+
+template <int STORAGE>
+struct Store;
+template <>
+struct Store<0> {
+    using state_t = int32_t;
+    using age_t = float;
+};
+template <>
+struct Store<1> {
+    using state_t = uint8_t;
+    using age_t = uint16_t;
+};
+
+__device__ __forceinline__ uint32_t age_bits(float a) { return __float_as_uint(a); }
+__device__ __forceinline__ uint32_t age_bits(uint16_t a) { return a; }
+template <class T>
+__device__ __forceinline__ float age_from_bits(uint32_t w);
+template <>
+__device__ __forceinline__ float age_from_bits<float>(uint32_t w) { return __uint_as_float(w); }
+template <>
+__device__ __forceinline__ float age_from_bits<uint16_t>(uint32_t w) { return (float)w; }
+__device__ __forceinline__ float age_units(float a) { return a; }
+__device__ __forceinline__ float age_units(uint16_t a) { return (float)a; }
+__device__ __forceinline__ float age_next(float a, float dt) { return a + dt; }
+__device__ __forceinline__ uint16_t age_next(uint16_t a, float) { return a == 65535 ? a : (uint16_t)(a + 1); }
+template <class T>
+__device__ __forceinline__ T age_from_raw(uint32_t w);
+template <>
+__device__ __forceinline__ float age_from_raw<float>(uint32_t w) { return __uint_as_float(w); }
+template <>
+__device__ __forceinline__ uint16_t age_from_raw<uint16_t>(uint32_t w) { return (uint16_t)w; }
+__device__ __forceinline__ uint32_t age_to_raw(float a) { return __float_as_uint(a); }
+__device__ __forceinline__ uint32_t age_to_raw(uint16_t a) { return a; }
+
+// Infectivity is held as one bit per unit (bit u = 1{X_u = I}); with constant
+// shedding s = 1 this is the exact value of Eq. (infectivity) without beta.
+__device__ __forceinline__ uint32_t bit_at(const uint32_t* __restrict__ w, uint32_t b)
+{
+    return (w[b >> 5] >> (b & 31)) & 1u;
+}
+
+__device__ __forceinline__ uint32_t lds_bit(const uint32_t* __restrict__ w, uint32_t b)
+{
+    return __builtin_amdgcn_ubfe(w[b >> 5], b & 31, 1);
+}
+
+// Raw buffer accesses.  Word 3 of the descriptor (0x00020000) is the gfx9
+// raw-buffer format: 32-bit data, no swizzle, range checked against the byte
+// count in word 2.  An access whose offset is outside that range reads 0 and
+// writes nothing, with no memory request.  The step uses this instead of
+// branches: lanes and slots that must not touch memory get offset OOB, and
+// every path issues the same memory instructions, so the compiler can wait
+// for exactly the loads it needs while later loads are still in flight.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int BUF_WORD3 = 0x00020000;
+constexpr uint32_t OOB = 0x80000000u; // beyond every byte range used here (< 2^31)
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, BUF_WORD3);
+}
+__device__ __forceinline__ uint32_t ld32(rsrc_t r, uint32_t off) { return __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0); }
+__device__ __forceinline__ void st32(rsrc_t r, uint32_t off, uint32_t v) { __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)off, 0, 0); }
+
+// Element access of the storage types through a buffer descriptor.
+template <class T>
+struct BufIO;
+template <>
+struct BufIO<int32_t> {
+    __device__ static uint32_t ld(rsrc_t r, uint32_t i) { return ld32(r, i << 2); }
+    __device__ static void st(rsrc_t r, uint32_t i, uint32_t v) { st32(r, i << 2, v); }
+};
+template <>
+struct BufIO<float> {
+    __device__ static uint32_t ld(rsrc_t r, uint32_t i) { return ld32(r, i << 2); }
+    __device__ static void st(rsrc_t r, uint32_t i, uint32_t v) { st32(r, i << 2, v); }
+};
+template <>
+struct BufIO<uint8_t> {
+    __device__ static uint32_t ld(rsrc_t r, uint32_t i) { return __builtin_amdgcn_raw_buffer_load_b8(r, (int)i, 0, 0); }
+    __device__ static void st(rsrc_t r, uint32_t i, uint32_t v)
+    {
+        __builtin_amdgcn_raw_buffer_store_b8((uint8_t)v, r, (int)i, 0, 0);
+    }
+};
+template <>
+struct BufIO<uint16_t> {
+    __device__ static uint32_t ld(rsrc_t r, uint32_t i)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, (int)(i << 1), 0, 0);
+    }
+    __device__ static void st(rsrc_t r, uint32_t i, uint32_t v)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)v, r, (int)(i << 1), 0, 0);
+    }
+};
+// Element index that is out of range for every descriptor built here.
+constexpr uint32_t OOB_ELEM = OOB >> 2;
+
+// Infectivity bit b of the step's input for a lane that wants it (use):
+// from the LDS copy (MODE_RESIDENT), from global memory (MODE_STREAM), or
+// from global memory only when the LDS summary says its group holds an
+// infectious unit (MODE_SUMMARY).  Lanes that do not want it read nothing
+// from global memory and get 0.  b must be a valid unit index.
+template <int MODE>
+__device__ __forceinline__ uint32_t fetch_bit(const uint32_t* __restrict__ lds, rsrc_t gbits, uint32_t b,
+                                              int32_t lg_gran, bool use)
+{
+    if (MODE == MODE_RESIDENT) return use ? lds_bit(lds, b) : 0u;
+    bool go = use;
+    if (MODE == MODE_SUMMARY) go = go && lds_bit(lds, b >> lg_gran) != 0u;
+    const uint32_t w = ld32(gbits, go ? (b >> 5) << 2 : OOB);
+    return (w >> (b & 31)) & 1u;
+}
+
+// Light-row edge slots loaded ahead for chunks whose rows share one light
+// degree (every chunk of a regular graph): slot j of row q is col_t[base +
+// j*Q + q], so these loads need only the chunk's metadata and are issued with
+// the state and age loads.
+constexpr int UMAX = UNIFORM_MAX_DEG;
+// Edge slots per batch of the general (mixed-degree) gather.
+constexpr int JB = 8;
+// Chunks of 64 units each wavefront takes per pass; the hazards and draws of
+// a pass are evaluated on compacted lanes.
+#ifndef FS_CU
+#define FS_CU 1
+#endif
+constexpr int CU = FS_CU;
+// Issue the next pass's loads before processing the current one.
+#ifndef FS_PREFETCH
+#define FS_PREFETCH 1
+#endif
+constexpr bool PREFETCH = FS_PREFETCH != 0;
+
+// The loads of one pass, as issued: chunk numbers and metadata are
+// wave-uniform; xr, agw and dgr are the raw state, age and degree words
+// (0 for lanes past the chunk's valid units), used only after the pass's
+// wait.
+template <class age_t>
+struct Pass {
+    uint32_t chk[CU], base[CU], ud[CU], nvalid[CU];
+    bool live[CU];
+    uint32_t xr[CU], agw[CU], dgr[CU], org[CU];
+    int32_t c[CU][UMAX];
+};
+
+// Issues every load of a pass that does not depend on the state: chunk
+// metadata (one scalar load), state, age and light degree, and the edge
+// slots of uniform chunks (whose rows are all present).  Each array is read
+// through a descriptor covering only this chunk's valid entries, so no lane
+// branches and a pass past the last chunk reads nothing.  `first` is a
+// position in the walk of `walk` chunks: the chunk itself, or with
+// compaction (EXTRA kernels with an active list) the list entry at that
+// position, which the issue of the previous pass (or the walk's start)
+// loaded into ahead[u]; this issue loads the entry one stride further.  That
+// load is a vector load (every lane reads the same word) issued before the
+// pass's other loads: a scalar load would be waited for by the pass's first
+// LDS wait (scalar and LDS results share one counter), a vector load only by
+// the next issue, behind loads that are older anyway.
+template <int STORAGE, bool UNIFORM, bool EXTRA, class age_t>
+__device__ __forceinline__ void issue_pass(const StepArgs& a, uint32_t first, uint32_t nwaves, uint32_t stride,
+                                           uint32_t nchunks, uint32_t walk, uint32_t total, uint32_t lane,
+                                           Pass<age_t>& P, uint32_t* ahead)
+{
+    using state_t = typename Store<STORAGE>::state_t;
+    const uint32_t rows = 64u >> a.lgR;
+    const uint32_t q = lane >> a.lgR;
+#pragma unroll
+    for (int u = 0; u < CU; ++u) {
+        const uint32_t pos = __builtin_amdgcn_readfirstlane(first + (uint32_t)u * nwaves);
+        P.live[u] = pos < walk;
+        uint32_t c = P.live[u] ? pos : nchunks - 1; // (a pass past the walk reads nothing)
+        if (EXTRA && a.act) {
+            if (P.live[u]) c = __builtin_amdgcn_readfirstlane(ahead[u]);
+            ahead[u] = ld32(make_rsrc(a.act, (2u + walk) * 4u), (2u + pos + stride) << 2);
+        }
+        P.chk[u] = c;
+        if (UNIFORM) {
+            P.base[u] = P.chk[u] * rows * (uint32_t)a.udeg;
+            P.ud[u] = P.live[u] ? (uint32_t)a.udeg : 0u;
+        } else {
+            const uint2 meta = a.chunk_meta[P.chk[u]];
+            P.base[u] = meta.x;
+            P.ud[u] = P.live[u] ? meta.y : 0u;
+        }
+        const uint32_t u0 = P.chk[u] << 6;
+        P.nvalid[u] = P.live[u] ? min(64u, total - u0) : 0u;
+        const uint32_t n0 = u0 >> a.lgR;
+        const uint32_t nrows = P.live[u] ? min(rows, (uint32_t)a.n - n0) : 0u;
+        P.xr[u] = BufIO<state_t>::ld(make_rsrc((const state_t*)a.state + u0, P.nvalid[u] * sizeof(state_t)), lane);
+        P.agw[u] = BufIO<age_t>::ld(make_rsrc((const age_t*)a.age + u0, P.nvalid[u] * sizeof(age_t)), lane);
+        P.dgr[u] = BufIO<uint16_t>::ld(make_rsrc(a.ldeg + n0, nrows * 2u), q);
+        // graphs in a degree-sorted order (never uniform ones) key the draws
+        // by the caller's node id
+        P.org[u] = UNIFORM ? n0 + q : ld32(make_rsrc(a.orig_id + n0, nrows * 4u), q << 2);
+        const bool pre = P.ud[u] <= (uint32_t)UMAX;
+        const rsrc_t cr = make_rsrc(a.col_t + P.base[u], pre ? P.ud[u] * rows * 4u : 0u);
+#pragma unroll
+        for (int j = 0; j < UMAX; ++j) P.c[u][j] = (int32_t)ld32(cr, ((uint32_t)j * rows + q) << 2);
+    }
+}
+
+// Shedding values of the preloaded edge slots of a pass (resident variant):
+// the LDS bit of every slot a susceptible light row uses, then, for set bits,
+// the source's s(tau).  Issued before the next pass's loads, so the wait for
+// these values leaves the next pass's loads in flight (loads complete in
+// order).  Slots not used read nothing and hold 0.
+struct ShedPre {
+    float v[CU][UMAX];
+};
+
+template <bool UNIFORM, class age_t>
+__device__ __forceinline__ void shed_pre(const StepArgs& a, const Pass<age_t>& P, uint32_t lane,
+                                         const uint32_t* __restrict__ lds, rsrc_t shedr, ShedPre& S)
+{
+    const int32_t lgR = a.lgR;
+    const uint32_t rep = lane & ((1u << lgR) - 1u);
+#pragma unroll
+    for (int u = 0; u < CU; ++u) {
+        const bool valid = lane < P.nvalid[u];
+        const int x = valid ? (int)P.xr[u] : ST_R;
+        const uint32_t dg = valid ? P.dgr[u] : 0u;
+        const bool want = x == ST_S && (UNIFORM || dg != HEAVY_ROW);
+        const bool pre = UNIFORM || P.ud[u] <= (uint32_t)UMAX;
+#pragma unroll
+        for (int j = 0; j < UMAX; ++j) {
+            const bool use = pre && (uint32_t)j < P.ud[u] && want;
+            const uint32_t src = ((uint32_t)P.c[u][j] << lgR) + rep;
+            const uint32_t b = use ? lds_bit(lds, src) : 0u;
+            S.v[u][j] = __uint_as_float(ld32(shedr, b ? src << 2 : OOB));
+        }
+    }
+}
+
+// Pressure of one chunk's light row for this lane (Eq. (influence) without
+// beta).  Uniform chunks use the preloaded slots; mixed chunks find a row's
+// position in run j as its rank among the rows with more than j edges (ballot
+// prefix count), JB slots at a time.  With age-dependent shedding (SHED) a
+// source whose bit is set contributes its s(tau) from `shedr`; the value load
+// of every other slot is out of range and reads nothing.
+template <int MODE, bool WEIGHTED, bool UNIFORM, bool SHED, class age_t>
+__device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_t>& P, int u, bool want,
+                                              uint32_t dg, const uint32_t* __restrict__ lds, rsrc_t gbits,
+                                              rsrc_t shedr, const ShedPre& S, uint32_t lane)
+{
+    // shedding values of preloaded slots come from shed_pre (resident variant)
+    constexpr bool SPLIT = SHED && MODE == MODE_RESIDENT;
+    const int32_t lgR = a.lgR;
+    const uint32_t R = 1u << lgR;
+    const uint32_t rep = lane & (R - 1);
+    const uint32_t d = dg == HEAVY_ROW ? 0u : dg;
+    uint32_t pi = 0;
+    float pw = 0.0f;
+    if (UNIFORM || P.ud[u] <= (uint32_t)UMAX) {
+        // uniform chunk: slots past the degree hold 0 (a valid node) and are
+        // not used; weights come through the same per-chunk range
+        const uint32_t rows = 64u >> lgR;
+        const uint32_t q = lane >> lgR;
+        const rsrc_t wr = make_rsrc(WEIGHTED ? (const void*)(a.w_t + P.base[u]) : (const void*)a.w_t,
+                                    WEIGHTED ? P.ud[u] * rows * 4u : 0u);
+#pragma unroll
+        for (int j = 0; j < UMAX; ++j) {
+            const bool use = (uint32_t)j < P.ud[u] && want;
+            uint32_t b = 0;
+            float v;
+            if (SPLIT) {
+                v = S.v[u][j];
+            } else {
+                const uint32_t src = ((uint32_t)P.c[u][j] << lgR) + rep;
+                b = fetch_bit<MODE>(lds, gbits, src, a.lg_gran, use);
+                v = SHED ? __uint_as_float(ld32(shedr, b ? src << 2 : OOB)) : (float)b;
+            }
+            if (WEIGHTED) {
+                const float w = __uint_as_float(ld32(wr, use ? ((uint32_t)j * rows + q) << 2 : OOB));
+                pw = __builtin_fmaf(w, v, pw);
+            } else if (SHED) {
+                pw += v;
+            } else {
+                pi += b;
+            }
+        }
+    } else {
+        const unsigned long long below = (1ull << (lane & ~(R - 1))) - 1ull;
+        uint32_t off = P.base[u];
+        for (uint32_t j0 = 0;; j0 += JB) {
+            if (__ballot(rep == 0 && d > j0) == 0ull) break;
+            int32_t c[JB];
+            float wv[JB];
+#pragma unroll
+            for (int jj = 0; jj < JB; ++jj) {
+                const unsigned long long m = __ballot(rep == 0 && d > j0 + jj);
+                c[jj] = 0;
+                wv[jj] = 0.0f;
+                if (want && d > j0 + jj) {
+                    const uint32_t idx = off + (uint32_t)__popcll(m & below);
+                    c[jj] = a.col_t[idx];
+                    if (WEIGHTED) wv[jj] = a.w_t[idx];
+                }
+                off += (uint32_t)__popcll(m);
+            }
+#pragma unroll
+            for (int jj = 0; jj < JB; ++jj) {
+                if (want && d > j0 + jj) {
+                    const uint32_t src = ((uint32_t)c[jj] << lgR) + rep;
+                    const uint32_t b = fetch_bit<MODE>(lds, gbits, src, a.lg_gran, true);
+                    const float v = SHED ? __uint_as_float(ld32(shedr, b ? src << 2 : OOB)) : (float)b;
+                    if (WEIGHTED) pw = __builtin_fmaf(wv[jj], v, pw);
+                    else if (SHED) pw += v;
+                    else pi += b;
+                }
+            }
+        }
+    }
+    return (WEIGHTED || SHED) ? pw : (float)pi;
+}
+
+// Pressure of a degree-binned row: its segment partials in segment order
+// (float partials with weights or shedding values, else integer counts).
+template <bool FLOATP>
+__device__ __forceinline__ float pressure_heavy(const StepArgs& a, uint32_t node, uint32_t rep)
+{
+    const size_t R = (size_t)1 << a.lgR;
+    const int32_t dg = a.row_ptr[node + 1] - a.row_ptr[node];
+    const int32_t first = a.heavy_first[node];
+    const int32_t nseg = (dg + a.seg_edges - 1) / a.seg_edges;
+    if (FLOATP) {
+        const float* sp = (const float*)a.seg_part;
+        float p = 0.0f;
+        for (int32_t j = 0; j < nseg; ++j) p += sp[(size_t)(first + j) * R + rep];
+        return p;
+    }
+    const uint32_t* sp = (const uint32_t*)a.seg_part;
+    uint32_t p = 0;
+    for (int32_t j = 0; j < nseg; ++j) p += sp[(size_t)(first + j) * R + rep];
+    return (float)p;
+}
+
+// Evaluates f on the flagged items of CU chunks with the items packed into
+// consecutive lanes (64 per round), so a computation most lanes skip costs one
+// wavefront pass per 64 items instead of one per chunk.  xch is this
+// wavefront's 64-entry LDS exchange row; f maps a payload word to a result
+// word.  Only flagged items receive a result.
+template <int CU, class F>
+__device__ __forceinline__ void compact_apply(uint32_t* xch, uint32_t lane, const bool* flag,
+                                              const uint32_t* payload, uint32_t* result, F f)
+{
+    unsigned long long m[CU];
+    uint32_t pre[CU + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int u = 0; u < CU; ++u) {
+        m[u] = __ballot(flag[u]);
+        pre[u + 1] = pre[u] + (uint32_t)__popcll(m[u]);
+    }
+    const uint32_t total = pre[CU];
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    uint32_t slot[CU];
+#pragma unroll
+    for (int u = 0; u < CU; ++u) slot[u] = pre[u] + (uint32_t)__popcll(m[u] & lt);
+    for (uint32_t r0 = 0; r0 < total; r0 += 64) {
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+            if (flag[u] && slot[u] >= r0 && slot[u] < r0 + 64) xch[slot[u] - r0] = payload[u];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (r0 + lane < total) xch[lane] = f(xch[lane]);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+            if (flag[u] && slot[u] >= r0 && slot[u] < r0 + 64) result[u] = xch[slot[u] - r0];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// Everything of one pass after its loads were issued: rates (gather,
+// hazards), draws, stores, next-infectivity words (and, with SHED, the
+// s(tau') values of the units infectious after the step), counts, and the
+// chunk's live flag for compaction.
+template <int STORAGE, bool WEIGHTED, int MODE, bool UNIFORM, bool SHED, bool EXTRA, class age_t>
+__device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t>& P, uint32_t lane,
+                                             const uint32_t* __restrict__ s_bits, rsrc_t gbits, rsrc_t shedr,
+                                             float* __restrict__ shed_out, const ShedPre& sv,
+                                             uint32_t* xch, unsigned long long k,
+                                             unsigned long long* __restrict__ bits_out, uint32_t* s_cnt,
+                                             uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, float dt,
+                                             float& lmax)
+{
+    using state_t = typename Store<STORAGE>::state_t;
+    const uint32_t R = 1u << a.lgR;
+
+    // the pass's loaded words; lanes past the chunk's valid units act as R
+    bool valid[CU];
+    int x[CU];
+    age_t ag[CU];
+    uint32_t dg[CU], unit[CU];
+#pragma unroll
+    for (int u = 0; u < CU; ++u) {
+        valid[u] = lane < P.nvalid[u];
+        unit[u] = (P.chk[u] << 6) + lane;
+        x[u] = valid[u] ? (int)P.xr[u] : ST_R;
+        ag[u] = valid[u] ? age_from_raw<age_t>(P.agw[u]) : (age_t)0;
+        dg[u] = valid[u] ? P.dgr[u] : 0u;
+    }
+
+    // 1.-2. rate: beta * pressure for S; hazard at the start-of-step age for E/I; 0 for R
+    float lam[CU];
+#pragma unroll
+    for (int u = 0; u < CU; ++u) {
+        lam[u] = 0.0f;
+        const bool heavy = !UNIFORM && dg[u] == HEAVY_ROW;
+        const bool want = x[u] == ST_S && !heavy;
+        const float p =
+            pressure_row<MODE, WEIGHTED, UNIFORM, SHED>(a, P, u, want, dg[u], s_bits, gbits, shedr, sv, lane);
+        if (want) lam[u] = a.beta * p;
+        if (!UNIFORM && heavy && x[u] == ST_S)
+            lam[u] = a.beta * pressure_heavy<WEIGHTED || SHED>(a, unit[u] >> a.lgR, unit[u] & (R - 1));
+    }
+
+    // hazards of the E/I units of the pass, on compacted lanes; the payload
+    // is the age bit pattern with bit 31 marking the I -> R law (ages are
+    // non-negative, so bit 31 is free)
+    {
+        bool need[CU];
+        uint32_t pay[CU], res[CU];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            need[u] = x[u] == ST_E || x[u] == ST_I;
+            pay[u] = age_bits(ag[u]) | (x[u] == ST_I ? 0x80000000u : 0u);
+            res[u] = 0;
+        }
+        auto hz = [&](uint32_t w, bool isI) {
+            const float xa = age_from_bits<age_t>(w & 0x7FFFFFFFu);
+            float h;
+            if (a.same_kind) {
+                HazardDev hd = a.hz[0];
+                if (isI) hd = a.hz[1];
+                hd.kind = a.hz[0].kind;
+                h = fsd::hazard(hd, xa);
+            } else {
+                h = isI ? fsd::hazard(a.hz[1], xa) : fsd::hazard(a.hz[0], xa);
+            }
+            return h;
+        };
+        compact_apply<CU>(xch, lane, need, pay, res, [&](uint32_t w) {
+            return __float_as_uint(hz(w, (w & 0x80000000u) != 0u));
+        });
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+            if (need[u]) lam[u] = __uint_as_float(res[u]);
+    }
+
+    // 3.-4. Bernoulli tau-leap: fire when u < 1 - exp(-lambda dt); no draw at
+    // lambda = 0.  The Philox draws of the pass run on compacted lanes.
+    bool fire[CU];
+    {
+        bool need[CU];
+        uint32_t pay[CU], res[CU];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            need[u] = lam[u] > 0.0f;
+            pay[u] = (P.org[u] << a.lgR) | (lane & (R - 1)); // the caller's node id and the replica
+            res[u] = 0;
+        }
+        const uint32_t kk = (uint32_t)k;
+        compact_apply<CU>(xch, lane, need, pay, res, [&](uint32_t un) {
+            return fsd::philox4x32_10(make_uint4(un >> a.lgR, kk, un & (R - 1), 0u), a.key0, a.key1).x >> 8;
+        });
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            fire[u] = false;
+            if (need[u]) {
+                const float uu = (float)res[u] * 0x1p-24f;
+                const float qq = -expm1f(-lam[u] * dt);
+                fire[u] = uu < qq;
+            }
+        }
+    }
+
+    int xns[CU];
+    age_t ans[CU];
+#pragma unroll
+    for (int u = 0; u < CU; ++u) {
+        // 5.-6. advance state and age in place (the chunk's descriptors drop
+        // the lanes past its valid units; the state only changes on a firing)
+        const int xn = x[u] + (fire[u] ? 1 : 0);
+        xns[u] = xn;
+        ans[u] = fire[u] ? (age_t)0 : age_next(ag[u], dt);
+        const uint32_t u0 = P.chk[u] << 6;
+        BufIO<state_t>::st(make_rsrc((state_t*)a.state + u0, P.nvalid[u] * sizeof(state_t)),
+                           fire[u] ? lane : OOB_ELEM, (uint32_t)xn);
+        BufIO<age_t>::st(make_rsrc((age_t*)a.age + u0, P.nvalid[u] * sizeof(age_t)), lane, age_to_raw(ans[u]));
+        lmax = fmaxf(lmax, lam[u]);
+        // the rates, when recorded (EXTRA kernels)
+        if (EXTRA && a.rates) st32(make_rsrc(a.rates + u0, P.nvalid[u] * 4u), lane << 2, __float_as_uint(lam[u]));
+        // 7. next-step infectivity bits (one 64-bit word per chunk, written by
+        // lanes 0 and 1) and 8. counts
+        const unsigned long long mI = __ballot(valid[u] && xn == ST_I);
+        st32(make_rsrc(bits_out + P.chk[u], P.live[u] ? 8u : 0u), lane < 2 ? lane << 2 : OOB,
+             lane == 0 ? (uint32_t)mI : (uint32_t)(mI >> 32));
+        if (R == 1) {
+            c0 += (uint32_t)__popcll(__ballot(valid[u] && xn == ST_S));
+            c1 += (uint32_t)__popcll(__ballot(valid[u] && xn == ST_E));
+            c2 += (uint32_t)__popcll(mI);
+            c3 += (uint32_t)__popcll(__ballot(valid[u] && xn == ST_R));
+        } else if (valid[u]) {
+            atomicAdd(&s_cnt[(unit[u] & (R - 1)) * 4 + xn], 1u); // LDS
+        }
+        // compaction: whether the chunk held a unit that is not R at the start
+        // of the step.  A chunk is dropped only after a step that began with
+        // all its units in R, so both of its ping-pong bitmap words are 0
+        // (it held no I unit before or after that step) and stay 0.
+        if (EXTRA && a.live) {
+            const bool alive = __ballot(valid[u] && x[u] != ST_R) != 0ull;
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(alive ? 1 : 0),
+                                                 make_rsrc(a.live + P.chk[u], P.live[u] ? 1u : 0u),
+                                                 lane == 0 ? 0 : (int)OOB, 0, 0);
+        }
+    }
+
+    if (SHED) {
+        // 7'. infectivity values s(tau') of the units infectious after the
+        // step (Eq. (infectivity)), on compacted lanes (a separate round
+        // measured faster than folding s(tau + dt) into the hazard round)
+        bool need[CU];
+        uint32_t pay[CU], res[CU];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            need[u] = valid[u] && xns[u] == ST_I;
+            pay[u] = age_bits(ans[u]);
+            res[u] = 0;
+        }
+        compact_apply<CU>(xch, lane, need, pay, res, [&](uint32_t w) {
+            return __float_as_uint(fsd::shed(a.shed, age_from_bits<age_t>(w)));
+        });
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+            st32(make_rsrc(shed_out + (P.chk[u] << 6), P.nvalid[u] * 4u), need[u] ? lane << 2 : OOB, res[u]);
+    }
+}
+
+// One fused step.  Units are processed in chunks of 64 (one wavefront, one
+// 64-bit word of the next infectivity bitmap); every wavefront walks its own
+// chunks, CU per pass, with no workgroup barrier inside the walk.
+//  MODE_RESIDENT: the whole start-of-step bitmap (units <= RESIDENT_BITS) is
+//    copied into LDS once per workgroup (direct global-to-LDS loads, overlapped
+//    with the first pass's loads) and every gather reads LDS;
+//  MODE_SUMMARY: the bitmap's summary is copied into LDS the same way, and a
+//    gather reads the global bitmap only where the summary bit is set (when
+//    infection is sparse most neighbours fall in empty groups);
+//  MODE_STREAM: gathers read the bitmap through the caches.
+// The LDS variants run one workgroup of RESIDENT_TPB threads per compute unit.
+template <int STORAGE, bool WEIGHTED, int MODE, bool UNIFORM, bool SHED, bool EXTRA, int TPB>
+__device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uint32_t nblocks)
+{
+    constexpr bool USE_LDS = MODE != MODE_STREAM;
+    using age_t = typename Store<STORAGE>::age_t;
+    constexpr int NW = TPB / 64;
+
+    __shared__ uint32_t s_cnt[4 * 64];
+    __shared__ __attribute__((aligned(16))) uint32_t s_bits[USE_LDS ? RESIDENT_BITS / 32 : 4];
+    static_assert(SUMMARY_BITS <= RESIDENT_BITS, "the summary shares the LDS bitmap array");
+    __shared__ uint32_t s_xch[NW][64];
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6); // wave-uniform, in a scalar register
+    const uint32_t R = 1u << a.lgR;
+    const unsigned long long k = a.ctl->step + a.step_off;
+    const uint32_t* __restrict__ bits_in = (const uint32_t*)((k & 1) ? a.iota1 : a.iota0);
+    unsigned long long* __restrict__ bits_out = (unsigned long long*)((k & 1) ? a.iota0 : a.iota1);
+    const uint32_t total = (uint32_t)a.n << a.lgR;
+    const uint32_t nchunks = (total + 63) >> 6;
+    // the input bitmap: whole 512-unit tiles of 64 bytes
+    const rsrc_t gbits = make_rsrc(bits_in, ((total + 511u) >> 9) << 6);
+    // shedding values: read from the step's input, written to the other buffer
+    const rsrc_t shedr = make_rsrc((k & 1) ? a.shed1 : a.shed0, SHED ? total * 4u : 0u);
+    float* __restrict__ shed_out = (k & 1) ? a.shed0 : a.shed1;
+    // the chunks this launch walks: all, or the active list
+    const uint32_t walk = (EXTRA && a.act) ? a.act[0] : nchunks;
+    // this step's size: fixed, or (adaptive) from the largest rate of the
+    // previous step, folded by every wave from the per-workgroup maxima
+    float dt = a.dt;
+    if (a.adaptive && k != a.ctl->adapt_from) {
+        const float* prev = a.lam_part + (size_t)((k - 1) & 1) * nblocks;
+        float m = 0.0f;
+        for (uint32_t i = lane; i < nblocks; i += 64) m = fmaxf(m, prev[i]);
+        for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+        dt = fminf(a.dt, a.eps / (m + a.delta));
+    }
+    float lmax = 0.0f;
+    const uint32_t wave_id = block * NW + wave;
+    const uint32_t nwaves = nblocks * NW;
+
+    // first pass loads, then the bitmap fill, then one wait for both
+    Pass<age_t> P;
+    uint32_t first = wave_id;
+    const uint32_t stride = nwaves * CU;
+    uint32_t ahead[CU];
+#pragma unroll
+    for (int u = 0; u < CU; ++u) {
+        const uint32_t pos = first + (uint32_t)u * nwaves;
+        ahead[u] = (EXTRA && a.act && pos < walk) ? a.act[2 + pos] : 0u;
+    }
+    issue_pass<STORAGE, UNIFORM, EXTRA>(a, first, nwaves, stride, nchunks, walk, total, lane, P, ahead);
+    if (R > 1)
+        for (uint32_t i = tid; i < 4 * R; i += TPB) s_cnt[i] = 0;
+    if (USE_LDS) {
+        // 16 bytes per lane straight into LDS: wave w fills the blocks of 64
+        // uint4 it owns; lane l's block element lands at base + 16 l
+        const uint32_t nbits = MODE == MODE_RESIDENT ? total : a.sum_bits;
+        const uint32_t n4 = (((nbits + 31) >> 5) + 3) >> 2;
+        const uint4* src = (const uint4*)(MODE == MODE_RESIDENT ? bits_in : a.summary);
+        for (uint32_t b0 = wave * 64; b0 < n4; b0 += TPB) {
+            if (b0 + lane < n4)
+                __builtin_amdgcn_global_load_lds((const void*)(src + b0 + lane),
+                                                 (__attribute__((address_space(3))) void*)((uint4*)s_bits + b0), 16, 0, 0);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+    }
+    if (R > 1 || USE_LDS) __syncthreads();
+
+    uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0; // per-wave counts (R == 1)
+
+    // passes: the loads of the next pass are issued (always: a pass past the
+    // end reads nothing) before the current pass is processed; two register
+    // sets, unrolled by two
+    Pass<age_t> P1;
+    // resident variant with shedding: the pass's shedding values are loaded
+    // before the next pass's loads are issued
+    constexpr bool SPLIT = SHED && MODE == MODE_RESIDENT;
+    ShedPre sv;
+    for (;;) {
+        if (first >= walk) break;
+        if (SPLIT) shed_pre<UNIFORM>(a, P, lane, s_bits, shedr, sv);
+        if (PREFETCH)
+            issue_pass<STORAGE, UNIFORM, EXTRA>(a, first + stride, nwaves, stride, nchunks, walk, total, lane, P1,
+                                                ahead);
+        process_pass<STORAGE, WEIGHTED, MODE, UNIFORM, SHED, EXTRA>(a, P, lane, s_bits, gbits, shedr, shed_out, sv,
+                                                                    s_xch[wave], k, bits_out, s_cnt, c0, c1, c2,
+                                                                    c3, dt, lmax);
+        first += stride;
+        if (first >= walk) break;
+        if (!PREFETCH)
+            issue_pass<STORAGE, UNIFORM, EXTRA>(a, first, nwaves, stride, nchunks, walk, total, lane, P1, ahead);
+        if (SPLIT) shed_pre<UNIFORM>(a, P1, lane, s_bits, shedr, sv);
+        if (PREFETCH)
+            issue_pass<STORAGE, UNIFORM, EXTRA>(a, first + stride, nwaves, stride, nchunks, walk, total, lane, P,
+                                                ahead);
+        process_pass<STORAGE, WEIGHTED, MODE, UNIFORM, SHED, EXTRA>(a, P1, lane, s_bits, gbits, shedr, shed_out, sv,
+                                                                    s_xch[wave], k, bits_out, s_cnt, c0, c1, c2,
+                                                                    c3, dt, lmax);
+        first += stride;
+        if (!PREFETCH && first < walk)
+            issue_pass<STORAGE, UNIFORM, EXTRA>(a, first, nwaves, stride, nchunks, walk, total, lane, P, ahead);
+    }
+
+    // one plain store of this workgroup's counts; the reduce kernel sums them
+    // (workgroup 0 also counts the R units of the chunks compaction skipped)
+    uint32_t* out = a.part + ((size_t)a.step_off * nblocks + block) * (4 * R);
+    const uint32_t skipped = (EXTRA && a.act && block == 0) ? a.act[1] : 0u;
+    if (R == 1) {
+        if (lane == 0) {
+            s_cnt[wave * 4 + 0] = c0;
+            s_cnt[wave * 4 + 1] = c1;
+            s_cnt[wave * 4 + 2] = c2;
+            s_cnt[wave * 4 + 3] = c3;
+        }
+        __syncthreads();
+        if (tid < 4) {
+            uint32_t t = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) t += s_cnt[w * 4 + tid];
+            out[tid] = t + (tid == ST_R ? skipped : 0u);
+        }
+    } else {
+        __syncthreads();
+        for (uint32_t i = tid; i < 4 * R; i += TPB) out[i] = s_cnt[i] + ((i & 3) == ST_R ? skipped : 0u);
+    }
+    if (a.adaptive) {
+        // the workgroup's largest rate, for the next step's size; block 0
+        // records this step's size
+        __shared__ float s_lmax[NW];
+        for (int off = 32; off > 0; off >>= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, off, 64));
+        if (lane == 0) s_lmax[wave] = lmax;
+        __syncthreads();
+        if (tid == 0) {
+            float m = 0.0f;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) m = fmaxf(m, s_lmax[w]);
+            a.lam_part[(size_t)(k & 1) * nblocks + block] = m;
+            if (block == 0) a.dt_hist[k % a.hist_len] = dt;
+        }
+    }
+}
+
+// EXTRA: the instantiation that records rates when StepArgs::rates is set
+// and walks the active-chunk list when StepArgs::act is set; without it
+// neither check is compiled in.
+template <int STORAGE, bool WEIGHTED, int MODE, bool UNIFORM, bool SHED, bool EXTRA, int TPB>
+__global__ __launch_bounds__(TPB) void step_kernel(StepArgs a)
+{
+    step_body<STORAGE, WEIGHTED, MODE, UNIFORM, SHED, EXTRA, TPB>(a, blockIdx.x, gridDim.x);
+}
+
+// Address of the step kernel of one configuration (each (SHED, EXTRA)
+// combination is instantiated by a kernel source of its own).
+template <bool SHED, bool EXTRA, int S, bool W, bool U>
+const void* step_kernel_sel(int mode)
+{
+    if (mode == MODE_RESIDENT) return (const void*)&step_kernel<S, W, MODE_RESIDENT, U, SHED, EXTRA, RESIDENT_TPB>;
+    if (mode == MODE_SUMMARY) return (const void*)&step_kernel<S, W, MODE_SUMMARY, U, SHED, EXTRA, RESIDENT_TPB>;
+    return (const void*)&step_kernel<S, W, MODE_STREAM, U, SHED, EXTRA, STREAM_TPB>;
+}
+
+template <bool SHED, bool EXTRA>
+const void* step_kernel_pick(int storage, bool weighted, int mode, bool uniform)
+{
+    if (storage == 0 && !weighted)
+        return uniform ? step_kernel_sel<SHED, EXTRA, 0, false, true>(mode)
+                       : step_kernel_sel<SHED, EXTRA, 0, false, false>(mode);
+    if (storage == 0 && weighted)
+        return uniform ? step_kernel_sel<SHED, EXTRA, 0, true, true>(mode)
+                       : step_kernel_sel<SHED, EXTRA, 0, true, false>(mode);
+    if (storage == 1 && !weighted)
+        return uniform ? step_kernel_sel<SHED, EXTRA, 1, false, true>(mode)
+                       : step_kernel_sel<SHED, EXTRA, 1, false, false>(mode);
+    if (storage == 1 && weighted)
+        return uniform ? step_kernel_sel<SHED, EXTRA, 1, true, true>(mode)
+                       : step_kernel_sel<SHED, EXTRA, 1, true, false>(mode);
+    return nullptr;
+}
+
+// Index of the table entry that owns workgroup b: first[m] <= b < first[m + 1]
+// (a uniform binary search over the members' block ranges).
+__device__ __forceinline__ uint32_t owner_of(const uint32_t* __restrict__ first, uint32_t members, uint32_t b)
+{
+    uint32_t lo = 0, hi = members;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (first[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// One fused step for every member of a batch of simulations (each with its
+// own graph, laws, replicas and step index): member m owns the workgroups
+// [first[m], first[m + 1]) and runs exactly the streaming step on them, so
+// its results are those it gets alone.  step_off is the launch's position in
+// its sequence (member m runs step table[m].ctl->step + step_off).
+template <int STORAGE, bool WEIGHTED, bool EXTRA>
+__global__ __launch_bounds__(STREAM_TPB) void step_batch_kernel(const StepArgs* __restrict__ table,
+                                                                const uint32_t* __restrict__ first,
+                                                                uint32_t members, uint32_t step_off)
+{
+    const uint32_t m = owner_of(first, members, blockIdx.x);
+    StepArgs a = table[m];
+    a.step_off = step_off;
+    step_body<STORAGE, WEIGHTED, MODE_STREAM, false, false, EXTRA, STREAM_TPB>(a, blockIdx.x - first[m],
+                                                                               first[m + 1] - first[m]);
+}
+
+
+// Pressure partials of heavy-row segments (degree-binned dispatch).  One
+// wavefront per segment: lane l covers edge offset l / R and replica l % R,
+// so the 64 lanes read 64 / R edges per pass; the per-replica totals are
+// folded with a fixed shuffle tree (deterministic) and lanes 0..R-1 store
+// them.  Reads the same start-of-step bitmap (and, with SHED, shedding
+// values) as the step launch that follows.
+template <bool WEIGHTED, bool SHED>
+__device__ __forceinline__ void heavy_body(const HeavyArgs& h, uint32_t block, uint32_t nblocks)
+{
+    constexpr bool FLOATP = WEIGHTED || SHED;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t R = 1u << h.lgR;
+    const uint32_t per = 64u >> h.lgR; // edges per pass
+    const uint32_t eoff = lane >> h.lgR;
+    const uint32_t rep = lane & (R - 1);
+    const unsigned long long k = h.ctl->step + h.step_off;
+    const uint32_t* __restrict__ bits = (const uint32_t*)((k & 1) ? h.iota1 : h.iota0);
+    const float* __restrict__ shv = (k & 1) ? h.shed1 : h.shed0;
+    const uint32_t nwaves = nblocks * (WG / 64);
+    for (uint32_t s = block * (WG / 64) + (threadIdx.x >> 6); s < h.nseg; s += nwaves) {
+        const Segment sg = h.segs[s];
+        // only rows that are susceptible (in some replica) read their pressure
+        const uint32_t ru = ((uint32_t)sg.row << h.lgR) + rep;
+        const int x = h.storage ? (int)((const uint8_t*)h.state)[ru] : (int)((const int32_t*)h.state)[ru];
+        if (__ballot(x == ST_S) == 0ull) continue;
+        uint32_t ci = 0;
+        float cw = 0.0f;
+        for (int32_t e = sg.e_begin + (int32_t)eoff; e < sg.e_end; e += (int32_t)per) {
+            const uint32_t src = ((uint32_t)h.col_ind[e] << h.lgR) + rep;
+            const uint32_t b = bit_at(bits, src);
+            const float v = SHED ? (b ? shv[src] : 0.0f) : (float)b;
+            if (WEIGHTED) cw = __builtin_fmaf(h.weights[e], v, cw);
+            else if (SHED) cw += v;
+            else ci += b;
+        }
+        for (uint32_t off = 32; off >= R && off > 0; off >>= 1) {
+            if (FLOATP) cw += __shfl_down(cw, off, 64);
+            else ci += __shfl_down(ci, off, 64);
+        }
+        if (lane < R) {
+            if (FLOATP) ((float*)h.seg_part)[(size_t)s * R + lane] = cw;
+            else ((uint32_t*)h.seg_part)[(size_t)s * R + lane] = ci;
+        }
+    }
+}
+
+template <bool WEIGHTED, bool SHED>
+__global__ __launch_bounds__(WG) void heavy_pressure_kernel(HeavyArgs h)
+{
+    heavy_body<WEIGHTED, SHED>(h, blockIdx.x, gridDim.x);
+}
+
+// Batched heavy-row partials: member m owns workgroups [first[m], first[m + 1]).
+template <bool WEIGHTED>
+__global__ __launch_bounds__(WG) void heavy_batch_kernel(const HeavyArgs* __restrict__ table,
+                                                         const uint32_t* __restrict__ first, uint32_t members,
+                                                         uint32_t step_off)
+{
+    const uint32_t m = owner_of(first, members, blockIdx.x);
+    HeavyArgs h = table[m];
+    h.step_off = step_off;
+    heavy_body<WEIGHTED, false>(h, blockIdx.x - first[m], first[m + 1] - first[m]);
+}
+
+
+} // namespace fsk

@@ -104,3 +104,47 @@ def test_batch_and_server_host_validation():
     assert L.fs_server_submit(None, None, ctypes.byref(rid)) == 1
     assert L.fs_server_stats(None, None) == 1
     assert b"NULL" in L.fs_last_error()
+
+
+def test_bad_shedding_parameters_rejected_on_host():
+    ages = np.array([1.0], np.float32)
+    for shed in [("density", ("weibull", 0.5, 3.0), 1.0), ("hazard", ("lognormal", 0.0, -1.0), 1.0),
+                 ("density", ("exp", 1.0), -2.0), ("density", ("exp", 1.0), float("inf"))]:
+        with pytest.raises(fs.FsError) as ei:
+            fs.fs_eval_shedding(shed, ages)
+        assert ei.value.status == 1
+    import ctypes
+    d = fs.make_dist(("exp", 1.0))
+    out = np.zeros(1, np.float32)
+    assert fs.lib().fs_eval_shedding(ctypes.byref(d), 0, 1.0, 0, 1.0, 1, ages.ctypes.data,
+                                     out.ctypes.data) == 1   # the constant form has no profile
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Sizes and field offsets of the ABI structs as a C compiler lays them
+    out from include/fs.h, against the binding's ctypes mirrors."""
+    import ctypes
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"fs_dist": fs.fs_dist, "fs_sim_params": fs.fs_sim_params,
+               "fs_server_params": fs.fs_server_params, "fs_request": fs.fs_request,
+               "fs_request_info": fs.fs_request_info}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fs.h"', 'int main(void) {']
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f in cls._fields_:
+            lines.append(f'printf("{name}.{f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+    lines += ['return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                text=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for f in cls._fields_:
+            assert int(got[f"{name}.{f[0]}"]) == getattr(cls, f[0]).offset, (name, f[0])
