@@ -36,7 +36,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("FS_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
-SOURCES = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "gillespie.c")]
+SOURCES = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "gillespie.c"), os.path.join(_HERE, "markov.c")]
 
 S, E, I, R = 0, 1, 2, 3
 AGE_DAYS_F32, AGE_STEPS_U16 = 0, 1
@@ -105,6 +105,23 @@ def make_params(model: dict, age_mode: int = AGE_DAYS_F32) -> Params:
                   mode, law, scale)
 
 
+class MarkovParams(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("pad", ctypes.c_int32), ("beta", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("gamma", ctypes.c_double), ("theta", ctypes.c_double),
+                ("p_max", ctypes.c_double), ("tau_max", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+MARKOV_MODELS = {"seir": 0, "sir": 1, "sis": 2}
+
+
+def make_markov_params(m: dict) -> MarkovParams:
+    """m: {"model": "seir"|"sir"|"sis", "beta", "sigma" (SEIR), "gamma",
+    "theta", "p_max", "tau_max", "seed"}."""
+    return MarkovParams(MARKOV_MODELS[m["model"]], 0, float(m["beta"]), float(m.get("sigma", 0.0)),
+                        float(m["gamma"]), float(m["theta"]), float(m["p_max"]), float(m["tau_max"]),
+                        int(m.get("seed", 0)) & (2**64 - 1))
+
+
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
 _U64 = ctypes.c_uint64
@@ -131,6 +148,12 @@ def _declare(L):
     L.or_run_adaptive.argtypes = [_I64, _P, _P, _P, ctypes.POINTER(Params), ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, _U64, _I64, _U32, _P, _P, _P,
                                   _P, _P]
+    L.mk_influence.argtypes = [_I64, _P, _P, _P, _P]
+    L.mk_tau.argtypes = [ctypes.POINTER(MarkovParams), _I64, _P, _P, _P, _P]
+    L.mk_tau.restype = ctypes.c_double
+    L.mk_step.argtypes = [_I64, _P, _P, ctypes.POINTER(MarkovParams), _U64, _P, _P, _P, _P, _P, _P, _P]
+    L.mk_step.restype = ctypes.c_double
+    L.mk_run.argtypes = [_I64, _P, _P, ctypes.POINTER(MarkovParams), _U64, _I64, _P, _P, _P, _P, _P]
     L.gx_run.argtypes = [_I64, _P, _P, _P, ctypes.POINTER(Dist), ctypes.POINTER(Dist),
                          ctypes.c_double, ctypes.c_double, _P, _U64, _P, _P, _I64, _P, _P]
     L.gx_run.restype = _I64
@@ -331,3 +354,59 @@ def gillespie(graph, ei, ir, beta: float, t_end: float, init_state, seed: int,
                       ctypes.byref(dir_), float(beta), float(t_end), _ptr(st), int(seed),
                       _ptr(peaks), _ptr(counts))
     return peaks, counts
+
+
+# ------------------------------------------------------------ Markovian engine
+
+def markov_influence(graph, state) -> np.ndarray:
+    """Infectious in-neighbours of every node (unit weights)."""
+    rp, ci, _ = _graph(graph)
+    st = _c(state, np.int32)
+    out = np.empty(len(rp) - 1, dtype=np.int32)
+    lib().mk_influence(len(rp) - 1, _ptr(rp), _ptr(ci), _ptr(st), _ptr(out))
+    return out
+
+
+def markov_tau(graph, m: dict, state):
+    """(tau, Lambda, max lambda) of the step from `state`."""
+    rp, ci, _ = _graph(graph)
+    st = _c(state, np.int32)
+    infl = markov_influence(graph, st)
+    L = ctypes.c_double()
+    M = ctypes.c_double()
+    p = make_markov_params(m)
+    tau = lib().mk_tau(ctypes.byref(p), len(st), _ptr(st), _ptr(infl), ctypes.byref(L), ctypes.byref(M))
+    return tau, L.value, M.value
+
+
+def markov_step(graph, m: dict, state, k: int) -> dict:
+    """One step k of the Markovian engine from `state`."""
+    rp, ci, _ = _graph(graph)
+    n = len(rp) - 1
+    st = np.array(state, dtype=np.int32, copy=True)
+    infl = markov_influence(graph, st)
+    counts = np.zeros(4, np.int64)
+    ev = ctypes.c_int64()
+    lam = np.empty(n)
+    q = np.empty(n)
+    u = np.empty(n)
+    p = make_markov_params(m)
+    tau = lib().mk_step(n, _ptr(rp), _ptr(ci), ctypes.byref(p), int(k), _ptr(st), _ptr(infl), _ptr(counts),
+                        ctypes.byref(ev), _ptr(lam), _ptr(q), _ptr(u))
+    return {"state": st, "infl": infl, "counts": counts, "events": ev.value, "tau": tau, "lam": lam, "p": q,
+            "u": u}
+
+
+def markov_run(graph, m: dict, state, n_steps: int, k0: int = 0):
+    """n_steps steps; returns (state, history[n_steps, 4], taus[n_steps], events[n_steps])."""
+    rp, ci, _ = _graph(graph)
+    n = len(rp) - 1
+    st = np.array(state, dtype=np.int32, copy=True)
+    scratch = np.empty(n, np.int32)
+    hist = np.zeros((n_steps, 4), np.int64)
+    taus = np.zeros(n_steps)
+    evs = np.zeros(n_steps, np.int64)
+    p = make_markov_params(m)
+    lib().mk_run(n, _ptr(rp), _ptr(ci), ctypes.byref(p), int(k0), int(n_steps), _ptr(st), _ptr(scratch),
+                 _ptr(hist), _ptr(taus), _ptr(evs))
+    return st, hist, taus, evs
