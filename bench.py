@@ -26,6 +26,13 @@ default line is the cost of the shedding path itself).  --compaction turns on ac
 compaction; --beta overrides the transmission rate (a saturating epidemic is
 where compaction pays).
 
+--markov measures the Markovian engine instead (Section "Markovian
+engine"): SIR on an Erdos-Renyi graph with N = 1e6 and mean degree 8, beta =
+0.25, gamma = 0.15, theta = 0.01, p_max = 0.1 (the paper's validation
+model), 100 initially infectious nodes, captured replays of 50 steps, the
+whole epidemic timed; it prints realized transitions per second, the
+paper's measure for this engine, beside node-updates per second.
+
 --serving measures the scenario server instead: a seeded Poisson stream of
 scenario solves (16 replicas, 300 steps, graphs of 1e4..2e6 nodes from a
 resident pool, laws and beta drawn per request) through the server, and the
@@ -234,6 +241,79 @@ def serving_main(args):
     print(json.dumps(out), flush=True)
 
 
+MARKOV_MODEL = {"model": "sir", "beta": 0.25, "gamma": 0.15, "theta": 0.01, "p_max": 0.1, "tau_max": 1.0,
+                "seed": 21}
+
+
+def markov_main(args):
+    import numpy as np
+    import torch
+
+    import paper_2604_22092_amd as fs
+    import workloads as W
+
+    fs.lib()
+    t0 = time.perf_counter()
+    rp, ci = W.erdos_renyi(1_000_000, 8.0, 1)
+    n = len(rp) - 1
+    seeds = W.seed_nodes(n, 100, 5)
+    print(f"[markov] ER N={n} E={len(ci)} built in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(device=dev)
+    steps = args.markov_steps
+    g = fs.Graph(rp, ci)
+    eng = fs.Markov(g, MARKOV_MODEL, steps_per_graph=STEPS_PER_GRAPH, history_len=steps, stream=stream.cuda_stream)
+    st0 = np.zeros(n, np.int32)
+    st0[seeds] = 2
+    eng.set_state(st0, step_index=0)
+    eng.step(STEPS_PER_GRAPH)
+    eng.sync()
+    eng.set_state(st0, step_index=0)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    eng.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    counts, taus, events = eng.history(0, steps)
+    _, _, _, elapsed = eng.get_state()
+    eng.close()
+    g.close()
+    trans = int(events.sum())
+    sec = ms / 1e3
+    print(f"[markov] {steps} steps ({elapsed:.1f} days): {ms:.3f} ms, {trans} transitions, "
+          f"{trans / sec:.3e} transitions/s, {n * steps / sec / 1e9:.2f} GNUPS, final {counts[-1].tolist()}",
+          file=sys.stderr, flush=True)
+    cpu = None
+    if args.cpu_budget > 0:
+        import oracle
+        st = st0.copy()
+        done, tr, t1 = 0, 0, time.perf_counter()
+        while time.perf_counter() - t1 < args.cpu_budget and done < steps:
+            st, _, _, ev = oracle.markov_run((rp, ci), MARKOV_MODEL, st, 5, k0=done)
+            done += 5
+            tr += int(ev.sum())
+        el = time.perf_counter() - t1
+        cpu = {"value": tr / el, "unit": "transitions/s", "cores": 1, "kind": "oracle",
+               "sample": f"steps 0..{done - 1} of the same run, single-threaded FP64 oracle, {el:.1f} s"}
+    rec = {
+        "metric": "Markovian engine: realized transitions per second",
+        "value": round(trans / sec, 1),
+        "unit": "transitions/s",
+        "n_gpus": 1, "steps": steps, "warmup": STEPS_PER_GRAPH, "ms_per_step": round(ms / steps, 6),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "er8_n1e6_sir", "graph": "Erdos-Renyi, N=1e6, mean degree 8, seed 1",
+                   "model": "SIR beta=0.25 gamma=0.15", "theta": 0.01, "p_max": 0.1, "tau_max": 1.0, "seeds": 100,
+                   "simulated_days": round(elapsed, 3), "transitions": trans,
+                   "gnups": round(n * steps / sec / 1e9, 3), "parallelism": "single GPU"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -257,6 +337,8 @@ def main():
                          "unit (s = 1 through the shedding kernels)")
     ap.add_argument("--compaction", action="store_true", help="active-node compaction")
     ap.add_argument("--beta", type=float, default=None, help="override the workload's beta")
+    ap.add_argument("--markov", action="store_true", help="measure the Markovian engine instead")
+    ap.add_argument("--markov-steps", type=int, default=600)
     ap.add_argument("--serving", action="store_true",
                     help="measure the scenario server on the seeded request mix instead")
     ap.add_argument("--serving-requests", type=int, default=400)
@@ -275,6 +357,9 @@ def main():
         sys.exit(2)
     if args.serving:
         serving_main(args)
+        return
+    if args.markov:
+        markov_main(args)
         return
 
     import numpy as np

@@ -317,6 +317,69 @@ fs_status fs_eval_philox(int64_t n, const uint32_t* ctr, uint64_t seed, uint32_t
 /* Library version string. */
 const char* fs_version(void);
 
+/* ------------------------------------------------------- Markovian engine
+ * The companion engine for Markovian dynamics (Section "Markovian engine",
+ * Algorithm "Markovian Engine: One Tau-Leaping Step").  Rates are piecewise
+ * constant: a susceptible node beta * I_i (I_i: its infectious in-neighbours;
+ * unit-weight graphs only), an exposed node sigma, an infectious node gamma,
+ * a removed node 0.  Every step takes
+ *   tau = min(theta N / Lambda, p_max / max_i lambda_i, tau_max)
+ * (Lambda: the total rate; a zero denominator drops its term), fires node i
+ * with probability 1 - exp(-lambda_i tau) (Philox keyed by (seed, step,
+ * node) as for the renewal step, replica 0), and updates the influences:
+ * by integer pushes along the outgoing edges of the nodes whose
+ * infectiousness changed when they are few (Inertial Mode), else by a full
+ * recount (Control Mode).  Both give the same integer influences, so the
+ * result does not depend on the mode.  One replica per engine.
+ */
+#define FS_MARKOV_SEIR 0 /* S -> E -> I -> R */
+#define FS_MARKOV_SIR 1  /* S -> I -> R */
+#define FS_MARKOV_SIS 2  /* S -> I -> S */
+
+typedef struct fs_markov fs_markov;
+
+typedef struct fs_markov_params {
+    int32_t model;           /* FS_MARKOV_* */
+    int32_t pad;
+    double beta;             /* per infectious in-neighbour (per day), >= 0 */
+    double sigma;            /* E -> I rate (FS_MARKOV_SEIR), >= 0 */
+    double gamma;            /* I -> R (or I -> S) rate, >= 0 */
+    double theta;            /* expected events per node per step bound, > 0 (the paper's default 0.01) */
+    double p_max;            /* largest transition probability per step, > 0 (default 0.1) */
+    double tau_max;          /* largest step (days), > 0 */
+    uint64_t seed;
+    int32_t steps_per_graph; /* b: steps per captured hipGraph replay; 0 = launch eagerly */
+    int32_t history_len;     /* per-step ring length (>= 2); 0 = 1024 */
+    int64_t inertial_max;    /* events per step up to which pushes update the influences;
+                                0 = automatic (events * mean degree < nnz / 8), -1 = always recount */
+    void* stream;            /* hipStream_t; NULL = a stream owned by the engine */
+} fs_markov_params;
+
+/* Creates an engine on a unit-weight graph, every node in S.  Errors:
+ * FS_ERR_INVALID_ARG (a weighted graph, unknown model, bad rates or step
+ * parameters), FS_ERR_OUT_OF_MEMORY, FS_ERR_DEVICE.  The first engine of a
+ * graph builds the graph's outgoing CSR (kept with the graph). */
+fs_status fs_markov_create(fs_graph* g, const fs_markov_params* p, fs_markov** out);
+fs_status fs_markov_destroy(fs_markov* m);
+/* Puts `count` listed nodes (caller's ids) into `compartment`.  Synchronises. */
+fs_status fs_markov_seed(fs_markov* m, int64_t count, const int64_t* nodes, int32_t compartment);
+/* Loads n states (caller's order), sets the step index (-1: keep) and the
+ * elapsed time.  Synchronises. */
+fs_status fs_markov_set_state(fs_markov* m, const int32_t* state, int64_t step_index, double elapsed);
+/* Queues n_steps steps (asynchronous, like fs_step). */
+fs_status fs_markov_step(fs_markov* m, int64_t n_steps);
+fs_status fs_markov_sync(fs_markov* m);
+/* States and influences (n int32 each, caller's order, either may be NULL),
+ * the step index and the elapsed time.  Synchronises. */
+fs_status fs_markov_get_state(fs_markov* m, int32_t* state, int32_t* influence, int64_t* step_index,
+                              double* elapsed);
+/* Per-step records of steps [first_step, first_step + n) within the ring:
+ * counts (n x 4 int64), step sizes tau (n double, as the device used them,
+ * FP32) and events (n int64, nodes that changed infectiousness); any may be
+ * NULL.  Synchronises. */
+fs_status fs_markov_history(fs_markov* m, int64_t first_step, int64_t n, int64_t* counts, double* taus,
+                            int64_t* events);
+
 /* ---------------------------------------------------------------- batches
  * A batch advances several sims together, one fused step launch per step
  * for all of them (Algorithm 3's fused step over a table of simulations

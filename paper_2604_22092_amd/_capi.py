@@ -38,6 +38,8 @@ EXPORTS = [
     "fs_batch_step", "fs_batch_sync",
     "fs_server_create", "fs_server_submit", "fs_server_wait", "fs_server_result",
     "fs_server_stats", "fs_server_destroy", "fs_server_clock",
+    "fs_markov_create", "fs_markov_destroy", "fs_markov_seed", "fs_markov_set_state", "fs_markov_step",
+    "fs_markov_sync", "fs_markov_get_state", "fs_markov_history",
 ]
 
 
@@ -68,6 +70,14 @@ class fs_sim_params(ctypes.Structure):
                 ("epsilon", ctypes.c_double), ("delta", ctypes.c_double),
                 ("shedding", ctypes.c_int32), ("compaction", ctypes.c_int32),
                 ("shed_law", fs_dist), ("shed_scale", ctypes.c_double)]
+
+
+class fs_markov_params(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("pad", ctypes.c_int32), ("beta", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("gamma", ctypes.c_double), ("theta", ctypes.c_double),
+                ("p_max", ctypes.c_double), ("tau_max", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("steps_per_graph", ctypes.c_int32), ("history_len", ctypes.c_int32),
+                ("inertial_max", ctypes.c_int64), ("stream", ctypes.c_void_p)]
 
 
 class fs_server_params(ctypes.Structure):
@@ -120,6 +130,14 @@ def _declare(L):
         "fs_graph_destroy": ([P], I32),
         "fs_graph_get_info": ([P, ctypes.POINTER(fs_graph_info)], I32),
         "fs_sim_create": ([P, ctypes.POINTER(fs_sim_params), PP], I32),
+        "fs_markov_create": ([P, ctypes.POINTER(fs_markov_params), PP], I32),
+        "fs_markov_destroy": ([P], I32),
+        "fs_markov_seed": ([P, I64, P, I32], I32),
+        "fs_markov_set_state": ([P, P, I64, ctypes.c_double], I32),
+        "fs_markov_step": ([P, I64], I32),
+        "fs_markov_sync": ([P], I32),
+        "fs_markov_get_state": ([P, P, P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)], I32),
+        "fs_markov_history": ([P, I64, I64, P, P, P], I32),
         "fs_sim_destroy": ([P], I32),
         "fs_sim_seed": ([P, I32, I64, P, I32], I32),
         "fs_step": ([P, I64], I32),
@@ -381,6 +399,83 @@ def make_params(ei, ir, beta: float, dt: float, seed: int = 0, replicas: int = 1
         p.shed_scale = float(shed[2])
     p.compaction = 1 if compaction else 0
     return p
+
+
+FS_MARKOV_SEIR, FS_MARKOV_SIR, FS_MARKOV_SIS = 0, 1, 2
+MARKOV_MODELS = {"seir": FS_MARKOV_SEIR, "sir": FS_MARKOV_SIR, "sis": FS_MARKOV_SIS}
+
+
+class Markov:
+    """The Markovian engine (one replica) on a unit-weight Graph.  model:
+    {"model": "seir"|"sir"|"sis", "beta", "sigma", "gamma", "theta",
+    "p_max", "tau_max", "seed"}."""
+
+    def __init__(self, graph: Graph, model: dict, steps_per_graph: int = 0, history_len: int = 0,
+                 inertial_max: int = 0, stream=None):
+        p = fs_markov_params()
+        p.model = MARKOV_MODELS[model["model"]]
+        p.beta = float(model["beta"])
+        p.sigma = float(model.get("sigma", 0.0))
+        p.gamma = float(model["gamma"])
+        p.theta = float(model.get("theta", 0.01))
+        p.p_max = float(model.get("p_max", 0.1))
+        p.tau_max = float(model.get("tau_max", 1.0))
+        p.seed = int(model.get("seed", 0)) & (2**64 - 1)
+        p.steps_per_graph = int(steps_per_graph)
+        p.history_len = int(history_len)
+        p.inertial_max = int(inertial_max)
+        p.stream = None if stream is None else ctypes.c_void_p(int(stream))
+        h = ctypes.c_void_p()
+        _check(lib().fs_markov_create(graph.handle, ctypes.byref(p), ctypes.byref(h)), "fs_markov_create")
+        self.handle = h
+        self.n = graph.n
+
+    def seed(self, nodes, compartment: int = FS_I):
+        a = np.ascontiguousarray(nodes, dtype=np.int64)
+        _check(lib().fs_markov_seed(self.handle, len(a), _ptr(a), int(compartment)), "fs_markov_seed")
+
+    def set_state(self, state, step_index: int = -1, elapsed: float = 0.0):
+        a = np.ascontiguousarray(state, dtype=np.int32)
+        if len(a) != self.n:
+            raise ValueError("state must hold one value per node")
+        _check(lib().fs_markov_set_state(self.handle, _ptr(a), int(step_index), float(elapsed)),
+               "fs_markov_set_state")
+
+    def step(self, n_steps: int = 1):
+        _check(lib().fs_markov_step(self.handle, int(n_steps)), "fs_markov_step")
+
+    def sync(self):
+        _check(lib().fs_markov_sync(self.handle), "fs_markov_sync")
+
+    def get_state(self):
+        """(state, influence, step index, elapsed time)."""
+        st = np.empty(self.n, np.int32)
+        inf = np.empty(self.n, np.int32)
+        k = ctypes.c_int64()
+        t = ctypes.c_double()
+        _check(lib().fs_markov_get_state(self.handle, _ptr(st), _ptr(inf), ctypes.byref(k), ctypes.byref(t)),
+               "fs_markov_get_state")
+        return st, inf, k.value, t.value
+
+    def history(self, first_step: int, n: int):
+        """(counts[n, 4], taus[n], events[n]) of steps first_step .. first_step + n - 1."""
+        c = np.empty((n, 4), np.int64)
+        t = np.empty(n, np.float64)
+        e = np.empty(n, np.int64)
+        _check(lib().fs_markov_history(self.handle, int(first_step), int(n), _ptr(c), _ptr(t), _ptr(e)),
+               "fs_markov_history")
+        return c, t, e
+
+    def close(self):
+        if self.handle is not None:
+            _check(lib().fs_markov_destroy(self.handle), "fs_markov_destroy")
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class Sim:

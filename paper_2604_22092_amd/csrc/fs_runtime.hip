@@ -766,6 +766,8 @@ fs_status fs_graph_destroy(fs_graph* g)
     dev_free(g->d_col_ind);
     dev_free(g->d_weights);
     dev_free(g->d_orig);
+    dev_free(g->d_out_ptr);
+    dev_free(g->d_out_ind);
     delete g;
     return FS_OK;
     FS_GUARD_END

@@ -64,8 +64,12 @@ struct fs_graph {
     std::vector<int32_t> h_row_ptr; // host copies (internal order) for degree binning and layouts
     std::vector<int32_t> h_col_ind;
     std::vector<float> h_weights;
+    // outgoing CSR of the internal order (the Markovian engine's sparse
+    // pushes), built on first use
+    int32_t* d_out_ptr = nullptr;
+    int32_t* d_out_ind = nullptr;
     std::atomic<int> users{0};
-    std::mutex layout_mu;        // guards layouts (sims of one graph may live on several threads)
+    std::mutex layout_mu;        // guards layouts and the outgoing CSR (sims of one graph may live on several threads)
     std::map<fsr::LayoutKey, std::shared_ptr<fsr::Layout>> layouts;
 };
 

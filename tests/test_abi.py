@@ -131,7 +131,7 @@ def test_struct_layouts_match_the_header(tmp_path):
         pytest.skip("no C compiler")
     structs = {"fs_dist": fs.fs_dist, "fs_sim_params": fs.fs_sim_params,
                "fs_server_params": fs.fs_server_params, "fs_request": fs.fs_request,
-               "fs_request_info": fs.fs_request_info}
+               "fs_request_info": fs.fs_request_info, "fs_markov_params": fs.fs_markov_params}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fs.h"', 'int main(void) {']
     for name, cls in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
@@ -148,3 +148,15 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert int(got[name]) == ctypes.sizeof(cls), name
         for f in cls._fields_:
             assert int(got[f"{name}.{f[0]}"]) == getattr(cls, f[0]).offset, (name, f[0])
+
+
+def test_markov_host_validation():
+    import ctypes
+    L = fs.lib()
+    h = ctypes.c_void_p()
+    p = fs.fs_markov_params()
+    assert L.fs_markov_create(None, ctypes.byref(p), ctypes.byref(h)) == 1 and h.value is None
+    assert L.fs_markov_step(None, 1) == 1
+    assert L.fs_markov_sync(None) == 1
+    assert L.fs_markov_destroy(None) == 1
+    assert L.fs_markov_get_state(None, None, None, None, None) == 1
