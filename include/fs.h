@@ -329,8 +329,12 @@ const char* fs_version(void);
  * node) as for the renewal step, replica 0), and updates the influences:
  * by integer pushes along the outgoing edges of the nodes whose
  * infectiousness changed when they are few (Inertial Mode), else by a full
- * recount (Control Mode).  Both give the same integer influences, so the
- * result does not depend on the mode.  One replica per engine.
+ * recount (Control Mode).  Both give the same integer influences on every
+ * node that can still use them, so the result does not depend on the mode:
+ * under SEIR and SIR pushes skip targets that are no longer susceptible (no
+ * such node becomes susceptible again), so there the influence reported for
+ * a node outside S may be stale; under SIS every node's is exact.  One
+ * replica per engine.
  */
 #define FS_MARKOV_SEIR 0 /* S -> E -> I -> R */
 #define FS_MARKOV_SIR 1  /* S -> I -> R */

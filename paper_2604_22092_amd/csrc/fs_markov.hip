@@ -4,21 +4,25 @@
 // Rates are piecewise constant: S nodes beta * I_i (I_i: infectious
 // in-neighbours, unit weights), E nodes sigma, I nodes gamma, R nodes 0.
 // One step is three launches, all inside a captured graph:
-//   draw   (dense): every wavefront folds the per-workgroup rate partials of
-//          the previous launch into Lambda and max lambda (exact integers),
+//   draw   (dense): one wavefront per workgroup folds the per-workgroup rate
+//          partials of the previous launch into Lambda and max lambda (exact integers),
 //          takes tau = min(theta N / Lambda, p_max / max lambda, tau_max),
 //          draws every node with a positive rate and applies the transitions;
 //          a node whose infectiousness changed is appended to its
 //          workgroup's event region (no global counter);
 //   push   (sparse, Inertial Mode): when the step's events are few, each
 //          event adds +-1 to the influence of its out-neighbours (integer
-//          atomics on the outgoing CSR: exact and order-independent);
-//          otherwise it exits at once;
+//          atomics on the outgoing CSR: exact and order-independent), the
+//          events spread over every lane of the grid; otherwise it exits.
+//          Without I -> S (SEIR, SIR) only susceptible targets are updated:
+//          no other node reads its influence again;
 //   rates  (dense): when the events were many (Control Mode) it recounts
 //          every influence from the incoming CSR, then writes per-workgroup
-//          (sum of S influences, max S influence, #E, #I) for the next draw.
-// Both modes give the same integer influences, so results do not depend on
-// which ran.  Per-step counts, tau and event totals go to rings on the
+//          (sum of S influences, max S influence, #E, #I) for the next draw;
+//          after a step without transitions it keeps the old partials.
+// Both modes give the same integer influences on every node that can still
+// read them (every susceptible node; every node under SIS), so results do not
+// depend on which ran.  Per-step counts, tau and event totals go to rings on the
 // device; a launch sequence ends with the count reduce and the step advance.
 #include <hip/hip_runtime.h>
 
@@ -49,6 +53,8 @@ struct MkArgs {
     const int32_t* orig_id; // caller's id of each node: the draws are keyed by it
     uint32_t* events;       // [G][span]: node | EV_LEAVE when it stopped being infectious
     uint32_t* ev_cnt;       // [G] events of the current step per region
+    uint32_t* fired;        // [G] transitions of the current step per region (events or not);
+                            // fired[G] receives their total (written by the push launch)
     uint4* rpart;           // [G]: (sum of S influences, max S influence, #E, #I)
     uint32_t* part;         // count partials [slot][G][4]
     float* tau_hist;        // [H]
@@ -106,22 +112,32 @@ __device__ double markov_tau(const MkArgs& a, uint32_t lane)
 __global__ __launch_bounds__(MTPB) void mk_draw_kernel(MkArgs a)
 {
     constexpr int NW = MTPB / 64;
-    __shared__ uint32_t s_ev;
+    __shared__ uint32_t s_ev, s_fired;
     __shared__ uint32_t s_cnt[NW][4];
+    __shared__ double s_tau;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const unsigned long long k = a.ctl->step + a.step_off;
-    const double tau = markov_tau(a, lane);
-    const float tf = (float)tau;
-    if (tid == 0) s_ev = 0;
+    // one wave per workgroup folds the rate partials
+    if (wave == 0) {
+        const double t = markov_tau(a, lane);
+        if (lane == 0) {
+            s_tau = t;
+            s_ev = 0;
+            s_fired = 0;
+        }
+    }
     __syncthreads();
+    const double tau = s_tau;
+    const float tf = (float)tau;
     const uint32_t base = blockIdx.x * a.span;
     const uint32_t end = min(a.n, base + a.span);
     uint32_t c[4] = {0, 0, 0, 0};
+    uint32_t nfire = 0;
     for (uint32_t i0 = base + wave * 64; i0 < end; i0 += MTPB) {
         const uint32_t i = i0 + lane;
         const bool valid = i < end;
         const int x = valid ? (int)a.state[i] : ST_R;
-        const int f = valid ? a.infl[i] : 0;
+        const int f = x == ST_S ? a.infl[i] : 0;
         const float lam = x == ST_S ? a.beta * (float)f : x == ST_E ? a.sigma : x == ST_I ? a.gamma : 0.0f;
         bool fire = false;
         if (lam > 0.0f) {
@@ -131,6 +147,7 @@ __global__ __launch_bounds__(MTPB) void mk_draw_kernel(MkArgs a)
         }
         const int xn = fire ? next_state(a.model, x) : x;
         if (fire) a.state[i] = (uint8_t)xn;
+        nfire += (uint32_t)__popcll(__ballot(fire));
         // a change of infectiousness is an event of this workgroup's region
         const bool ev = fire && ((xn == ST_I) != (x == ST_I));
         const unsigned long long m = __ballot(ev);
@@ -143,8 +160,10 @@ __global__ __launch_bounds__(MTPB) void mk_draw_kernel(MkArgs a)
 #pragma unroll
         for (int q = 0; q < 4; ++q) c[q] += (uint32_t)__popcll(__ballot(valid && xn == q));
     }
-    if (lane == 0)
+    if (lane == 0) {
         for (int q = 0; q < 4; ++q) s_cnt[wave][q] = c[q];
+        atomicAdd(&s_fired, nfire); // LDS
+    }
     __syncthreads();
     if (tid < 4) {
         uint32_t t = 0;
@@ -153,6 +172,7 @@ __global__ __launch_bounds__(MTPB) void mk_draw_kernel(MkArgs a)
     }
     if (tid == 0) {
         a.ev_cnt[blockIdx.x] = s_ev;
+        a.fired[blockIdx.x] = s_fired;
         if (blockIdx.x == 0) {
             a.tau_hist[k % a.H] = tf;
             *a.elapsed += tau;
@@ -160,30 +180,85 @@ __global__ __launch_bounds__(MTPB) void mk_draw_kernel(MkArgs a)
     }
 }
 
-__device__ __forceinline__ uint32_t total_events(const MkArgs& a, uint32_t lane)
-{
-    uint32_t t = 0;
-    for (uint32_t g = lane; g < a.G; g += 64) t += a.ev_cnt[g];
-    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-    return t;
-}
+// Inertial Mode.  The events of all regions, taken in region order, are
+// spread over every lane of the grid: each workgroup builds the exclusive
+// prefix of the region counts in LDS and each lane finds the region of its
+// event by binary search, then pushes +-1 to the event's out-neighbours
+// (non-returning integer atomics).
+constexpr uint32_t MAX_REGIONS = 1024;
 
-// Inertial Mode: one wavefront per event region, one lane per event.
 __global__ __launch_bounds__(PTPB) void mk_push_kernel(MkArgs a)
 {
-    const uint32_t lane = threadIdx.x & 63;
+    __shared__ uint32_t s_pre[MAX_REGIONS + 1];
+    __shared__ uint32_t s_fire[PTPB / 64];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const unsigned long long k = a.ctl->step + a.step_off;
-    const uint32_t total = total_events(a, lane);
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.ev_hist[k % a.H] = total;
+    // region counts into LDS (all threads), transitions summed per wave
+    uint32_t f = 0;
+    for (uint32_t g = tid; g < a.G; g += PTPB) {
+        s_pre[g] = a.ev_cnt[g];
+        f += a.fired[g];
+    }
+    for (int off = 32; off > 0; off >>= 1) f += __shfl_xor(f, off, 64);
+    if (lane == 0) s_fire[wave] = f;
+    __syncthreads();
+    // exclusive prefix of the counts by wave 0: lane l scans its block of
+    // ceil(G / 64) regions, then the block sums are scanned across lanes
+    if (wave == 0) {
+        const uint32_t per = (a.G + 63) / 64;
+        const uint32_t g0 = lane * per, g1 = min(a.G, g0 + per);
+        uint32_t sum = 0;
+        for (uint32_t g = g0; g < g1; ++g) sum += s_pre[g];
+        uint32_t inc = sum;
+        for (uint32_t off = 1; off < 64; off <<= 1) {
+            const uint32_t v = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += v;
+        }
+        uint32_t run = inc - sum;
+        for (uint32_t g = g0; g < g1; ++g) {
+            const uint32_t c = s_pre[g];
+            s_pre[g] = run;
+            run += c;
+        }
+        if (lane == 63) s_pre[a.G] = inc;
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && tid == 0) {
+        a.ev_hist[k % a.H] = s_pre[a.G];
+        uint32_t t = 0;
+        for (int w = 0; w < PTPB / 64; ++w) t += s_fire[w];
+        a.fired[a.G] = t;
+    }
+    const uint32_t total = s_pre[a.G];
     if (total > a.inertial_max) return;
-    const uint32_t nwaves = gridDim.x * (PTPB / 64);
-    for (uint32_t r = blockIdx.x * (PTPB / 64) + (threadIdx.x >> 6); r < a.G; r += nwaves) {
-        const uint32_t cnt = a.ev_cnt[r];
-        for (uint32_t j = lane; j < cnt; j += 64) {
-            const uint32_t e = a.events[(size_t)r * a.span + j];
-            const uint32_t node = e & ~EV_LEAVE;
-            const int d = (e & EV_LEAVE) ? -1 : 1;
-            for (int32_t t = a.out_ptr[node]; t < a.out_ptr[node + 1]; ++t) atomicAdd(&a.infl[a.out_ind[t]], d);
+    const int32_t* __restrict__ out_ind = a.out_ind;
+    const uint8_t* __restrict__ state = a.state;
+    for (uint32_t j = blockIdx.x * PTPB + tid; j < total; j += gridDim.x * PTPB) {
+        uint32_t lo = 0, hi = a.G; // s_pre[lo] <= j < s_pre[hi]
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s_pre[mid] <= j) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t e = a.events[(size_t)lo * a.span + (j - s_pre[lo])];
+        const uint32_t node = e & ~EV_LEAVE;
+        const int d = (e & EV_LEAVE) ? -1 : 1;
+        // without I -> S, a node that is not susceptible never reads its
+        // influence again: only susceptible targets are updated.  Targets go
+        // eight at a time: their ids, then their states, then the atomics,
+        // so a lane waits for two loads per eight targets, not per target.
+        const bool all = a.model == FS_MARKOV_SIS;
+        const int32_t t1 = a.out_ptr[node + 1];
+        for (int32_t t = a.out_ptr[node]; t < t1; t += 8) {
+            int32_t tg[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) tg[q] = t + q < t1 ? out_ind[t + q] : -1;
+            bool go[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) go[q] = tg[q] >= 0 && (all || state[tg[q]] == ST_S);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (go[q]) atomicAdd(&a.infl[tg[q]], d);
         }
     }
 }
@@ -196,7 +271,10 @@ __global__ __launch_bounds__(MTPB) void mk_rates_kernel(MkArgs a)
     __shared__ uint4 s_p[NW];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const unsigned long long k = a.ctl->step + a.step_off;
-    const bool control = a.force_control || a.ev_hist[k % a.H] > a.inertial_max;
+    const uint32_t events = a.ev_hist[k % a.H];
+    // a step without transitions changed nothing: the partials still hold
+    if (!a.force_control && a.fired[a.G] == 0) return;
+    const bool control = a.force_control || events > a.inertial_max;
     const uint32_t base = blockIdx.x * a.span;
     const uint32_t end = min(a.n, base + a.span);
     uint32_t A = 0, M = 0, nE = 0, nI = 0;
@@ -209,7 +287,7 @@ __global__ __launch_bounds__(MTPB) void mk_rates_kernel(MkArgs a)
             if (control) {
                 for (int32_t e = a.row_ptr[i]; e < a.row_ptr[i + 1]; ++e) f += a.state[a.col_ind[e]] == ST_I;
                 a.infl[i] = f;
-            } else {
+            } else if (x == ST_S) {
                 f = a.infl[i];
             }
         }
@@ -272,6 +350,7 @@ struct fs_markov {
     int32_t* d_infl = nullptr;
     uint32_t* d_events = nullptr;
     uint32_t* d_ev_cnt = nullptr;
+    uint32_t* d_fired = nullptr;
     uint4* d_rpart = nullptr;
     uint32_t* d_part = nullptr;
     uint32_t* d_hist = nullptr;
@@ -325,7 +404,8 @@ void release_markov(fs_markov* m)
     if (!m) return;
     if (m->exec) (void)hipGraphExecDestroy(m->exec);
     if (m->graph) (void)hipGraphDestroy(m->graph);
-    for (void* p : {(void*)m->d_state, (void*)m->d_infl, (void*)m->d_events, (void*)m->d_ev_cnt, (void*)m->d_rpart,
+    for (void* p : {(void*)m->d_state, (void*)m->d_infl, (void*)m->d_events, (void*)m->d_ev_cnt, (void*)m->d_fired,
+                    (void*)m->d_rpart,
                     (void*)m->d_part, (void*)m->d_hist, (void*)m->d_tau, (void*)m->d_evh, (void*)m->d_elapsed,
                     (void*)m->d_ctl})
         dev_free(p);
@@ -471,7 +551,8 @@ fs_status fs_markov_create(fs_graph* g, const fs_markov_params* p, fs_markov** o
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device)) != hipSuccess)
         return bad(e, "device attribute");
     // one workgroup region per compute unit, in whole wavefronts
-    m->G = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(cus, ((int64_t)n + 63) / 64));
+    m->G = (uint32_t)std::max<int64_t>(1, std::min<int64_t>({(int64_t)cus, (int64_t)fsm::MAX_REGIONS,
+                                                              ((int64_t)n + 63) / 64}));
     m->span = (((n + m->G - 1) / m->G) + 63) / 64 * 64;
     m->G = (n + m->span - 1) / m->span;
     if (p->stream) {
@@ -485,6 +566,7 @@ fs_status fs_markov_create(fs_graph* g, const fs_markov_params* p, fs_markov** o
         (e = dev_alloc((void**)&m->d_infl, (size_t)n * 4)) != hipSuccess ||
         (e = dev_alloc((void**)&m->d_events, (size_t)m->G * m->span * 4)) != hipSuccess ||
         (e = dev_alloc((void**)&m->d_ev_cnt, (size_t)m->G * 4)) != hipSuccess ||
+        (e = dev_alloc((void**)&m->d_fired, ((size_t)m->G + 1) * 4)) != hipSuccess ||
         (e = dev_alloc((void**)&m->d_rpart, (size_t)m->G * sizeof(uint4))) != hipSuccess ||
         (e = dev_alloc((void**)&m->d_part, part_words * 4)) != hipSuccess ||
         (e = dev_alloc((void**)&m->d_hist, (size_t)m->H * 16)) != hipSuccess ||
@@ -496,6 +578,7 @@ fs_status fs_markov_create(fs_graph* g, const fs_markov_params* p, fs_markov** o
     if ((e = hipMemsetAsync(m->d_state, 0, n, m->stream)) != hipSuccess ||
         (e = hipMemsetAsync(m->d_infl, 0, (size_t)n * 4, m->stream)) != hipSuccess ||
         (e = hipMemsetAsync(m->d_ev_cnt, 0, (size_t)m->G * 4, m->stream)) != hipSuccess ||
+        (e = hipMemsetAsync(m->d_fired, 0, ((size_t)m->G + 1) * 4, m->stream)) != hipSuccess ||
         (e = hipMemsetAsync(m->d_hist, 0, (size_t)m->H * 16, m->stream)) != hipSuccess ||
         (e = hipMemsetAsync(m->d_tau, 0, (size_t)m->H * 4, m->stream)) != hipSuccess ||
         (e = hipMemsetAsync(m->d_evh, 0, (size_t)m->H * 4, m->stream)) != hipSuccess ||
@@ -512,6 +595,7 @@ fs_status fs_markov_create(fs_graph* g, const fs_markov_params* p, fs_markov** o
     a.orig_id = g->d_orig;
     a.events = m->d_events;
     a.ev_cnt = m->d_ev_cnt;
+    a.fired = m->d_fired;
     a.rpart = m->d_rpart;
     a.part = m->d_part;
     a.tau_hist = m->d_tau;
