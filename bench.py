@@ -81,11 +81,16 @@ def bytes_per_update(d_mean: float, storage: str) -> float:
     return (28.0 if storage == "fp32" else 14.0) + 4.0 * d_mean
 
 
+STEP_KERNEL_SOURCES = ("fs_step.hpp", "fs_kernels.hip", "fs_device.hpp", "fs_internal.hpp")
+
+
 def kernel_source_hash() -> str:
+    """Hash of the sources that define the step kernel (the counters of a
+    committed profile stand only while it matches)."""
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2604_22092_amd", "csrc", "*"))):
-        with open(p, "rb") as f:
-            h.update(os.path.basename(p).encode())
+    for name in STEP_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2604_22092_amd", "csrc", name), "rb") as f:
+            h.update(name.encode())
             h.update(f.read())
     return h.hexdigest()[:16]
 
@@ -125,6 +130,24 @@ def cpu_baseline(rp, ci, model, seeds, budget_s: float, compact: bool):
     return {"value": n * steps / el / 1e9, "unit": "GNUPS", "cores": 1, "kind": "oracle",
             "sample": f"{steps} steps (steps 1..{steps}) of the same N={n:.0e} trajectory, "
                       f"single-threaded FP64 oracle, {el:.1f} s"}
+
+
+def copy_bandwidth(torch, dev, mib: int = 1024, reps: int = 5) -> float:
+    """Measured device-to-device copy bandwidth (bytes read + written per
+    second, GB/s): the best of `reps` copies of `mib` MiB."""
+    src = torch.empty(mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    best = float("inf")
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    del src, dst
+    return 2.0 * (mib << 20) / (best / 1e3) / 1e9
 
 
 def percentile(xs, q):
@@ -327,6 +350,8 @@ def main():
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default: the workload's trajectory length)")
     ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed runs of the K-step trajectory (value: their mean; CoV reported)")
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
     ap.add_argument("--variant", choices=["auto", "stream", "resident", "summary"], default="auto",
@@ -425,16 +450,25 @@ def main():
     sim.set_state(init_state, init_age, 0, step_index=0)
     torch.cuda.synchronize()
 
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    e0.record(stream)
-    sim.step(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms = e0.elapsed_time(e1)
+    # each timed run replays the same K-step trajectory from the seeded start
+    runs = []
+    wall = 0.0
+    for rep in range(max(1, args.repeats)):
+        if rep:
+            sim.set_state(init_state, init_age, 0, step_index=0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        e0.record(stream)
+        sim.step(args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - w0
+        runs.append(e0.elapsed_time(e1))
+    ms = float(np.mean(runs))
+    cov = float(np.std(runs) / ms) if len(runs) > 1 else 0.0
+    wall /= len(runs)
     hist = sim.history(0, args.steps)
     assert np.all(hist.sum(1) == n)
     final = sim.counts(0)
@@ -450,7 +484,9 @@ def main():
     plain = args.shed == "none" and not args.compaction
     traffic = measured_traffic(workload if storage == wl["storage"] else f"{workload}_{storage}") if plain else None
     s_frac = float(hist[:, 0].mean() / n)
-    print(f"[bench] {args.steps} steps: {ms:.3f} ms (wall {wall * 1e3:.1f} ms), {gnups:.2f} GNUPS, "
+    copy_gbs = copy_bandwidth(torch, dev)
+    print(f"[bench] {args.steps} steps: {ms:.3f} ms mean of {len(runs)} (CoV {cov:.3f}, wall {wall * 1e3:.1f} ms), "
+          f"{gnups:.2f} GNUPS, copy {copy_gbs:.0f} GB/s, "
           f"final counts {final.tolist()}, mean S fraction {s_frac:.3f}", file=sys.stderr, flush=True)
 
     cpu = None
@@ -481,7 +517,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "bytes_per_update": b_alg,
-                     "per_launch_us": round(per_launch_s * 1e6, 3)},
+                     "per_launch_us": round(per_launch_s * 1e6, 3),
+                     "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
+                     "repeats": len(runs), "cov": round(cov, 4)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

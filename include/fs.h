@@ -106,6 +106,22 @@ typedef struct fs_dist {
 #define FS_STORAGE_FP32 0
 #define FS_STORAGE_COMPACT 1
 
+/* ----------------------------------------------------------- memory hook
+ * Routes the library's persistent device arrays (graphs and their layouts,
+ * sims, Markovian engines) through the caller's allocator, e.g. a framework's
+ * caching allocator.  alloc(bytes, ctx) returns device memory on the current
+ * device or NULL (reported as FS_ERR_OUT_OF_MEMORY); free(ptr, ctx) releases
+ * it, called only after the owning stream has finished with the block.
+ * Process-wide; a block is always released by the allocator that gave it
+ * out, also after the hook changes.  Both NULL restores hipMalloc (graphs)
+ * and the stream-ordered pool (sims).  Batch and server tables and call-local
+ * temporaries always use the library's own allocator.
+ * Errors: FS_ERR_INVALID_ARG when exactly one of alloc, free is NULL.
+ */
+typedef void* (*fs_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*fs_free_fn)(void* ptr, void* ctx);
+fs_status fs_set_allocator(fs_alloc_fn alloc, fs_free_fn free, void* ctx);
+
 /* ------------------------------------------------------------------- graph */
 typedef struct fs_graph fs_graph;
 

@@ -39,7 +39,7 @@ EXPORTS = [
     "fs_server_create", "fs_server_submit", "fs_server_wait", "fs_server_result",
     "fs_server_stats", "fs_server_destroy", "fs_server_clock",
     "fs_markov_create", "fs_markov_destroy", "fs_markov_seed", "fs_markov_set_state", "fs_markov_step",
-    "fs_markov_sync", "fs_markov_get_state", "fs_markov_history",
+    "fs_markov_sync", "fs_markov_get_state", "fs_markov_history", "fs_set_allocator",
 ]
 
 
@@ -132,6 +132,7 @@ def _declare(L):
         "fs_sim_create": ([P, ctypes.POINTER(fs_sim_params), PP], I32),
         "fs_markov_create": ([P, ctypes.POINTER(fs_markov_params), PP], I32),
         "fs_markov_destroy": ([P], I32),
+        "fs_set_allocator": ([P, P, P], I32),
         "fs_markov_seed": ([P, I64, P, I32], I32),
         "fs_markov_set_state": ([P, P, I64, ctypes.c_double], I32),
         "fs_markov_step": ([P, I64], I32),
@@ -399,6 +400,45 @@ def make_params(ei, ir, beta: float, dt: float, seed: int = 0, replicas: int = 1
         p.shed_scale = float(shed[2])
     p.compaction = 1 if compaction else 0
     return p
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_hooks = []   # the installed callbacks stay referenced while the library may call them
+
+
+def set_allocator(alloc=None, free=None):
+    """Routes the library's persistent device arrays through alloc(bytes) ->
+    int pointer and free(pointer); no arguments restores the library's own
+    allocator."""
+    if alloc is None and free is None:
+        _check(lib().fs_set_allocator(None, None, None), "fs_set_allocator")
+        return
+    a = _ALLOC_FN(lambda nbytes, ctx: int(alloc(int(nbytes))) or None)
+    f = _FREE_FN(lambda ptr, ctx: free(int(ptr)))
+    _hooks.append((a, f))
+    _check(lib().fs_set_allocator(ctypes.cast(a, ctypes.c_void_p), ctypes.cast(f, ctypes.c_void_p), None),
+           "fs_set_allocator")
+
+
+def hip_runtimes() -> set:
+    """Paths of the HIP runtimes mapped into this process."""
+    with open("/proc/self/maps") as f:
+        return {line.split()[-1] for line in f if "libamdhip64" in line}
+
+
+def use_torch_allocator(device: int = 0):
+    """Device arrays of the library come from PyTorch's caching allocator.
+    PyTorch must share the library's HIP runtime: import torch before the
+    library's first call (otherwise PyTorch maps a second runtime)."""
+    import torch
+
+    if len(hip_runtimes()) > 1:
+        raise RuntimeError("PyTorch and the library run on different HIP runtimes: import torch before the "
+                           "first call into the library")
+
+    set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n, device=device),
+                  lambda p: torch.cuda.caching_allocator_delete(p))
 
 
 FS_MARKOV_SEIR, FS_MARKOV_SIR, FS_MARKOV_SIS = 0, 1, 2

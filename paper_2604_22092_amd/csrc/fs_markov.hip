@@ -402,6 +402,7 @@ fs_status ensure_out_csr(fs_graph* g)
 void release_markov(fs_markov* m)
 {
     if (!m) return;
+    if (m->stream) (void)hipStreamSynchronize(m->stream); // (blocks may return to a caller's allocator)
     if (m->exec) (void)hipGraphExecDestroy(m->exec);
     if (m->graph) (void)hipGraphDestroy(m->graph);
     for (void* p : {(void*)m->d_state, (void*)m->d_infl, (void*)m->d_events, (void*)m->d_ev_cnt, (void*)m->d_fired,

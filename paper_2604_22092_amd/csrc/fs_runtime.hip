@@ -11,6 +11,8 @@
 #include <exception>
 #include <new>
 #include <string>
+#include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "fs_runtime.hpp"
@@ -25,16 +27,62 @@ fs_status fail(fs_status s, const std::string& msg)
     return s;
 }
 
+// The caller's device allocator (fs_set_allocator), and the release path of
+// every block it gave out: a block is returned to whoever allocated it, also
+// after the hook has changed.
+struct Hook {
+    fs_alloc_fn alloc = nullptr;
+    fs_free_fn free = nullptr;
+    void* ctx = nullptr;
+};
+std::mutex g_hook_mu;
+Hook g_hook;
+std::unordered_map<void*, Hook> g_hooked;
+
+hipError_t hook_alloc(void** p, size_t bytes, bool* used)
+{
+    Hook h;
+    {
+        std::lock_guard<std::mutex> lk(g_hook_mu);
+        h = g_hook;
+    }
+    *used = h.alloc != nullptr;
+    if (!*used) return hipSuccess;
+    *p = h.alloc(bytes, h.ctx);
+    if (!*p) return hipErrorOutOfMemory;
+    std::lock_guard<std::mutex> lk(g_hook_mu);
+    g_hooked[*p] = h;
+    return hipSuccess;
+}
+
+// Returns true when p came from a caller's allocator (and releases it).
+bool hook_free(void* p)
+{
+    Hook h;
+    {
+        std::lock_guard<std::mutex> lk(g_hook_mu);
+        auto it = g_hooked.find(p);
+        if (it == g_hooked.end()) return false;
+        h = it->second;
+        g_hooked.erase(it);
+    }
+    h.free(p, h.ctx);
+    return true;
+}
+
 hipError_t dev_alloc(void** p, size_t bytes)
 {
     *p = nullptr;
     if (bytes == 0) bytes = 256;
+    bool used = false;
+    hipError_t e = hook_alloc(p, bytes, &used);
+    if (used) return e;
     return hipMalloc(p, bytes);
 }
 
 void dev_free(void* p)
 {
-    if (p) (void)hipFree(p);
+    if (p && !hook_free(p)) (void)hipFree(p);
 }
 
 // Per-sim buffers are stream-ordered allocations on the sim's stream: making
@@ -58,12 +106,28 @@ hipError_t sim_alloc(fs_sim* s, void** p, size_t bytes)
 {
     *p = nullptr;
     if (bytes == 0) bytes = 256;
+    bool used = false;
+    hipError_t e = hook_alloc(p, bytes, &used);
+    if (used) return e;
     return hipMallocAsync(p, bytes, s->stream);
 }
 
+// A block from the caller's allocator is released once the sim's stream has
+// finished with it; the library's own blocks are freed in stream order.
 void sim_free(fs_sim* s, void* p)
 {
-    if (p) (void)hipFreeAsync(p, s->stream);
+    if (!p) return;
+    bool hooked;
+    {
+        std::lock_guard<std::mutex> lk(g_hook_mu);
+        hooked = g_hooked.count(p) != 0;
+    }
+    if (hooked) {
+        (void)hipStreamSynchronize(s->stream);
+        hook_free(p);
+    } else {
+        (void)hipFreeAsync(p, s->stream);
+    }
 }
 
 // Per-node arrays between the caller's node order and a graph's internal
@@ -644,6 +708,17 @@ using namespace fsr;
 extern "C" {
 
 const char* fs_version(void) { return "flashspread-hip 0.1 (gfx950)"; }
+
+fs_status fs_set_allocator(fs_alloc_fn alloc, fs_free_fn free_fn, void* ctx)
+{
+    if ((alloc == nullptr) != (free_fn == nullptr))
+        return fail(FS_ERR_INVALID_ARG, "give both alloc and free, or neither");
+    std::lock_guard<std::mutex> lk(g_hook_mu);
+    g_hook.alloc = alloc;
+    g_hook.free = free_fn;
+    g_hook.ctx = alloc ? ctx : nullptr;
+    return FS_OK;
+}
 
 const char* fs_status_string(fs_status s)
 {

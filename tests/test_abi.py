@@ -160,3 +160,12 @@ def test_markov_host_validation():
     assert L.fs_markov_sync(None) == 1
     assert L.fs_markov_destroy(None) == 1
     assert L.fs_markov_get_state(None, None, None, None, None) == 1
+
+
+def test_allocator_hook_arguments():
+    import ctypes
+    L = fs.lib()
+    assert L.fs_set_allocator(None, None, None) == 0
+    cb = fs._capi._ALLOC_FN(lambda n, c: None)
+    assert L.fs_set_allocator(ctypes.cast(cb, ctypes.c_void_p), None, None) == 1
+    assert b"both" in L.fs_last_error()
