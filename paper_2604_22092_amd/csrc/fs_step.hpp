@@ -136,6 +136,11 @@ __device__ __forceinline__ uint32_t fetch_bit(const uint32_t* __restrict__ lds, 
 constexpr int UMAX = UNIFORM_MAX_DEG;
 // Edge slots per batch of the general (mixed-degree) gather.
 constexpr int JB = 8;
+// Edge slots past the preload depth of a uniform chunk are loaded JT at a
+// time, every load of a batch issued before its first use.
+constexpr int JT = 16;
+// chunk_meta[c].y of a chunk whose rows do not share one light degree.
+constexpr uint32_t MIXED_CHUNK = 255u;
 // Chunks of 64 units each wavefront takes per pass; the hazards and draws of
 // a pass are evaluated on compacted lanes.
 #ifndef FS_CU
@@ -205,11 +210,15 @@ __device__ __forceinline__ void issue_pass(const StepArgs& a, uint32_t first, ui
         const uint32_t nrows = P.live[u] ? min(rows, (uint32_t)a.n - n0) : 0u;
         P.xr[u] = BufIO<state_t>::ld(make_rsrc((const state_t*)a.state + u0, P.nvalid[u] * sizeof(state_t)), lane);
         P.agw[u] = BufIO<age_t>::ld(make_rsrc((const age_t*)a.age + u0, P.nvalid[u] * sizeof(age_t)), lane);
-        P.dgr[u] = BufIO<uint16_t>::ld(make_rsrc(a.ldeg + n0, nrows * 2u), q);
+        // (uniform layouts have no heavy rows and arithmetic metadata: the
+        // degree array is not needed)
+        P.dgr[u] = UNIFORM ? 0u : BufIO<uint16_t>::ld(make_rsrc(a.ldeg + n0, nrows * 2u), q);
         // graphs in a degree-sorted order (never uniform ones) key the draws
         // by the caller's node id
         P.org[u] = UNIFORM ? n0 + q : ld32(make_rsrc(a.orig_id + n0, nrows * 4u), q << 2);
-        const bool pre = P.ud[u] <= (uint32_t)UMAX;
+        // every uniform chunk preloads its first UMAX slots (slots past its
+        // degree are out of range)
+        const bool pre = P.ud[u] != MIXED_CHUNK;
         const rsrc_t cr = make_rsrc(a.col_t + P.base[u], pre ? P.ud[u] * rows * 4u : 0u);
 #pragma unroll
         for (int j = 0; j < UMAX; ++j) P.c[u][j] = (int32_t)ld32(cr, ((uint32_t)j * rows + q) << 2);
@@ -237,7 +246,7 @@ __device__ __forceinline__ void shed_pre(const StepArgs& a, const Pass<age_t>& P
         const int x = valid ? (int)P.xr[u] : ST_R;
         const uint32_t dg = valid ? P.dgr[u] : 0u;
         const bool want = x == ST_S && (UNIFORM || dg != HEAVY_ROW);
-        const bool pre = UNIFORM || P.ud[u] <= (uint32_t)UMAX;
+        const bool pre = UNIFORM || P.ud[u] != MIXED_CHUNK;
 #pragma unroll
         for (int j = 0; j < UMAX; ++j) {
             const bool use = pre && (uint32_t)j < P.ud[u] && want;
@@ -249,7 +258,8 @@ __device__ __forceinline__ void shed_pre(const StepArgs& a, const Pass<age_t>& P
 }
 
 // Pressure of one chunk's light row for this lane (Eq. (influence) without
-// beta).  Uniform chunks use the preloaded slots; mixed chunks find a row's
+// beta).  Uniform chunks use the preloaded slots (and load any further ones
+// in batches of JT, each batch's loads issued together); mixed chunks find a row's
 // position in run j as its rank among the rows with more than j edges (ballot
 // prefix count), JB slots at a time.  With age-dependent shedding (SHED) a
 // source whose bit is set contributes its s(tau) from `shedr`; the value load
@@ -267,7 +277,7 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
     const uint32_t d = dg == HEAVY_ROW ? 0u : dg;
     uint32_t pi = 0;
     float pw = 0.0f;
-    if (UNIFORM || P.ud[u] <= (uint32_t)UMAX) {
+    if (UNIFORM || P.ud[u] != MIXED_CHUNK) {
         // uniform chunk: slots past the degree hold 0 (a valid node) and are
         // not used; weights come through the same per-chunk range
         const uint32_t rows = 64u >> lgR;
@@ -293,6 +303,31 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
                 pw += v;
             } else {
                 pi += b;
+            }
+        }
+        // a uniform chunk deeper than the preload: its remaining slots, JT
+        // per batch (same layout; slots past the degree are out of range)
+        if (!UNIFORM && P.ud[u] > (uint32_t)UMAX) {
+            const rsrc_t cr = make_rsrc(a.col_t + P.base[u], P.ud[u] * rows * 4u);
+            for (uint32_t j0 = UMAX; j0 < P.ud[u]; j0 += JT) {
+                int32_t c[JT];
+                float wv[JT];
+#pragma unroll
+                for (int jj = 0; jj < JT; ++jj) {
+                    const uint32_t off = want ? ((j0 + jj) * rows + q) << 2 : OOB;
+                    c[jj] = (int32_t)ld32(cr, off);
+                    wv[jj] = WEIGHTED ? __uint_as_float(ld32(wr, off)) : 0.0f;
+                }
+#pragma unroll
+                for (int jj = 0; jj < JT; ++jj) {
+                    const bool use = want && j0 + jj < P.ud[u];
+                    const uint32_t src = ((uint32_t)c[jj] << lgR) + rep;
+                    const uint32_t b = fetch_bit<MODE>(lds, gbits, src, a.lg_gran, use);
+                    const float v = SHED ? __uint_as_float(ld32(shedr, b ? src << 2 : OOB)) : (float)b;
+                    if (WEIGHTED) pw = __builtin_fmaf(wv[jj], v, pw);
+                    else if (SHED) pw += v;
+                    else pi += b;
+                }
             }
         }
     } else {
@@ -360,6 +395,14 @@ template <int CU, class F>
 __device__ __forceinline__ void compact_apply(uint32_t* xch, uint32_t lane, const bool* flag,
                                               const uint32_t* payload, uint32_t* result, F f)
 {
+    if constexpr (CU == 1) {
+        // one chunk per pass holds at most 64 items: packing would still
+        // evaluate f once, so evaluate it on the flagged lanes in place
+        (void)xch;
+        (void)lane;
+        if (flag[0]) result[0] = f(payload[0]);
+        return;
+    }
     unsigned long long m[CU];
     uint32_t pre[CU + 1];
     pre[0] = 0;
