@@ -29,6 +29,8 @@ constexpr uint32_t SUMMARY_BITS = 1u << 20;
 #define FS_UMAX 12
 #endif
 constexpr int UNIFORM_MAX_DEG = FS_UMAX;
+// Entries of the hazard table of a fixed-step sim (StepArgs::htab).
+constexpr uint32_t HTAB_LEN = 8192;
 // Bitmaps are allocated in whole 512-unit tiles (8 words of 64 bits).
 constexpr uint32_t BITMAP_TILE = 512;
 // Active-chunk compaction: the refresh runs one workgroup of WG_REFRESH
@@ -158,6 +160,17 @@ struct StepArgs {
     // of the step, else 0.
     const uint32_t* act;
     uint8_t* live;
+    // hazards at the ages fixed steps reach (fixed-step sims; nullptr: none).
+    // A unit entering E or I has age 0, and each step without a transition
+    // adds dt in FP32, so its age is a_m after m steps: a_0 = 0, a_{m+1} =
+    // a_m + dt (compact storage: a_m = m).  htab[m] = (a_m, hazard of the
+    // E -> I law at a_m, of the I -> R law, 0) for m < htab_len, evaluated by
+    // the step's own hazard code; a unit whose age equals a_m, m = rint(age *
+    // htab_inv), takes its hazard from the table, any other age (a state
+    // load's arbitrary ages, ages past the table) is evaluated.
+    const float4* htab;
+    uint32_t htab_len;
+    float htab_inv;
 };
 
 // Arguments of the summary launch that follows a step launch (or a bitmap

@@ -253,7 +253,8 @@ void release_sim(fs_sim* s)
         for (void* p : {s->d_state, s->d_age, s->d_iota[0], s->d_iota[1], (void*)s->d_rates, (void*)s->d_ctl,
                         (void*)s->d_hist, (void*)s->d_part, (void*)s->d_rc_part, (void*)s->d_cnt4,
                         (void*)s->d_summary, s->d_seg_part, (void*)s->d_lam_part, (void*)s->d_dt_hist,
-                        (void*)s->d_shed[0], (void*)s->d_shed[1], (void*)s->d_live, (void*)s->d_act})
+                        (void*)s->d_shed[0], (void*)s->d_shed[1], (void*)s->d_live, (void*)s->d_act,
+                        (void*)s->d_htab})
             sim_free(s, p);
     }
     s->layout.reset();
@@ -1037,6 +1038,25 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
     a.shed = shed;
     a.act = s->d_act;
     a.live = s->d_live;
+    if (!p->adaptive) {
+        // the hazard table: the ages fixed steps reach from 0, then both
+        // laws' hazards there (on the device, by the step's own code)
+        std::vector<float4> tab(fsi::HTAB_LEN);
+        float x = 0.0f;
+        for (uint32_t m = 0; m < fsi::HTAB_LEN; ++m) {
+            tab[m] = make_float4(s->storage == 0 ? x : (float)m, 0.0f, 0.0f, 0.0f);
+            x = x + a.dt;
+        }
+        if ((e = sim_alloc(s, (void**)&s->d_htab, tab.size() * sizeof(float4))) != hipSuccess ||
+            (e = hipMemcpyAsync(s->d_htab, tab.data(), tab.size() * sizeof(float4), hipMemcpyHostToDevice,
+                                s->stream)) != hipSuccess ||
+            (e = fsk::launch_hazard_table(a.hz, a.same_kind, s->d_htab, fsi::HTAB_LEN, s->stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(s->stream)) != hipSuccess)
+            return bad(e, "hazard table");
+        a.htab = s->d_htab;
+        a.htab_len = fsi::HTAB_LEN;
+        a.htab_inv = s->storage == 0 ? 1.0f / a.dt : 1.0f;
+    }
     s->kfn = fsk::step_kernel_fn(s->storage, g->d_weights != nullptr, s->mode, false, shedding,
                                  s->d_rates != nullptr || s->d_act != nullptr);
     s->hfn = fsk::heavy_kernel_fn(g->d_weights != nullptr, shedding);

@@ -153,6 +153,20 @@ constexpr int CU = FS_CU;
 #endif
 constexpr bool PREFETCH = FS_PREFETCH != 0;
 
+// The rate of an E (isI false) or I unit of age xa: the hazard of its law.
+// With both laws of one kind the E/I choice only selects parameters, so one
+// hazard evaluation serves a wavefront holding both.
+__device__ __forceinline__ float unit_hazard(const HazardDev* hz, int32_t same_kind, float xa, bool isI)
+{
+    if (same_kind) {
+        HazardDev hd = hz[0];
+        if (isI) hd = hz[1];
+        hd.kind = hz[0].kind;
+        return fsd::hazard(hd, xa);
+    }
+    return isI ? fsd::hazard(hz[1], xa) : fsd::hazard(hz[0], xa);
+}
+
 // The loads of one pass, as issued: chunk numbers and metadata are
 // wave-uniform; xr, agw and dgr are the raw state, age and degree words
 // (0 for lanes past the chunk's valid units), used only after the pass's
@@ -163,7 +177,31 @@ struct Pass {
     bool live[CU];
     uint32_t xr[CU], agw[CU], dgr[CU], org[CU];
     int32_t c[CU][UMAX];
+    float tab[CU][3]; // hazard-table entry of the lane's age (issue_table)
 };
+
+// Hazard-table loads of a pass's E/I lanes (StepArgs::htab), issued once its
+// state and age have arrived and before the next pass's loads, so that
+// waiting for them never waits for a later pass.  Lanes without an entry
+// read nothing (0).
+template <bool UNIFORM, class age_t>
+__device__ __forceinline__ void issue_table(const StepArgs& a, Pass<age_t>& P, uint32_t lane)
+{
+    const rsrc_t tr = make_rsrc(a.htab, a.htab ? a.htab_len * 16u : 0u);
+#pragma unroll
+    for (int u = 0; u < CU; ++u) {
+        const int x = lane < P.nvalid[u] ? (int)P.xr[u] : ST_R;
+        const float af = age_units(age_from_raw<age_t>(P.agw[u]));
+        const float mf = rintf(af * a.htab_inv);
+        const bool want = (x == ST_E || x == ST_I) && mf < (float)a.htab_len;
+        const auto t = __builtin_amdgcn_raw_buffer_load_b128(tr, want ? (int)((uint32_t)mf << 4) : (int)OOB, 0, 0);
+        P.tab[u][0] = __uint_as_float(t[0]);
+        P.tab[u][1] = __uint_as_float(t[1]);
+        P.tab[u][2] = __uint_as_float(t[2]);
+    }
+    // (keep the scheduler from moving the next pass's loads above these)
+    __builtin_amdgcn_sched_barrier(0);
+}
 
 // Issues every load of a pass that does not depend on the state: chunk
 // metadata (one scalar load), state, age and light degree, and the edge
@@ -492,21 +530,17 @@ __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t
             pay[u] = age_bits(ag[u]) | (x[u] == ST_I ? 0x80000000u : 0u);
             res[u] = 0;
         }
-        auto hz = [&](uint32_t w, bool isI) {
-            const float xa = age_from_bits<age_t>(w & 0x7FFFFFFFu);
-            float h;
-            if (a.same_kind) {
-                HazardDev hd = a.hz[0];
-                if (isI) hd = a.hz[1];
-                hd.kind = a.hz[0].kind;
-                h = fsd::hazard(hd, xa);
-            } else {
-                h = isI ? fsd::hazard(a.hz[1], xa) : fsd::hazard(a.hz[0], xa);
-            }
-            return h;
-        };
+        // ages the table holds take their hazard from it
+        bool hit[CU];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            hit[u] = a.htab != nullptr && need[u] && P.tab[u][0] == age_units(ag[u]);
+            if (hit[u]) lam[u] = x[u] == ST_I ? P.tab[u][2] : P.tab[u][1];
+            need[u] = need[u] && !hit[u];
+        }
         compact_apply<CU>(xch, lane, need, pay, res, [&](uint32_t w) {
-            return __float_as_uint(hz(w, (w & 0x80000000u) != 0u));
+            return __float_as_uint(
+                unit_hazard(a.hz, a.same_kind, age_from_bits<age_t>(w & 0x7FFFFFFFu), (w & 0x80000000u) != 0u));
         });
 #pragma unroll
         for (int u = 0; u < CU; ++u)
@@ -682,6 +716,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
         __builtin_amdgcn_s_waitcnt(0);
     }
     if (R > 1 || USE_LDS) __syncthreads();
+    issue_table<UNIFORM>(a, P, lane);
 
     uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0; // per-wave counts (R == 1)
 
@@ -706,6 +741,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
         if (first >= walk) break;
         if (!PREFETCH)
             issue_pass<STORAGE, UNIFORM, EXTRA>(a, first, nwaves, stride, nchunks, walk, total, lane, P1, ahead);
+        issue_table<UNIFORM>(a, P1, lane);
         if (SPLIT) shed_pre<UNIFORM>(a, P1, lane, s_bits, shedr, sv);
         if (PREFETCH)
             issue_pass<STORAGE, UNIFORM, EXTRA>(a, first + stride, nwaves, stride, nchunks, walk, total, lane, P,
@@ -716,6 +752,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
         first += stride;
         if (!PREFETCH && first < walk)
             issue_pass<STORAGE, UNIFORM, EXTRA>(a, first, nwaves, stride, nchunks, walk, total, lane, P, ahead);
+        if (first < walk) issue_table<UNIFORM>(a, P, lane);
     }
 
     // one plain store of this workgroup's counts; the reduce kernel sums them

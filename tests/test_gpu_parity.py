@@ -80,6 +80,42 @@ def test_device_hazard_compact_steps_within_2e6(law, dt):
     check_rates(got, ref, f"hazard {law} steps dt={dt}")
 
 
+@pytest.mark.parametrize("compact", [False, True], ids=["fp32", "compact"])
+@pytest.mark.parametrize("laws", [(W.LN_E, W.LN_I), (("erlang", 3, 1.0), ("weibull", 2.0, 6.0))],
+                         ids=["lognormal", "erlang-weibull"])
+def test_hazard_table_serves_the_evaluated_hazards(small_graph, laws, compact):
+    """Fixed-step sims take the hazard of an E/I unit whose age is one that
+    fixed steps reach from 0 (a_m, m below the table length) from a table;
+    the rates the step records must be exactly the directly evaluated
+    hazards, for table ages, ages next to them and ages past the table."""
+    rp, ci, g = small_graph
+    n = len(rp) - 1
+    dt = 0.1
+    rng = np.random.default_rng(11)
+    st = np.where(rng.random(n) < 0.5, fs.FS_E, fs.FS_I).astype(np.int32)
+    m = rng.integers(0, 9000, n)                      # 8192 entries: some ages lie past the table
+    if compact:
+        age = m.astype(np.uint16)
+    else:
+        a = np.concatenate([[0], np.cumsum(np.full(9000, dt, np.float32), dtype=np.float32)]).astype(np.float32)
+        age = a[m]
+        off = rng.random(n) < 0.3                     # ages next to a table age: evaluated
+        age[off] = np.nextafter(age[off], np.float32(np.inf))
+    model = {"ei": laws[0], "ir": laws[1], "beta": 0.06, "dt": dt, "seed": 1}
+    sim = fs.Sim.from_model(g, model, storage=storage_of(compact), record_rates=True)
+    try:
+        sim.set_state(st, age, 0, step_index=0)
+        sim.step(1)
+        got = sim.rates(0)
+    finally:
+        sim.close()
+    storage = storage_of(compact)
+    for comp, law in [(fs.FS_E, laws[0]), (fs.FS_I, laws[1])]:
+        sel = st == comp
+        want = fs.fs_eval_hazard(law, age[sel], storage, dt)
+        np.testing.assert_array_equal(got[sel], want)
+
+
 # ----------------------------------------------------------- one-step parity
 
 def oracle_checkpoints(rp, ci, model, seeds, ks, compact):
