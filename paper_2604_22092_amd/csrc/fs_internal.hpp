@@ -207,7 +207,7 @@ struct HeavyArgs {
     uint32_t nseg;
     int32_t lgR;
     uint32_t step_off;
-    uint32_t pad;
+    uint32_t units;     // N * R: the bits the resident variant copies into LDS
     const float* shed0; // shedding kernels: the s(tau) buffers of StepArgs
     const float* shed1;
     const void* state;  // start-of-step states: segments of rows that are not S

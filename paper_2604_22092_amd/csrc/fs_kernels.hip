@@ -331,9 +331,11 @@ hipError_t launch_recount(int storage, const void* state, int32_t n, int32_t lgR
 }
 
 const void* reduce_kernel_fn() { return (const void*)&reduce_kernel; }
-const void* heavy_kernel_fn(bool weighted, bool shed)
+const void* heavy_kernel_fn(bool weighted, bool shed, bool resident)
 {
-    if (shed) return heavy_kernel_fn_shed(weighted);
+    if (shed) return heavy_kernel_fn_shed(weighted, resident);
+    if (resident)
+        return weighted ? (const void*)&heavy_resident_kernel<true, false> : (const void*)&heavy_resident_kernel<false, false>;
     return weighted ? (const void*)&heavy_pressure_kernel<true, false> : (const void*)&heavy_pressure_kernel<false, false>;
 }
 const void* advance_kernel_fn() { return (const void*)&advance_kernel; }

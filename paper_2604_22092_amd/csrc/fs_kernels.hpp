@@ -21,7 +21,7 @@ const void* step_kernel_fn(int storage, bool weighted, int mode, bool uniform, b
 const void* step_kernel_fn_extra(int storage, bool weighted, int mode, bool uniform);
 const void* step_kernel_fn_shed(int storage, bool weighted, int mode, bool uniform);
 const void* step_kernel_fn_shed_extra(int storage, bool weighted, int mode, bool uniform);
-const void* heavy_kernel_fn_shed(bool weighted);
+const void* heavy_kernel_fn_shed(bool weighted, bool resident);
 
 // Exact counts of one replica: per-workgroup partials (at most max_grid rows
 // of 4 in `part`) reduced into out4.
@@ -30,8 +30,11 @@ hipError_t launch_recount(int storage, const void* state, int32_t n, int32_t lgR
 // reduce_kernel(const Ctl*, const uint32_t* part, uint32_t G, uint32_t C, uint32_t* out, uint32_t H):
 // one block per slot, WG threads.
 const void* reduce_kernel_fn();
-// heavy_pressure_kernel(HeavyArgs): segment partials of degree-binned rows; WG threads.
-const void* heavy_kernel_fn(bool weighted, bool shed);
+// Segment partials of degree-binned rows (HeavyArgs): heavy_pressure_kernel
+// (WG threads, bits from global memory), or with resident set
+// heavy_resident_kernel (RESIDENT_TPB threads, at most one workgroup per CU,
+// the bitmap copied into LDS).
+const void* heavy_kernel_fn(bool weighted, bool shed, bool resident);
 // advance_kernel(Ctl*, uint32_t r): adds r to the step index; one thread.
 const void* advance_kernel_fn();
 // summary_kernel(SumArgs): one thread per summary bit (sum_words * 64 threads

@@ -14,8 +14,10 @@ const void* step_kernel_fn_shed(int storage, bool weighted, int mode, bool unifo
     return step_kernel_pick<true, false>(storage, weighted, mode, uniform);
 }
 
-const void* heavy_kernel_fn_shed(bool weighted)
+const void* heavy_kernel_fn_shed(bool weighted, bool resident)
 {
+    if (resident)
+        return weighted ? (const void*)&heavy_resident_kernel<true, true> : (const void*)&heavy_resident_kernel<false, true>;
     return weighted ? (const void*)&heavy_pressure_kernel<true, true> : (const void*)&heavy_pressure_kernel<false, true>;
 }
 

@@ -300,6 +300,17 @@ uint32_t heavy_grid(const fs_sim* s)
     return std::max(1u, std::min((s->nseg + per_wg - 1) / per_wg, 8192u));
 }
 
+// The sim's own heavy-row launch: with the resident step, the LDS-resident
+// kernel (at most one workgroup per CU), else heavy_grid WG-thread workgroups.
+uint32_t sim_heavy_block(const fs_sim* s) { return s->mode == fsi::MODE_RESIDENT ? fsi::RESIDENT_TPB : WG; }
+
+uint32_t sim_heavy_grid(const fs_sim* s)
+{
+    if (s->mode != fsi::MODE_RESIDENT) return heavy_grid(s);
+    const uint32_t per_wg = fsi::RESIDENT_TPB / 64;
+    return std::max(1u, std::min((s->nseg + per_wg - 1) / per_wg, std::max(s->cus, 1u)));
+}
+
 void drop_graph_exec(fs_sim* s)
 {
     if (s->exec) (void)hipGraphExecDestroy(s->exec);
@@ -576,6 +587,7 @@ fsi::HeavyArgs heavy_args(const fs_sim* s)
     h.shed1 = s->d_shed[1];
     h.state = s->d_state;
     h.storage = s->storage;
+    h.units = (uint32_t)((size_t)s->g->n << s->lgR);
     return h;
 }
 
@@ -646,7 +658,7 @@ fs_status build_graph_exec(fs_sim* s, int b)
     for (int j = 0; j < b; ++j) {
         if (s->nseg) {
             void* hargv[] = {&q.heavy[j]};
-            if ((st = add(s->hfn, dim3(heavy_grid(s)), dim3(WG), hargv)) != FS_OK) return st;
+            if ((st = add(s->hfn, dim3(sim_heavy_grid(s)), dim3(sim_heavy_block(s)), hargv)) != FS_OK) return st;
         }
         void* argv[] = {&q.step[j]};
         if ((st = add(s->kfn, dim3(s->G), dim3(s->tpb), argv)) != FS_OK) return st;
@@ -679,7 +691,7 @@ fs_status launch_sequence(fs_sim* s, uint32_t r)
     for (uint32_t j = 0; j < r; ++j) {
         if (s->nseg) {
             void* hargv[] = {&q.heavy[j]};
-            FS_HIP(hipLaunchKernel(s->hfn, dim3(heavy_grid(s)), dim3(WG), hargv, 0, s->stream));
+            FS_HIP(hipLaunchKernel(s->hfn, dim3(sim_heavy_grid(s)), dim3(sim_heavy_block(s)), hargv, 0, s->stream));
         }
         void* argv[] = {&q.step[j]};
         FS_HIP(hipLaunchKernel(s->kfn, dim3(s->G), dim3(s->tpb), argv, 0, s->stream));
@@ -955,6 +967,7 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
         if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device)) != hipSuccess)
             return bad(e, "device attribute");
         s->G = (uint32_t)std::min<size_t>(tiles, (size_t)std::max(cus, 1));
+        s->cus = (uint32_t)std::max(cus, 1);
     } else {
         s->G = (uint32_t)std::min<size_t>(tiles, fsi::max_step_grid(R));
     }
@@ -1059,7 +1072,7 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
     }
     s->kfn = fsk::step_kernel_fn(s->storage, g->d_weights != nullptr, s->mode, false, shedding,
                                  s->d_rates != nullptr || s->d_act != nullptr);
-    s->hfn = fsk::heavy_kernel_fn(g->d_weights != nullptr, shedding);
+    s->hfn = fsk::heavy_kernel_fn(g->d_weights != nullptr, shedding, s->mode == fsi::MODE_RESIDENT);
     if (!s->kfn || !s->hfn) {
         release_sim(s);
         return fail(FS_ERR_DEVICE, "no step kernel for this configuration");

@@ -101,6 +101,7 @@ struct fs_sim {
     fsi::ShedDev shed{};
     int H = 1024;
     uint32_t G = 0;                // step workgroups
+    uint32_t cus = 0;              // compute units of the device (LDS variants)
     uint32_t tpb = 0;              // threads (units) per step workgroup / tile
     int mode = fsi::MODE_STREAM;   // step kernel variant
     unsigned long long* d_summary = nullptr; // MODE_SUMMARY: summary of the current bitmap
@@ -181,7 +182,9 @@ struct StreamBuf {
 void release_sim(fs_sim* s);
 size_t state_bytes(int storage);
 size_t age_bytes(int storage);
-uint32_t heavy_grid(const fs_sim* s);
+uint32_t heavy_grid(const fs_sim* s);       // WG-thread heavy workgroups (batches too)
+uint32_t sim_heavy_grid(const fs_sim* s);   // the sim's own heavy launch
+uint32_t sim_heavy_block(const fs_sim* s);
 fsi::HeavyArgs heavy_args(const fs_sim* s);
 // Device bytes a sim of this graph and these parameters holds (an estimate
 // used for admission by memory budget).

@@ -914,6 +914,145 @@ __global__ __launch_bounds__(WG) void heavy_pressure_kernel(HeavyArgs h)
     heavy_body<WEIGHTED, SHED>(h, blockIdx.x, gridDim.x);
 }
 
+// Column slots of a heavy segment each lane loads ahead (HC * 64 / R edges).
+constexpr int HC = 4;
+
+// The loads of one heavy segment, as issued.
+struct HeavySeg {
+    uint32_t seg, len;          // segment index, edge count (0: none)
+    uint32_t x;                 // the row's state in this lane's replica
+    int32_t c[HC];
+    float w[HC];
+};
+
+// Heavy-row partials with the bitmap resident in LDS (sims whose step runs
+// the resident variant): one RESIDENT_TPB-thread workgroup per CU copies the
+// step's input bitmap into LDS as the step kernel does.  Wave v takes
+// segments v, v + nwaves, ...; their descriptors come 64 at a time from one
+// vector load (lane j: the group's j-th segment), and the state word, the
+// first HC column slots (and weights) of the next segment are issued before
+// the current one is gathered.  Per lane the edges are summed in the same
+// order, and folded by the same shuffle tree, as in heavy_body.
+template <bool WEIGHTED, bool SHED>
+__device__ __forceinline__ void heavy_resident_body(const HeavyArgs& h, uint32_t block, uint32_t nblocks)
+{
+    constexpr bool FLOATP = WEIGHTED || SHED;
+    constexpr uint32_t NW = RESIDENT_TPB / 64;
+    __shared__ __attribute__((aligned(16))) uint32_t s_bits[RESIDENT_BITS / 32];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int32_t lgR = h.lgR;
+    const uint32_t R = 1u << lgR;
+    const uint32_t per = 64u >> lgR;
+    const uint32_t eoff = lane >> lgR;
+    const uint32_t rep = lane & (R - 1);
+    const unsigned long long k = h.ctl->step + h.step_off;
+    const uint32_t* __restrict__ bits = (const uint32_t*)((k & 1) ? h.iota1 : h.iota0);
+    const rsrc_t shedr = make_rsrc((k & 1) ? h.shed1 : h.shed0, SHED ? h.units * 4u : 0u);
+    const uint32_t nw = nblocks * NW;
+    const uint32_t s0 = block * NW + wave;
+    const uint32_t cnt = h.nseg > s0 ? (h.nseg - s0 + nw - 1) / nw : 0u;
+    const rsrc_t segr = make_rsrc(h.segs, h.nseg * (uint32_t)sizeof(Segment));
+    const rsrc_t str = make_rsrc(h.state, h.units * (h.storage ? 1u : 4u));
+
+    // this wave's first descriptor group is loaded with the bitmap fill
+    uint32_t dr = 0, db = 0, de = 0;
+    auto load_group = [&](uint32_t i0) {
+        const uint32_t off = i0 + lane < cnt ? (s0 + (i0 + lane) * nw) * (uint32_t)sizeof(Segment) : OOB;
+        const auto d = __builtin_amdgcn_raw_buffer_load_b128(segr, (int)off, 0, 0);
+        dr = d[0];
+        db = d[1];
+        de = d[2];
+    };
+    load_group(0);
+    {
+        const uint32_t n4 = (((h.units + 31) >> 5) + 3) >> 2;
+        const uint4* src = (const uint4*)bits;
+        for (uint32_t b0 = wave * 64; b0 < n4; b0 += RESIDENT_TPB) {
+            if (b0 + lane < n4)
+                __builtin_amdgcn_global_load_lds((const void*)(src + b0 + lane),
+                                                 (__attribute__((address_space(3))) void*)((uint4*)s_bits + b0), 16, 0, 0);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+    }
+    __syncthreads();
+
+    // the loads of the group's segment j (none past the group's end)
+    auto issue = [&](uint32_t i0, uint32_t j, HeavySeg& S) {
+        const bool has = j < 64u && i0 + j < cnt;
+        const uint32_t jj = has ? j : 0u;
+        const uint32_t row = __builtin_amdgcn_readlane(dr, jj);
+        const uint32_t eb = __builtin_amdgcn_readlane(db, jj);
+        const uint32_t ee = __builtin_amdgcn_readlane(de, jj);
+        S.seg = s0 + (i0 + jj) * nw;
+        S.len = has ? ee - eb : 0u;
+        const uint32_t ru = (row << lgR) + rep;
+        S.x = h.storage ? __builtin_amdgcn_raw_buffer_load_b8(str, has ? (int)ru : (int)OOB, 0, 0)
+                        : ld32(str, has ? ru << 2 : OOB);
+        const rsrc_t cr = make_rsrc(h.col_ind + eb, S.len * 4u);
+        const rsrc_t wr = make_rsrc(WEIGHTED ? (const void*)(h.weights + eb) : (const void*)h.weights,
+                                    WEIGHTED ? S.len * 4u : 0u);
+#pragma unroll
+        for (int i = 0; i < HC; ++i) {
+            const uint32_t off = ((uint32_t)i * per + eoff) << 2;
+            S.c[i] = (int32_t)ld32(cr, off);
+            S.w[i] = WEIGHTED ? __uint_as_float(ld32(wr, off)) : 0.0f;
+        }
+    };
+    auto process = [&](const HeavySeg& S) {
+        // only rows that are susceptible (in some replica) read their pressure
+        if (S.len == 0u || __ballot(S.x == (uint32_t)ST_S) == 0ull) return;
+        uint32_t ci = 0;
+        float cw = 0.0f;
+        auto add = [&](int32_t c, float w) {
+            const uint32_t src = ((uint32_t)c << lgR) + rep;
+            const uint32_t b = lds_bit(s_bits, src);
+            const float v = SHED ? __uint_as_float(ld32(shedr, b ? src << 2 : OOB)) : (float)b;
+            if (WEIGHTED) cw = __builtin_fmaf(w, v, cw);
+            else if (SHED) cw += v;
+            else ci += b;
+        };
+#pragma unroll
+        for (int i = 0; i < HC; ++i)
+            if ((uint32_t)i * per + eoff < S.len) add(S.c[i], S.w[i]);
+        if (S.len > (uint32_t)HC * per) {
+            // the rest of a long segment, unprefetched
+            const uint32_t eb = (uint32_t)h.segs[S.seg].e_begin;
+            for (uint32_t e = HC * per + eoff; e < S.len; e += per)
+                add(h.col_ind[eb + e], WEIGHTED ? h.weights[eb + e] : 0.0f);
+        }
+        for (uint32_t off = 32; off >= R && off > 0; off >>= 1) {
+            if (FLOATP) cw += __shfl_down(cw, off, 64);
+            else ci += __shfl_down(ci, off, 64);
+        }
+        if (lane < R) {
+            if (FLOATP) ((float*)h.seg_part)[(size_t)S.seg * R + lane] = cw;
+            else ((uint32_t*)h.seg_part)[(size_t)S.seg * R + lane] = ci;
+        }
+    };
+
+    for (uint32_t i0 = 0; i0 < cnt; i0 += 64) {
+        if (i0 > 0) load_group(i0);
+        const uint32_t m = min(64u, cnt - i0);
+        HeavySeg A, B;
+        issue(i0, 0, A);
+        for (uint32_t j = 0; j < m; j += 2) {
+            issue(i0, j + 1, B);
+            process(A);
+            if (j + 1 >= m) break;
+            issue(i0, j + 2, A);
+            process(B);
+        }
+    }
+}
+
+template <bool WEIGHTED, bool SHED>
+__global__ __launch_bounds__(RESIDENT_TPB) void heavy_resident_kernel(HeavyArgs h)
+{
+    heavy_resident_body<WEIGHTED, SHED>(h, blockIdx.x, gridDim.x);
+}
+
 // Batched heavy-row partials: member m owns workgroups [first[m], first[m + 1]).
 template <bool WEIGHTED>
 __global__ __launch_bounds__(WG) void heavy_batch_kernel(const HeavyArgs* __restrict__ table,
