@@ -203,23 +203,33 @@ __device__ __forceinline__ void issue_table(const StepArgs& a, Pass<age_t>& P, u
     __builtin_amdgcn_sched_barrier(0);
 }
 
+// Lookahead of the pass issues: the active-list entry (compaction) and the
+// chunk metadata (mixed layouts) the next issue uses, loaded by this one.
+struct Ahead {
+    uint32_t chunk[CU];
+    uint32_t mx[CU], my[CU];
+};
+
 // Issues every load of a pass that does not depend on the state: chunk
-// metadata (one scalar load), state, age and light degree, and the edge
+// metadata, state, age and light degree, and the edge
 // slots of uniform chunks (whose rows are all present).  Each array is read
 // through a descriptor covering only this chunk's valid entries, so no lane
 // branches and a pass past the last chunk reads nothing.  `first` is a
 // position in the walk of `walk` chunks: the chunk itself, or with
 // compaction (EXTRA kernels with an active list) the list entry at that
 // position, which the issue of the previous pass (or the walk's start)
-// loaded into ahead[u]; this issue loads the entry one stride further.  That
+// loaded into ah.chunk[u]; this issue loads the entry one stride further.  That
 // load is a vector load (every lane reads the same word) issued before the
 // pass's other loads: a scalar load would be waited for by the pass's first
 // LDS wait (scalar and LDS results share one counter), a vector load only by
-// the next issue, behind loads that are older anyway.
+// the next issue, behind loads that are older anyway.  The metadata of a
+// mixed layout's chunk comes the same way (without compaction): loaded in
+// this pass's issue it would hold the issue up, the column loads depending
+// on it, until every older load (the pass being processed) had arrived.
 template <int STORAGE, bool UNIFORM, bool EXTRA, class age_t>
 __device__ __forceinline__ void issue_pass(const StepArgs& a, uint32_t first, uint32_t nwaves, uint32_t stride,
                                            uint32_t nchunks, uint32_t walk, uint32_t total, uint32_t lane,
-                                           Pass<age_t>& P, uint32_t* ahead)
+                                           Pass<age_t>& P, Ahead& ah)
 {
     using state_t = typename Store<STORAGE>::state_t;
     const uint32_t rows = 64u >> a.lgR;
@@ -230,17 +240,27 @@ __device__ __forceinline__ void issue_pass(const StepArgs& a, uint32_t first, ui
         P.live[u] = pos < walk;
         uint32_t c = P.live[u] ? pos : nchunks - 1; // (a pass past the walk reads nothing)
         if (EXTRA && a.act) {
-            if (P.live[u]) c = __builtin_amdgcn_readfirstlane(ahead[u]);
-            ahead[u] = ld32(make_rsrc(a.act, (2u + walk) * 4u), (2u + pos + stride) << 2);
+            if (P.live[u]) c = __builtin_amdgcn_readfirstlane(ah.chunk[u]);
+            ah.chunk[u] = ld32(make_rsrc(a.act, (2u + walk) * 4u), (2u + pos + stride) << 2);
         }
         P.chk[u] = c;
         if (UNIFORM) {
             P.base[u] = P.chk[u] * rows * (uint32_t)a.udeg;
             P.ud[u] = P.live[u] ? (uint32_t)a.udeg : 0u;
-        } else {
+        } else if (EXTRA && a.act) {
             const uint2 meta = a.chunk_meta[P.chk[u]];
             P.base[u] = meta.x;
             P.ud[u] = P.live[u] ? meta.y : 0u;
+        } else {
+            // (a pass past the walk takes its predecessor's clamped entry and
+            // reads nothing)
+            P.base[u] = __builtin_amdgcn_readfirstlane(ah.mx[u]);
+            P.ud[u] = P.live[u] ? __builtin_amdgcn_readfirstlane(ah.my[u]) : 0u;
+            const uint32_t nxt = min(pos + stride, nchunks - 1u);
+            const auto m = __builtin_amdgcn_raw_buffer_load_b64(make_rsrc(a.chunk_meta, nchunks * 8u), (int)(nxt << 3),
+                                                                0, 0);
+            ah.mx[u] = m[0];
+            ah.my[u] = m[1];
         }
         const uint32_t u0 = P.chk[u] << 6;
         P.nvalid[u] = P.live[u] ? min(64u, total - u0) : 0u;
@@ -693,11 +713,18 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
     Pass<age_t> P;
     uint32_t first = wave_id;
     const uint32_t stride = nwaves * CU;
-    uint32_t ahead[CU];
+    Ahead ahead;
 #pragma unroll
     for (int u = 0; u < CU; ++u) {
         const uint32_t pos = first + (uint32_t)u * nwaves;
-        ahead[u] = (EXTRA && a.act && pos < walk) ? a.act[2 + pos] : 0u;
+        ahead.chunk[u] = (EXTRA && a.act && pos < walk) ? a.act[2 + pos] : 0u;
+        ahead.mx[u] = ahead.my[u] = 0u;
+        if (!UNIFORM) {
+            const auto m = __builtin_amdgcn_raw_buffer_load_b64(make_rsrc(a.chunk_meta, nchunks * 8u),
+                                                                (int)(min(pos, nchunks - 1u) << 3), 0, 0);
+            ahead.mx[u] = m[0];
+            ahead.my[u] = m[1];
+        }
     }
     issue_pass<STORAGE, UNIFORM, EXTRA>(a, first, nwaves, stride, nchunks, walk, total, lane, P, ahead);
     if (R > 1)
