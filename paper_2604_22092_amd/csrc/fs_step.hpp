@@ -941,8 +941,10 @@ __global__ __launch_bounds__(WG) void heavy_pressure_kernel(HeavyArgs h)
     heavy_body<WEIGHTED, SHED>(h, blockIdx.x, gridDim.x);
 }
 
-// Column slots of a heavy segment each lane loads ahead (HC * 64 / R edges).
+// Column slots of a heavy segment each lane loads ahead (HC * 64 / R edges),
+// and segments whose loads are issued together (HB).
 constexpr int HC = 4;
+constexpr int HB = 8;
 
 // The loads of one heavy segment, as issued.
 struct HeavySeg {
@@ -956,10 +958,11 @@ struct HeavySeg {
 // the resident variant): one RESIDENT_TPB-thread workgroup per CU copies the
 // step's input bitmap into LDS as the step kernel does.  Wave v takes
 // segments v, v + nwaves, ...; their descriptors come 64 at a time from one
-// vector load (lane j: the group's j-th segment), and the state word, the
-// first HC column slots (and weights) of the next segment are issued before
-// the current one is gathered.  Per lane the edges are summed in the same
-// order, and folded by the same shuffle tree, as in heavy_body.
+// vector load (lane j: the group's j-th segment), and the state words and
+// first HC column slots (and weights) of HB segments are issued together
+// before any of them is gathered, so a wave waits about one memory latency
+// per HB segments.  Per lane the edges are summed in the same order, and
+// folded by the same shuffle tree, as in heavy_body.
 template <bool WEIGHTED, bool SHED>
 __device__ __forceinline__ void heavy_resident_body(const HeavyArgs& h, uint32_t block, uint32_t nblocks)
 {
@@ -979,6 +982,9 @@ __device__ __forceinline__ void heavy_resident_body(const HeavyArgs& h, uint32_t
     const rsrc_t shedr = make_rsrc((k & 1) ? h.shed1 : h.shed0, SHED ? h.units * 4u : 0u);
     const uint32_t nw = nblocks * NW;
     const uint32_t s0 = block * NW + wave;
+    // lanes of replica 0: every R-th lane
+    unsigned long long rmask = 1ull;
+    for (uint32_t sh = R; sh < 64u; sh <<= 1) rmask |= rmask << sh;
     const uint32_t cnt = h.nseg > s0 ? (h.nseg - s0 + nw - 1) / nw : 0u;
     const rsrc_t segr = make_rsrc(h.segs, h.nseg * (uint32_t)sizeof(Segment));
     const rsrc_t str = make_rsrc(h.state, h.units * (h.storage ? 1u : 4u));
@@ -1030,6 +1036,10 @@ __device__ __forceinline__ void heavy_resident_body(const HeavyArgs& h, uint32_t
     auto process = [&](const HeavySeg& S) {
         // only rows that are susceptible (in some replica) read their pressure
         if (S.len == 0u || __ballot(S.x == (uint32_t)ST_S) == 0ull) return;
+        // integer counts: each edge pass's bits are counted per replica with
+        // one ballot (lanes r, r + R, ... hold replica r; lanes below R take
+        // part in every pass, their edge offset being 0), which gives the
+        // same totals as the shuffle tree without its LDS round trips
         uint32_t ci = 0;
         float cw = 0.0f;
         auto add = [&](int32_t c, float w) {
@@ -1038,7 +1048,7 @@ __device__ __forceinline__ void heavy_resident_body(const HeavyArgs& h, uint32_t
             const float v = SHED ? __uint_as_float(ld32(shedr, b ? src << 2 : OOB)) : (float)b;
             if (WEIGHTED) cw = __builtin_fmaf(w, v, cw);
             else if (SHED) cw += v;
-            else ci += b;
+            else ci += (uint32_t)__popcll(__ballot(b != 0u) & (rmask << rep));
         };
 #pragma unroll
         for (int i = 0; i < HC; ++i)
@@ -1049,10 +1059,8 @@ __device__ __forceinline__ void heavy_resident_body(const HeavyArgs& h, uint32_t
             for (uint32_t e = HC * per + eoff; e < S.len; e += per)
                 add(h.col_ind[eb + e], WEIGHTED ? h.weights[eb + e] : 0.0f);
         }
-        for (uint32_t off = 32; off >= R && off > 0; off >>= 1) {
-            if (FLOATP) cw += __shfl_down(cw, off, 64);
-            else ci += __shfl_down(ci, off, 64);
-        }
+        if (FLOATP)
+            for (uint32_t off = 32; off >= R && off > 0; off >>= 1) cw += __shfl_down(cw, off, 64);
         if (lane < R) {
             if (FLOATP) ((float*)h.seg_part)[(size_t)S.seg * R + lane] = cw;
             else ((uint32_t*)h.seg_part)[(size_t)S.seg * R + lane] = ci;
@@ -1062,14 +1070,12 @@ __device__ __forceinline__ void heavy_resident_body(const HeavyArgs& h, uint32_t
     for (uint32_t i0 = 0; i0 < cnt; i0 += 64) {
         if (i0 > 0) load_group(i0);
         const uint32_t m = min(64u, cnt - i0);
-        HeavySeg A, B;
-        issue(i0, 0, A);
-        for (uint32_t j = 0; j < m; j += 2) {
-            issue(i0, j + 1, B);
-            process(A);
-            if (j + 1 >= m) break;
-            issue(i0, j + 2, A);
-            process(B);
+        for (uint32_t j0 = 0; j0 < m; j0 += HB) {
+            HeavySeg S[HB];
+#pragma unroll
+            for (int b = 0; b < HB; ++b) issue(i0, j0 + b < m ? j0 + b : 64u, S[b]);
+#pragma unroll
+            for (int b = 0; b < HB; ++b) process(S[b]);
         }
     }
 }
