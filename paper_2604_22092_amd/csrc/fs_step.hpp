@@ -908,12 +908,17 @@ __device__ __forceinline__ void heavy_body(const HeavyArgs& h, uint32_t block, u
     const uint32_t* __restrict__ bits = (const uint32_t*)((k & 1) ? h.iota1 : h.iota0);
     const float* __restrict__ shv = (k & 1) ? h.shed1 : h.shed0;
     const uint32_t nwaves = nblocks * (WG / 64);
+    unsigned long long rmask = 1ull; // lanes of replica 0: every R-th lane
+    for (uint32_t sh = R; sh < 64u; sh <<= 1) rmask |= rmask << sh;
     for (uint32_t s = block * (WG / 64) + (threadIdx.x >> 6); s < h.nseg; s += nwaves) {
         const Segment sg = h.segs[s];
         // only rows that are susceptible (in some replica) read their pressure
         const uint32_t ru = ((uint32_t)sg.row << h.lgR) + rep;
         const int x = h.storage ? (int)((const uint8_t*)h.state)[ru] : (int)((const int32_t*)h.state)[ru];
         if (__ballot(x == ST_S) == 0ull) continue;
+        // integer counts by one ballot per edge pass and replica (lanes r,
+        // r + R, ... hold replica r; lanes below R, at edge offset 0, take
+        // part in every pass), float sums by a fixed shuffle tree
         uint32_t ci = 0;
         float cw = 0.0f;
         for (int32_t e = sg.e_begin + (int32_t)eoff; e < sg.e_end; e += (int32_t)per) {
@@ -922,12 +927,10 @@ __device__ __forceinline__ void heavy_body(const HeavyArgs& h, uint32_t block, u
             const float v = SHED ? (b ? shv[src] : 0.0f) : (float)b;
             if (WEIGHTED) cw = __builtin_fmaf(h.weights[e], v, cw);
             else if (SHED) cw += v;
-            else ci += b;
+            else ci += (uint32_t)__popcll(__ballot(b != 0u) & (rmask << rep));
         }
-        for (uint32_t off = 32; off >= R && off > 0; off >>= 1) {
-            if (FLOATP) cw += __shfl_down(cw, off, 64);
-            else ci += __shfl_down(ci, off, 64);
-        }
+        if (FLOATP)
+            for (uint32_t off = 32; off >= R && off > 0; off >>= 1) cw += __shfl_down(cw, off, 64);
         if (lane < R) {
             if (FLOATP) ((float*)h.seg_part)[(size_t)s * R + lane] = cw;
             else ((uint32_t*)h.seg_part)[(size_t)s * R + lane] = ci;
