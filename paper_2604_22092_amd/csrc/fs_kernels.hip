@@ -305,12 +305,12 @@ __global__ __launch_bounds__(WG_REFRESH) void compact_refresh_kernel(const uint8
 
 // ---------------------------------------------------------------- launchers
 
-const void* step_kernel_fn(int storage, bool weighted, int mode, bool uniform, bool shed, bool extra)
+const void* step_kernel_fn(int storage, bool weighted, int mode, int udeg, bool shed, bool extra)
 {
-    if (shed) return extra ? step_kernel_fn_shed_extra(storage, weighted, mode, uniform)
-                           : step_kernel_fn_shed(storage, weighted, mode, uniform);
-    if (extra) return step_kernel_fn_extra(storage, weighted, mode, uniform);
-    return step_kernel_pick<false, false>(storage, weighted, mode, uniform);
+    if (shed) return extra ? step_kernel_fn_shed_extra(storage, weighted, mode, udeg)
+                           : step_kernel_fn_shed(storage, weighted, mode, udeg);
+    if (extra) return step_kernel_fn_extra(storage, weighted, mode, udeg);
+    return step_kernel_pick<false, false>(storage, weighted, mode, udeg);
 }
 
 static unsigned grid_for(size_t n, unsigned block) { return (unsigned)((n + block - 1) / block); }

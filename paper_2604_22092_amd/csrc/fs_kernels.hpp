@@ -12,15 +12,16 @@ namespace fsk {
 // (launched with one StepArgs argument); mode is fsi::MODE_*: the LDS
 // variants run RESIDENT_TPB threads, one workgroup per compute unit, the
 // streaming variant STREAM_TPB threads per workgroup.
-// uniform selects the instantiation for layouts with StepArgs::udeg >= 0;
+// udeg (StepArgs::udeg: a uniform layout's degree, or -1) selects the
+// instantiation: mixed, or uniform with a preload depth of 8, 10 or 12;
 // shed the one for age-dependent shedding (StepArgs::shed0/shed1/shed);
 // extra the one that records rates (StepArgs::rates) and walks the
 // active-chunk list of compaction (StepArgs::act, live).
-const void* step_kernel_fn(int storage, bool weighted, int mode, bool uniform, bool shed, bool extra);
+const void* step_kernel_fn(int storage, bool weighted, int mode, int udeg, bool shed, bool extra);
 // (the other (shed, extra) instantiations, each defined by a source of its own)
-const void* step_kernel_fn_extra(int storage, bool weighted, int mode, bool uniform);
-const void* step_kernel_fn_shed(int storage, bool weighted, int mode, bool uniform);
-const void* step_kernel_fn_shed_extra(int storage, bool weighted, int mode, bool uniform);
+const void* step_kernel_fn_extra(int storage, bool weighted, int mode, int udeg);
+const void* step_kernel_fn_shed(int storage, bool weighted, int mode, int udeg);
+const void* step_kernel_fn_shed_extra(int storage, bool weighted, int mode, int udeg);
 const void* heavy_kernel_fn_shed(bool weighted, bool resident);
 
 // Exact counts of one replica: per-workgroup partials (at most max_grid rows

@@ -7,9 +7,9 @@
 
 namespace fsk {
 
-const void* step_kernel_fn_extra(int storage, bool weighted, int mode, bool uniform)
+const void* step_kernel_fn_extra(int storage, bool weighted, int mode, int udeg)
 {
-    return step_kernel_pick<false, true>(storage, weighted, mode, uniform);
+    return step_kernel_pick<false, true>(storage, weighted, mode, udeg);
 }
 
 } // namespace fsk

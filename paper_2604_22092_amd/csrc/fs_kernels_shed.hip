@@ -9,9 +9,9 @@
 
 namespace fsk {
 
-const void* step_kernel_fn_shed(int storage, bool weighted, int mode, bool uniform)
+const void* step_kernel_fn_shed(int storage, bool weighted, int mode, int udeg)
 {
-    return step_kernel_pick<true, false>(storage, weighted, mode, uniform);
+    return step_kernel_pick<true, false>(storage, weighted, mode, udeg);
 }
 
 const void* heavy_kernel_fn_shed(bool weighted, bool resident)

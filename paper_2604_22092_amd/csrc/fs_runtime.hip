@@ -516,7 +516,7 @@ fs_status apply_bins(fs_sim* s, int32_t heavy_deg, int32_t seg_edges)
     s->args.chunk_meta = L->d_chunk_meta;
     s->args.orig_id = g->d_orig;
     s->args.udeg = L->udeg;
-    s->kfn = fsk::step_kernel_fn(s->storage, g->d_weights != nullptr, s->mode, L->udeg >= 0, s->d_shed[0] != nullptr,
+    s->kfn = fsk::step_kernel_fn(s->storage, g->d_weights != nullptr, s->mode, L->udeg, s->d_shed[0] != nullptr,
                                  s->d_rates != nullptr || s->d_act != nullptr);
     s->args.col_t = L->d_col_t;
     s->args.w_t = L->d_w_t;
@@ -1070,7 +1070,7 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
         a.htab_len = fsi::HTAB_LEN;
         a.htab_inv = s->storage == 0 ? 1.0f / a.dt : 1.0f;
     }
-    s->kfn = fsk::step_kernel_fn(s->storage, g->d_weights != nullptr, s->mode, false, shedding,
+    s->kfn = fsk::step_kernel_fn(s->storage, g->d_weights != nullptr, s->mode, -1, shedding,
                                  s->d_rates != nullptr || s->d_act != nullptr);
     s->hfn = fsk::heavy_kernel_fn(g->d_weights != nullptr, shedding, s->mode == fsi::MODE_RESIDENT);
     if (!s->kfn || !s->hfn) {

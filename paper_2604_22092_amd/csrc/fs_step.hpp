@@ -226,11 +226,13 @@ struct Ahead {
 // mixed layout's chunk comes the same way (without compaction): loaded in
 // this pass's issue it would hold the issue up, the column loads depending
 // on it, until every older load (the pass being processed) had arrived.
-template <int STORAGE, bool UNIFORM, bool EXTRA, class age_t>
+template <int STORAGE, int UD, bool EXTRA, class age_t>
 __device__ __forceinline__ void issue_pass(const StepArgs& a, uint32_t first, uint32_t nwaves, uint32_t stride,
                                            uint32_t nchunks, uint32_t walk, uint32_t total, uint32_t lane,
                                            Pass<age_t>& P, Ahead& ah)
 {
+    constexpr bool UNIFORM = UD != 0;
+    constexpr int DEPTH = UNIFORM ? UD : UMAX;
     using state_t = typename Store<STORAGE>::state_t;
     const uint32_t rows = 64u >> a.lgR;
     const uint32_t q = lane >> a.lgR;
@@ -279,7 +281,7 @@ __device__ __forceinline__ void issue_pass(const StepArgs& a, uint32_t first, ui
         const bool pre = P.ud[u] != MIXED_CHUNK;
         const rsrc_t cr = make_rsrc(a.col_t + P.base[u], pre ? P.ud[u] * rows * 4u : 0u);
 #pragma unroll
-        for (int j = 0; j < UMAX; ++j) P.c[u][j] = (int32_t)ld32(cr, ((uint32_t)j * rows + q) << 2);
+        for (int j = 0; j < DEPTH; ++j) P.c[u][j] = (int32_t)ld32(cr, ((uint32_t)j * rows + q) << 2);
     }
 }
 
@@ -292,10 +294,12 @@ struct ShedPre {
     float v[CU][UMAX];
 };
 
-template <bool UNIFORM, class age_t>
+template <int UD, class age_t>
 __device__ __forceinline__ void shed_pre(const StepArgs& a, const Pass<age_t>& P, uint32_t lane,
                                          const uint32_t* __restrict__ lds, rsrc_t shedr, ShedPre& S)
 {
+    constexpr bool UNIFORM = UD != 0;
+    constexpr int DEPTH = UNIFORM ? UD : UMAX;
     const int32_t lgR = a.lgR;
     const uint32_t rep = lane & ((1u << lgR) - 1u);
 #pragma unroll
@@ -306,7 +310,7 @@ __device__ __forceinline__ void shed_pre(const StepArgs& a, const Pass<age_t>& P
         const bool want = x == ST_S && (UNIFORM || dg != HEAVY_ROW);
         const bool pre = UNIFORM || P.ud[u] != MIXED_CHUNK;
 #pragma unroll
-        for (int j = 0; j < UMAX; ++j) {
+        for (int j = 0; j < DEPTH; ++j) {
             const bool use = pre && (uint32_t)j < P.ud[u] && want;
             const uint32_t src = ((uint32_t)P.c[u][j] << lgR) + rep;
             const uint32_t b = use ? lds_bit(lds, src) : 0u;
@@ -322,11 +326,13 @@ __device__ __forceinline__ void shed_pre(const StepArgs& a, const Pass<age_t>& P
 // prefix count), JB slots at a time.  With age-dependent shedding (SHED) a
 // source whose bit is set contributes its s(tau) from `shedr`; the value load
 // of every other slot is out of range and reads nothing.
-template <int MODE, bool WEIGHTED, bool UNIFORM, bool SHED, class age_t>
+template <int MODE, bool WEIGHTED, int UD, bool SHED, class age_t>
 __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_t>& P, int u, bool want,
                                               uint32_t dg, const uint32_t* __restrict__ lds, rsrc_t gbits,
                                               rsrc_t shedr, const ShedPre& S, uint32_t lane)
 {
+    constexpr bool UNIFORM = UD != 0;
+    constexpr int DEPTH = UNIFORM ? UD : UMAX;
     // shedding values of preloaded slots come from shed_pre (resident variant)
     constexpr bool SPLIT = SHED && MODE == MODE_RESIDENT;
     const int32_t lgR = a.lgR;
@@ -343,7 +349,7 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
         const rsrc_t wr = make_rsrc(WEIGHTED ? (const void*)(a.w_t + P.base[u]) : (const void*)a.w_t,
                                     WEIGHTED ? P.ud[u] * rows * 4u : 0u);
 #pragma unroll
-        for (int j = 0; j < UMAX; ++j) {
+        for (int j = 0; j < DEPTH; ++j) {
             const bool use = (uint32_t)j < P.ud[u] && want;
             uint32_t b = 0;
             float v;
@@ -498,7 +504,7 @@ __device__ __forceinline__ void compact_apply(uint32_t* xch, uint32_t lane, cons
 // hazards), draws, stores, next-infectivity words (and, with SHED, the
 // s(tau') values of the units infectious after the step), counts, and the
 // chunk's live flag for compaction.
-template <int STORAGE, bool WEIGHTED, int MODE, bool UNIFORM, bool SHED, bool EXTRA, class age_t>
+template <int STORAGE, bool WEIGHTED, int MODE, int UD, bool SHED, bool EXTRA, class age_t>
 __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t>& P, uint32_t lane,
                                              const uint32_t* __restrict__ s_bits, rsrc_t gbits, rsrc_t shedr,
                                              float* __restrict__ shed_out, const ShedPre& sv,
@@ -507,6 +513,7 @@ __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t
                                              uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, float dt,
                                              float& lmax)
 {
+    constexpr bool UNIFORM = UD != 0;
     using state_t = typename Store<STORAGE>::state_t;
     const uint32_t R = 1u << a.lgR;
 
@@ -532,7 +539,7 @@ __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t
         const bool heavy = !UNIFORM && dg[u] == HEAVY_ROW;
         const bool want = x[u] == ST_S && !heavy;
         const float p =
-            pressure_row<MODE, WEIGHTED, UNIFORM, SHED>(a, P, u, want, dg[u], s_bits, gbits, shedr, sv, lane);
+            pressure_row<MODE, WEIGHTED, UD, SHED>(a, P, u, want, dg[u], s_bits, gbits, shedr, sv, lane);
         if (want) lam[u] = a.beta * p;
         if (!UNIFORM && heavy && x[u] == ST_S)
             lam[u] = a.beta * pressure_heavy<WEIGHTED || SHED>(a, unit[u] >> a.lgR, unit[u] & (R - 1));
@@ -667,9 +674,10 @@ __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t
 //    infection is sparse most neighbours fall in empty groups);
 //  MODE_STREAM: gathers read the bitmap through the caches.
 // The LDS variants run one workgroup of RESIDENT_TPB threads per compute unit.
-template <int STORAGE, bool WEIGHTED, int MODE, bool UNIFORM, bool SHED, bool EXTRA, int TPB>
+template <int STORAGE, bool WEIGHTED, int MODE, int UD, bool SHED, bool EXTRA, int TPB>
 __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uint32_t nblocks)
 {
+    constexpr bool UNIFORM = UD != 0;
     constexpr bool USE_LDS = MODE != MODE_STREAM;
     using age_t = typename Store<STORAGE>::age_t;
     constexpr int NW = TPB / 64;
@@ -726,7 +734,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
             ahead.my[u] = m[1];
         }
     }
-    issue_pass<STORAGE, UNIFORM, EXTRA>(a, first, nwaves, stride, nchunks, walk, total, lane, P, ahead);
+    issue_pass<STORAGE, UD, EXTRA>(a, first, nwaves, stride, nchunks, walk, total, lane, P, ahead);
     if (R > 1)
         for (uint32_t i = tid; i < 4 * R; i += TPB) s_cnt[i] = 0;
     if (USE_LDS) {
@@ -757,28 +765,28 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
     ShedPre sv;
     for (;;) {
         if (first >= walk) break;
-        if (SPLIT) shed_pre<UNIFORM>(a, P, lane, s_bits, shedr, sv);
+        if (SPLIT) shed_pre<UD>(a, P, lane, s_bits, shedr, sv);
         if (PREFETCH)
-            issue_pass<STORAGE, UNIFORM, EXTRA>(a, first + stride, nwaves, stride, nchunks, walk, total, lane, P1,
+            issue_pass<STORAGE, UD, EXTRA>(a, first + stride, nwaves, stride, nchunks, walk, total, lane, P1,
                                                 ahead);
-        process_pass<STORAGE, WEIGHTED, MODE, UNIFORM, SHED, EXTRA>(a, P, lane, s_bits, gbits, shedr, shed_out, sv,
+        process_pass<STORAGE, WEIGHTED, MODE, UD, SHED, EXTRA>(a, P, lane, s_bits, gbits, shedr, shed_out, sv,
                                                                     s_xch[wave], k, bits_out, s_cnt, c0, c1, c2,
                                                                     c3, dt, lmax);
         first += stride;
         if (first >= walk) break;
         if (!PREFETCH)
-            issue_pass<STORAGE, UNIFORM, EXTRA>(a, first, nwaves, stride, nchunks, walk, total, lane, P1, ahead);
+            issue_pass<STORAGE, UD, EXTRA>(a, first, nwaves, stride, nchunks, walk, total, lane, P1, ahead);
         issue_table<UNIFORM>(a, P1, lane);
-        if (SPLIT) shed_pre<UNIFORM>(a, P1, lane, s_bits, shedr, sv);
+        if (SPLIT) shed_pre<UD>(a, P1, lane, s_bits, shedr, sv);
         if (PREFETCH)
-            issue_pass<STORAGE, UNIFORM, EXTRA>(a, first + stride, nwaves, stride, nchunks, walk, total, lane, P,
+            issue_pass<STORAGE, UD, EXTRA>(a, first + stride, nwaves, stride, nchunks, walk, total, lane, P,
                                                 ahead);
-        process_pass<STORAGE, WEIGHTED, MODE, UNIFORM, SHED, EXTRA>(a, P1, lane, s_bits, gbits, shedr, shed_out, sv,
+        process_pass<STORAGE, WEIGHTED, MODE, UD, SHED, EXTRA>(a, P1, lane, s_bits, gbits, shedr, shed_out, sv,
                                                                     s_xch[wave], k, bits_out, s_cnt, c0, c1, c2,
                                                                     c3, dt, lmax);
         first += stride;
         if (!PREFETCH && first < walk)
-            issue_pass<STORAGE, UNIFORM, EXTRA>(a, first, nwaves, stride, nchunks, walk, total, lane, P, ahead);
+            issue_pass<STORAGE, UD, EXTRA>(a, first, nwaves, stride, nchunks, walk, total, lane, P, ahead);
         if (first < walk) issue_table<UNIFORM>(a, P, lane);
     }
 
@@ -824,15 +832,18 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
 // EXTRA: the instantiation that records rates when StepArgs::rates is set
 // and walks the active-chunk list when StepArgs::act is set; without it
 // neither check is compiled in.
-template <int STORAGE, bool WEIGHTED, int MODE, bool UNIFORM, bool SHED, bool EXTRA, int TPB>
+// UD: 0 for mixed layouts, else the preload depth of a uniform layout (the
+// smallest of 8, 10, 12 that holds its degree: slots past the degree would
+// cost an issued load and a gather each)
+template <int STORAGE, bool WEIGHTED, int MODE, int UD, bool SHED, bool EXTRA, int TPB>
 __global__ __launch_bounds__(TPB) void step_kernel(StepArgs a)
 {
-    step_body<STORAGE, WEIGHTED, MODE, UNIFORM, SHED, EXTRA, TPB>(a, blockIdx.x, gridDim.x);
+    step_body<STORAGE, WEIGHTED, MODE, UD, SHED, EXTRA, TPB>(a, blockIdx.x, gridDim.x);
 }
 
 // Address of the step kernel of one configuration (each (SHED, EXTRA)
 // combination is instantiated by a kernel source of its own).
-template <bool SHED, bool EXTRA, int S, bool W, bool U>
+template <bool SHED, bool EXTRA, int S, bool W, int U>
 const void* step_kernel_sel(int mode)
 {
     if (mode == MODE_RESIDENT) return (const void*)&step_kernel<S, W, MODE_RESIDENT, U, SHED, EXTRA, RESIDENT_TPB>;
@@ -840,21 +851,24 @@ const void* step_kernel_sel(int mode)
     return (const void*)&step_kernel<S, W, MODE_STREAM, U, SHED, EXTRA, STREAM_TPB>;
 }
 
-template <bool SHED, bool EXTRA>
-const void* step_kernel_pick(int storage, bool weighted, int mode, bool uniform)
+template <bool SHED, bool EXTRA, int S, bool W>
+const void* step_kernel_depth(int mode, int udeg)
 {
-    if (storage == 0 && !weighted)
-        return uniform ? step_kernel_sel<SHED, EXTRA, 0, false, true>(mode)
-                       : step_kernel_sel<SHED, EXTRA, 0, false, false>(mode);
-    if (storage == 0 && weighted)
-        return uniform ? step_kernel_sel<SHED, EXTRA, 0, true, true>(mode)
-                       : step_kernel_sel<SHED, EXTRA, 0, true, false>(mode);
-    if (storage == 1 && !weighted)
-        return uniform ? step_kernel_sel<SHED, EXTRA, 1, false, true>(mode)
-                       : step_kernel_sel<SHED, EXTRA, 1, false, false>(mode);
-    if (storage == 1 && weighted)
-        return uniform ? step_kernel_sel<SHED, EXTRA, 1, true, true>(mode)
-                       : step_kernel_sel<SHED, EXTRA, 1, true, false>(mode);
+    static_assert(UMAX == 12, "uniform preload depths 8, 10, 12");
+    if (udeg < 0) return step_kernel_sel<SHED, EXTRA, S, W, 0>(mode);
+    if (udeg <= 8) return step_kernel_sel<SHED, EXTRA, S, W, 8>(mode);
+    if (udeg <= 10) return step_kernel_sel<SHED, EXTRA, S, W, 10>(mode);
+    return step_kernel_sel<SHED, EXTRA, S, W, 12>(mode);
+}
+
+// udeg: the layout's uniform degree, or -1 for a mixed layout
+template <bool SHED, bool EXTRA>
+const void* step_kernel_pick(int storage, bool weighted, int mode, int udeg)
+{
+    if (storage == 0 && !weighted) return step_kernel_depth<SHED, EXTRA, 0, false>(mode, udeg);
+    if (storage == 0 && weighted) return step_kernel_depth<SHED, EXTRA, 0, true>(mode, udeg);
+    if (storage == 1 && !weighted) return step_kernel_depth<SHED, EXTRA, 1, false>(mode, udeg);
+    if (storage == 1 && weighted) return step_kernel_depth<SHED, EXTRA, 1, true>(mode, udeg);
     return nullptr;
 }
 
