@@ -188,17 +188,43 @@ fs_status rebuild_tables(fs_batch* b)
     return FS_OK;
 }
 
+// The member rules of a batch (include/fs.h): every member runs the
+// streaming step of the batch's storage with fixed steps, constant shedding
+// and no compaction, and the members agree on weights (the batch kernel is
+// instantiated for one of the two).
+fs_status member_check(const fs_batch* b, const fs_sim* s)
+{
+    if (s->batch) return fail(FS_ERR_BUSY, "sim already belongs to a batch");
+    if (s->device != b->device) return fail(FS_ERR_INVALID_ARG, "sim and batch are on different devices");
+    if (s->mode != fsi::MODE_STREAM)
+        return fail(FS_ERR_INVALID_ARG, "batch members run the streaming step: create the sim with variant = 1");
+    if (s->storage != b->storage) return fail(FS_ERR_INVALID_ARG, "sim storage differs from the batch's");
+    if (s->p.adaptive) return fail(FS_ERR_INVALID_ARG, "adaptive-step sims cannot join a batch");
+    if (s->p.shedding != FS_SHED_CONSTANT)
+        return fail(FS_ERR_INVALID_ARG, "sims with age-dependent shedding cannot join a batch");
+    if (s->p.compaction) return fail(FS_ERR_INVALID_ARG, "sims with compaction cannot join a batch");
+    const int w = s->g->d_weights != nullptr;
+    if (!b->members.empty() && w != b->weighted)
+        return fail(FS_ERR_INVALID_ARG, "batch members must agree on weights");
+    return FS_OK;
+}
+
 // Membership changes without waiting: the caller guarantees that queued
 // batch work never touches a sim after it leaves (the next launch uses
 // rebuilt tables) and that an added sim's own queued work is finished.
-void attach(fs_batch* b, fs_sim* s)
+// The member rules are checked here too, so no path can add a sim the
+// batch kernel would run with the wrong instantiation.
+fs_status attach(fs_batch* b, fs_sim* s)
 {
+    const fs_status st = member_check(b, s);
+    if (st != FS_OK) return st;
     b->weighted = s->g->d_weights != nullptr;
     s->saved_stream = s->stream;
     s->stream = b->stream;
     s->batch = b;
     b->members.push_back(s);
     b->dirty = true;
+    return FS_OK;
 }
 
 void detach(fs_batch* b, fs_sim* s)
@@ -302,21 +328,11 @@ fs_status fs_batch_add(fs_batch* b, fs_sim* s)
 {
     FS_GUARD_BEGIN
     if (!b || !s) return fail(FS_ERR_INVALID_ARG, "NULL argument");
-    if (s->batch) return fail(FS_ERR_BUSY, "sim already belongs to a batch");
-    if (s->device != b->device) return fail(FS_ERR_INVALID_ARG, "sim and batch are on different devices");
-    if (s->mode != fsi::MODE_STREAM)
-        return fail(FS_ERR_INVALID_ARG, "batch members run the streaming step: create the sim with variant = 1");
-    if (s->storage != b->storage) return fail(FS_ERR_INVALID_ARG, "sim storage differs from the batch's");
-    if (s->p.adaptive) return fail(FS_ERR_INVALID_ARG, "adaptive-step sims cannot join a batch");
-    if (s->p.shedding != FS_SHED_CONSTANT) return fail(FS_ERR_INVALID_ARG, "sims with age-dependent shedding cannot join a batch");
-    if (s->p.compaction) return fail(FS_ERR_INVALID_ARG, "sims with compaction cannot join a batch");
-    const int w = s->g->d_weights != nullptr;
-    if (!b->members.empty() && w != b->weighted)
-        return fail(FS_ERR_INVALID_ARG, "batch members must agree on weights");
+    const fs_status st = member_check(b, s);
+    if (st != FS_OK) return st;
     DeviceGuard dg(b->device);
     FS_HIP(hipStreamSynchronize(s->stream));
-    attach(b, s);
-    return FS_OK;
+    return attach(b, s);
     FS_GUARD_END
 }
 
@@ -422,7 +438,9 @@ struct fs_server {
     hipStream_t stream = nullptr;       // rounds: every admitted request's steps
     hipStream_t admit_stream = nullptr; // creation and seeding of new requests
     bool own_stream = false;
-    fs_batch* batch = nullptr;
+    // small requests share one batch per weightedness ([0]: unit weights,
+    // [1]: weighted graphs), since a batch launch runs one instantiation
+    fs_batch* batch[2] = {nullptr, nullptr};
     size_t budget = 0, in_use = 0;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -471,7 +489,7 @@ fs_status start_request(fs_server* sv, Request& q)
 void drop_sim(fs_server* sv, Request& q)
 {
     if (q.sim) {
-        if (q.sim->batch) detach(sv->batch, q.sim);
+        if (q.sim->batch) detach(q.sim->batch, q.sim);
         release_sim(q.sim);
         q.sim = nullptr;
     }
@@ -529,7 +547,16 @@ void worker_loop(fs_server* sv)
         //    the server stream, small ones into the batch
         for (auto& q : joining) {
             q->sim->stream = sv->stream;
-            if (!q->solo) attach(sv->batch, q->sim);
+            const fs_status jst = q->solo ? FS_OK : attach(sv->batch[q->g->d_weights ? 1 : 0], q->sim);
+            if (jst != FS_OK) {
+                // (not reached with sims the server created itself)
+                const std::string jerr = g_err;
+                drop_sim(sv, *q);
+                sv->in_use -= q->bytes;
+                end_request(*q, jst, jerr);
+                sv->cv_done.notify_all();
+                continue;
+            }
             sv->active.push_back(q);
         }
         joining.clear();
@@ -541,7 +568,8 @@ void worker_loop(fs_server* sv)
             for (auto& q : sv->active) r = std::min(r, q->n_steps - q->done_steps);
             std::vector<std::shared_ptr<Request>> act = sv->active;
             lk.unlock();
-            st = batch_step(sv->batch, r);
+            for (fs_batch* b : sv->batch)
+                if (st == FS_OK) st = batch_step(b, r);
             for (auto& q : act)
                 if (st == FS_OK && q->solo) st = fs_step(q->sim, r);
             for (auto& q : act) {
@@ -553,7 +581,7 @@ void worker_loop(fs_server* sv)
                 if (hipMemcpyAsync(q->pinned_hist, q->sim->d_hist, bytes, hipMemcpyDeviceToHost, sv->stream) !=
                     hipSuccess)
                     st = fail(FS_ERR_DEVICE, "history copy");
-                if (q->sim->batch) detach(sv->batch, q->sim); // the next round's tables leave it out
+                if (q->sim->batch) detach(q->sim->batch, q->sim); // the next round's tables leave it out
             }
             if (st == FS_OK && hipEventRecord(now.ev, sv->stream) != hipSuccess) st = fail(FS_ERR_DEVICE, "event record");
             if (st != FS_OK) err = g_err;
@@ -694,11 +722,16 @@ fs_status fs_server_create(const fs_server_params* p, fs_server** out)
         if (sv->own_stream) (void)hipStreamDestroy(sv->stream);
         return fail(FS_ERR_DEVICE, "admission stream");
     }
-    fs_status st = fs_batch_create(p->storage, sv->stream, &sv->batch);
+    fs_status st = FS_OK;
+    for (fs_batch*& b : sv->batch)
+        if (st == FS_OK) st = fs_batch_create(p->storage, sv->stream, &b);
     if (st != FS_OK) {
+        const std::string err = g_err;
+        for (fs_batch* b : sv->batch)
+            if (b) (void)fs_batch_destroy(b);
         (void)hipStreamDestroy(sv->admit_stream);
         if (sv->own_stream) (void)hipStreamDestroy(sv->stream);
-        return st;
+        return fail(st, err);
     }
     fs_server* raw = sv.release();
     raw->worker = std::thread(worker_loop, raw);
@@ -815,7 +848,7 @@ fs_status fs_server_destroy(fs_server* sv)
     const std::string err = sv->worker_error;
     {
         DeviceGuard dg(sv->device);
-        (void)fs_batch_destroy(sv->batch);
+        for (fs_batch* b : sv->batch) (void)fs_batch_destroy(b);
         (void)hipStreamSynchronize(sv->admit_stream);
         (void)hipStreamDestroy(sv->admit_stream);
         if (sv->own_stream) (void)hipStreamDestroy(sv->stream);

@@ -1,5 +1,7 @@
 """Batches of simulations and the scenario server: every member's and every
-request's results equal those of the same simulation run alone.
+request's results equal the FP64 oracle's (whole trajectories per replica,
+and one step from a fixed mid-epidemic state under the guard-band rule), and
+equal those of the same simulation run alone.
 
 The members differ in graph family and size (random regular, Erdos-Renyi,
 Barabasi-Albert with degree-binned hub rows), holding-time laws, beta, dt,
@@ -11,8 +13,10 @@ import time
 import numpy as np
 import pytest
 
+import oracle
 import paper_2604_22092_amd as fs
 import workloads as W
+from _parity import check_mismatch_budget, check_one_step
 
 pytestmark = pytest.mark.gpu
 
@@ -62,6 +66,26 @@ def assert_same(a, b, label):
             np.testing.assert_array_equal(u, v, err_msg=f"{label} replica {r} {what}")
 
 
+def oracle_trajectory(rp, ci, model, nseed, steps, replica, compact, weights=None):
+    """The oracle's (state, age, history) of one replica from the seeded start."""
+    n = len(rp) - 1
+    graph = (rp, ci) if weights is None else (rp, ci, weights)
+    age = np.zeros(n, np.uint16 if compact else np.float32)
+    return oracle.run(graph, model, W.initial_state(n, W.seed_nodes(n, nseed, 5)), age, steps,
+                      replica=replica, compact=compact)
+
+
+def assert_matches_oracle(got, rp, ci, model, nseed, steps, compact, label, weights=None):
+    """got: per replica (state, age, history) of a GPU run from the seeded
+    start.  A divergence would have to start at a guard-band draw (about 1e-3
+    expected over all these runs), so whole trajectories compare exactly."""
+    for r, (gst, gage, ghist) in enumerate(got):
+        ost, oage, ohist = oracle_trajectory(rp, ci, model, nseed, steps, r, compact, weights)
+        np.testing.assert_array_equal(ghist, ohist, err_msg=f"{label} replica {r} history")
+        np.testing.assert_array_equal(gst, ost, err_msg=f"{label} replica {r} state")
+        np.testing.assert_array_equal(gage, oage, err_msg=f"{label} replica {r} age")
+
+
 @pytest.mark.parametrize("compact", [False, True], ids=["fp32", "compact"])
 def test_batch_members_equal_alone(graphs, compact):
     storage = fs.FS_STORAGE_COMPACT if compact else fs.FS_STORAGE_FP32
@@ -84,8 +108,64 @@ def test_batch_members_equal_alone(graphs, compact):
             s.close()
     for i, (x, y) in enumerate(zip(got, ref)):
         assert_same(x, y, f"member {i}")
+    # every member, every replica: the oracle's trajectory
+    for i, (x, (rp, ci, _), (_, m, R, ns)) in enumerate(zip(got, graphs, SCEN)):
+        assert_matches_oracle(x, rp, ci, m, ns, steps, compact, f"member {i}")
     # the epidemics moved
     assert all(h[-1, 0] < len(rp) - 1 for ((_, _, h), *_), (rp, _, _) in zip(got, graphs))
+
+
+def mid_epidemic_state(n, rng, dt, compact):
+    """A state with every compartment present and ages of both kinds: the
+    ages steps reach (m steps of dt, summed in FP32) and arbitrary ones."""
+    st = rng.choice(4, size=n, p=[0.55, 0.15, 0.2, 0.1]).astype(np.int32)
+    m = rng.integers(0, 150, n)
+    if compact:
+        return st, m.astype(np.uint16)
+    table = np.zeros(151, np.float32)
+    for j in range(1, 151):
+        table[j] = np.float32(table[j - 1] + np.float32(dt))
+    age = table[m]
+    odd = rng.random(n) < 0.3
+    age[odd] = (rng.random(odd.sum()) * 20.0).astype(np.float32)
+    return st, age
+
+
+@pytest.mark.parametrize("compact", [False, True], ids=["fp32", "compact"])
+def test_batch_one_step_matches_oracle(graphs, compact):
+    # every member from its own mid-epidemic state in every replica, one step
+    # of the batch launch (member lookup by block range), against the oracle
+    # node by node: states up to guard-band draws, ages, FP32 rates within
+    # the hazard tolerance
+    storage = fs.FS_STORAGE_COMPACT if compact else fs.FS_STORAGE_FP32
+    rng = np.random.default_rng(7)
+    total, flips = 0, 0
+    with fs.Batch(storage) as b:
+        sims, states = [], []
+        for (rp, _, g), (_, m, R, _) in zip(graphs, SCEN):
+            s = new_sim(g, m, R, storage, record_rates=True)
+            per = [mid_epidemic_state(len(rp) - 1, rng, m["dt"], compact) for _ in range(R)]
+            for r, (st, age) in enumerate(per):
+                s.set_state(st, age, r, step_index=37 if r == 0 else -1)
+            b.add(s)
+            sims.append(s)
+            states.append(per)
+        b.step(1)
+        b.sync()
+        for i, (s, per, (rp, ci, _), (_, m, R, _)) in enumerate(zip(sims, states, graphs, SCEN)):
+            for r, (st, age) in enumerate(per):
+                gst, gage, gk = s.get_state(r)
+                assert gk == 38
+                iota = (st == 2).astype(np.float64)
+                ora = oracle.step((rp, ci), m, st, age, iota, 37, replica=r, compact=compact)
+                nm, _ = check_one_step({"state": gst, "age": gage, "rates": s.rates(r)}, ora, st,
+                                       f"member {i} replica {r}")
+                flips += nm
+                total += len(st)
+        for s in sims:
+            b.remove(s)
+            s.close()
+    check_mismatch_budget(flips, total, "batch one step")
 
 
 def test_batch_membership_changes_mid_run(graphs):
@@ -179,10 +259,13 @@ def test_server_results_equal_alone(graphs):
         assert st["queued"] == 0 and st["active"] == 0 and st["rounds"] > 0
     overlapped = 0
     for (j, m, R, ns, steps), (hist, info) in zip(reqs, results):
-        rp, _, g = graphs[j]
+        rp, ci, g = graphs[j]
         ref = alone(g, rp, m, R, ns, steps, fs.FS_STORAGE_FP32)
         for r in range(R):
             np.testing.assert_array_equal(hist[:, r, :], ref[r][2], err_msg=f"request scenario {j} replica {r}")
+            # and the oracle's per-step counts of the same replica
+            _, _, ohist = oracle_trajectory(rp, ci, m, ns, steps, r, False)
+            np.testing.assert_array_equal(hist[:, r, :], ohist, err_msg=f"request scenario {j} replica {r} (oracle)")
         assert info["status"] == 0 and info["t_submit"] <= info["t_admit"] <= info["t_done"]
         assert info["n_steps"] == steps and info["n_replicas"] == R
     # requests overlapped on the device: some admission happened before an
@@ -223,3 +306,41 @@ def test_server_budget_slots_and_errors(graphs):
         with pytest.raises(fs.FsError):
             sv.result(good[0])                        # already collected
     big.close()
+
+
+def test_server_mixes_weighted_and_unit_weight_requests(graphs):
+    # small requests on a weighted graph and on unit-weight graphs arrive
+    # together: each runs in the batch of its own kind and gets its solo
+    # results and the oracle's
+    rp, ci = W.random_regular(4000, 6, 12)
+    w = (0.5 + np.random.default_rng(3).random(len(ci))).astype(np.float32)
+    model = {"ei": W.LN_E, "ir": ("weibull", 2.0, 5.0), "beta": 0.12, "dt": 0.1, "seed": 99}
+    steps, R, ns = 60, 2, 12
+    with fs.Graph(rp, ci, w) as gw:
+        ref_w = alone(gw, rp, model, R, ns, steps, fs.FS_STORAGE_FP32, variant=fs.VARIANT_STREAM)
+        with fs.Server(max_active=8, steps_per_round=9) as sv:
+            ids = []
+            for i in range(6):
+                if i % 2 == 0:
+                    ids.append(("w", sv.submit(gw, model["ei"], model["ir"], model["beta"], model["dt"],
+                                               model["seed"], R, steps, W.seed_nodes(len(rp) - 1, ns, 5))))
+                else:
+                    rq, _, gq = graphs[0]
+                    _, mq, Rq, nsq = SCEN[0]
+                    ids.append(("u", sv.submit(gq, mq["ei"], mq["ir"], mq["beta"], mq["dt"], mq["seed"], Rq,
+                                               steps, W.seed_nodes(len(rq) - 1, nsq, 5))))
+            out = []
+            for kind, rid in ids:
+                assert sv.wait(rid, 120.0)
+                out.append((kind, sv.result(rid)[0]))
+    rq, cq, gq = graphs[0]
+    _, mq, Rq, nsq = SCEN[0]
+    ref_u = alone(gq, rq, mq, Rq, nsq, steps, fs.FS_STORAGE_FP32)
+    for kind, hist in out:
+        ref = ref_w if kind == "w" else ref_u
+        for r in range(hist.shape[1]):
+            np.testing.assert_array_equal(hist[:, r, :], ref[r][2], err_msg=f"{kind} replica {r}")
+    for r in range(R):
+        _, _, ohist = oracle_trajectory(rp, ci, model, ns, steps, r, False, weights=w)
+        np.testing.assert_array_equal(ref_w[r][2], ohist, err_msg=f"weighted replica {r} (oracle)")
+    assert ref_w[0][2][-1, 0] < len(rp) - 1  # the weighted epidemic moved
