@@ -707,6 +707,32 @@ fs_status launch_sequence(fs_sim* s, uint32_t r)
     return FS_OK;
 }
 
+fs_status check_seed(const fs_sim* s, int32_t replica, int64_t count, const int64_t* nodes, int32_t compartment)
+{
+    if (!s) return fail(FS_ERR_INVALID_ARG, "sim is NULL");
+    fs_status st = check_replica(s, replica, true);
+    if (st != FS_OK) return st;
+    if (compartment < 0 || compartment > 3) return fail(FS_ERR_INVALID_ARG, "compartment must be in [0, 3]");
+    if (count < 0) return fail(FS_ERR_INVALID_ARG, "count < 0");
+    if (count == 0) return FS_OK;
+    if (!nodes) return fail(FS_ERR_INVALID_ARG, "nodes is NULL");
+    for (int64_t j = 0; j < count; ++j)
+        if (nodes[j] < 0 || nodes[j] >= s->g->n) return fail(FS_ERR_INVALID_ARG, "seed node out of range");
+    return FS_OK;
+}
+
+fs_status seed_staged(fs_sim* s, int32_t replica, const int64_t* d_nodes, int64_t count, int32_t compartment)
+{
+    FS_HIP(fsk::launch_seed(s->storage, s->d_state, s->d_age, d_nodes, count, s->lgR, replica, compartment,
+                            s->stream));
+    FS_HIP(fsk::launch_rebuild_bits(s->storage, s->d_state, (uint32_t)(s->g->n * s->R),
+                                    (unsigned long long*)s->d_iota[s->step & 1], s->bit_words, s->stream));
+    FS_HIP(refresh_derived(s, s->step));
+    FS_HIP(refresh_summary(s));
+    FS_HIP(hipStreamSynchronize(s->stream));
+    return FS_OK;
+}
+
 } // namespace fsr
 
 using namespace fsr;
@@ -1108,15 +1134,8 @@ fs_status fs_sim_destroy(fs_sim* s)
 fs_status fs_sim_seed(fs_sim* s, int32_t replica, int64_t count, const int64_t* nodes, int32_t compartment)
 {
     FS_GUARD_BEGIN
-    if (!s) return fail(FS_ERR_INVALID_ARG, "sim is NULL");
-    fs_status st = check_replica(s, replica, true);
-    if (st != FS_OK) return st;
-    if (compartment < 0 || compartment > 3) return fail(FS_ERR_INVALID_ARG, "compartment must be in [0, 3]");
-    if (count < 0) return fail(FS_ERR_INVALID_ARG, "count < 0");
-    if (count == 0) return FS_OK;
-    if (!nodes) return fail(FS_ERR_INVALID_ARG, "nodes is NULL");
-    for (int64_t j = 0; j < count; ++j)
-        if (nodes[j] < 0 || nodes[j] >= s->g->n) return fail(FS_ERR_INVALID_ARG, "seed node out of range");
+    fs_status st = check_seed(s, replica, count, nodes, compartment);
+    if (st != FS_OK || count == 0) return st;
     DeviceGuard dg(s->device);
     // stream-ordered staging buffer: allocating and freeing it does not wait
     // for work queued on other streams
@@ -1129,14 +1148,7 @@ fs_status fs_sim_seed(fs_sim* s, int32_t replica, int64_t count, const int64_t* 
     StreamBuf tmp(s->stream);
     FS_HIP(hipMallocAsync(&tmp.p, sizeof(int64_t) * (size_t)count, s->stream));
     FS_HIP(hipMemcpyAsync(tmp.p, nodes, sizeof(int64_t) * (size_t)count, hipMemcpyHostToDevice, s->stream));
-    FS_HIP(fsk::launch_seed(s->storage, s->d_state, s->d_age, (const int64_t*)tmp.p, count, s->lgR, replica,
-                            compartment, s->stream));
-    FS_HIP(fsk::launch_rebuild_bits(s->storage, s->d_state, (uint32_t)(s->g->n * s->R),
-                                    (unsigned long long*)s->d_iota[s->step & 1], s->bit_words, s->stream));
-    FS_HIP(refresh_derived(s, s->step));
-    FS_HIP(refresh_summary(s));
-    FS_HIP(hipStreamSynchronize(s->stream));
-    return FS_OK;
+    return seed_staged(s, replica, (const int64_t*)tmp.p, count, compartment);
     FS_GUARD_END
 }
 

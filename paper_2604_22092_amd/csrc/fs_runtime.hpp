@@ -189,5 +189,10 @@ fsi::HeavyArgs heavy_args(const fs_sim* s);
 // Device bytes a sim of this graph and these parameters holds (an estimate
 // used for admission by memory budget).
 size_t sim_footprint(fs_graph* g, const fs_sim_params* p);
+// Seeding (fs_sim_seed and its variants): the argument rules, and the device
+// part once the internal node ids of `count` seeds sit in device memory at
+// d_nodes (synchronises the sim's stream, so d_nodes may be reused after).
+fs_status check_seed(const fs_sim* s, int32_t replica, int64_t count, const int64_t* nodes, int32_t compartment);
+fs_status seed_staged(fs_sim* s, int32_t replica, const int64_t* d_nodes, int64_t count, int32_t compartment);
 
 } // namespace fsr

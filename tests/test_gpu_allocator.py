@@ -58,3 +58,84 @@ def test_torch_caching_allocator_backs_the_library():
     # and the library's own allocator serves again
     again = run(rp, ci, seeds)
     np.testing.assert_array_equal(again[1], ref[1])
+
+
+class CountingHook:
+    """A device allocator that serves `grant` blocks from PyTorch's caching
+    allocator and then returns NULL, and tracks the blocks it has out."""
+
+    def __init__(self, grant):
+        self.grant = grant
+        self.live = {}
+        self.calls = 0
+
+    def alloc(self, nbytes):
+        self.calls += 1
+        if self.grant == 0:
+            return 0
+        self.grant -= 1
+        p = torch.cuda.caching_allocator_alloc(nbytes, device=0)
+        self.live[p] = nbytes
+        return p
+
+    def free(self, p):
+        assert p in self.live, "freed a block this allocator did not give out"
+        del self.live[p]
+        torch.cuda.caching_allocator_delete(p)
+
+
+def test_failing_allocator_gives_out_of_memory_and_leaks_nothing():
+    # every allocation of fs_graph_create and of fs_sim_create fails in turn:
+    # FS_ERR_OUT_OF_MEMORY, *out stays NULL, and every block the allocator
+    # gave out before the failure has come back
+    import ctypes
+
+    L = fs.lib()
+    rp, ci = W.barabasi_albert(5000, 3, 4)
+    w = np.ones(len(ci), np.float32)
+    rp32, ci32 = rp.astype(np.int32), ci.astype(np.int32)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    for grant in range(0, 10):
+        hook = CountingHook(grant)
+        fs.set_allocator(hook.alloc, hook.free)
+        try:
+            h = ctypes.c_void_p()
+            st = L.fs_graph_create(len(rp) - 1, ptr(rp32), ptr(ci32), ptr(w), ctypes.byref(h))
+        finally:
+            fs.set_allocator()
+        if st == 0:
+            assert grant >= 4  # row_ptr, col_ind, node ids, weights
+            fs.fs_graph_destroy(h)
+            assert not hook.live
+            break
+        assert st == 3 and h.value is None, (grant, st)
+        assert hook.calls == grant + 1 and not hook.live, grant
+    else:
+        raise AssertionError("fs_graph_create never succeeded")
+
+    succeeded = False
+    for grant in range(0, 64):
+        with fs.Graph(rp, ci) as g:
+            hook = CountingHook(grant)
+            p = fs.make_params(W.LN_E, W.LN_I, 0.1, 0.1, replicas=4, steps_per_graph=10, record_rates=True,
+                               heavy_degree=16, segment_edges=64)
+            fs.set_allocator(hook.alloc, hook.free)
+            try:
+                h = ctypes.c_void_p()
+                st = L.fs_sim_create(g.handle, ctypes.byref(p), ctypes.byref(h))
+            finally:
+                fs.set_allocator()
+            if st == 0:
+                fs.fs_sim_destroy(h)
+                succeeded = True
+            else:
+                assert st == 3 and h.value is None, (grant, st)
+                assert hook.calls == grant + 1, grant
+        # the sim's blocks, and the graph's layout built through the hook,
+        # are all back once the graph is released
+        torch.cuda.synchronize()
+        assert not hook.live, (grant, len(hook.live))
+        if succeeded:
+            assert grant >= 5
+            break
+    assert succeeded

@@ -504,6 +504,57 @@ def test_full_size_regular10_n1e6_sampled_parity():
     assert (st != 0).sum() > 1000  # the epidemic is under way at the checkpoint
 
 
+def test_full_size_ba5_n1e6_sampled_parity():
+    # the Barabasi-Albert workload at its full size in the benchmark's launch
+    # configuration: explicit degree bins (32, 256) (heavy rows of up to ~4200
+    # edges in segments of 256, i.e. up to 17 segments each), the resident
+    # variant, captured b = 50 steps; one step from steps 250 and 350 (the
+    # epidemic under way) compared node by node on every heavy row and
+    # 100000 others
+    wl = W.WORKLOADS["ba5_n1e6"]
+    rp, ci = W.workload_graph(wl["graph"])
+    n = len(rp) - 1
+    model = wl["model"]
+    seeds = W.seed_nodes(n, wl["seeds"], wl["seed_rng"])
+    deg = np.diff(rp)
+    heavy = np.flatnonzero(deg > 32)
+    rest = np.setdiff1d(np.random.default_rng(1).choice(n, 100_000, replace=False), heavy)
+    nodes = np.concatenate([heavy, rest])
+    multi = 0
+    with fs.Graph(rp, ci) as g:
+        sim = fs.Sim.from_model(g, model, steps_per_graph=50, record_rates=True,
+                                heavy_degree=32, segment_edges=256)
+        hd, se, nseg = sim.bins()
+        assert (hd, se) == (32, 256) and nseg >= len(heavy)
+        sim.seed(seeds, replica=0)
+        done = 0
+        for k0 in (250, 350):
+            sim.step(k0 - done)
+            st, age, k = sim.get_state(0)
+            assert k == k0
+            hist = sim.history(k0 - 50, 50)
+            np.testing.assert_array_equal(hist[-1], np.bincount(st, minlength=4))
+            sim.step(1)
+            done = k0 + 1
+            gst, gage, _ = sim.get_state(0)
+            rates = sim.rates(0)
+            iota = (st == 2).astype(np.float64)
+            ora = oracle.step_nodes((rp, ci), model, st, age, iota, k, nodes)
+            label = f"BA N=1e6 sample, step {k}"
+            nm = guard_band_mismatches(gst[nodes], ora["state"], ora["u"], ora["q"], label)
+            check_mismatch_budget(nm, len(nodes), label)
+            same = gst[nodes] == ora["state"]
+            np.testing.assert_array_equal(gage[nodes][same], ora["age"][same], err_msg=label)
+            check_rates(rates[nodes], ora["lam"], label)
+            # susceptible hub rows with infectious neighbours were exercised
+            hub_s = heavy[(st[heavy] == 0) & (ora["lam"][:len(heavy)] > 0)]
+            assert len(hub_s) > 1000, label
+            multi += int((deg[hub_s] > 256).sum())
+        sim.close()
+    assert multi >= 5  # multi-segment rows among them
+    assert (st != 0).sum() > 50_000
+
+
 # ------------------------------------------------------ ensemble statistics
 
 def test_ensemble_peak_prevalence_and_attack_rate(small_graph):
