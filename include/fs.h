@@ -245,14 +245,16 @@ fs_status fs_step_index(fs_sim* s, int64_t* out);
 
 /*
  * Exact S, E, I, R counts of one replica after the latest queued step,
- * recounted from the stored states (synchronises).  out: 4 int64.
+ * recounted from the stored states (synchronises): the count_by_state() of
+ * Listing "python_api", [S, E, I, R].  out: 4 int64.
  */
 fs_status fs_counts(fs_sim* s, int32_t replica, int64_t out[4]);
 
 /*
- * Per-step counts (the S, E, I, R tallies each step kernel records) for steps
- * first_step .. first_step+n-1, where step k's row holds the counts after
- * step k ran.  Only the last history_len steps since creation or the last
+ * Per-step counts (the S, E, I, R tallies each step kernel records: the
+ * count_by_state() of Listing "python_api" after every step, from which peak
+ * prevalence and attack rate follow) for steps first_step ..
+ * first_step+n-1, where step k's row holds the counts after step k ran.  Only the last history_len steps since creation or the last
  * fs_set_state are kept; older or future rows give FS_ERR_INVALID_ARG.
  *   out: n x 4 int64, row-major.  Synchronises.
  */
@@ -265,7 +267,9 @@ fs_status fs_history(fs_sim* s, int32_t replica, int64_t first_step, int64_t n, 
 fs_status fs_step_sizes(fs_sim* s, int64_t first_step, int64_t n, double* out);
 
 /*
- * Copies one replica's state out (synchronises).
+ * Copies one replica's state out (synchronises): the snapshot of the
+ * persistent state X, tau and step_id that the capture algorithm takes
+ * (Algorithm "Fused Renewal Engine with CUDA Graph: Capture").
  *   state       n int32 compartments
  *   age_days    n float32 ages in days   (FS_STORAGE_FP32; NULL otherwise)
  *   age_steps   n uint16 ages in steps   (FS_STORAGE_COMPACT; NULL otherwise)
@@ -275,8 +279,9 @@ fs_status fs_get_state(fs_sim* s, int32_t replica, int32_t* state, float* age_da
                        uint16_t* age_steps, int64_t* step_index);
 
 /*
- * Overwrites one replica's state and age and rebuilds its infectivity
- * (checkpoint restore; test set-up).  step_index >= 0 also sets the sim-wide
+ * Overwrites one replica's state and age and rebuilds its infectivity: the
+ * restore from a snapshot of the capture algorithm (Algorithm "Fused Renewal
+ * Engine with CUDA Graph: Capture"); checkpoint restore and test set-up.  step_index >= 0 also sets the sim-wide
  * step index (all replicas share it) and resets the count history; -1 keeps
  * it.  Argument formats as in fs_get_state; states must lie in [0, 3].
  */
@@ -442,8 +447,9 @@ fs_status fs_batch_sync(fs_batch* b);
  * graph, laws and rates, replicas, seeds, a number of steps) from any
  * thread; a worker thread admits queued requests in arrival order while the
  * device-memory budget and the slot limit allow, advances every admitted
- * request with one batch (see above) a few steps at a time, and retires the
- * requests that reach their step count, so a request that arrives while
+ * request with batches (see above; requests on weighted graphs and on
+ * unit-weight graphs form one batch each) a few steps at a time, and retires
+ * the requests that reach their step count, so a request that arrives while
  * others are on the GPU joins them at the next round.  A request's counts
  * equal those of the same sim run alone.
  */
