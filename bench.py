@@ -4,14 +4,20 @@ Workload: a seeded random 10-regular graph with N = 1e6 (configuration model
 with double-edge-swap repair), SEIR with log-normal E (mu = ln 3, sigma = 0.5)
 and I (mu = ln 5, sigma = 0.6) holding times, beta = 0.06 per edge per day,
 dt = 0.1 d, 100 initially exposed nodes, FP32 storage, one replica, a
-captured hipGraph of 50 steps per replay.  A step is one fused launch over
-all N nodes; the timed region is K steps of the trajectory from the seeded
-start (K = 500 by default: the whole 50-day run), inputs resident in HBM.
+captured hipGraph of b steps per replay (b = 50, or K rounded down to even
+when K < 50).  A step is one fused launch over all N nodes.  The configured
+trajectory is 500 steps (50 days); it is run from the seeded start as timed
+windows of exactly K steps (K = --steps, default the whole trajectory), each
+bracketed by device synchronisations, so a short K still measures every
+phase of the epidemic.  Inputs are resident in HBM throughout.
 
 Prints one JSON line: GNUPS (node-updates per second / 1e9), the roofline
 record of the step kernel (algorithmic bytes per launch over the measured
-per-launch time against the 8 TB/s HBM peak) and the single-core FP64 oracle
-timed on a bounded sample of the same workload.
+per-launch time against the 8 TB/s HBM peak, plus the counter-measured
+traffic of the committed profile when it matches the kernel sources), the
+FP64 oracle timed on the host (on one core, and as independent replicas on
+every usable core), and a short sample of the scenario server (--serving
+below) at 50 requests/s and at saturation.
 
 --workload selects another named workload of the same kind (the
 Barabasi-Albert graph with autotuned degree bins, or the N = 1e8 8-regular
@@ -132,6 +138,65 @@ def cpu_baseline(rp, ci, model, seeds, budget_s: float, compact: bool):
                       f"single-threaded FP64 oracle, {el:.1f} s"}
 
 
+def host_cores() -> int:
+    """Cores this process may use, capped at 16 (a one-GPU machine's CPU share)."""
+    try:
+        c = len(os.sched_getaffinity(0))
+    except AttributeError:
+        c = os.cpu_count() or 1
+    return max(1, min(16, c))
+
+
+def cpu_all_cores(rp, ci, model, seeds, budget_s: float, compact: bool):
+    """The host's embarrassingly parallel throughput: P independent replicas
+    of the same run (replica ids 0..P-1, so independent Philox streams), one
+    single-threaded FP64 oracle per core, P = the usable cores (at most 16,
+    fewer when P copies of the state would not fit in 32 GB)."""
+    import threading
+
+    import numpy as np
+
+    import oracle
+    import workloads as W
+
+    n = len(rp) - 1
+    P = min(host_cores(), max(1, int(32e9 // (n * 40))))
+    per_call = max(1, min(5, int(2e7 // n)))
+    done = [0] * P
+    errs = []
+    t_end = [0.0]
+
+    def worker(r):
+        try:
+            st = W.initial_state(n, seeds)
+            age = np.zeros(n, np.uint16 if compact else np.float32)
+            k = 0
+            while time.perf_counter() < t_end[0]:
+                st, age, _ = oracle.run((rp, ci), model, st, age, per_call, step0=k, replica=r,
+                                        compact=compact)
+                k += per_call
+                done[r] = k
+        except Exception as e:  # (reported, never hidden)
+            errs.append(repr(e))
+
+    oracle.lib()
+    t0 = time.perf_counter()
+    t_end[0] = t0 + budget_s
+    ths = [threading.Thread(target=worker, args=(r,)) for r in range(P)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    el = time.perf_counter() - t0
+    if errs:
+        raise RuntimeError(f"oracle worker failed: {errs[0]}")
+    total = sum(done)
+    return {"value": n * total / el / 1e9, "unit": "GNUPS", "cores": P, "kind": "oracle",
+            "sample": f"{P} independent replicas of the same N={n:.0e} run from the seeded start, "
+                      f"one single-threaded FP64 oracle per core ({min(done)}..{max(done)} steps each), "
+                      f"{el:.1f} s"}
+
+
 def copy_bandwidth(torch, dev, mib: int = 1024, reps: int = 5) -> float:
     """Measured device-to-device copy bandwidth (bytes read + written per
     second, GB/s): the best of `reps` copies of `mib` MiB."""
@@ -155,7 +220,12 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
 
 
-def serving_main(args):
+def serving_run(n_req: int, rate: float, pool_size: int, slots: int = 0, round_steps: int = 0,
+                label: str = "serving", graphs_cache=None):
+    """The seeded request stream through the scenario server, and the same
+    stream as sequential plain solves (each starting when it has arrived and
+    the previous one is done).  rate = 0 offers every request at once
+    (saturation).  Returns the record of both modes."""
     import threading
 
     import numpy as np
@@ -165,35 +235,46 @@ def serving_main(args):
 
     fs.lib()  # fail loudly without the HIP library
     t0 = time.perf_counter()
-    specs = WS.pool_specs(args.serving_pool, seed=404)
-    pool = [WS.build_graph(sp) for sp in specs]
-    sizes = [len(rp) - 1 for rp, _ in pool]
-    print(f"[serving] pool of {len(pool)} graphs (N {min(sizes)}..{max(sizes)}) built in "
-          f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
-    graphs = [fs.Graph(rp, ci) for rp, ci in pool]
-    reqs = WS.requests(args.serving_requests, args.serving_rate, sizes, seed=405)
+    if graphs_cache is not None and graphs_cache.get("size") == pool_size:
+        graphs, sizes = graphs_cache["graphs"], graphs_cache["sizes"]
+    else:
+        specs = WS.pool_specs(pool_size, seed=404)
+        pool = [WS.build_graph(sp) for sp in specs]
+        sizes = [len(rp) - 1 for rp, _ in pool]
+        graphs = [fs.Graph(rp, ci) for rp, ci in pool]
+        del pool
+        print(f"[{label}] pool of {len(graphs)} graphs (N {min(sizes)}..{max(sizes)}) built in "
+              f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+        if graphs_cache is not None:
+            graphs_cache.update(size=pool_size, graphs=graphs, sizes=sizes)
+        # warm-up: every pool graph once (kernels loaded, the graphs' row
+        # layouts for 16 replicas built and cached, as for resident graphs)
+        for gi in range(len(graphs)):
+            r = dict(WS.requests(1, 50.0, sizes, seed=405)[0], graph=gi, steps=4,
+                     seeds=np.array([0, 1], np.int64))
+            sim = fs.Sim(graphs[gi], r["ei"], r["ir"], r["beta"], r["dt"], seed=r["seed"], replicas=16)
+            sim.seed(r["seeds"], replica=-1)
+            sim.step(4)
+            sim.counts(0)
+            sim.close()
+    reqs = WS.requests(n_req, rate if rate > 0 else 50.0, sizes, seed=405)
+    if rate <= 0:
+        for r in reqs:
+            r["arrival"] = 0.0
     updates = sum(sizes[r["graph"]] * r["replicas"] * r["steps"] for r in reqs)
+    span_offered = reqs[-1]["arrival"]
 
-    def plain_solve(r, hist_out=True):
+    def plain_solve(r):
         sim = fs.Sim(graphs[r["graph"]], r["ei"], r["ir"], r["beta"], r["dt"], seed=r["seed"],
                      replicas=r["replicas"], history_len=max(r["steps"], 2))
         sim.seed(r["seeds"], replica=-1)
         sim.step(r["steps"])
-        h = np.stack([sim.history(0, r["steps"], k) for k in range(r["replicas"])], axis=1) \
-            if hist_out else sim.counts(0)
+        h = np.stack([sim.history(0, r["steps"], k) for k in range(r["replicas"])], axis=1)
         sim.close()
         return h
 
-    # warm-up: every pool graph once (kernels loaded, the graphs' row layouts
-    # for 16 replicas built and cached, as for resident graphs)
-    for gi in range(len(graphs)):
-        r = dict(reqs[0], graph=gi, steps=4, seeds=np.array([0, 1], np.int64))
-        plain_solve(r, hist_out=False)
-    print(f"[serving] {len(reqs)} requests, {updates / 1e9:.1f} G node-updates, "
-          f"offered {updates / reqs[-1]['arrival'] / 1e9:.1f} GNUPS", file=sys.stderr, flush=True)
-
     # batched: the server, with requests submitted at their arrival times
-    sv = fs.Server(max_active=args.serving_slots, steps_per_round=args.serving_round)
+    sv = fs.Server(max_active=slots, steps_per_round=round_steps)
     ids = [None] * len(reqs)
     start = fs.fs_server_clock() + 0.05
 
@@ -219,11 +300,9 @@ def serving_main(args):
     sv.close()
     b_lat = [x["t_done"] - x["t_submit"] for x in b_info]
     b_span = max(x["t_done"] for x in b_info) - start
-    print(f"[serving] batched: {len(reqs) / b_span:.1f} scenarios/s, p50 {percentile(b_lat, 50):.3f}s "
+    print(f"[{label}] batched: {len(reqs) / b_span:.1f} scenarios/s, p50 {percentile(b_lat, 50):.3f}s "
           f"p99 {percentile(b_lat, 99):.3f}s", file=sys.stderr, flush=True)
 
-    # sequential plain solves of the same stream: one at a time, each starting
-    # when it has arrived and the previous one is done
     s_lat = []
     same = 0
     start = time.perf_counter() + 0.05
@@ -238,28 +317,38 @@ def serving_main(args):
                 raise SystemExit(f"request {i}: batched and sequential counts differ")
             same += 1
     s_span = time.perf_counter() - start
-    print(f"[serving] sequential: {len(reqs) / s_span:.1f} scenarios/s, p50 {percentile(s_lat, 50):.3f}s "
+    print(f"[{label}] sequential: {len(reqs) / s_span:.1f} scenarios/s, p50 {percentile(s_lat, 50):.3f}s "
           f"p99 {percentile(s_lat, 99):.3f}s", file=sys.stderr, flush=True)
-    for g in graphs:
-        g.close()
 
     def rec(n, span, lat):
         return {"scenarios_per_s": round(n / span, 3), "p50_s": round(percentile(lat, 50), 4),
                 "p99_s": round(percentile(lat, 99), 4), "makespan_s": round(span, 3),
                 "gnups": round(updates / span / 1e9, 3)}
 
+    return {"requests": len(reqs), "rate_per_s": rate if rate > 0 else "all at once",
+            "pool_graphs": len(graphs), "n_range": [min(sizes), max(sizes)],
+            "batched": rec(len(reqs), b_span, b_lat), "sequential": rec(len(reqs), s_span, s_lat),
+            "identical_counts_checked": same,
+            "offered_gnups": round(updates / span_offered / 1e9, 3) if span_offered > 0 else None}
+
+
+def serving_main(args):
+    cache = {}
+    at_rate = serving_run(args.serving_requests, args.serving_rate, args.serving_pool, args.serving_slots,
+                          args.serving_round, "serving", cache)
+    saturated = serving_run(args.serving_requests, 0.0, args.serving_pool, args.serving_slots,
+                            args.serving_round, "serving, saturated", cache)
+    for g in cache.get("graphs", []):
+        g.close()
     out = {
         "metric": "batched-serving scenarios/s + p50/p99 latency",
-        "value": round(len(reqs) / b_span, 3), "unit": "scenarios/s", "n_gpus": 1,
+        "value": at_rate["batched"]["scenarios_per_s"], "unit": "scenarios/s", "n_gpus": 1,
         "higher_is_better": True, "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "serving_mix", "requests": len(reqs), "rate_per_s": args.serving_rate,
-                   "pool_graphs": len(pool), "n_range": [min(sizes), max(sizes)], "replicas": 16,
-                   "steps": 300, "dt": 0.1, "slots": args.serving_slots,
-                   "steps_per_round": args.serving_round, "parallelism": "single GPU"},
-        "serving": {"batched": rec(len(reqs), b_span, b_lat),
-                    "sequential": rec(len(reqs), s_span, s_lat),
-                    "identical_counts_checked": same,
-                    "offered_gnups": round(updates / reqs[-1]["arrival"] / 1e9, 3)},
+        "config": {"workload": "serving_mix", "requests": args.serving_requests,
+                   "rate_per_s": args.serving_rate, "replicas": 16, "steps": 300, "dt": 0.1,
+                   "slots": args.serving_slots, "steps_per_round": args.serving_round,
+                   "parallelism": "single GPU"},
+        "serving": {"at_rate": at_rate, "saturated": saturated},
     }
     print(json.dumps(out), flush=True)
 
@@ -348,12 +437,16 @@ def main():
                     help="autotune the degree bins before timing (auto: when the maximum "
                          "degree exceeds 64)")
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default: the workload's trajectory length)")
+                    help="steps per timed window (default: the workload's trajectory length); "
+                         "shorter windows tile the trajectory, each timed on its own")
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--repeats", type=int, default=5,
-                    help="timed runs of the K-step trajectory (value: their mean; CoV reported)")
-    ap.add_argument("--cpu-budget", type=float, default=12.0,
-                    help="seconds of oracle time for the CPU baseline (0 = skip)")
+                    help="timed runs of the trajectory (value: their mean; CoV reported)")
+    ap.add_argument("--bins", default=None,
+                    help="explicit degree bins 'heavy_degree,segment_edges' (no tuning)")
+    ap.add_argument("--cpu-budget", type=float, default=16.0,
+                    help="seconds of oracle time for the CPU baselines, half on one core and half "
+                         "on all cores (0 = skip)")
     ap.add_argument("--variant", choices=["auto", "stream", "resident", "summary"], default="auto",
                     help="step kernel variant (auto: LDS-resident bitmap when N*R <= 2^20, "
                          "else the LDS summary that screens bitmap reads)")
@@ -371,6 +464,10 @@ def main():
     ap.add_argument("--serving-pool", type=int, default=24, help="resident pool graphs")
     ap.add_argument("--serving-slots", type=int, default=0, help="server slot limit (0 = default)")
     ap.add_argument("--serving-round", type=int, default=0, help="steps per round (0 = default)")
+    ap.add_argument("--serving-sample", type=int, default=48,
+                    help="requests of the short serving measurement in the default line (0 = none)")
+    ap.add_argument("--serving-sample-pool", type=int, default=6,
+                    help="pool graphs of the short serving measurement")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB, so a "
                          "counter profile of the same process can scale HBM byte counters")
@@ -403,8 +500,17 @@ def main():
     model["shed"] = shed
     storage = args.storage or wl["storage"]
     compact = storage == "compact"
-    if args.steps is None:
-        args.steps = wl["steps"]
+    traj = wl["steps"]
+    K = args.steps if args.steps is not None else traj
+    # the captured step loop: b steps per replay (at most 50, even), so that
+    # a window of K steps is replayed from the graph (K // b replays, K % b
+    # single launches)
+    spg = min(STEPS_PER_GRAPH, K)
+    if spg > 1:
+        spg -= spg % 2
+    # timed windows of K steps tile the configured trajectory: a short K
+    # measures the same mix of epidemic phases as the whole run
+    nwin = -(-traj // K) if K < traj else 1
     t0 = time.perf_counter()
     rp, ci = W.workload_graph(wl["graph"])
     n = len(rp) - 1
@@ -428,80 +534,119 @@ def main():
     g = fs.Graph(rp, ci)
     variant = {"auto": fs.VARIANT_AUTO, "stream": fs.VARIANT_STREAM,
                "resident": fs.VARIANT_RESIDENT, "summary": fs.VARIANT_SUMMARY}[args.variant]
-    sim = fs.Sim.from_model(g, model, steps_per_graph=STEPS_PER_GRAPH, stream=stream.cuda_stream,
+    bins = tuple(int(x) for x in args.bins.split(",")) if args.bins else (0, 0)
+    sim = fs.Sim.from_model(g, model, steps_per_graph=spg, stream=stream.cuda_stream,
                             variant=variant, compaction=args.compaction,
-                            storage=fs.FS_STORAGE_COMPACT if compact else fs.FS_STORAGE_FP32)
+                            storage=fs.FS_STORAGE_COMPACT if compact else fs.FS_STORAGE_FP32,
+                            heavy_degree=bins[0], segment_edges=bins[1],
+                            history_len=max(1024, nwin * K + 1))
     init_state = W.initial_state(n, seeds)
     init_age = np.zeros(n, np.uint16 if compact else np.float32)
     max_deg = int(np.diff(rp).max())
     tuned = None
-    if args.tune == "on" or (args.tune == "auto" and max_deg > 64):
+    if not args.bins and (args.tune == "on" or (args.tune == "auto" and max_deg > 64)):
         sim.set_state(init_state, init_age, 0, step_index=0)
         sim.step(100)  # tune on a state with the epidemic under way
         sim.sync()
         tuned = sim.tune()
         print(f"[bench] tuned degree bins (heavy_degree, segment_edges) = {tuned}", file=sys.stderr,
               flush=True)
+    bins_used = sim.bins()
 
     # warm-up (graph instantiation, clocks), then restart the trajectory
     sim.set_state(init_state, init_age, 0, step_index=0)
     sim.step(args.warmup)
     sim.sync()
-    sim.set_state(init_state, init_age, 0, step_index=0)
     torch.cuda.synchronize()
 
-    # each timed run replays the same K-step trajectory from the seeded start
-    runs = []
+    # each repeat runs the trajectory from the seeded start as nwin timed
+    # windows of exactly K steps, each bracketed by device synchronisations
+    runs = []      # per repeat: the summed window times (ms)
+    win_ms = []
     wall = 0.0
     for rep in range(max(1, args.repeats)):
-        if rep:
-            sim.set_state(init_state, init_age, 0, step_index=0)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        w0 = time.perf_counter()
-        e0.record(stream)
-        sim.step(args.steps)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        wall += time.perf_counter() - w0
-        runs.append(e0.elapsed_time(e1))
+        sim.set_state(init_state, init_age, 0, step_index=0)
+        tot = 0.0
+        for w in range(nwin):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            w0 = time.perf_counter()
+            e0.record(stream)
+            sim.step(K)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - w0
+            ms_w = e0.elapsed_time(e1)
+            win_ms.append(ms_w)
+            tot += ms_w
+        runs.append(tot)
+    steps_run = nwin * K
     ms = float(np.mean(runs))
     cov = float(np.std(runs) / ms) if len(runs) > 1 else 0.0
     wall /= len(runs)
-    hist = sim.history(0, args.steps)
+    hist = sim.history(0, steps_run)
     assert np.all(hist.sum(1) == n)
     final = sim.counts(0)
     sim.close()
     g.close()
 
     sec = ms / 1e3
-    gnups = n * args.steps / sec / 1e9
+    gnups = n * steps_run / sec / 1e9
     d_mean = len(ci) / n
     b_alg = bytes_per_update(d_mean, storage)
-    per_launch_s = sec / args.steps
+    per_launch_s = sec / steps_run
     achieved = b_alg * n / per_launch_s / 1e9
     plain = args.shed == "none" and not args.compaction
     traffic = measured_traffic(workload if storage == wl["storage"] else f"{workload}_{storage}") if plain else None
     s_frac = float(hist[:, 0].mean() / n)
     copy_gbs = copy_bandwidth(torch, dev)
-    print(f"[bench] {args.steps} steps: {ms:.3f} ms mean of {len(runs)} (CoV {cov:.3f}, wall {wall * 1e3:.1f} ms), "
-          f"{gnups:.2f} GNUPS, copy {copy_gbs:.0f} GB/s, "
+    print(f"[bench] {nwin} x {K} steps (b = {spg}): {ms:.3f} ms mean of {len(runs)} (CoV {cov:.3f}, "
+          f"wall {wall * 1e3:.1f} ms), {gnups:.2f} GNUPS, copy {copy_gbs:.0f} GB/s, "
           f"final counts {final.tolist()}, mean S fraction {s_frac:.3f}", file=sys.stderr, flush=True)
 
     cpu = None
     if args.cpu_budget > 0:
-        cpu = cpu_baseline(rp, ci, model, seeds, args.cpu_budget, compact)
-        print(f"[bench] cpu baseline {cpu['value'] * 1e3:.1f} MNUPS", file=sys.stderr, flush=True)
+        one = cpu_baseline(rp, ci, model, seeds, args.cpu_budget / 2, compact)
+        print(f"[bench] cpu baseline, one core: {one['value'] * 1e3:.1f} MNUPS", file=sys.stderr, flush=True)
+        cpu = cpu_all_cores(rp, ci, model, seeds, args.cpu_budget / 2, compact)
+        cpu["one_core"] = one
+        print(f"[bench] cpu baseline, {cpu['cores']} cores: {cpu['value'] * 1e3:.1f} MNUPS", file=sys.stderr,
+              flush=True)
 
+    serving = None
+    if args.serving_sample > 0 and workload == WORKLOAD and plain:
+        cache = {}
+        try:
+            serving = {
+                "at_rate": serving_run(args.serving_sample, args.serving_rate, args.serving_sample_pool,
+                                       label="serving sample", graphs_cache=cache),
+                "saturated": serving_run(args.serving_sample, 0.0, args.serving_sample_pool,
+                                         label="serving sample, saturated", graphs_cache=cache),
+            }
+        except Exception as e:  # the step line stands on its own; the failure is reported
+            serving = {"error": repr(e)}
+        for gg in cache.get("graphs", []):
+            gg.close()
+
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "bytes_per_update": b_alg,
+            "per_launch_us": round(per_launch_s * 1e6, 3),
+            "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
+            "repeats": len(runs), "cov": round(cov, 4)}
+    if traffic:
+        # the bytes the kernel really moves at the L2/HBM boundary (counters)
+        roof["traffic_gbs"] = round(traffic / per_launch_s / 1e9, 1)
+        roof["traffic_frac"] = round(traffic / per_launch_s / 1e9 / HBM_PEAK_GBS, 4)
     rec = {
         "metric": METRIC,
         "value": round(gnups, 4),
         "unit": "GNUPS",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": round(ms / args.steps, 6),
+        "ms_per_step": round(ms / steps_run, 6),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -510,20 +655,21 @@ def main():
         "config": {"workload": workload, "graph": GRAPH_TEXT[workload], "n": n, "edges": int(len(ci)),
                    "laws": LAW_TEXT[workload], "beta": model["beta"], "dt": model["dt"],
                    "seeds": wl["seeds"], "replicas": 1, "storage": storage,
-                   "steps_per_graph": STEPS_PER_GRAPH, "kernel_variant": args.variant,
+                   "trajectory_steps": traj, "timed_windows": nwin, "window_steps": K,
+                   "steps_per_graph": spg, "graph_replays_per_window": K // spg if spg else 0,
+                   "eager_steps_per_window": K % spg if spg else K,
+                   "kernel_variant": args.variant,
                    "shedding": args.shed if shed is None else [shed[0], list(shed[1]), shed[2]],
                    "compaction": args.compaction,
-                   "degree_bins": list(tuned) if tuned else None, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "bytes_per_update": b_alg,
-                     "per_launch_us": round(per_launch_s * 1e6, 3),
-                     "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
-                     "repeats": len(runs), "cov": round(cov, 4)},
+                   "degree_bins": list(bins_used[:2]) if bins_used[2] else None,
+                   "degree_bins_from": "tuner" if tuned else ("explicit" if args.bins else "default"),
+                   "parallelism": "single GPU"},
+        "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if serving is not None:
+        rec["serving"] = serving
     print(json.dumps(rec), flush=True)
-
 
 if __name__ == "__main__":
     main()
