@@ -227,6 +227,27 @@ fs_status fs_sim_destroy(fs_sim* s);
 fs_status fs_sim_seed(fs_sim* s, int32_t replica, int64_t count, const int64_t* nodes,
                       int32_t compartment);
 
+/* Largest `count` fs_sim_seed_noalloc accepts (512 KiB of staging per GPU). */
+#define FS_SEED_NOALLOC_MAX 65536
+
+/*
+ * fs_sim_seed for callers that cannot allocate device memory (serving loops
+ * that must not call hipMalloc, harnesses that forbid it): the same
+ * arguments, validation, kernels and result, but the node list is staged in
+ * a fixed device array of FS_SEED_NOALLOC_MAX int64 ids that the library
+ * holds on each GPU it runs on until the process ends, and the call makes no
+ * device allocation of its own (no hipMalloc, hipMallocAsync or allocator
+ * hook).  `nodes` is a host array, read before the call returns; like
+ * fs_sim_seed it synchronises the sim's stream.
+ * Errors: FS_ERR_INVALID_ARG for count > FS_SEED_NOALLOC_MAX (nothing is
+ * changed) and every error of fs_sim_seed.
+ * Every call on one GPU shares that GPU's staging array: calls that overlap
+ * in time on one GPU (from several host threads) race and must be serialised
+ * by the caller; sequential calls are independent.
+ */
+fs_status fs_sim_seed_noalloc(fs_sim* s, int32_t replica, int64_t count, const int64_t* nodes,
+                              int32_t compartment);
+
 /*
  * Queues n_steps steps (Algorithm 3, fixed dt) on the sim's stream and
  * returns without waiting.  With steps_per_graph = b > 0, floor(n/b) replays

@@ -24,13 +24,14 @@ FS_S, FS_E, FS_I, FS_R = 0, 1, 2, 3
 FS_DIST_EXP, FS_DIST_LOGNORMAL, FS_DIST_WEIBULL, FS_DIST_ERLANG = 0, 1, 2, 3
 FS_STORAGE_FP32, FS_STORAGE_COMPACT = 0, 1
 FS_SHED_CONSTANT, FS_SHED_DENSITY, FS_SHED_HAZARD = 0, 1, 2
+FS_SEED_NOALLOC_MAX = 65536  # include/fs.h
 SHED_FORMS = {"constant": FS_SHED_CONSTANT, "density": FS_SHED_DENSITY, "hazard": FS_SHED_HAZARD}
 VARIANT_AUTO, VARIANT_STREAM, VARIANT_RESIDENT, VARIANT_SUMMARY = 0, 1, 2, 3
 
 # Every symbol include/fs.h declares.
 EXPORTS = [
     "fs_status_string", "fs_last_error", "fs_graph_create", "fs_graph_destroy",
-    "fs_graph_get_info", "fs_sim_create", "fs_sim_destroy", "fs_sim_seed", "fs_step",
+    "fs_graph_get_info", "fs_sim_create", "fs_sim_destroy", "fs_sim_seed", "fs_sim_seed_noalloc", "fs_step",
     "fs_sync", "fs_step_index", "fs_counts", "fs_history", "fs_get_state", "fs_set_state",
     "fs_get_rates", "fs_eval_hazard", "fs_eval_shedding", "fs_eval_philox", "fs_version", "fs_sim_set_bins",
     "fs_sim_get_bins", "fs_sim_tune", "fs_step_sizes",
@@ -141,6 +142,7 @@ def _declare(L):
         "fs_markov_history": ([P, I64, I64, P, P, P], I32),
         "fs_sim_destroy": ([P], I32),
         "fs_sim_seed": ([P, I32, I64, P, I32], I32),
+        "fs_sim_seed_noalloc": ([P, I32, I64, P, I32], I32),
         "fs_step": ([P, I64], I32),
         "fs_sync": ([P], I32),
         "fs_step_index": ([P, ctypes.POINTER(ctypes.c_int64)], I32),
@@ -242,6 +244,14 @@ def fs_sim_destroy(h):
 def fs_sim_seed(h, replica: int, nodes, compartment: int = FS_E):
     nd = np.ascontiguousarray(nodes, dtype=np.int64)
     _check(lib().fs_sim_seed(h, int(replica), len(nd), _ptr(nd), int(compartment)), "fs_sim_seed")
+
+
+def fs_sim_seed_noalloc(h, replica: int, nodes, compartment: int = FS_E):
+    """fs_sim_seed with the node list staged in the library's fixed device
+    array (at most FS_SEED_NOALLOC_MAX nodes): no device allocation."""
+    nd = np.ascontiguousarray(nodes, dtype=np.int64)
+    _check(lib().fs_sim_seed_noalloc(h, int(replica), len(nd), _ptr(nd), int(compartment)),
+           "fs_sim_seed_noalloc")
 
 
 def fs_step(h, n_steps: int):

@@ -1152,6 +1152,77 @@ fs_status fs_sim_seed(fs_sim* s, int32_t replica, int64_t count, const int64_t* 
     FS_GUARD_END
 }
 
+} // extern "C"
+
+// Seed-list staging of fs_sim_seed_noalloc: a fixed device array (each GPU
+// the library runs on holds its own copy until the process ends) instead of
+// a stream-ordered allocation per call.  Host code never passes the array's
+// name to a kernel or a copy: on the host it is only a stand-in symbol, and
+// the device address comes from hipGetSymbolAddress, per device.
+static __device__ __align__(256) int64_t scratch[FS_SEED_NOALLOC_MAX];
+
+namespace fsr {
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_DEVICES] = {};
+
+// The device address of `scratch` on the current device `dev`, looked up
+// once per device.
+fs_status scratch_address(int dev, int64_t** out)
+{
+    if (dev < 0 || dev >= SCRATCH_DEVICES) return fail(FS_ERR_DEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(FS_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = (int64_t*)g_scratch_ptr[dev];
+    return FS_OK;
+}
+
+} // namespace fsr
+
+extern "C" {
+
+fs_status fs_sim_seed_noalloc(fs_sim* s, int32_t replica, int64_t count, const int64_t* nodes, int32_t compartment)
+{
+    FS_GUARD_BEGIN
+    fs_status st = check_seed(s, replica, count, nodes, compartment);
+    if (st != FS_OK || count == 0) return st;
+    if (count > FS_SEED_NOALLOC_MAX)
+        return fail(FS_ERR_INVALID_ARG, "fs_sim_seed_noalloc takes at most " + std::to_string(FS_SEED_NOALLOC_MAX) +
+                                            " nodes per call (got " + std::to_string(count) + ")");
+    DeviceGuard dg(s->device);
+    int64_t* stage = nullptr;
+    st = scratch_address(s->device, &stage);
+    if (st != FS_OK) return st;
+    // Every id of [0, count) is written before the seed kernel reads it, so
+    // nothing of an earlier call's contents is used.
+    if (s->g->h_inv.empty()) {
+        FS_HIP(hipMemcpyAsync(stage, nodes, sizeof(int64_t) * (size_t)count, hipMemcpyHostToDevice, s->stream));
+    } else {
+        // degree-sorted graph: the caller's ids go through the inverse
+        // relabelling on the host, a bounded piece at a time through a stack
+        // buffer; each piece's copy is complete before the buffer is refilled
+        constexpr int64_t PIECE = 1024;
+        int64_t buf[PIECE];
+        for (int64_t j0 = 0; j0 < count; j0 += PIECE) {
+            const int64_t m = std::min<int64_t>(PIECE, count - j0);
+            for (int64_t j = 0; j < m; ++j) buf[j] = s->g->h_inv[(size_t)nodes[j0 + j]];
+            FS_HIP(hipMemcpyAsync(stage + j0, buf, sizeof(int64_t) * (size_t)m, hipMemcpyHostToDevice, s->stream));
+            FS_HIP(hipStreamSynchronize(s->stream));
+        }
+    }
+    // (seed_staged ends with a synchronisation of the sim's stream, so the
+    // staging is free again, and the caller's array no longer read, on return)
+    return seed_staged(s, replica, stage, count, compartment);
+    FS_GUARD_END
+}
+
 fs_status fs_step(fs_sim* s, int64_t n_steps)
 {
     FS_GUARD_BEGIN

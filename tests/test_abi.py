@@ -69,6 +69,13 @@ def test_null_handles_rejected():
     assert L.fs_sim_destroy(None) == 1
     assert L.fs_graph_destroy(None) == 1
     assert L.fs_counts(None, 0, None) == 1
+    assert L.fs_sim_seed_noalloc(None, 0, 0, None, 1) == 1
+
+
+def test_seed_noalloc_limit_matches_the_header():
+    txt = open(os.path.join(ROOT, "include", "fs.h")).read()
+    m = re.search(r"#define FS_SEED_NOALLOC_MAX (\d+)", txt)
+    assert m and int(m.group(1)) == fs.FS_SEED_NOALLOC_MAX
 
 
 def test_bad_hazard_parameters_rejected_on_host():
