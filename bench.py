@@ -52,6 +52,7 @@ import hashlib
 import glob
 import json
 import os
+import re
 import sys
 import time
 
@@ -136,6 +137,24 @@ def cpu_baseline(rp, ci, model, seeds, budget_s: float, compact: bool):
     return {"value": n * steps / el / 1e9, "unit": "GNUPS", "cores": 1, "kind": "oracle",
             "sample": f"{steps} steps (steps 1..{steps}) of the same N={n:.0e} trajectory, "
                       f"single-threaded FP64 oracle, {el:.1f} s"}
+
+
+def load_graph(spec, cache_dir=None):
+    """The workload graph of `spec`, generated, or loaded from (and saved to)
+    cache_dir as .npy files (the generators are deterministic in spec)."""
+    import numpy as np
+
+    import workloads as W
+    if not cache_dir:
+        return W.workload_graph(spec)
+    os.makedirs(cache_dir, exist_ok=True)
+    base = os.path.join(cache_dir, "graph_" + "_".join(str(x) for x in spec))
+    if os.path.exists(base + "_ci.npy"):
+        return np.load(base + "_rp.npy"), np.load(base + "_ci.npy")
+    rp, ci = W.workload_graph(spec)
+    np.save(base + "_rp.npy", rp)
+    np.save(base + "_ci.npy", ci)
+    return rp, ci
 
 
 def host_cores() -> int:
@@ -434,8 +453,12 @@ def main():
     ap.add_argument("--storage", choices=["fp32", "compact"], default=None,
                     help="state/age storage (default: the workload's)")
     ap.add_argument("--tune", choices=["auto", "on", "off"], default="auto",
-                    help="autotune the degree bins before timing (auto: when the maximum "
-                         "degree exceeds 64)")
+                    help="run the autotuner (step variant and degree bins) before timing "
+                         "(auto: for every workload but the default one, whose plain step is "
+                         "configuration 1 as stated)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="tune cache file: a choice cached for the run's signature is applied "
+                         "without trials, a new one is appended")
     ap.add_argument("--steps", type=int, default=None,
                     help="steps per timed window (default: the workload's trajectory length); "
                          "shorter windows tile the trajectory, each timed on its own")
@@ -468,6 +491,10 @@ def main():
                     help="requests of the short serving measurement in the default line (0 = none)")
     ap.add_argument("--serving-sample-pool", type=int, default=6,
                     help="pool graphs of the short serving measurement")
+    ap.add_argument("--n", type=float, default=0,
+                    help="run the workload's graph family at this many nodes instead (an N sweep)")
+    ap.add_argument("--graph-cache", default=None,
+                    help="directory where generated graphs are kept as .npy files and reused")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB, so a "
                          "counter profile of the same process can scale HBM byte counters")
@@ -512,7 +539,11 @@ def main():
     # measures the same mix of epidemic phases as the whole run
     nwin = -(-traj // K) if K < traj else 1
     t0 = time.perf_counter()
-    rp, ci = W.workload_graph(wl["graph"])
+    spec = wl["graph"]
+    if args.n:
+        # the workload's graph family and degree at another size (an N sweep)
+        spec = (spec[0], int(args.n) + (int(args.n) & 1 if spec[0] == "regular_m" else 0)) + tuple(spec[2:])
+    rp, ci = load_graph(spec, args.graph_cache)
     n = len(rp) - 1
     seeds = W.seed_nodes(n, wl["seeds"], wl["seed_rng"])
     print(f"[bench] graph {workload}: N={n} E={len(ci)} built in {time.perf_counter() - t0:.1f}s",
@@ -542,16 +573,15 @@ def main():
                             history_len=max(1024, nwin * K + 1))
     init_state = W.initial_state(n, seeds)
     init_age = np.zeros(n, np.uint16 if compact else np.float32)
-    max_deg = int(np.diff(rp).max())
     tuned = None
-    if not args.bins and (args.tune == "on" or (args.tune == "auto" and max_deg > 64)):
+    if not args.bins and (args.tune == "on" or (args.tune == "auto" and workload != WORKLOAD)):
         sim.set_state(init_state, init_age, 0, step_index=0)
         sim.step(100)  # tune on a state with the epidemic under way
         sim.sync()
-        tuned = sim.tune()
-        print(f"[bench] tuned degree bins (heavy_degree, segment_edges) = {tuned}", file=sys.stderr,
-              flush=True)
+        tuned = sim.autotune(20, variants=args.variant == "auto", cache_path=args.tune_cache)
+        print(f"[bench] autotuner: {tuned}", file=sys.stderr, flush=True)
     bins_used = sim.bins()
+    variant_used = sim.variant()
 
     # warm-up (graph instantiation, clocks), then restart the trajectory
     sim.set_state(init_state, init_age, 0, step_index=0)
@@ -652,17 +682,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",  # hazard and pressure arithmetic; compact storage changes only what is stored
         "data": "synthetic",
-        "config": {"workload": workload, "graph": GRAPH_TEXT[workload], "n": n, "edges": int(len(ci)),
+        "config": {"workload": workload if not args.n else f"{workload} at N={n}",
+                   "graph": GRAPH_TEXT[workload] if not args.n else re.sub(r"N=[0-9e.]+", f"N={n}", GRAPH_TEXT[workload]),
+                   "n": n, "edges": int(len(ci)),
                    "laws": LAW_TEXT[workload], "beta": model["beta"], "dt": model["dt"],
                    "seeds": wl["seeds"], "replicas": 1, "storage": storage,
                    "trajectory_steps": traj, "timed_windows": nwin, "window_steps": K,
                    "steps_per_graph": spg, "graph_replays_per_window": K // spg if spg else 0,
                    "eager_steps_per_window": K % spg if spg else K,
-                   "kernel_variant": args.variant,
+                   "kernel_variant": variant_used,
                    "shedding": args.shed if shed is None else [shed[0], list(shed[1]), shed[2]],
                    "compaction": args.compaction,
                    "degree_bins": list(bins_used[:2]) if bins_used[2] else None,
                    "degree_bins_from": "tuner" if tuned else ("explicit" if args.bins else "default"),
+                   "autotuner": tuned,
                    "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -332,6 +332,48 @@ fs_status fs_sim_set_bins(fs_sim* s, int32_t heavy_degree, int32_t segment_edges
 fs_status fs_sim_get_bins(fs_sim* s, int32_t* heavy_degree, int32_t* segment_edges, int64_t* segments);
 fs_status fs_sim_tune(fs_sim* s, int32_t trial_steps, int32_t* heavy_degree, int32_t* segment_edges);
 
+/*
+ * The autotuner (Appendix "Degree-heterogeneous graphs and auto-dispatch",
+ * subsection "Auto-dispatch", which picks the traversal strategy from a
+ * graph's degree statistics): times trial_steps steps from the current
+ * state for each candidate configuration -- the step variant (when
+ * `variants` is set: every variant the sim may switch to; the resident one
+ * holds at most 2^20 units, adaptive sims keep an LDS variant) and the
+ * degree bins (heavy_degree in {none, 8, 12, 16, 24, 32, 64, 128, 256} below
+ * the maximum degree; segment_edges in {256, 1024} where binned rows gather
+ * segment partials, one value where they take pushed pressure) -- restores
+ * the state after each trial and keeps the fastest.  The sim's configuration
+ * at entry is always among the candidates.
+ * With cache_path set, the choice is keyed by a signature of the graph and
+ * the run (n, edges, degree histogram, replicas, storage, weights, shedding,
+ * adaptive steps, compaction, rate recording, device compute units): a
+ * cached choice is applied without trials, and a new one is appended to the
+ * file (one text line per signature; the last line of a signature wins), so
+ * it persists across processes.  Synchronises.
+ */
+typedef struct {
+    int32_t trial_steps;    /* steps per timed trial, in [1, 4096] */
+    int32_t variants;       /* 1: also choose the step variant; 0: bins only */
+    const char* cache_path; /* NULL: no cache */
+} fs_tune_params;
+
+typedef struct {
+    int32_t variant;        /* chosen step variant: 1 stream, 2 resident, 3 summary */
+    int32_t heavy_degree;   /* chosen bins (as fs_sim_get_bins reports them) */
+    int32_t segment_edges;
+    int32_t from_cache;     /* 1: taken from the cache, no trials run */
+    int32_t trials;         /* timed candidates */
+    int32_t pad;
+    double us_per_step;     /* the chosen candidate's trial time per step (0 from the cache) */
+    double entry_us_per_step; /* the trial time of the configuration at entry (0 from the cache) */
+    uint64_t signature;
+} fs_tune_result;
+
+fs_status fs_sim_autotune(fs_sim* s, const fs_tune_params* p, fs_tune_result* out);
+
+/* The sim's current step variant: 1 stream, 2 resident, 3 summary. */
+fs_status fs_sim_get_variant(fs_sim* s, int32_t* variant);
+
 /* ------------------------------------------------- building-block checks */
 /*
  * Evaluates the device hazard of `law` at n ages with the same code the step

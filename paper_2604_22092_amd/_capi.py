@@ -34,7 +34,7 @@ EXPORTS = [
     "fs_graph_get_info", "fs_sim_create", "fs_sim_destroy", "fs_sim_seed", "fs_sim_seed_noalloc", "fs_step",
     "fs_sync", "fs_step_index", "fs_counts", "fs_history", "fs_get_state", "fs_set_state",
     "fs_get_rates", "fs_eval_hazard", "fs_eval_shedding", "fs_eval_philox", "fs_version", "fs_sim_set_bins",
-    "fs_sim_get_bins", "fs_sim_tune", "fs_step_sizes",
+    "fs_sim_get_bins", "fs_sim_tune", "fs_sim_autotune", "fs_sim_get_variant", "fs_step_sizes",
     "fs_batch_create", "fs_batch_destroy", "fs_batch_add", "fs_batch_remove", "fs_batch_size",
     "fs_batch_step", "fs_batch_sync",
     "fs_server_create", "fs_server_submit", "fs_server_wait", "fs_server_result",
@@ -53,6 +53,19 @@ class FsError(RuntimeError):
 class fs_dist(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("a", ctypes.c_double), ("b", ctypes.c_double)]
+
+
+class fs_tune_params(ctypes.Structure):
+    _fields_ = [("trial_steps", ctypes.c_int32), ("variants", ctypes.c_int32),
+                ("cache_path", ctypes.c_char_p)]
+
+
+class fs_tune_result(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("heavy_degree", ctypes.c_int32),
+                ("segment_edges", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("trials", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("us_per_step", ctypes.c_double), ("entry_us_per_step", ctypes.c_double),
+                ("signature", ctypes.c_uint64)]
 
 
 class fs_graph_info(ctypes.Structure):
@@ -160,6 +173,8 @@ def _declare(L):
         "fs_sim_get_bins": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                              ctypes.POINTER(ctypes.c_int64)], I32),
         "fs_sim_tune": ([P, I32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], I32),
+        "fs_sim_autotune": ([P, ctypes.POINTER(fs_tune_params), ctypes.POINTER(fs_tune_result)], I32),
+        "fs_sim_get_variant": ([P, ctypes.POINTER(ctypes.c_int32)], I32),
         "fs_batch_create": ([I32, P, PP], I32),
         "fs_batch_destroy": ([P], I32),
         "fs_batch_add": ([P, P], I32),
@@ -325,6 +340,28 @@ def fs_sim_tune(h, trial_steps: int) -> tuple:
     a, b = ctypes.c_int32(), ctypes.c_int32()
     _check(lib().fs_sim_tune(h, int(trial_steps), ctypes.byref(a), ctypes.byref(b)), "fs_sim_tune")
     return a.value, b.value
+
+
+VARIANT_NAMES = {1: "stream", 2: "resident", 3: "summary"}
+
+
+def fs_sim_autotune(h, trial_steps: int = 20, variants: bool = True, cache_path=None) -> dict:
+    """The autotuner: the chosen step variant and bins, whether they came
+    from the cache, and the trial times (include/fs.h)."""
+    p = fs_tune_params(int(trial_steps), 1 if variants else 0,
+                       None if cache_path is None else os.fsencode(cache_path))
+    r = fs_tune_result()
+    _check(lib().fs_sim_autotune(h, ctypes.byref(p), ctypes.byref(r)), "fs_sim_autotune")
+    return {"variant": VARIANT_NAMES[r.variant], "heavy_degree": r.heavy_degree,
+            "segment_edges": r.segment_edges, "from_cache": bool(r.from_cache), "trials": r.trials,
+            "us_per_step": r.us_per_step, "entry_us_per_step": r.entry_us_per_step,
+            "signature": f"{r.signature:016x}"}
+
+
+def fs_sim_get_variant(h) -> str:
+    v = ctypes.c_int32()
+    _check(lib().fs_sim_get_variant(h, ctypes.byref(v)), "fs_sim_get_variant")
+    return VARIANT_NAMES[v.value]
 
 
 def fs_eval_hazard(spec, ages, storage: int = FS_STORAGE_FP32, dt: float = 1.0) -> np.ndarray:
@@ -593,6 +630,12 @@ class Sim:
 
     def tune(self, trial_steps: int = 20) -> tuple:
         return fs_sim_tune(self.handle, trial_steps)
+
+    def autotune(self, trial_steps: int = 20, variants: bool = True, cache_path=None) -> dict:
+        return fs_sim_autotune(self.handle, trial_steps, variants, cache_path)
+
+    def variant(self) -> str:
+        return fs_sim_get_variant(self.handle)
 
     def close(self):
         if self.handle is not None:

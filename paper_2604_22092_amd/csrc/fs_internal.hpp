@@ -116,6 +116,23 @@ struct StepArgs {
     const void* seg_part; // [segment][R]: uint32 counts, or float with weights
     int32_t heavy_deg;
     int32_t seg_edges;
+    // pushed pressure of the binned rows (unit weights and constant shedding,
+    // where a row's pressure is the integer count of its infectious
+    // in-neighbours; nullptr hub_T: the rows read their segment partials).
+    // Binned rows are the internal nodes [hub_base, n) of the degree-sorted
+    // order, hub unit h = (node - hub_base) * R + replica.  Step k takes h's
+    // pressure as hub_T[(k - 1) & 1][h] + hub_D[k % 3][h] (modulo 2^32),
+    // stores it into hub_T[k & 1][h] and clears hub_D[(k + 2) % 3][h]; a unit
+    // of node j entering I (E -> I) or leaving it (I -> R) in step k adds +1
+    // or -1 to hub_D[(k + 1) % 3][h] of every binned row listing j as an
+    // in-neighbour (hub_out_idx[hub_out_ptr[j] .. hub_out_ptr[j + 1]), the
+    // rows' hub indices, once per occurrence).
+    uint32_t* hub_T;      // [2][hub_units]
+    uint32_t* hub_D;      // [3][hub_units]
+    const int32_t* hub_out_ptr;
+    const int32_t* hub_out_idx;
+    int32_t hub_base;
+    uint32_t hub_units;
     // light rows in wavefront-transposed order: for the Q = 64/R nodes of chunk
     // c, edge j of every row with more than j light edges is stored at
     // chunk_meta[c].x + (edges j' < j of the chunk) + (rank of the row among

@@ -90,6 +90,40 @@ __global__ __launch_bounds__(WG) void summary_kernel(SumArgs q)
     if ((threadIdx.x & 63) == 0 && (s >> 6) < q.sum_words) q.summary[s >> 6] = m;
 }
 
+// Pushed pressure of the binned rows recounted from a bitmap (after a change
+// of states from the host): out[h] for hub unit h = (row - hub_base) * R + r
+// is the number of infectious in-neighbours of the row in replica r, counted
+// with multiplicity.  One wavefront per row: lane l takes edge offset l / R
+// and replica l % R, and each edge pass's bits are counted per replica by a
+// ballot, as the heavy-row kernels count integer partials.
+__global__ __launch_bounds__(WG) void hub_recount_kernel(const int32_t* __restrict__ row_ptr,
+                                                         const int32_t* __restrict__ col_ind, int32_t hub_base,
+                                                         uint32_t hubs, int32_t lgR,
+                                                         const uint32_t* __restrict__ bits,
+                                                         uint32_t* __restrict__ out)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t R = 1u << lgR;
+    const uint32_t per = 64u >> lgR;
+    const uint32_t eoff = lane >> lgR;
+    const uint32_t rep = lane & (R - 1);
+    unsigned long long rmask = 1ull; // lanes of replica 0: every R-th lane
+    for (uint32_t sh = R; sh < 64u; sh <<= 1) rmask |= rmask << sh;
+    const uint32_t nw = gridDim.x * (WG / 64);
+    for (uint32_t h = blockIdx.x * (WG / 64) + (threadIdx.x >> 6); h < hubs; h += nw) {
+        const int32_t row = hub_base + (int32_t)h;
+        const int32_t e1 = row_ptr[row + 1];
+        uint32_t c = 0;
+        for (int32_t e = row_ptr[row] + (int32_t)eoff;; e += (int32_t)per) {
+            const bool in = e < e1;
+            if (__ballot(in) == 0ull) break;
+            const uint32_t b = in ? bit_at(bits, ((uint32_t)col_ind[e] << lgR) + rep) : 0u;
+            c += (uint32_t)__popcll(__ballot(b != 0u) & (rmask << rep));
+        }
+        if (lane < R) out[(size_t)h * R + lane] = c;
+    }
+}
+
 template <int STORAGE>
 __global__ __launch_bounds__(WG) void recount_kernel(const void* state_v, int32_t n, int32_t lgR,
                                                      int32_t replica, uint32_t* part)
@@ -314,6 +348,17 @@ const void* step_kernel_fn(int storage, bool weighted, int mode, int udeg, bool 
 }
 
 static unsigned grid_for(size_t n, unsigned block) { return (unsigned)((n + block - 1) / block); }
+
+hipError_t launch_hub_recount(const int32_t* row_ptr, const int32_t* col_ind, int32_t hub_base, uint32_t hubs,
+                              int32_t lgR, const uint32_t* bits, uint32_t* out, hipStream_t s)
+{
+    if (hubs == 0) return hipSuccess;
+    unsigned g = grid_for((size_t)hubs, WG / 64);
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(hub_recount_kernel, dim3(g), dim3(WG), 0, s, row_ptr, col_ind, hub_base, hubs, lgR, bits,
+                       out);
+    return hipGetLastError();
+}
 
 hipError_t launch_recount(int storage, const void* state, int32_t n, int32_t lgR, int32_t replica,
                           uint32_t* part, uint32_t max_grid, uint32_t* out4, hipStream_t s)

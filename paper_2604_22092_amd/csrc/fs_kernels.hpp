@@ -28,6 +28,11 @@ const void* heavy_kernel_fn_shed(bool weighted, bool resident);
 // of 4 in `part`) reduced into out4.
 hipError_t launch_recount(int storage, const void* state, int32_t n, int32_t lgR, int32_t replica,
                           uint32_t* part, uint32_t max_grid, uint32_t* out4, hipStream_t s);
+// Pushed pressure of the binned rows [hub_base, hub_base + hubs) from the
+// bitmap `bits`: out[(row - hub_base) * R + r] = infectious in-neighbours of
+// the row in replica r (StepArgs::hub_T).
+hipError_t launch_hub_recount(const int32_t* row_ptr, const int32_t* col_ind, int32_t hub_base, uint32_t hubs,
+                              int32_t lgR, const uint32_t* bits, uint32_t* out, hipStream_t s);
 // reduce_kernel(const Ctl*, const uint32_t* part, uint32_t G, uint32_t C, uint32_t* out, uint32_t H):
 // one block per slot, WG threads.
 const void* reduce_kernel_fn();

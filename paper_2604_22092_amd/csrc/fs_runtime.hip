@@ -254,7 +254,7 @@ void release_sim(fs_sim* s)
                         (void*)s->d_hist, (void*)s->d_part, (void*)s->d_rc_part, (void*)s->d_cnt4,
                         (void*)s->d_summary, s->d_seg_part, (void*)s->d_lam_part, (void*)s->d_dt_hist,
                         (void*)s->d_shed[0], (void*)s->d_shed[1], (void*)s->d_live, (void*)s->d_act,
-                        (void*)s->d_htab})
+                        (void*)s->d_htab, (void*)s->d_hub})
             sim_free(s, p);
     }
     s->layout.reset();
@@ -331,6 +331,8 @@ Layout::~Layout()
     dev_free(d_chunk_meta);
     dev_free(d_col_t);
     dev_free(d_w_t);
+    dev_free(d_hub_out_ptr);
+    dev_free(d_hub_out_idx);
 }
 
 // Builds the layout of graph g for R replicas (Q = 64/R nodes per chunk).
@@ -429,8 +431,36 @@ fs_status build_layout(const fs_graph* g, int32_t R, int32_t limit, int32_t seg_
         FS_HIP(dev_alloc((void**)&L->d_w_t, wt.size() * sizeof(float)));
         if (!wt.empty()) FS_HIP(hipMemcpy(L->d_w_t, wt.data(), wt.size() * sizeof(float), hipMemcpyHostToDevice));
     }
+    // pushes into binned rows (unit weights): the rows are the last nodes of
+    // the degree-sorted order; per node, the rows listing it
+    size_t hub_bytes = 0;
+    if (!segs.empty() && !weighted) {
+        int64_t hb = n;
+        while (hb > 0 && ldeg[(size_t)hb - 1] == fsi::HEAVY_ROW) --hb;
+        bool tail = true;
+        for (int64_t i = 0; i < hb && tail; ++i) tail = ldeg[(size_t)i] != fsi::HEAVY_ROW;
+        if (tail) {
+            std::vector<int32_t> optr((size_t)n + 1, 0);
+            for (int64_t i = hb; i < n; ++i)
+                for (int32_t e = rp[i]; e < rp[i + 1]; ++e) ++optr[(size_t)g->h_col_ind[e] + 1];
+            for (int64_t j = 0; j < n; ++j) optr[(size_t)j + 1] += optr[(size_t)j];
+            std::vector<int32_t> oidx((size_t)optr[(size_t)n]);
+            std::vector<int32_t> fill(optr.begin(), optr.end() - 1);
+            for (int64_t i = hb; i < n; ++i)
+                for (int32_t e = rp[i]; e < rp[i + 1]; ++e)
+                    oidx[(size_t)fill[(size_t)g->h_col_ind[e]]++] = (int32_t)(i - hb);
+            FS_HIP(dev_alloc((void**)&L->d_hub_out_ptr, optr.size() * sizeof(int32_t)));
+            FS_HIP(dev_alloc((void**)&L->d_hub_out_idx, oidx.size() * sizeof(int32_t)));
+            FS_HIP(hipMemcpy(L->d_hub_out_ptr, optr.data(), optr.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+            if (!oidx.empty())
+                FS_HIP(hipMemcpy(L->d_hub_out_idx, oidx.data(), oidx.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+            L->hub_base = (int32_t)hb;
+            L->hubs = (uint32_t)(n - hb);
+            hub_bytes = optr.size() * 4 + oidx.size() * 4;
+        }
+    }
     L->bytes = first.size() * 4 + segs.size() * sizeof(fsi::Segment) + ldeg.size() * 2 + cbase.size() * 4 +
-               cdeg.size() + colt.size() * 4 + wt.size() * 4;
+               cdeg.size() + colt.size() * 4 + wt.size() * 4 + hub_bytes;
     out = std::move(L);
     return FS_OK;
 }
@@ -465,10 +495,31 @@ size_t sim_footprint(fs_graph* g, const fs_sim_params* p)
         b += (size_t)g->nnz / 64 * 16 + (size_t)g->n * 4;   // heavy segments (upper bound)
     }
     b += (size_t)g->nnz / 64 * 4 * R;                       // heavy-segment partials (upper bound)
+    if (g->max_degree > hd && hd > 0) {
+        // pushed pressure of binned rows: at most nnz / (hd + 1) rows
+        const size_t hubs = std::min<size_t>((size_t)g->n, (size_t)g->nnz / ((size_t)hd + 1));
+        b += 5 * hubs * R * 4;
+        if (!layout_cached(g, (int32_t)R, hd, se)) b += ((size_t)g->n + 1) * 4 + (size_t)g->nnz * 4;
+    }
     if (p->record_rates) b += units * 4;
     if (p->shedding != FS_SHED_CONSTANT) b += units * 8;
     if (p->compaction) b += (units / 64 + 1) * 5 + fsi::LIVE_TILE;
     return b + ((size_t)1 << 20);
+}
+
+// Pushed pressure of the binned rows (StepArgs::hub_T) recounted from the
+// bitmap step `step` reads, with every delta slot cleared: the state the
+// steps maintain, rebuilt after a change of states from the host.
+hipError_t refresh_hubs(fs_sim* s, int64_t step)
+{
+    if (!s->hub_push) return hipSuccess;
+    const Layout& L = *s->layout;
+    const uint32_t HU = L.hubs * (uint32_t)s->R;
+    hipError_t e = fsk::launch_hub_recount(s->g->d_row_ptr, s->g->d_col_ind, L.hub_base, L.hubs, s->lgR,
+                                           (const uint32_t*)s->d_iota[step & 1],
+                                           s->d_hub + (size_t)((step - 1) & 1) * HU, s->stream);
+    if (e != hipSuccess) return e;
+    return fsk::launch_clear_u32(s->d_hub + 2 * (size_t)HU, 3 * (size_t)HU, s->stream);
 }
 
 // Points sim s at the layout of its graph for (R, heavy_deg, seg_edges),
@@ -495,6 +546,10 @@ fs_status apply_bins(fs_sim* s, int32_t heavy_deg, int32_t seg_edges)
     drop_graph_exec(s);
     sim_free(s, s->d_seg_part);
     s->d_seg_part = nullptr;
+    sim_free(s, s->d_hub);
+    s->d_hub = nullptr;
+    s->hub_push = false;
+    s->args.hub_T = s->args.hub_D = nullptr;
     s->layout = L;
     {
         std::lock_guard<std::mutex> lk(g->layout_mu);
@@ -507,7 +562,22 @@ fs_status apply_bins(fs_sim* s, int32_t heavy_deg, int32_t seg_edges)
     s->d_segs = L->d_segs;
     s->heavy_deg = heavy_deg;
     s->seg_edges = seg_edges;
-    if (s->nseg) FS_HIP(sim_alloc(s, &s->d_seg_part, (size_t)s->nseg * (size_t)s->R * sizeof(uint32_t)));
+    // binned rows of an unweighted graph with constant shedding take pushed
+    // pressure; the others (and batches of such sims) read segment partials
+    s->hub_push = L->hubs > 0 && s->d_shed[0] == nullptr;
+    if (s->nseg && !s->hub_push)
+        FS_HIP(sim_alloc(s, &s->d_seg_part, (size_t)s->nseg * (size_t)s->R * sizeof(uint32_t)));
+    if (s->hub_push) {
+        const size_t HU = (size_t)L->hubs * (size_t)s->R;
+        FS_HIP(sim_alloc(s, (void**)&s->d_hub, 5 * HU * sizeof(uint32_t)));
+        s->args.hub_T = s->d_hub;
+        s->args.hub_D = s->d_hub + 2 * HU;
+        s->args.hub_out_ptr = L->d_hub_out_ptr;
+        s->args.hub_out_idx = L->d_hub_out_idx;
+        s->args.hub_base = L->hub_base;
+        s->args.hub_units = (uint32_t)HU;
+        FS_HIP(refresh_hubs(s, s->step));
+    }
     s->args.heavy_first = L->d_heavy_first;
     s->args.seg_part = s->d_seg_part;
     s->args.heavy_deg = limit;
@@ -567,8 +637,10 @@ hipError_t refresh_derived(fs_sim* s, int64_t step)
         (e = fsk::launch_rebuild_shed(s->storage, s->d_state, s->d_age, total, s->shed, s->d_shed[step & 1],
                                       s->stream)) != hipSuccess)
         return e;
-    if (s->d_live) e = fsk::launch_chunk_live(s->storage, s->d_state, total, s->d_live, s->nchunks, s->stream);
-    return e;
+    if (s->d_live &&
+        (e = fsk::launch_chunk_live(s->storage, s->d_state, total, s->d_live, s->nchunks, s->stream)) != hipSuccess)
+        return e;
+    return refresh_hubs(s, step);
 }
 
 fsi::HeavyArgs heavy_args(const fs_sim* s)
@@ -600,7 +672,7 @@ void make_seq(fs_sim* s, uint32_t r, SeqArgs& q)
     // next refresh reads
     for (uint32_t j = 0; j + 1 < r; ++j) q.step[j].live = nullptr;
     q.heavy.clear();
-    if (s->nseg) {
+    if (s->nseg && !s->hub_push) {
         q.heavy.assign(r, heavy_args(s));
         for (uint32_t j = 0; j < r; ++j) q.heavy[j].step_off = j;
     }
@@ -656,7 +728,7 @@ fs_status build_graph_exec(fs_sim* s, int b)
         if ((st = add(fsk::compact_refresh_kernel_fn(), dim3(1), dim3(fsi::WG_REFRESH), fargv)) != FS_OK) return st;
     }
     for (int j = 0; j < b; ++j) {
-        if (s->nseg) {
+        if (!q.heavy.empty()) {
             void* hargv[] = {&q.heavy[j]};
             if ((st = add(s->hfn, dim3(sim_heavy_grid(s)), dim3(sim_heavy_block(s)), hargv)) != FS_OK) return st;
         }
@@ -689,7 +761,7 @@ fs_status launch_sequence(fs_sim* s, uint32_t r)
         FS_HIP(hipLaunchKernel(fsk::compact_refresh_kernel_fn(), dim3(1), dim3(fsi::WG_REFRESH), fargv, 0, s->stream));
     }
     for (uint32_t j = 0; j < r; ++j) {
-        if (s->nseg) {
+        if (!q.heavy.empty()) {
             void* hargv[] = {&q.heavy[j]};
             FS_HIP(hipLaunchKernel(s->hfn, dim3(sim_heavy_grid(s)), dim3(sim_heavy_block(s)), hargv, 0, s->stream));
         }
@@ -730,6 +802,268 @@ fs_status seed_staged(fs_sim* s, int32_t replica, const int64_t* d_nodes, int64_
     FS_HIP(refresh_derived(s, s->step));
     FS_HIP(refresh_summary(s));
     FS_HIP(hipStreamSynchronize(s->stream));
+    return FS_OK;
+}
+
+// Switches sim s to another step variant (mode): workgroup shape and
+// count, count partials, the summary buffer and the kernels.  Adaptive sims
+// only move between the LDS variants, which share the workgroup count, so
+// the per-workgroup rate maxima the next step folds keep their meaning.
+fs_status apply_variant(fs_sim* s, int mode)
+{
+    if (mode == s->mode) return FS_OK;
+    const size_t units = (size_t)s->g->n * (size_t)s->R;
+    if (mode == fsi::MODE_RESIDENT && units > fsi::RESIDENT_BITS)
+        return fail(FS_ERR_INVALID_ARG, "the resident variant holds at most 2^20 units");
+    if (mode == fsi::MODE_STREAM && s->p.adaptive) return fail(FS_ERR_INVALID_ARG, "adaptive sims keep an LDS variant");
+    const uint32_t tpb = mode == fsi::MODE_STREAM ? fsi::STREAM_TPB : fsi::RESIDENT_TPB;
+    const size_t chunks = (units + 63) / 64;
+    const size_t tiles = (chunks + tpb / 64 - 1) / (tpb / 64);
+    uint32_t G;
+    if (mode != fsi::MODE_STREAM) {
+        int cus = 0;
+        FS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device));
+        s->cus = (uint32_t)std::max(cus, 1);
+        G = (uint32_t)std::min<size_t>(tiles, s->cus);
+    } else {
+        G = (uint32_t)std::min<size_t>(tiles, fsi::max_step_grid(s->R));
+    }
+    drop_graph_exec(s);
+    if (G != s->G) {
+        // count partials are written and reduced within one launch sequence:
+        // nothing of them outlives it
+        sim_free(s, s->d_part);
+        s->d_part = nullptr;
+        FS_HIP(sim_alloc(s, (void**)&s->d_part, (size_t)s->chunk * G * (size_t)s->R * 4 * sizeof(uint32_t)));
+    }
+    if (mode == fsi::MODE_SUMMARY && !s->d_summary)
+        FS_HIP(sim_alloc(s, (void**)&s->d_summary, ((size_t)s->sum_bits + 511) / 512 * 64));
+    s->mode = mode;
+    s->tpb = tpb;
+    s->G = G;
+    s->args.part = s->d_part;
+    s->args.summary = (const uint32_t*)s->d_summary;
+    const bool weighted = s->g->d_weights != nullptr, shed = s->d_shed[0] != nullptr;
+    s->kfn = fsk::step_kernel_fn(s->storage, weighted, mode, s->layout ? s->layout->udeg : -1, shed,
+                                 s->d_rates != nullptr || s->d_act != nullptr);
+    s->hfn = fsk::heavy_kernel_fn(weighted, shed, mode == fsi::MODE_RESIDENT);
+    if (!s->kfn || !s->hfn) return fail(FS_ERR_DEVICE, "no step kernel for this configuration");
+    FS_HIP(refresh_summary(s));
+    return FS_OK;
+}
+
+// FNV-1a over a run's signature: what the fastest configuration depends on.
+struct Fnv {
+    uint64_t h = 1469598103934665603ull;
+    void add(const void* p, size_t n)
+    {
+        const unsigned char* b = (const unsigned char*)p;
+        for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    }
+    template <class T>
+    void put(T v) { add(&v, sizeof v); }
+};
+
+uint64_t tune_signature(const fs_sim* s)
+{
+    const fs_graph* g = s->g;
+    Fnv f;
+    const char* ver = "flashspread-tune-1";
+    f.add(ver, std::strlen(ver));
+    int cus = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device);
+    f.put<int32_t>(cus);
+    f.put<int64_t>(g->n);
+    f.put<int64_t>(g->nnz);
+    f.put<int32_t>(s->R);
+    f.put<int32_t>(s->storage);
+    f.put<int32_t>(g->d_weights != nullptr);
+    f.put<int32_t>(s->p.shedding);
+    f.put<int32_t>(s->p.adaptive != 0);
+    f.put<int32_t>(s->d_act != nullptr);
+    f.put<int32_t>(s->d_rates != nullptr);
+    // degree histogram: (degree, count) for every degree present
+    std::vector<int64_t> hist((size_t)g->max_degree + 1, 0);
+    for (int64_t i = 0; i < g->n; ++i) ++hist[(size_t)(g->h_row_ptr[(size_t)i + 1] - g->h_row_ptr[(size_t)i])];
+    for (size_t d = 0; d < hist.size(); ++d)
+        if (hist[d]) {
+            f.put<int64_t>((int64_t)d);
+            f.put<int64_t>(hist[d]);
+        }
+    return f.h;
+}
+
+// A cached choice: the last line of the file with this signature.
+bool cache_lookup(const char* path, uint64_t sig, int* mode, int32_t* hd, int32_t* se)
+{
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[256];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        unsigned long long k = 0;
+        int v = 0, h = 0, c = 0;
+        if (std::sscanf(line, "%llx variant=%d heavy_degree=%d segment_edges=%d", &k, &v, &h, &c) == 4 && k == sig &&
+            v >= 1 && v <= 3 && h >= -1 && c >= 64 && c <= (1 << 20)) {
+            *mode = v - 1;
+            *hd = h;
+            *se = c;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+fs_status cache_store(const char* path, uint64_t sig, int mode, int32_t hd, int32_t se, double us)
+{
+    FILE* f = std::fopen(path, "a");
+    if (!f) return fail(FS_ERR_INVALID_ARG, std::string("cannot append to the tune cache ") + path);
+    std::fprintf(f, "%016llx variant=%d heavy_degree=%d segment_edges=%d us_per_step=%.3f\n",
+                 (unsigned long long)sig, mode + 1, hd, se, us);
+    const bool ok = std::fclose(f) == 0;
+    return ok ? FS_OK : fail(FS_ERR_INVALID_ARG, std::string("cannot write the tune cache ") + path);
+}
+
+fs_status autotune(fs_sim* s, const fs_tune_params& tp, fs_tune_result* out)
+{
+    if (!s) return fail(FS_ERR_INVALID_ARG, "sim is NULL");
+    if (s->batch) return fail(FS_ERR_BUSY, "sim belongs to a batch");
+    const int32_t trial_steps = tp.trial_steps;
+    if (trial_steps < 1 || trial_steps > 4096) return fail(FS_ERR_INVALID_ARG, "trial_steps must be in [1, 4096]");
+    DeviceGuard dg(s->device);
+    *out = fs_tune_result{};
+    out->signature = tune_signature(s);
+    if (tp.cache_path) {
+        int mode = 0;
+        int32_t hd = 0, se = 0;
+        if (cache_lookup(tp.cache_path, out->signature, &mode, &hd, &se) && (tp.variants || mode == s->mode)) {
+            FS_HIP(hipStreamSynchronize(s->stream));
+            fs_status st = apply_variant(s, mode);
+            if (st == FS_OK) st = apply_bins(s, hd, se);
+            if (st != FS_OK) return st;
+            FS_HIP(hipStreamSynchronize(s->stream));
+            out->variant = s->mode + 1;
+            out->heavy_degree = s->heavy_deg;
+            out->segment_edges = s->seg_edges;
+            out->from_cache = 1;
+            return FS_OK;
+        }
+    }
+    FS_HIP(hipStreamSynchronize(s->stream));
+    const size_t units = (size_t)s->g->n * s->R;
+    // snapshot everything a step changes (cf. Algorithm 2: snapshot, warm up, restore)
+    struct Buf {
+        void* live;
+        size_t bytes;
+        DevBuf copy;
+    };
+    Buf bufs[] = {{s->d_state, units * state_bytes(s->storage), {}},
+                  {s->d_age, units * age_bytes(s->storage), {}},
+                  {s->d_iota[0], (size_t)s->bit_words * 8, {}},
+                  {s->d_iota[1], (size_t)s->bit_words * 8, {}},
+                  {s->d_ctl, sizeof(fsi::Ctl), {}},
+                  {s->d_hist, (size_t)s->H * s->R * 4 * sizeof(uint32_t), {}},
+                  {s->d_lam_part, 2 * (size_t)s->G * sizeof(float), {}},
+                  {s->d_shed[0], (size_t)s->g->n * s->R * sizeof(float), {}},
+                  {s->d_shed[1], (size_t)s->g->n * s->R * sizeof(float), {}},
+                  {s->d_live, s->live_bytes, {}},
+                  {s->d_act, (2 + (size_t)s->nchunks) * sizeof(uint32_t), {}},
+                  {s->d_dt_hist, (size_t)s->H * sizeof(float), {}}};
+    for (auto& b : bufs) {
+        if (!b.live) continue;
+        FS_HIP(dev_alloc(&b.copy.p, b.bytes));
+        FS_HIP(hipMemcpyAsync(b.copy.p, b.live, b.bytes, hipMemcpyDeviceToDevice, s->stream));
+    }
+    // candidates: the entry configuration first, then the other variants and bins
+    std::vector<int> modes{s->mode};
+    if (tp.variants) {
+        for (int m : {fsi::MODE_RESIDENT, fsi::MODE_SUMMARY, fsi::MODE_STREAM}) {
+            if (m == s->mode) continue;
+            if (m == fsi::MODE_RESIDENT && units > fsi::RESIDENT_BITS) continue;
+            if (m == fsi::MODE_STREAM && s->p.adaptive) continue;
+            modes.push_back(m);
+        }
+    }
+    const bool pushed = s->g->d_weights == nullptr && s->d_shed[0] == nullptr;
+    std::vector<std::pair<int32_t, int32_t>> bins{{s->heavy_deg, s->seg_edges}};
+    auto add_bins = [&](int32_t t, int32_t c) {
+        if (std::find(bins.begin(), bins.end(), std::make_pair(t, c)) == bins.end()) bins.push_back({t, c});
+    };
+    // (thresholds at or above the largest degree bin nothing: the same run as
+    // no bins, which is a candidate when the entry bins any row)
+    if (s->nseg) add_bins(-1, 512);
+    for (int32_t t : {8, 12, 16, 24, 32, 64, 128, 256}) {
+        if (t >= s->g->max_degree) continue;
+        if (pushed) add_bins(t, s->seg_edges); // pushed rows read no segments
+        else
+            for (int32_t c : {256, 1024}) add_bins(t, c);
+    }
+    hipEvent_t e0, e1;
+    FS_HIP(hipEventCreate(&e0));
+    FS_HIP(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    int best_mode = s->mode;
+    std::pair<int32_t, int32_t> best = bins[0];
+    fs_status st = FS_OK;
+    int trials = 0;
+    for (int m : modes) {
+        if (st != FS_OK) break;
+        if ((st = apply_variant(s, m)) != FS_OK) break;
+        for (const auto& c : bins) {
+            if ((st = apply_bins(s, c.first, c.second)) != FS_OK) break;
+            // (the summary of the restored bitmap)
+            if (refresh_summary(s) != hipSuccess) { st = fail(FS_ERR_DEVICE, "summary"); break; }
+            // one untimed warm-up step, then the timed trial, then restore
+            uint32_t done = 0;
+            if ((st = launch_sequence(s, 1)) != FS_OK) break;
+            if (hipEventRecord(e0, s->stream) != hipSuccess) { st = fail(FS_ERR_DEVICE, "event"); break; }
+            while (done < (uint32_t)trial_steps && st == FS_OK) {
+                const uint32_t r = std::min<uint32_t>(s->chunk, (uint32_t)trial_steps - done);
+                st = launch_sequence(s, r);
+                done += r;
+            }
+            if (st != FS_OK) break;
+            float ms = 0.0f;
+            if (hipEventRecord(e1, s->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                st = fail(FS_ERR_DEVICE, "event timing");
+                break;
+            }
+            if (trials == 0) out->entry_us_per_step = 1e3 * ms / trial_steps;
+            ++trials;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_mode = m;
+                best = c;
+            }
+            for (auto& b : bufs)
+                if (b.live && hipMemcpyAsync(b.live, b.copy.p, b.bytes, hipMemcpyDeviceToDevice, s->stream) != hipSuccess) {
+                    st = fail(FS_ERR_DEVICE, "restore");
+                    break;
+                }
+            if (st != FS_OK) break;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (auto& b : bufs)
+        if (b.live) (void)hipMemcpyAsync(b.live, b.copy.p, b.bytes, hipMemcpyDeviceToDevice, s->stream);
+    FS_HIP(hipStreamSynchronize(s->stream));
+    if (st != FS_OK) return st;
+    // the choice, on the restored state (bins recount pushed pressure, the
+    // summary is rebuilt from the restored bitmap)
+    if ((st = apply_variant(s, best_mode)) != FS_OK) return st;
+    if ((st = apply_bins(s, best.first, best.second)) != FS_OK) return st;
+    FS_HIP(refresh_summary(s));
+    FS_HIP(hipStreamSynchronize(s->stream));
+    out->variant = s->mode + 1;
+    out->heavy_degree = s->heavy_deg;
+    out->segment_edges = s->seg_edges;
+    out->trials = trials;
+    out->us_per_step = 1e3 * best_ms / trial_steps;
+    if (tp.cache_path)
+        return cache_store(tp.cache_path, out->signature, s->mode, s->heavy_deg, s->seg_edges, out->us_per_step);
     return FS_OK;
 }
 
@@ -1461,86 +1795,30 @@ fs_status fs_sim_get_bins(fs_sim* s, int32_t* heavy_degree, int32_t* segment_edg
 fs_status fs_sim_tune(fs_sim* s, int32_t trial_steps, int32_t* heavy_degree, int32_t* segment_edges)
 {
     FS_GUARD_BEGIN
-    if (!s) return fail(FS_ERR_INVALID_ARG, "sim is NULL");
-    if (s->batch) return fail(FS_ERR_BUSY, "sim belongs to a batch");
-    if (trial_steps < 1 || trial_steps > 4096) return fail(FS_ERR_INVALID_ARG, "trial_steps must be in [1, 4096]");
-    DeviceGuard dg(s->device);
-    FS_HIP(hipStreamSynchronize(s->stream));
-    const size_t units = (size_t)s->g->n * s->R;
-    // snapshot everything a step changes (cf. Algorithm 2: snapshot, warm up, restore)
-    struct Buf {
-        void* live;
-        size_t bytes;
-        DevBuf copy;
-    };
-    Buf bufs[] = {{s->d_state, units * state_bytes(s->storage), {}},
-                  {s->d_age, units * age_bytes(s->storage), {}},
-                  {s->d_iota[0], (size_t)s->bit_words * 8, {}},
-                  {s->d_iota[1], (size_t)s->bit_words * 8, {}},
-                  {s->d_ctl, sizeof(fsi::Ctl), {}},
-                  {s->d_hist, (size_t)s->H * s->R * 4 * sizeof(uint32_t), {}},
-                  {s->d_summary, s->d_summary ? ((size_t)s->sum_bits + 511) / 512 * 64 : 0, {}},
-                  {s->d_lam_part, 2 * (size_t)s->G * sizeof(float), {}},
-                  {s->d_shed[0], (size_t)s->g->n * s->R * sizeof(float), {}},
-                  {s->d_shed[1], (size_t)s->g->n * s->R * sizeof(float), {}},
-                  {s->d_live, s->live_bytes, {}},
-                  {s->d_act, (2 + (size_t)s->nchunks) * sizeof(uint32_t), {}},
-                  {s->d_dt_hist, (size_t)s->H * sizeof(float), {}}};
-    for (auto& b : bufs) {
-        if (!b.live) continue;
-        FS_HIP(dev_alloc(&b.copy.p, b.bytes));
-        FS_HIP(hipMemcpyAsync(b.copy.p, b.live, b.bytes, hipMemcpyDeviceToDevice, s->stream));
-    }
-    std::vector<std::pair<int32_t, int32_t>> cands;
-    cands.push_back({-1, 512});
-    for (int32_t t : {16, 32, 64, 128, 256})
-        if (t < s->g->max_degree)
-            for (int32_t c : {256, 1024}) cands.push_back({t, c});
-    hipEvent_t e0, e1;
-    FS_HIP(hipEventCreate(&e0));
-    FS_HIP(hipEventCreate(&e1));
-    float best_ms = 1e30f;
-    std::pair<int32_t, int32_t> best = {s->heavy_deg, s->seg_edges};
-    fs_status st = FS_OK;
-    for (const auto& c : cands) {
-        if ((st = apply_bins(s, c.first, c.second)) != FS_OK) break;
-        // one untimed warm-up step, then the timed trial, then restore
-        uint32_t done = 0;
-        if ((st = launch_sequence(s, 1)) != FS_OK) break;
-        if (hipEventRecord(e0, s->stream) != hipSuccess) { st = fail(FS_ERR_DEVICE, "event"); break; }
-        while (done < (uint32_t)trial_steps && st == FS_OK) {
-            const uint32_t r = std::min<uint32_t>(s->chunk, (uint32_t)trial_steps - done);
-            st = launch_sequence(s, r);
-            done += r;
-        }
-        if (st != FS_OK) break;
-        float ms = 0.0f;
-        if (hipEventRecord(e1, s->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-            st = fail(FS_ERR_DEVICE, "event timing");
-            break;
-        }
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = c;
-        }
-        for (auto& b : bufs)
-            if (b.live && hipMemcpyAsync(b.live, b.copy.p, b.bytes, hipMemcpyDeviceToDevice, s->stream) != hipSuccess) {
-                st = fail(FS_ERR_DEVICE, "restore");
-                break;
-            }
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    for (auto& b : bufs)
-        if (b.live) (void)hipMemcpyAsync(b.live, b.copy.p, b.bytes, hipMemcpyDeviceToDevice, s->stream);
-    FS_HIP(hipStreamSynchronize(s->stream));
+    fs_tune_params p{};
+    p.trial_steps = trial_steps;
+    fs_tune_result r{};
+    fs_status st = autotune(s, p, &r);
     if (st != FS_OK) return st;
-    if ((st = apply_bins(s, best.first, best.second)) != FS_OK) return st;
-    if (heavy_degree) *heavy_degree = best.first;
-    if (segment_edges) *segment_edges = best.second;
+    if (heavy_degree) *heavy_degree = r.heavy_degree;
+    if (segment_edges) *segment_edges = r.segment_edges;
     return FS_OK;
     FS_GUARD_END
+}
+
+fs_status fs_sim_autotune(fs_sim* s, const fs_tune_params* p, fs_tune_result* out)
+{
+    FS_GUARD_BEGIN
+    if (!p || !out) return fail(FS_ERR_INVALID_ARG, "NULL argument");
+    return autotune(s, *p, out);
+    FS_GUARD_END
+}
+
+fs_status fs_sim_get_variant(fs_sim* s, int32_t* variant)
+{
+    if (!s || !variant) return fail(FS_ERR_INVALID_ARG, "NULL argument");
+    *variant = s->mode + 1;
+    return FS_OK;
 }
 
 fs_status fs_eval_hazard(const fs_dist* law, int32_t storage, double dt, int64_t n, const void* ages, float* out)

@@ -38,6 +38,13 @@ struct Layout {
     uint2* d_chunk_meta = nullptr;    // per chunk: (first slot in col_t, shared degree or 255)
     int32_t* d_col_t = nullptr;
     float* d_w_t = nullptr;
+    // binned rows, which are the internal nodes [hub_base, n), for pushes
+    // (unweighted graphs): per node j the hub indices of the binned rows
+    // listing j, hub_out_idx[hub_out_ptr[j] .. hub_out_ptr[j + 1])
+    int32_t hub_base = 0;
+    uint32_t hubs = 0;                // 0: no pushes (weighted graph or no binned row)
+    int32_t* d_hub_out_ptr = nullptr;
+    int32_t* d_hub_out_idx = nullptr;
     size_t bytes = 0;
     ~Layout();
 };
@@ -119,6 +126,8 @@ struct fs_sim {
     uint32_t nseg = 0;
     std::shared_ptr<fsr::Layout> layout; // shared with the graph's other sims
     void* d_seg_part = nullptr;          // this sim's heavy-segment partials [segment][R]
+    bool hub_push = false;               // binned rows take pushed pressure (StepArgs::hub_T)
+    uint32_t* d_hub = nullptr;           // hub_T [2][hub units] then hub_D [3][hub units]
     fsi::Segment* d_segs = nullptr;      // = layout->d_segs
     const void* hfn = nullptr;
     hipGraph_t graph = nullptr;

@@ -178,7 +178,81 @@ struct Pass {
     uint32_t xr[CU], agw[CU], dgr[CU], org[CU];
     int32_t c[CU][UMAX];
     float tab[CU][3]; // hazard-table entry of the lane's age (issue_table)
+    uint32_t ht[CU], hd[CU]; // pushed pressure of a binned unit: count of the last step, delta
 };
+
+// Pushed pressure of binned rows (StepArgs::hub_T) within one step launch:
+// the slots of this step (offsets in units of the hub arrays), and the
+// wavefront's queue of units that enter or leave I, whose pushes are made
+// after its walk (so no dependent load waits inside a pass, where it would
+// also wait for the next pass's prefetched loads).
+constexpr uint32_t PUSHQ = 128;
+struct HubCtx {
+    bool on;
+    rsrc_t tr, dr;
+    uint32_t t_prev, t_cur, d_cur, d_clr, d_next; // element offsets of the slots
+    uint32_t* q;   // LDS queue: unit | (0x80000000 when leaving I), PUSHQ entries
+    uint32_t* pb;  // LDS: 64 list starts (flush)
+    uint32_t* px;  // LDS: 64 exclusive prefix sums (flush)
+    uint32_t n;    // queued entries (wave-uniform)
+};
+
+// The pushes of the queued units: +1 (entering I) or -1 (leaving I) into the
+// next step's delta of every binned row listing the unit's node, once per
+// occurrence.  The lists of up to 64 queued units are flattened over the
+// wavefront: lane l takes list entry f = f0 + l, finds its unit by a binary
+// search of the lists' prefix sums, and adds to the row it names.
+__device__ __forceinline__ void flush_pushes(const StepArgs& a, HubCtx& H, uint32_t lane)
+{
+    // (the queue was written by other lanes of this wavefront)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (uint32_t i0 = 0; i0 < H.n; i0 += 64) {
+        const uint32_t m = min(64u, H.n - i0);
+        const bool has = lane < m;
+        const uint32_t e = has ? H.q[i0 + lane] : 0u;
+        const uint32_t node = (e & 0x7FFFFFFFu) >> a.lgR;
+        const uint32_t b = has ? (uint32_t)a.hub_out_ptr[node] : 0u;
+        const uint32_t len = has ? (uint32_t)a.hub_out_ptr[node + 1] - b : 0u;
+        // inclusive prefix sum of the list lengths over the wavefront
+        uint32_t inc = len;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t v = __shfl_up(inc, off, 64);
+            if (lane >= (uint32_t)off) inc += v;
+        }
+        const uint32_t total = __shfl(inc, 63, 64);
+        H.px[lane] = has ? inc - len : total;
+        H.pb[lane] = b;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (uint32_t f0 = 0; f0 < total; f0 += 64) {
+            const uint32_t f = f0 + lane;
+            if (f < total) {
+                // the last list whose prefix is <= f (lists of length 0 share
+                // their prefix with the next one, which is then taken)
+                uint32_t lo = 0, hi = 64;
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (H.px[mid] <= f) lo = mid;
+                    else hi = mid;
+                }
+                const uint32_t eo = H.q[i0 + lo];
+                const uint32_t row = (uint32_t)a.hub_out_idx[H.pb[lo] + (f - H.px[lo])];
+                const uint32_t rep = (eo & 0x7FFFFFFFu) & ((1u << a.lgR) - 1u);
+                __hip_atomic_fetch_add(a.hub_D + H.d_next + (row << a.lgR) + rep,
+                                       (eo & 0x80000000u) ? 0xFFFFFFFFu : 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    H.n = 0;
+}
 
 // Hazard-table loads of a pass's E/I lanes (StepArgs::htab), issued once its
 // state and age have arrived and before the next pass's loads, so that
@@ -229,7 +303,7 @@ struct Ahead {
 template <int STORAGE, int UD, bool EXTRA, class age_t>
 __device__ __forceinline__ void issue_pass(const StepArgs& a, uint32_t first, uint32_t nwaves, uint32_t stride,
                                            uint32_t nchunks, uint32_t walk, uint32_t total, uint32_t lane,
-                                           Pass<age_t>& P, Ahead& ah)
+                                           Pass<age_t>& P, Ahead& ah, const HubCtx& H)
 {
     constexpr bool UNIFORM = UD != 0;
     constexpr int DEPTH = UNIFORM ? UD : UMAX;
@@ -276,6 +350,14 @@ __device__ __forceinline__ void issue_pass(const StepArgs& a, uint32_t first, ui
         // graphs in a degree-sorted order (never uniform ones) key the draws
         // by the caller's node id
         P.org[u] = UNIFORM ? n0 + q : ld32(make_rsrc(a.orig_id + n0, nrows * 4u), q << 2);
+        // binned rows with pushed pressure are the nodes from hub_base on:
+        // their last count and this step's delta come with the pass
+        if (!UNIFORM && H.on) {
+            const bool hub = lane < P.nvalid[u] && n0 + q >= (uint32_t)a.hub_base;
+            const uint32_t h = hub ? u0 + lane - ((uint32_t)a.hub_base << a.lgR) : 0u;
+            P.ht[u] = ld32(H.tr, hub ? (H.t_prev + h) << 2 : OOB);
+            P.hd[u] = ld32(H.dr, hub ? (H.d_cur + h) << 2 : OOB);
+        }
         // every uniform chunk preloads its first UMAX slots (slots past its
         // degree are out of range)
         const bool pre = P.ud[u] != MIXED_CHUNK;
@@ -511,7 +593,7 @@ __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t
                                              uint32_t* xch, unsigned long long k,
                                              unsigned long long* __restrict__ bits_out, uint32_t* s_cnt,
                                              uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, float dt,
-                                             float& lmax)
+                                             float& lmax, HubCtx& H)
 {
     constexpr bool UNIFORM = UD != 0;
     using state_t = typename Store<STORAGE>::state_t;
@@ -541,8 +623,20 @@ __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t
         const float p =
             pressure_row<MODE, WEIGHTED, UD, SHED>(a, P, u, want, dg[u], s_bits, gbits, shedr, sv, lane);
         if (want) lam[u] = a.beta * p;
-        if (!UNIFORM && heavy && x[u] == ST_S)
+        if (!UNIFORM && !WEIGHTED && !SHED && H.on) {
+            // pushed pressure: every binned unit, whatever its state, carries
+            // its count into this step's slot and clears the delta slot that
+            // the next step's pushes do not use
+            if (__ballot(heavy) != 0ull) {
+                const uint32_t h = heavy ? unit[u] - ((uint32_t)a.hub_base << a.lgR) : 0u;
+                const uint32_t pp = P.ht[u] + P.hd[u];
+                st32(H.tr, heavy ? (H.t_cur + h) << 2 : OOB, pp);
+                st32(H.dr, heavy ? (H.d_clr + h) << 2 : OOB, 0u);
+                if (heavy && x[u] == ST_S) lam[u] = a.beta * (float)pp;
+            }
+        } else if (!UNIFORM && heavy && x[u] == ST_S) {
             lam[u] = a.beta * pressure_heavy<WEIGHTED || SHED>(a, unit[u] >> a.lgR, unit[u] & (R - 1));
+        }
     }
 
     // hazards of the E/I units of the pass, on compacted lanes; the payload
@@ -615,6 +709,20 @@ __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t
                            fire[u] ? lane : OOB_ELEM, (uint32_t)xn);
         BufIO<age_t>::st(make_rsrc((age_t*)a.age + u0, P.nvalid[u] * sizeof(age_t)), lane, age_to_raw(ans[u]));
         lmax = fmaxf(lmax, lam[u]);
+        if (!UNIFORM && !WEIGHTED && !SHED && H.on) {
+            // a unit entering or leaving I is queued for its pushes into the
+            // next step's deltas of the binned rows that list its node
+            const bool push = fire[u] && (x[u] == ST_E || x[u] == ST_I);
+            const unsigned long long pm = __ballot(push);
+            if (pm != 0ull) {
+                const uint32_t cnt = (uint32_t)__popcll(pm);
+                if (H.n + cnt > PUSHQ) flush_pushes(a, H, lane);
+                if (push)
+                    H.q[H.n + (uint32_t)__popcll(pm & ((1ull << lane) - 1ull))] =
+                        unit[u] | (x[u] == ST_I ? 0x80000000u : 0u);
+                H.n += cnt;
+            }
+        }
         // the rates, when recorded (EXTRA kernels)
         if (EXTRA && a.rates) st32(make_rsrc(a.rates + u0, P.nvalid[u] * 4u), lane << 2, __float_as_uint(lam[u]));
         // 7. next-step infectivity bits (one 64-bit word per chunk, written by
@@ -686,6 +794,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
     __shared__ __attribute__((aligned(16))) uint32_t s_bits[USE_LDS ? RESIDENT_BITS / 32 : 4];
     static_assert(SUMMARY_BITS <= RESIDENT_BITS, "the summary shares the LDS bitmap array");
     __shared__ uint32_t s_xch[NW][64];
+    // pushed pressure of binned rows: per-wavefront push queue and flush tables
+    constexpr bool HUBS = !UNIFORM && !WEIGHTED && !SHED;
+    __shared__ uint32_t s_pq[HUBS ? NW : 1][HUBS ? PUSHQ : 1];
+    __shared__ uint32_t s_pb[HUBS ? NW : 1][HUBS ? 64 : 1];
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63;
@@ -716,6 +828,26 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
     float lmax = 0.0f;
     const uint32_t wave_id = block * NW + wave;
     const uint32_t nwaves = nblocks * NW;
+    HubCtx H;
+    H.on = HUBS && a.hub_T != nullptr;
+    H.n = 0;
+    H.q = s_pq[HUBS ? wave : 0];
+    H.pb = s_pb[HUBS ? wave : 0];
+    H.px = s_xch[wave];
+    H.t_prev = H.t_cur = H.d_cur = H.d_clr = H.d_next = 0;
+    if (H.on) {
+        const uint32_t HU = a.hub_units;
+        const uint32_t k2 = (uint32_t)(k & 1ull), k3 = (uint32_t)(k % 3ull);
+        H.tr = make_rsrc(a.hub_T, 2u * HU * 4u);
+        H.dr = make_rsrc(a.hub_D, 3u * HU * 4u);
+        H.t_prev = (k2 ^ 1u) * HU;
+        H.t_cur = k2 * HU;
+        H.d_cur = k3 * HU;
+        H.d_next = ((k3 + 1u) % 3u) * HU;
+        H.d_clr = ((k3 + 2u) % 3u) * HU;
+    } else {
+        H.tr = H.dr = make_rsrc(nullptr, 0u);
+    }
 
     // first pass loads, then the bitmap fill, then one wait for both
     Pass<age_t> P;
@@ -734,7 +866,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
             ahead.my[u] = m[1];
         }
     }
-    issue_pass<STORAGE, UD, EXTRA>(a, first, nwaves, stride, nchunks, walk, total, lane, P, ahead);
+    issue_pass<STORAGE, UD, EXTRA>(a, first, nwaves, stride, nchunks, walk, total, lane, P, ahead, H);
     if (R > 1)
         for (uint32_t i = tid; i < 4 * R; i += TPB) s_cnt[i] = 0;
     if (USE_LDS) {
@@ -768,27 +900,31 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
         if (SPLIT) shed_pre<UD>(a, P, lane, s_bits, shedr, sv);
         if (PREFETCH)
             issue_pass<STORAGE, UD, EXTRA>(a, first + stride, nwaves, stride, nchunks, walk, total, lane, P1,
-                                                ahead);
+                                                ahead, H);
         process_pass<STORAGE, WEIGHTED, MODE, UD, SHED, EXTRA>(a, P, lane, s_bits, gbits, shedr, shed_out, sv,
                                                                     s_xch[wave], k, bits_out, s_cnt, c0, c1, c2,
-                                                                    c3, dt, lmax);
+                                                                    c3, dt, lmax, H);
         first += stride;
         if (first >= walk) break;
         if (!PREFETCH)
-            issue_pass<STORAGE, UD, EXTRA>(a, first, nwaves, stride, nchunks, walk, total, lane, P1, ahead);
+            issue_pass<STORAGE, UD, EXTRA>(a, first, nwaves, stride, nchunks, walk, total, lane, P1, ahead, H);
         issue_table<UNIFORM>(a, P1, lane);
         if (SPLIT) shed_pre<UD>(a, P1, lane, s_bits, shedr, sv);
         if (PREFETCH)
             issue_pass<STORAGE, UD, EXTRA>(a, first + stride, nwaves, stride, nchunks, walk, total, lane, P,
-                                                ahead);
+                                                ahead, H);
         process_pass<STORAGE, WEIGHTED, MODE, UD, SHED, EXTRA>(a, P1, lane, s_bits, gbits, shedr, shed_out, sv,
                                                                     s_xch[wave], k, bits_out, s_cnt, c0, c1, c2,
-                                                                    c3, dt, lmax);
+                                                                    c3, dt, lmax, H);
         first += stride;
         if (!PREFETCH && first < walk)
-            issue_pass<STORAGE, UD, EXTRA>(a, first, nwaves, stride, nchunks, walk, total, lane, P, ahead);
+            issue_pass<STORAGE, UD, EXTRA>(a, first, nwaves, stride, nchunks, walk, total, lane, P, ahead, H);
         if (first < walk) issue_table<UNIFORM>(a, P, lane);
     }
+
+    // the queued pushes of binned rows, after the walk (no prefetched load is
+    // in flight any more)
+    if (H.on && H.n > 0) flush_pushes(a, H, lane);
 
     // one plain store of this workgroup's counts; the reduce kernel sums them
     // (workgroup 0 also counts the R units of the chunks compaction skipped)

@@ -70,6 +70,8 @@ def test_null_handles_rejected():
     assert L.fs_graph_destroy(None) == 1
     assert L.fs_counts(None, 0, None) == 1
     assert L.fs_sim_seed_noalloc(None, 0, 0, None, 1) == 1
+    assert L.fs_sim_autotune(None, None, None) == 1
+    assert L.fs_sim_get_variant(None, None) == 1
 
 
 def test_seed_noalloc_limit_matches_the_header():
@@ -138,7 +140,8 @@ def test_struct_layouts_match_the_header(tmp_path):
         pytest.skip("no C compiler")
     structs = {"fs_dist": fs.fs_dist, "fs_sim_params": fs.fs_sim_params,
                "fs_server_params": fs.fs_server_params, "fs_request": fs.fs_request,
-               "fs_request_info": fs.fs_request_info, "fs_markov_params": fs.fs_markov_params}
+               "fs_request_info": fs.fs_request_info, "fs_markov_params": fs.fs_markov_params,
+               "fs_tune_params": fs.fs_tune_params, "fs_tune_result": fs.fs_tune_result}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fs.h"', 'int main(void) {']
     for name, cls in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')

@@ -632,6 +632,47 @@ def test_degree_bins_weighted_one_step():
     check_one_step({"state": gst, "age": gage, "rates": rates}, ora, st, "weighted bins")
 
 
+@pytest.mark.parametrize("variant", list(VARIANTS))
+@pytest.mark.parametrize("replicas", [1, 4])
+def test_pushed_hub_pressure_equals_gathered(variant, replicas):
+    # Binned rows of an unweighted graph keep their pressure up to date by
+    # pushes from the units entering and leaving I; the same graph with every
+    # weight 1.0 gathers it from segment partials every step.  Both are the
+    # exact integer count of infectious in-neighbours, so the trajectories are
+    # identical, through a mid-run state load, a change of bins and a graph
+    # replay / eager mix, and equal the oracle's.
+    n = 20_000
+    rp, ci = W.barabasi_albert(n, 5, 13)
+    model = W.WORKLOADS["ba5_n1e6"]["model"]
+    seeds = W.seed_nodes(n, 40, 8)
+    ones = np.ones(len(ci), np.float32)
+    outs = []
+    for w in (None, ones):
+        with fs.Graph(rp, ci, w) as g:
+            sim = fs.Sim.from_model(g, model, steps_per_graph=20, replicas=replicas,
+                                    variant=VARIANTS[variant], heavy_degree=12, segment_edges=64)
+            sim.seed(seeds, replica=-1)
+            sim.step(47)
+            # a state load of replica 0 at a later step index (the pushed counts
+            # are rebuilt from the loaded bitmap)
+            st, age, _ = sim.get_state(0)
+            st = st.copy()
+            st[np.arange(0, n, 97)] = fs.FS_I
+            sim.set_state(st, age, 0, step_index=60)
+            sim.step(33)
+            sim.set_bins(24, 128)   # new bins mid-run
+            sim.step(41)
+            outs.append([(*sim.get_state(r)[:2], sim.history(60, 74, r)) for r in range(replicas)])
+            sim.close()
+    for ra, rb in zip(outs[0], outs[1]):
+        for x, y in zip(ra, rb):
+            np.testing.assert_array_equal(x, y)
+    # replica 0 from the loaded state against the oracle
+    ost, oage, ohist = oracle.run((rp, ci), model, st, age, 74, step0=60, replica=0)
+    np.testing.assert_array_equal(outs[0][0][2], ohist)
+    np.testing.assert_array_equal(outs[0][0][0], ost)
+
+
 def test_tune_restores_state_and_keeps_results():
     n = 30_000
     rp, ci = W.barabasi_albert(n, 5, 4)
@@ -658,6 +699,75 @@ def test_tune_restores_state_and_keeps_results():
         ref.close()
     for x, y in zip(tuned, plain):
         np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("replicas", [1, 4])
+def test_autotune_variants_cache_and_results(tmp_path, replicas):
+    # the autotuner times variants and bins from a mid-run state, restores
+    # it, and the run continues exactly as an untuned one; the choice is
+    # cached by signature, so a sim of another instance of the same graph
+    # family and size takes it from the file without trials
+    n = 30_000
+    model = W.WORKLOADS["ba5_n1e6"]["model"]
+    seeds = W.seed_nodes(n, 50, 6)
+    cache = str(tmp_path / "tune.txt")
+    runs = []
+    for gseed in (4, 4):
+        rp, ci = W.barabasi_albert(n, 5, gseed)
+        with fs.Graph(rp, ci) as g:
+            sim = fs.Sim.from_model(g, model, steps_per_graph=10, replicas=replicas)
+            sim.seed(seeds, replica=-1)
+            sim.step(30)
+            before = [sim.get_state(r) for r in range(replicas)]
+            res = sim.autotune(5, variants=True, cache_path=cache)
+            assert sim.variant() == res["variant"]
+            assert sim.bins()[:2] == (res["heavy_degree"], res["segment_edges"])
+            for r in range(replicas):
+                for x, y in zip(before[r], sim.get_state(r)):
+                    np.testing.assert_array_equal(x, y)
+            sim.step(40)
+            runs.append((res, [(*sim.get_state(r)[:2], sim.history(0, 70, r)) for r in range(replicas)]))
+            sim.close()
+            ref = fs.Sim.from_model(g, model, heavy_degree=-1, replicas=replicas, variant=fs.VARIANT_STREAM)
+            ref.seed(seeds, replica=-1)
+            ref.step(70)
+            plain = [(*ref.get_state(r)[:2], ref.history(0, 70, r)) for r in range(replicas)]
+            ref.close()
+        for a, b in zip(runs[-1][1], plain):
+            for x, y in zip(a, b):
+                np.testing.assert_array_equal(x, y)
+    first, second = runs[0][0], runs[1][0]
+    assert not first["from_cache"] and first["trials"] >= 3
+    assert second["from_cache"] and second["signature"] == first["signature"]
+    assert (second["variant"], second["heavy_degree"], second["segment_edges"]) == \
+        (first["variant"], first["heavy_degree"], first["segment_edges"])
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and lines[0].startswith(first["signature"])
+
+
+def test_autotune_adaptive_keeps_an_lds_variant():
+    n = 20_000
+    rp, ci = W.barabasi_albert(n, 4, 3)
+    model = {"ei": W.LN_E, "ir": W.LN_I, "beta": 0.2, "dt": 0.1, "seed": 9}
+    seeds = W.seed_nodes(n, 30, 2)
+    out = []
+    with fs.Graph(rp, ci) as g:
+        for tune in (True, False):
+            sim = fs.Sim.from_model(g, model, adaptive=True, epsilon=0.03, steps_per_graph=10)
+            sim.seed(seeds, replica=0)
+            sim.step(20)
+            if tune:
+                res = sim.autotune(4, variants=True)
+                assert res["variant"] in ("resident", "summary")
+            sim.step(30)
+            out.append((sim.get_state(0)[:2], sim.history(0, 50), sim.step_sizes(0, 50)))
+            sim.close()
+    for x, y in zip(out[0], out[1]):
+        if isinstance(x, tuple):
+            for u, v in zip(x, y):
+                np.testing.assert_array_equal(u, v)
+        else:
+            np.testing.assert_array_equal(x, y)
 
 
 def test_compact_and_fp32_storage_agree_up_to_threshold_cases(small_graph):
