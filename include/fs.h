@@ -509,12 +509,15 @@ fs_status fs_batch_sync(fs_batch* b);
  * A scenario server: callers submit independent scenario solves (a resident
  * graph, laws and rates, replicas, seeds, a number of steps) from any
  * thread; a worker thread admits queued requests in arrival order while the
- * device-memory budget and the slot limit allow, advances every admitted
- * request with batches (see above; requests on weighted graphs and on
- * unit-weight graphs form one batch each) a few steps at a time, and retires
- * the requests that reach their step count, so a request that arrives while
- * others are on the GPU joins them at the next round.  A request's counts
- * equal those of the same sim run alone.
+ * device-memory budget and the slot limit allow.  Small requests (fewer than
+ * 2^18 node-replica units) advance together in batches (see above; requests
+ * on weighted graphs and on unit-weight graphs form one batch each) a few
+ * steps at a time, so one that arrives while others are on the GPU joins
+ * them at the next round; large ones (which fill the GPU by themselves) run
+ * on a stream of their own, at most two at once, with every step queued at
+ * admission, so their kernels overlap each other's and the batch's.  The
+ * worker retires requests as they reach their step count.  A request's
+ * counts equal those of the same sim run alone.
  */
 typedef struct fs_server fs_server;
 

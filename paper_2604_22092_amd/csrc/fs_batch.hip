@@ -413,6 +413,20 @@ struct PinnedPool {
     }
 };
 
+// Requests with at least this many units give every wavefront of the GPU a
+// chunk by themselves: they run their own step kernels (the variant that
+// suits their size), each on a stream of its own, so that the kernels of two
+// such requests (and the batch's) overlap on the device.  Smaller ones share the batch's
+// fused launches.  At most MAX_SOLO large requests step at once (sharing the
+// GPU between more of them only lengthens each one's latency).  Measured on
+// the serving mix: with every request in the batch instead, the server
+// finished 42.7 scenarios/s at saturation against 71.4 with this threshold.
+constexpr size_t SOLO_UNITS = (size_t)1 << 18;
+#ifndef FS_MAX_SOLO
+#define FS_MAX_SOLO 2
+#endif
+constexpr int MAX_SOLO = FS_MAX_SOLO;
+
 struct Request {
     int64_t id = 0;
     fs_graph* g = nullptr;
@@ -422,6 +436,7 @@ struct Request {
     size_t bytes = 0;
     fs_sim* sim = nullptr;
     bool solo = false;               // runs its own step kernels instead of joining the batch
+    int slot = -1;                   // solo: its stream slot (fs_server::solo_stream)
     int64_t done_steps = 0;          // steps queued so far
     uint32_t* pinned_hist = nullptr; // [n_steps][R][4] counts, copied after the last round
     fs_request_info info{};
@@ -437,6 +452,9 @@ struct fs_server {
     int device = 0;
     hipStream_t stream = nullptr;       // rounds: every admitted request's steps
     hipStream_t admit_stream = nullptr; // creation and seeding of new requests
+    hipStream_t solo_stream[MAX_SOLO] = {}; // one per solo slot
+    hipEvent_t slot_ev[MAX_SOLO] = {};      // end of the slot's request (its steps and history copy)
+    bool slot_used[MAX_SOLO] = {};
     bool own_stream = false;
     // small requests share one batch per weightedness ([0]: unit weights,
     // [1]: weighted graphs), since a batch launch runs one instantiation
@@ -445,7 +463,8 @@ struct fs_server {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<std::shared_ptr<Request>> queue;             // submitted, not admitted
-    std::vector<std::shared_ptr<Request>> active;           // stepping in the next round
+    std::vector<std::shared_ptr<Request>> active;           // batch members stepping in the next round
+    std::vector<std::shared_ptr<Request>> running;          // solo requests, every step queued
     std::map<int64_t, std::shared_ptr<Request>> requests;   // every request not yet collected
     int64_t next_id = 1;
     bool stop = false;
@@ -457,15 +476,7 @@ struct fs_server {
 
 namespace {
 
-// Requests with at least this many units give every wavefront of the GPU a
-// chunk by themselves: they run their own step kernels (the variant that
-// suits their size) on the server stream.  Smaller ones share the batch's
-// fused launches.  At most MAX_SOLO large requests step at once (sharing the
-// GPU between more of them only lengthens each one's latency).  Measured on
-// the serving mix: with every request in the batch instead, the server
-// finished 42.7 scenarios/s at saturation against 71.4 with this threshold.
-constexpr size_t SOLO_UNITS = (size_t)1 << 18;
-constexpr int MAX_SOLO = 2;
+
 
 // Creates and seeds the sim of an admitted request on the admission stream,
 // while a round runs (worker thread, lock not held).
@@ -517,12 +528,38 @@ struct Round {
     std::vector<std::shared_ptr<Request>> ending; // requests whose last steps it holds
 };
 
-// The worker.  Each iteration: (1) requests admitted last time join the
-// active set; (2) one round of steps is queued for the active set, and the
-// count histories of the requests it finishes are queued for copying right
-// after it; (3) queued requests are admitted while that round runs; (4) the
-// previous round is waited for and its finished requests are retired.  The
-// device thus has a round queued while the host works.
+// Retires the solo requests whose queued work has finished (lock not held;
+// returns the retired ones).
+fs_status retire_solos(fs_server* sv, std::vector<std::shared_ptr<Request>>& running,
+                       std::vector<std::shared_ptr<Request>>& done)
+{
+    fs_status st = FS_OK;
+    for (auto& q : running) {
+        const hipError_t e = hipEventQuery(sv->slot_ev[q->slot]);
+        if (e == hipErrorNotReady) continue;
+        if (e != hipSuccess) {
+            st = fail(FS_ERR_DEVICE, std::string("request failed: ") + hipGetErrorString(e));
+            break;
+        }
+        const int R = q->p.n_replicas;
+        q->history.assign((size_t)q->n_steps * R * 4, 0);
+        for (size_t i = 0; i < q->history.size(); ++i) q->history[i] = q->pinned_hist[i];
+        drop_sim(sv, *q);
+        q->info.t_done = now_s();
+        done.push_back(q);
+    }
+    return st;
+}
+
+// The worker.  Each iteration: (1) requests admitted last time join: small
+// ones the batch, large ones a solo slot, where every step of theirs and the
+// copy of their count history are queued at once on the slot's stream; (2)
+// one round of steps is queued for the batch, and the count histories of the
+// members it finishes are queued for copying right after it; (3) queued
+// requests are admitted while that round runs; (4) the previous round is
+// waited for and its finished members retired, and finished solo requests
+// are retired.  The device thus has a round queued while the host works, and
+// a large request's steps wait for no round.
 void worker_loop(fs_server* sv)
 {
     (void)hipSetDevice(sv->device);
@@ -542,27 +579,45 @@ void worker_loop(fs_server* sv)
         Round& prev = rounds[cur ^ 1];
         Round& now = rounds[cur];
         if (sv->active.empty() && joining.empty() && !prev.pending) {
-            if (sv->stop && sv->queue.empty()) break;
-            sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
+            if (sv->stop && sv->queue.empty() && sv->running.empty()) break;
+            if (sv->running.empty())
+                sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
+            else // (solo requests to retire: look again shortly)
+                sv->cv_work.wait_for(lk, std::chrono::microseconds(200), [&] { return !sv->queue.empty(); });
         }
         // 1. join: admitted sims (their setup stream is synchronised) move to
-        //    the server stream, small ones into the batch
+        //    the server stream and into the batch, or (large ones) to the
+        //    stream of their solo slot with every step queued
         for (auto& q : joining) {
             q->sim->stream = sv->stream;
-            const fs_status jst = q->solo ? FS_OK : attach(sv->batch[q->g->d_weights ? 1 : 0], q->sim);
+            fs_status jst = FS_OK;
+            if (q->solo) {
+                q->sim->stream = sv->solo_stream[q->slot];
+                lk.unlock();
+                jst = fs_step(q->sim, q->n_steps);
+                const size_t bytes = (size_t)q->n_steps * q->p.n_replicas * 4 * sizeof(uint32_t);
+                if (jst == FS_OK && (hipMemcpyAsync(q->pinned_hist, q->sim->d_hist, bytes, hipMemcpyDeviceToHost,
+                                                    q->sim->stream) != hipSuccess ||
+                                     hipEventRecord(sv->slot_ev[q->slot], q->sim->stream) != hipSuccess))
+                    jst = fail(FS_ERR_DEVICE, "history copy");
+                lk.lock();
+            } else {
+                jst = attach(sv->batch[q->g->d_weights ? 1 : 0], q->sim);
+            }
             if (jst != FS_OK) {
-                // (not reached with sims the server created itself)
                 const std::string jerr = g_err;
+                if (q->solo) (void)hipStreamSynchronize(q->sim->stream);
                 drop_sim(sv, *q);
+                if (q->solo) sv->slot_used[q->slot] = false;
                 sv->in_use -= q->bytes;
                 end_request(*q, jst, jerr);
                 sv->cv_done.notify_all();
                 continue;
             }
-            sv->active.push_back(q);
+            (q->solo ? sv->running : sv->active).push_back(q);
         }
         joining.clear();
-        // 2. queue one round
+        // 2. queue one round of the batch
         now.ending.clear();
         now.pending = false;
         if (!sv->active.empty()) {
@@ -572,15 +627,13 @@ void worker_loop(fs_server* sv)
             lk.unlock();
             for (fs_batch* b : sv->batch)
                 if (st == FS_OK) st = batch_step(b, r);
-            for (auto& q : act)
-                if (st == FS_OK && q->solo) st = fs_step(q->sim, r);
             for (auto& q : act) {
                 if (st != FS_OK) break;
                 q->done_steps += r;
                 if (q->done_steps < q->n_steps) continue;
                 now.ending.push_back(q);
                 const size_t bytes = (size_t)q->n_steps * q->p.n_replicas * 4 * sizeof(uint32_t);
-                if (hipMemcpyAsync(q->pinned_hist, q->sim->d_hist, bytes, hipMemcpyDeviceToHost, sv->stream) !=
+                if (hipMemcpyAsync(q->pinned_hist, q->sim->d_hist, bytes, hipMemcpyDeviceToHost, q->sim->stream) !=
                     hipSuccess)
                     st = fail(FS_ERR_DEVICE, "history copy");
                 if (q->sim->batch) detach(q->sim->batch, q->sim); // the next round's tables leave it out
@@ -596,21 +649,26 @@ void worker_loop(fs_server* sv)
         // 3. admissions while the round runs: arrival order, except that a
         //    large request waiting for a solo slot does not hold back smaller
         //    ones; within the slot limit and the memory budget
-        int solos = 0;
-        for (auto& q : sv->active) solos += q->solo ? 1 : 0;
         for (auto it = sv->queue.begin(); it != sv->queue.end();) {
             std::shared_ptr<Request> q = *it;
             q->solo = (size_t)q->g->n * (size_t)q->p.n_replicas >= SOLO_UNITS;
-            const bool idle = sv->active.empty() && joining.empty() && !now.pending && !prev.pending;
-            if ((int)(sv->active.size() + joining.size()) >= sv->p.max_active) break;
+            const bool idle = sv->active.empty() && sv->running.empty() && joining.empty() && !now.pending &&
+                              !prev.pending;
+            if ((int)(sv->active.size() + sv->running.size() + joining.size()) >= sv->p.max_active) break;
             if (!idle && sv->in_use + q->bytes > sv->budget) break;
-            if (q->solo && solos >= MAX_SOLO) {
-                ++it;
-                continue;
+            int slot = -1;
+            if (q->solo) {
+                for (int i = 0; i < MAX_SOLO && slot < 0; ++i)
+                    if (!sv->slot_used[i]) slot = i;
+                if (slot < 0) {
+                    ++it;
+                    continue;
+                }
+                sv->slot_used[slot] = true;
+                q->slot = slot;
             }
             sv->queue.erase(it);
             sv->in_use += q->bytes;
-            solos += q->solo ? 1 : 0;
             lk.unlock();
             q->info.t_admit = now_s();
             const fs_status ast = start_request(sv, *q);
@@ -619,7 +677,7 @@ void worker_loop(fs_server* sv)
             lk.lock();
             if (ast != FS_OK) {
                 sv->in_use -= q->bytes;
-                solos -= q->solo ? 1 : 0;
+                if (q->solo) sv->slot_used[q->slot] = false;
                 end_request(*q, ast, aerr);
                 sv->cv_done.notify_all();
             } else {
@@ -653,6 +711,21 @@ void worker_loop(fs_server* sv)
             prev.ending.clear();
             prev.pending = false;
         }
+        //    and the solo requests that have finished
+        if (st == FS_OK && !sv->running.empty()) {
+            std::vector<std::shared_ptr<Request>> running = sv->running, done;
+            lk.unlock();
+            st = retire_solos(sv, running, done);
+            if (st != FS_OK) err = g_err;
+            lk.lock();
+            for (auto& q : done) {
+                sv->running.erase(std::remove(sv->running.begin(), sv->running.end(), q), sv->running.end());
+                sv->slot_used[q->slot] = false;
+                sv->in_use -= q->bytes;
+                end_request(*q, FS_OK, std::string());
+            }
+            if (!done.empty()) sv->cv_done.notify_all();
+        }
         cur ^= 1;
     }
     if (st != FS_OK) {
@@ -660,6 +733,8 @@ void worker_loop(fs_server* sv)
         sv->worker_error = err;
         lk.unlock();
         (void)hipStreamSynchronize(sv->stream);
+        for (hipStream_t ss : sv->solo_stream)
+            if (ss) (void)hipStreamSynchronize(ss);
         lk.lock();
         for (auto& r : rounds) {
             for (auto& q : r.ending) {
@@ -669,7 +744,7 @@ void worker_loop(fs_server* sv)
             }
             r.ending.clear();
         }
-        for (auto* list : {&sv->active, &joining}) {
+        for (auto* list : {&sv->active, &sv->running, &joining}) {
             for (auto& q : *list) {
                 drop_sim(sv, *q);
                 sv->in_use -= q->bytes;
@@ -684,6 +759,8 @@ void worker_loop(fs_server* sv)
     }
     lk.unlock();
     (void)hipStreamSynchronize(sv->stream);
+    for (hipStream_t ss : sv->solo_stream)
+        if (ss) (void)hipStreamSynchronize(ss);
     for (auto& r : rounds)
         if (r.ev) (void)hipEventDestroy(r.ev);
 }
@@ -724,6 +801,17 @@ fs_status fs_server_create(const fs_server_params* p, fs_server** out)
         if (sv->own_stream) (void)hipStreamDestroy(sv->stream);
         return fail(FS_ERR_DEVICE, "admission stream");
     }
+    for (int i = 0; i < MAX_SOLO; ++i)
+        if (hipStreamCreateWithFlags(&sv->solo_stream[i], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sv->slot_ev[i], hipEventDisableTiming) != hipSuccess) {
+            for (int j = 0; j <= i; ++j) {
+                if (sv->solo_stream[j]) (void)hipStreamDestroy(sv->solo_stream[j]);
+                if (sv->slot_ev[j]) (void)hipEventDestroy(sv->slot_ev[j]);
+            }
+            (void)hipStreamDestroy(sv->admit_stream);
+            if (sv->own_stream) (void)hipStreamDestroy(sv->stream);
+            return fail(FS_ERR_DEVICE, "solo stream");
+        }
     fs_status st = FS_OK;
     for (fs_batch*& b : sv->batch)
         if (st == FS_OK) st = fs_batch_create(p->storage, sv->stream, &b);
@@ -732,6 +820,8 @@ fs_status fs_server_create(const fs_server_params* p, fs_server** out)
         for (fs_batch* b : sv->batch)
             if (b) (void)fs_batch_destroy(b);
         (void)hipStreamDestroy(sv->admit_stream);
+        for (hipStream_t t : sv->solo_stream) (void)hipStreamDestroy(t);
+        for (hipEvent_t e : sv->slot_ev) (void)hipEventDestroy(e);
         if (sv->own_stream) (void)hipStreamDestroy(sv->stream);
         return fail(st, err);
     }
@@ -822,7 +912,7 @@ fs_status fs_server_stats(fs_server* sv, fs_server_stats_t* out)
     if (!sv || !out) return fail(FS_ERR_INVALID_ARG, "NULL argument");
     std::lock_guard<std::mutex> lk(sv->mu);
     out->queued = (int64_t)sv->queue.size();
-    out->active = (int64_t)sv->active.size();
+    out->active = (int64_t)(sv->active.size() + sv->running.size());
     out->memory_in_use = (int64_t)sv->in_use;
     out->memory_budget = (int64_t)sv->budget;
     out->rounds = (int64_t)sv->rounds;
@@ -853,6 +943,11 @@ fs_status fs_server_destroy(fs_server* sv)
         for (fs_batch* b : sv->batch) (void)fs_batch_destroy(b);
         (void)hipStreamSynchronize(sv->admit_stream);
         (void)hipStreamDestroy(sv->admit_stream);
+        for (hipStream_t ss : sv->solo_stream) {
+            (void)hipStreamSynchronize(ss);
+            (void)hipStreamDestroy(ss);
+        }
+        for (hipEvent_t e : sv->slot_ev) (void)hipEventDestroy(e);
         if (sv->own_stream) (void)hipStreamDestroy(sv->stream);
     }
     delete sv;

@@ -118,13 +118,22 @@ constexpr uint32_t OOB_ELEM = OOB >> 2;
 // from global memory only when the LDS summary says its group holds an
 // infectious unit (MODE_SUMMARY).  Lanes that do not want it read nothing
 // from global memory and get 0.  b must be a valid unit index.
+// The LDS words are read for every lane and the result selected afterwards:
+// with the read inside a condition, the compiler makes a branch of every
+// gathered slot and waits for each read on its own.
 template <int MODE>
 __device__ __forceinline__ uint32_t fetch_bit(const uint32_t* __restrict__ lds, rsrc_t gbits, uint32_t b,
                                               int32_t lg_gran, bool use)
 {
-    if (MODE == MODE_RESIDENT) return use ? lds_bit(lds, b) : 0u;
+    if (MODE == MODE_RESIDENT) {
+        const uint32_t w = lds_bit(lds, b);
+        return use ? w : 0u;
+    }
     bool go = use;
-    if (MODE == MODE_SUMMARY) go = go && lds_bit(lds, b >> lg_gran) != 0u;
+    if (MODE == MODE_SUMMARY) {
+        const uint32_t sb = lds_bit(lds, b >> lg_gran);
+        go = use & (sb != 0u);
+    }
     const uint32_t w = ld32(gbits, go ? (b >> 5) << 2 : OOB);
     return (w >> (b & 31)) & 1u;
 }
@@ -391,12 +400,18 @@ __device__ __forceinline__ void shed_pre(const StepArgs& a, const Pass<age_t>& P
         const uint32_t dg = valid ? P.dgr[u] : 0u;
         const bool want = x == ST_S && (UNIFORM || dg != HEAVY_ROW);
         const bool pre = UNIFORM || P.ud[u] != MIXED_CHUNK;
+        // (every LDS word read first, then the value loads of the set bits)
+        uint32_t src[DEPTH], wv[DEPTH];
+#pragma unroll
+        for (int j = 0; j < DEPTH; ++j) {
+            src[j] = ((uint32_t)P.c[u][j] << lgR) + rep;
+            wv[j] = lds[src[j] >> 5];
+        }
 #pragma unroll
         for (int j = 0; j < DEPTH; ++j) {
             const bool use = pre && (uint32_t)j < P.ud[u] && want;
-            const uint32_t src = ((uint32_t)P.c[u][j] << lgR) + rep;
-            const uint32_t b = use ? lds_bit(lds, src) : 0u;
-            S.v[u][j] = __uint_as_float(ld32(shedr, b ? src << 2 : OOB));
+            const uint32_t b = use ? __builtin_amdgcn_ubfe(wv[j], src[j] & 31u, 1) : 0u;
+            S.v[u][j] = __uint_as_float(ld32(shedr, b ? src[j] << 2 : OOB));
         }
     }
 }
@@ -430,25 +445,82 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
         const uint32_t q = lane >> lgR;
         const rsrc_t wr = make_rsrc(WEIGHTED ? (const void*)(a.w_t + P.base[u]) : (const void*)a.w_t,
                                     WEIGHTED ? P.ud[u] * rows * 4u : 0u);
+        if (!SHED) {
+            // every slot's LDS word is read before any is used (one wait for
+            // all); the global bitmap words, in the variants that need them,
+            // are loaded only where the slot is used (and, with the summary,
+            // its group holds an infectious unit), and not at all when no
+            // lane of the wavefront needs one: a load consumed here would
+            // also wait for the next pass's prefetched loads
+            uint32_t src[DEPTH], bit[DEPTH];
+            bool use[DEPTH];
 #pragma unroll
-        for (int j = 0; j < DEPTH; ++j) {
-            const bool use = (uint32_t)j < P.ud[u] && want;
-            uint32_t b = 0;
-            float v;
-            if (SPLIT) {
-                v = S.v[u][j];
-            } else {
-                const uint32_t src = ((uint32_t)P.c[u][j] << lgR) + rep;
-                b = fetch_bit<MODE>(lds, gbits, src, a.lg_gran, use);
-                v = SHED ? __uint_as_float(ld32(shedr, b ? src << 2 : OOB)) : (float)b;
+            for (int j = 0; j < DEPTH; ++j) {
+                use[j] = (uint32_t)j < P.ud[u] && want;
+                src[j] = ((uint32_t)P.c[u][j] << lgR) + rep;
             }
-            if (WEIGHTED) {
-                const float w = __uint_as_float(ld32(wr, use ? ((uint32_t)j * rows + q) << 2 : OOB));
-                pw = __builtin_fmaf(w, v, pw);
-            } else if (SHED) {
-                pw += v;
+            if (MODE == MODE_RESIDENT) {
+                uint32_t wv[DEPTH];
+                // (a mixed layout's chunk reads only its degree's slots: a
+                // wave-uniform test)
+#pragma unroll
+                for (int j = 0; j < DEPTH; ++j) wv[j] = (UNIFORM || (uint32_t)j < P.ud[u]) ? lds[src[j] >> 5] : 0u;
+#pragma unroll
+                for (int j = 0; j < DEPTH; ++j) bit[j] = __builtin_amdgcn_ubfe(wv[j], src[j] & 31u, 1) & (uint32_t)use[j];
             } else {
-                pi += b;
+                bool go[DEPTH];
+                if (MODE == MODE_SUMMARY) {
+                    uint32_t sw[DEPTH];
+#pragma unroll
+                    for (int j = 0; j < DEPTH; ++j)
+                        sw[j] = (UNIFORM || (uint32_t)j < P.ud[u]) ? lds[src[j] >> (a.lg_gran + 5)] : 0u;
+#pragma unroll
+                    for (int j = 0; j < DEPTH; ++j)
+                        go[j] = use[j] & (__builtin_amdgcn_ubfe(sw[j], (src[j] >> a.lg_gran) & 31u, 1) != 0u);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < DEPTH; ++j) go[j] = use[j];
+                }
+                bool anyg = false;
+#pragma unroll
+                for (int j = 0; j < DEPTH; ++j) anyg = anyg | go[j];
+#pragma unroll
+                for (int j = 0; j < DEPTH; ++j) bit[j] = 0u;
+                if (__ballot(anyg) != 0ull) {
+                    uint32_t w[DEPTH];
+#pragma unroll
+                    for (int j = 0; j < DEPTH; ++j) w[j] = ld32(gbits, go[j] ? (src[j] >> 5) << 2 : OOB);
+#pragma unroll
+                    for (int j = 0; j < DEPTH; ++j) bit[j] = __builtin_amdgcn_ubfe(w[j], src[j] & 31u, 1);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < DEPTH; ++j) {
+                if (WEIGHTED) {
+                    const float w = __uint_as_float(ld32(wr, use[j] ? ((uint32_t)j * rows + q) << 2 : OOB));
+                    pw = __builtin_fmaf(w, (float)bit[j], pw);
+                } else {
+                    pi += bit[j];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < DEPTH; ++j) {
+                const bool use = (uint32_t)j < P.ud[u] && want;
+                float v;
+                if (SPLIT) {
+                    v = S.v[u][j];
+                } else {
+                    const uint32_t src = ((uint32_t)P.c[u][j] << lgR) + rep;
+                    const uint32_t b = fetch_bit<MODE>(lds, gbits, src, a.lg_gran, use);
+                    v = __uint_as_float(ld32(shedr, b ? src << 2 : OOB));
+                }
+                if (WEIGHTED) {
+                    const float w = __uint_as_float(ld32(wr, use ? ((uint32_t)j * rows + q) << 2 : OOB));
+                    pw = __builtin_fmaf(w, v, pw);
+                } else {
+                    pw += v;
+                }
             }
         }
         // a uniform chunk deeper than the preload: its remaining slots, JT
