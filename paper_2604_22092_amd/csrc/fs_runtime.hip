@@ -587,7 +587,7 @@ fs_status apply_bins(fs_sim* s, int32_t heavy_deg, int32_t seg_edges)
     s->args.orig_id = g->d_orig;
     s->args.udeg = L->udeg;
     s->kfn = fsk::step_kernel_fn(s->storage, g->d_weights != nullptr, s->mode, L->udeg, s->d_shed[0] != nullptr,
-                                 s->d_rates != nullptr || s->d_act != nullptr);
+                                 s->d_rates != nullptr || s->d_act != nullptr, s->lgR);
     s->args.col_t = L->d_col_t;
     s->args.w_t = L->d_w_t;
     return FS_OK;
@@ -845,7 +845,7 @@ fs_status apply_variant(fs_sim* s, int mode)
     s->args.summary = (const uint32_t*)s->d_summary;
     const bool weighted = s->g->d_weights != nullptr, shed = s->d_shed[0] != nullptr;
     s->kfn = fsk::step_kernel_fn(s->storage, weighted, mode, s->layout ? s->layout->udeg : -1, shed,
-                                 s->d_rates != nullptr || s->d_act != nullptr);
+                                 s->d_rates != nullptr || s->d_act != nullptr, s->lgR);
     s->hfn = fsk::heavy_kernel_fn(weighted, shed, mode == fsi::MODE_RESIDENT);
     if (!s->kfn || !s->hfn) return fail(FS_ERR_DEVICE, "no step kernel for this configuration");
     FS_HIP(refresh_summary(s));
@@ -1431,7 +1431,7 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
         a.htab_inv = s->storage == 0 ? 1.0f / a.dt : 1.0f;
     }
     s->kfn = fsk::step_kernel_fn(s->storage, g->d_weights != nullptr, s->mode, -1, shedding,
-                                 s->d_rates != nullptr || s->d_act != nullptr);
+                                 s->d_rates != nullptr || s->d_act != nullptr, s->lgR);
     s->hfn = fsk::heavy_kernel_fn(g->d_weights != nullptr, shedding, s->mode == fsi::MODE_RESIDENT);
     if (!s->kfn || !s->hfn) {
         release_sim(s);

@@ -459,7 +459,20 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
                 use[j] = (uint32_t)j < P.ud[u] && want;
                 src[j] = ((uint32_t)P.c[u][j] << lgR) + rep;
             }
-            if (MODE == MODE_RESIDENT) {
+            if (MODE == MODE_RESIDENT && !WEIGHTED) {
+                // unit weights: the count of set bits, masked once (slots past
+                // a mixed chunk's degree read nothing and hold 0; the bit
+                // extract uses the low five bits of its offset)
+                uint32_t wv[DEPTH];
+#pragma unroll
+                for (int j = 0; j < DEPTH; ++j) wv[j] = (UNIFORM || (uint32_t)j < P.ud[u]) ? lds[src[j] >> 5] : 0u;
+                uint32_t sum = 0;
+#pragma unroll
+                for (int j = 0; j < DEPTH; ++j) sum += __builtin_amdgcn_ubfe(wv[j], src[j], 1);
+#pragma unroll
+                for (int j = 0; j < DEPTH; ++j) bit[j] = 0u;
+                pi += want ? sum : 0u;
+            } else if (MODE == MODE_RESIDENT) {
                 uint32_t wv[DEPTH];
                 // (a mixed layout's chunk reads only its degree's slots: a
                 // wave-uniform test)
@@ -490,8 +503,9 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
                     uint32_t w[DEPTH];
 #pragma unroll
                     for (int j = 0; j < DEPTH; ++j) w[j] = ld32(gbits, go[j] ? (src[j] >> 5) << 2 : OOB);
+                    // (slots not loaded read 0)
 #pragma unroll
-                    for (int j = 0; j < DEPTH; ++j) bit[j] = __builtin_amdgcn_ubfe(w[j], src[j] & 31u, 1);
+                    for (int j = 0; j < DEPTH; ++j) bit[j] = __builtin_amdgcn_ubfe(w[j], src[j], 1);
                 }
             }
 #pragma unroll
@@ -1047,6 +1061,35 @@ template <int STORAGE, bool WEIGHTED, int MODE, int UD, bool SHED, bool EXTRA, i
 __global__ __launch_bounds__(TPB) void step_kernel(StepArgs a)
 {
     step_body<STORAGE, WEIGHTED, MODE, UD, SHED, EXTRA, TPB>(a, blockIdx.x, gridDim.x);
+}
+
+// The plain step of a uniform layout with one replica: the same body with
+// R = 1 known at compile time, so replica shifts and masks, unit and node
+// indices and the column offsets (slot j of lane q at j * 64 + q, a constant
+// offset per slot) cost no instructions.
+template <int STORAGE, bool WEIGHTED, int MODE, int UD, int TPB>
+__global__ __launch_bounds__(TPB) void step_kernel_r1(StepArgs a)
+{
+    StepArgs b = a;
+    b.lgR = 0;
+    step_body<STORAGE, WEIGHTED, MODE, UD, false, false, TPB>(b, blockIdx.x, gridDim.x);
+}
+
+template <int S, bool W, int U>
+const void* step_kernel_r1_sel(int mode)
+{
+    if (mode == MODE_RESIDENT) return (const void*)&step_kernel_r1<S, W, MODE_RESIDENT, U, RESIDENT_TPB>;
+    if (mode == MODE_SUMMARY) return (const void*)&step_kernel_r1<S, W, MODE_SUMMARY, U, RESIDENT_TPB>;
+    return (const void*)&step_kernel_r1<S, W, MODE_STREAM, U, STREAM_TPB>;
+}
+
+// udeg: the uniform layout's degree (> 0)
+template <int S, bool W>
+const void* step_kernel_r1_depth(int mode, int udeg)
+{
+    if (udeg <= 8) return step_kernel_r1_sel<S, W, 8>(mode);
+    if (udeg <= 10) return step_kernel_r1_sel<S, W, 10>(mode);
+    return step_kernel_r1_sel<S, W, 12>(mode);
 }
 
 // Address of the step kernel of one configuration (each (SHED, EXTRA)
