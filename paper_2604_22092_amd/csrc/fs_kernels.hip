@@ -341,7 +341,7 @@ __global__ __launch_bounds__(WG_REFRESH) void compact_refresh_kernel(const uint8
 
 const void* step_kernel_fn(int storage, bool weighted, int mode, int udeg, bool shed, bool extra, int lgR)
 {
-    if (!shed && !extra && lgR == 0 && udeg > 0) return step_kernel_fn_r1(storage, weighted, mode, udeg);
+    if (!shed && !extra && lgR == 0) return step_kernel_fn_r1(storage, weighted, mode, udeg);
     if (shed) return extra ? step_kernel_fn_shed_extra(storage, weighted, mode, udeg)
                            : step_kernel_fn_shed(storage, weighted, mode, udeg);
     if (extra) return step_kernel_fn_extra(storage, weighted, mode, udeg);

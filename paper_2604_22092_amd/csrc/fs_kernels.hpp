@@ -17,8 +17,8 @@ namespace fsk {
 // shed the one for age-dependent shedding (StepArgs::shed0/shed1/shed);
 // extra the one that records rates (StepArgs::rates) and walks the
 // active-chunk list of compaction (StepArgs::act, live).
-// lgR: log2 of the replica count; uniform layouts with one replica (and
-// neither shedding nor the extra checks) take an instantiation that knows it.
+// lgR: log2 of the replica count; sims with one replica (and neither
+// shedding nor the extra checks) take an instantiation that knows it.
 const void* step_kernel_fn(int storage, bool weighted, int mode, int udeg, bool shed, bool extra, int lgR);
 const void* step_kernel_fn_r1(int storage, bool weighted, int mode, int udeg);
 // (the other (shed, extra) instantiations, each defined by a source of its own)

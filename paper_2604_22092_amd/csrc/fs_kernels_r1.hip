@@ -1,5 +1,5 @@
-// Plain step kernels of uniform layouts with one replica (compiled apart from
-// the others so the instantiations build in parallel).
+// Plain step kernels of sims with one replica (compiled apart from the others
+// so the instantiations build in parallel).
 #include <hip/hip_runtime.h>
 
 #include "fs_kernels.hpp"

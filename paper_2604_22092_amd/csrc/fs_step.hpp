@@ -1063,10 +1063,10 @@ __global__ __launch_bounds__(TPB) void step_kernel(StepArgs a)
     step_body<STORAGE, WEIGHTED, MODE, UD, SHED, EXTRA, TPB>(a, blockIdx.x, gridDim.x);
 }
 
-// The plain step of a uniform layout with one replica: the same body with
-// R = 1 known at compile time, so replica shifts and masks, unit and node
-// indices and the column offsets (slot j of lane q at j * 64 + q, a constant
-// offset per slot) cost no instructions.
+// The plain step of a sim with one replica: the same body with R = 1 known
+// at compile time, so replica shifts and masks, unit and node indices and
+// the column offsets (slot j of lane q at j * 64 + q, a constant offset per
+// slot) cost no instructions.
 template <int STORAGE, bool WEIGHTED, int MODE, int UD, int TPB>
 __global__ __launch_bounds__(TPB) void step_kernel_r1(StepArgs a)
 {
@@ -1083,10 +1083,11 @@ const void* step_kernel_r1_sel(int mode)
     return (const void*)&step_kernel_r1<S, W, MODE_STREAM, U, STREAM_TPB>;
 }
 
-// udeg: the uniform layout's degree (> 0)
+// udeg: the uniform layout's degree, or -1 for a mixed layout
 template <int S, bool W>
 const void* step_kernel_r1_depth(int mode, int udeg)
 {
+    if (udeg < 0) return step_kernel_r1_sel<S, W, 0>(mode);
     if (udeg <= 8) return step_kernel_r1_sel<S, W, 8>(mode);
     if (udeg <= 10) return step_kernel_r1_sel<S, W, 10>(mode);
     return step_kernel_r1_sel<S, W, 12>(mode);
