@@ -106,6 +106,9 @@ struct StepArgs {
     int32_t same_kind;    // E and I laws share a kind: one hazard call per lane
     int32_t pad0;
     HazardDev hz[2];      // [0] E -> I, [1] I -> R
+    // the same two laws in device memory: the step reads them from there,
+    // where a hazard is evaluated, so they hold no registers for the walk
+    const HazardDev* hz_dev;
     float beta;
     float dt;
     uint32_t key0, key1;  // Philox key = (seed low, seed high)

@@ -254,7 +254,7 @@ void release_sim(fs_sim* s)
                         (void*)s->d_hist, (void*)s->d_part, (void*)s->d_rc_part, (void*)s->d_cnt4,
                         (void*)s->d_summary, s->d_seg_part, (void*)s->d_lam_part, (void*)s->d_dt_hist,
                         (void*)s->d_shed[0], (void*)s->d_shed[1], (void*)s->d_live, (void*)s->d_act,
-                        (void*)s->d_htab, (void*)s->d_hub})
+                        (void*)s->d_htab, (void*)s->d_hz, (void*)s->d_hub})
             sim_free(s, p);
     }
     s->layout.reset();
@@ -1402,6 +1402,12 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
     a.same_kind = hz[0].kind == hz[1].kind;
     a.hz[0] = hz[0];
     a.hz[1] = hz[1];
+    if ((e = sim_alloc(s, (void**)&s->d_hz, 2 * sizeof(fsi::HazardDev))) != hipSuccess ||
+        (e = hipMemcpyAsync(s->d_hz, a.hz, 2 * sizeof(fsi::HazardDev), hipMemcpyHostToDevice, s->stream)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s->stream)) != hipSuccess)
+        return bad(e, "hazard laws");
+    a.hz_dev = s->d_hz;
     a.beta = (float)p->beta;
     a.dt = (float)p->dt;
     a.key0 = (uint32_t)p->seed;

@@ -162,11 +162,27 @@ constexpr int CU = FS_CU;
 #endif
 constexpr bool PREFETCH = FS_PREFETCH != 0;
 
+// A wave-uniform pointer passed through an empty asm where it is used, so
+// that neither it nor the addresses formed from it are hoisted out of the
+// walk (held through the walk they would be spilled to vector lanes, and
+// every use would pay lane reads).
+template <class T>
+__device__ __forceinline__ T* opaque_uniform(T* p)
+{
+    const unsigned long long v = (unsigned long long)p;
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v), hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    asm volatile("" : "+s"(lo), "+s"(hi));
+    return (T*)(((unsigned long long)hi << 32) | lo);
+}
+
 // The rate of an E (isI false) or I unit of age xa: the hazard of its law.
 // With both laws of one kind the E/I choice only selects parameters, so one
-// hazard evaluation serves a wavefront holding both.
+// hazard evaluation serves a wavefront holding both.  hz points to device
+// memory (StepArgs::hz_dev): read where a hazard is evaluated, the laws'
+// parameters and the tests on their kinds are not held through the walk.
 __device__ __forceinline__ float unit_hazard(const HazardDev* hz, int32_t same_kind, float xa, bool isI)
 {
+    hz = opaque_uniform(hz);
     if (same_kind) {
         HazardDev hd = hz[0];
         if (isI) hd = hz[1];
@@ -198,8 +214,8 @@ struct Pass {
 constexpr uint32_t PUSHQ = 128;
 struct HubCtx {
     bool on;
-    rsrc_t tr, dr;
-    uint32_t t_prev, t_cur, d_cur, d_clr, d_next; // element offsets of the slots
+    rsrc_t tr; // hub_T and hub_D, which follows it (2 * hub_units on)
+    uint32_t t_prev, t_cur, d_cur, d_clr, d_next; // element offsets of the slots from hub_T
     uint32_t* q;   // LDS queue: unit | (0x80000000 when leaving I), PUSHQ entries
     uint32_t* pb;  // LDS: 64 list starts (flush)
     uint32_t* px;  // LDS: 64 exclusive prefix sums (flush)
@@ -217,13 +233,16 @@ __device__ __forceinline__ void flush_pushes(const StepArgs& a, HubCtx& H, uint3
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int32_t* __restrict__ optr = opaque_uniform(a.hub_out_ptr);
+    const int32_t* __restrict__ oidx = opaque_uniform(a.hub_out_idx);
+    uint32_t* hub = opaque_uniform(a.hub_T);
     for (uint32_t i0 = 0; i0 < H.n; i0 += 64) {
         const uint32_t m = min(64u, H.n - i0);
         const bool has = lane < m;
         const uint32_t e = has ? H.q[i0 + lane] : 0u;
         const uint32_t node = (e & 0x7FFFFFFFu) >> a.lgR;
-        const uint32_t b = has ? (uint32_t)a.hub_out_ptr[node] : 0u;
-        const uint32_t len = has ? (uint32_t)a.hub_out_ptr[node + 1] - b : 0u;
+        const uint32_t b = has ? (uint32_t)optr[node] : 0u;
+        const uint32_t len = has ? (uint32_t)optr[node + 1] - b : 0u;
         // inclusive prefix sum of the list lengths over the wavefront
         uint32_t inc = len;
 #pragma unroll
@@ -249,9 +268,9 @@ __device__ __forceinline__ void flush_pushes(const StepArgs& a, HubCtx& H, uint3
                     else hi = mid;
                 }
                 const uint32_t eo = H.q[i0 + lo];
-                const uint32_t row = (uint32_t)a.hub_out_idx[H.pb[lo] + (f - H.px[lo])];
+                const uint32_t row = (uint32_t)oidx[H.pb[lo] + (f - H.px[lo])];
                 const uint32_t rep = (eo & 0x7FFFFFFFu) & ((1u << a.lgR) - 1u);
-                __hip_atomic_fetch_add(a.hub_D + H.d_next + (row << a.lgR) + rep,
+                __hip_atomic_fetch_add(hub + H.d_next + (row << a.lgR) + rep,
                                        (eo & 0x80000000u) ? 0xFFFFFFFFu : 1u, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
             }
@@ -365,7 +384,7 @@ __device__ __forceinline__ void issue_pass(const StepArgs& a, uint32_t first, ui
             const bool hub = lane < P.nvalid[u] && n0 + q >= (uint32_t)a.hub_base;
             const uint32_t h = hub ? u0 + lane - ((uint32_t)a.hub_base << a.lgR) : 0u;
             P.ht[u] = ld32(H.tr, hub ? (H.t_prev + h) << 2 : OOB);
-            P.hd[u] = ld32(H.dr, hub ? (H.d_cur + h) << 2 : OOB);
+            P.hd[u] = ld32(H.tr, hub ? (H.d_cur + h) << 2 : OOB);
         }
         // every uniform chunk preloads its first UMAX slots (slots past its
         // degree are out of range)
@@ -603,16 +622,23 @@ template <bool FLOATP>
 __device__ __forceinline__ float pressure_heavy(const StepArgs& a, uint32_t node, uint32_t rep)
 {
     const size_t R = (size_t)1 << a.lgR;
-    const int32_t dg = a.row_ptr[node + 1] - a.row_ptr[node];
-    const int32_t first = a.heavy_first[node];
-    const int32_t nseg = (dg + a.seg_edges - 1) / a.seg_edges;
+    // (the pointers and the segment length are read here, not held through
+    // the walk)
+    const int32_t* rp = opaque_uniform(a.row_ptr);
+    const int32_t* hf = opaque_uniform(a.heavy_first);
+    const void* spp = opaque_uniform(a.seg_part);
+    int32_t se = __builtin_amdgcn_readfirstlane(a.seg_edges);
+    asm volatile("" : "+s"(se));
+    const int32_t dg = rp[node + 1] - rp[node];
+    const int32_t first = hf[node];
+    const int32_t nseg = (dg + se - 1) / se;
     if (FLOATP) {
-        const float* sp = (const float*)a.seg_part;
+        const float* sp = (const float*)spp;
         float p = 0.0f;
         for (int32_t j = 0; j < nseg; ++j) p += sp[(size_t)(first + j) * R + rep];
         return p;
     }
-    const uint32_t* sp = (const uint32_t*)a.seg_part;
+    const uint32_t* sp = (const uint32_t*)spp;
     uint32_t p = 0;
     for (int32_t j = 0; j < nseg; ++j) p += sp[(size_t)(first + j) * R + rep];
     return (float)p;
@@ -717,7 +743,7 @@ __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t
                 const uint32_t h = heavy ? unit[u] - ((uint32_t)a.hub_base << a.lgR) : 0u;
                 const uint32_t pp = P.ht[u] + P.hd[u];
                 st32(H.tr, heavy ? (H.t_cur + h) << 2 : OOB, pp);
-                st32(H.dr, heavy ? (H.d_clr + h) << 2 : OOB, 0u);
+                st32(H.tr, heavy ? (H.d_clr + h) << 2 : OOB, 0u);
                 if (heavy && x[u] == ST_S) lam[u] = a.beta * (float)pp;
             }
         } else if (!UNIFORM && heavy && x[u] == ST_S) {
@@ -747,7 +773,7 @@ __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t
         }
         compact_apply<CU>(xch, lane, need, pay, res, [&](uint32_t w) {
             return __float_as_uint(
-                unit_hazard(a.hz, a.same_kind, age_from_bits<age_t>(w & 0x7FFFFFFFu), (w & 0x80000000u) != 0u));
+                unit_hazard(a.hz_dev, a.same_kind, age_from_bits<age_t>(w & 0x7FFFFFFFu), (w & 0x80000000u) != 0u));
         });
 #pragma unroll
         for (int u = 0; u < CU; ++u)
@@ -768,7 +794,16 @@ __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t
         }
         const uint32_t kk = (uint32_t)k;
         compact_apply<CU>(xch, lane, need, pay, res, [&](uint32_t un) {
-            return fsd::philox4x32_10(make_uint4(un >> a.lgR, kk, un & (R - 1), 0u), a.key0, a.key1).x >> 8;
+            // the key and step pass through an empty asm here, so the round
+            // keys and the key-step terms are formed by scalar adds at each
+            // draw instead of being hoisted out of the walk: held for the
+            // whole walk they would take 20 scalar registers and be spilled
+            // to vector lanes, each use a lane read
+            // (all three are wave-uniform)
+            uint32_t k0 = __builtin_amdgcn_readfirstlane(a.key0), k1 = __builtin_amdgcn_readfirstlane(a.key1),
+                     ks = __builtin_amdgcn_readfirstlane(kk);
+            asm volatile("" : "+s"(k0), "+s"(k1), "+s"(ks));
+            return fsd::philox4x32_10(make_uint4(un >> a.lgR, ks, un & (R - 1), 0u), k0, k1).x >> 8;
         });
 #pragma unroll
         for (int u = 0; u < CU; ++u) {
@@ -924,15 +959,14 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
     if (H.on) {
         const uint32_t HU = a.hub_units;
         const uint32_t k2 = (uint32_t)(k & 1ull), k3 = (uint32_t)(k % 3ull);
-        H.tr = make_rsrc(a.hub_T, 2u * HU * 4u);
-        H.dr = make_rsrc(a.hub_D, 3u * HU * 4u);
+        H.tr = make_rsrc(a.hub_T, 5u * HU * 4u);
         H.t_prev = (k2 ^ 1u) * HU;
         H.t_cur = k2 * HU;
-        H.d_cur = k3 * HU;
-        H.d_next = ((k3 + 1u) % 3u) * HU;
-        H.d_clr = ((k3 + 2u) % 3u) * HU;
+        H.d_cur = (2u + k3) * HU;
+        H.d_next = (2u + (k3 + 1u) % 3u) * HU;
+        H.d_clr = (2u + (k3 + 2u) % 3u) * HU;
     } else {
-        H.tr = H.dr = make_rsrc(nullptr, 0u);
+        H.tr = make_rsrc(nullptr, 0u);
     }
 
     // first pass loads, then the bitmap fill, then one wait for both
