@@ -488,6 +488,12 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
                 uint32_t sum = 0;
 #pragma unroll
                 for (int j = 0; j < DEPTH; ++j) sum += __builtin_amdgcn_ubfe(wv[j], src[j], 1);
+                if (UNIFORM) {
+                    // the slots of a uniform chunk past its degree loaded no
+                    // column (out of range: 0), so they counted unit `rep`
+                    // (node 0 of this replica): take those counts back
+                    sum -= ((uint32_t)DEPTH - P.ud[u]) * __builtin_amdgcn_ubfe(lds[rep >> 5], rep, 1);
+                }
 #pragma unroll
                 for (int j = 0; j < DEPTH; ++j) bit[j] = 0u;
                 pi += want ? sum : 0u;

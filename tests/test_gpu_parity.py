@@ -411,6 +411,39 @@ def test_weighted_graph_one_step():
 
 # ------------------------------------------------------------- edge cases
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("deg", [4, 6, 9, 11])
+def test_uniform_degree_below_preload_depth(deg):
+    # uniform graphs whose degree is below the kernel's preload depth (8, 10
+    # or 12 slots): the slots past the degree read no column and must not
+    # count node 0's bit, which is set here (Eq. (influence) sums over the
+    # row only); every variant, with and without rate recording, and a
+    # replicated sim
+    n = 2000
+    rp, ci = W.random_regular(n, deg, 5)
+    model = {"ei": W.LN_E, "ir": W.LN_I, "beta": 0.3, "dt": 0.1, "seed": 11}
+    rng = np.random.default_rng(deg)
+    st = np.where(rng.random(n) < 0.9, 0, rng.integers(1, 4, n)).astype(np.int32)
+    st[0] = 2
+    age = (rng.integers(0, 50, n) * np.float32(0.1)).astype(np.float32)
+    iota = (st == 2).astype(np.float64)
+    with fs.Graph(rp, ci) as g:
+        for variant in (fs.VARIANT_RESIDENT, fs.VARIANT_SUMMARY, fs.VARIANT_STREAM):
+            for rates in (True, False):
+                for R in (1, 4):
+                    sim = fs.Sim.from_model(g, model, variant=variant, record_rates=rates, replicas=R)
+                    for r in range(R):
+                        sim.set_state(st, age, r, step_index=5)
+                    sim.step(1)
+                    for r in range(R):
+                        gst, gage, _ = sim.get_state(r)
+                        ora = oracle.step((rp, ci), model, st, age, iota, 5, replica=r)
+                        check_one_step({"state": gst, "age": gage, "rates": sim.rates(r) if rates else None},
+                                       ora, st, f"degree {deg} variant {variant} rates {rates} R {R} r {r}")
+                    sim.close()
+
+
+
 def test_edge_cases_tiny_graphs():
     model = {"ei": W.LN_E, "ir": W.LN_I, "beta": 0.5, "dt": 0.1, "seed": 1}
     cases = {
