@@ -477,6 +477,8 @@ def main():
                     help="shedding profile s(tau): none (s = 1), hazard (h_IR), density (log-normal), "
                          "unit (s = 1 through the shedding kernels)")
     ap.add_argument("--compaction", action="store_true", help="active-node compaction")
+    ap.add_argument("--columns", choices=["auto", "plain"], default="auto",
+                    help="the step's graph copy: packed columns where supported (auto) or 32-bit")
     ap.add_argument("--beta", type=float, default=None, help="override the workload's beta")
     ap.add_argument("--markov", action="store_true", help="measure the Markovian engine instead")
     ap.add_argument("--markov-steps", type=int, default=600)
@@ -570,7 +572,8 @@ def main():
                             variant=variant, compaction=args.compaction,
                             storage=fs.FS_STORAGE_COMPACT if compact else fs.FS_STORAGE_FP32,
                             heavy_degree=bins[0], segment_edges=bins[1],
-                            history_len=max(1024, nwin * K + 1))
+                            history_len=max(1024, nwin * K + 1),
+                            columns=fs.FS_COLUMNS_PLAIN if args.columns == "plain" else fs.FS_COLUMNS_AUTO)
     init_state = W.initial_state(n, seeds)
     init_age = np.zeros(n, np.uint16 if compact else np.float32)
     tuned = None
@@ -582,6 +585,7 @@ def main():
         print(f"[bench] autotuner: {tuned}", file=sys.stderr, flush=True)
     bins_used = sim.bins()
     variant_used = sim.variant()
+    column_bits = sim.column_bits()
 
     # warm-up (graph instantiation, clocks), then restart the trajectory
     sim.set_state(init_state, init_age, 0, step_index=0)
@@ -691,6 +695,7 @@ def main():
                    "steps_per_graph": spg, "graph_replays_per_window": K // spg if spg else 0,
                    "eager_steps_per_window": K % spg if spg else K,
                    "kernel_variant": variant_used,
+                   "column_bits": column_bits,
                    "shedding": args.shed if shed is None else [shed[0], list(shed[1]), shed[2]],
                    "compaction": args.compaction,
                    "degree_bins": list(bins_used[:2]) if bins_used[2] else None,

@@ -106,6 +106,21 @@ typedef struct fs_dist {
 #define FS_STORAGE_FP32 0
 #define FS_STORAGE_COMPACT 1
 
+/* Column storage of the step's transposed copy of the graph (the gather of
+ * Eq. (influence) reads it every step; the caller's CSR is unchanged).
+ *   FS_COLUMNS_AUTO:  where the step supports it -- every row of an
+ *                     unweighted graph has one degree (at most 12), one
+ *                     replica, constant shedding, no rate recording and no
+ *                     compaction -- each column takes 20, 24 or 27 bits (the
+ *                     fewest of these that hold the node ids: n <= 2^20,
+ *                     2^24, 2^27), a row's columns packed into one bit
+ *                     stream; else 32 bits.
+ *   FS_COLUMNS_PLAIN: 32 bits per column always.
+ * Results are identical.  A sim with packed columns that joins a batch moves
+ * to 32-bit columns (the batch step reads those). */
+#define FS_COLUMNS_AUTO 0
+#define FS_COLUMNS_PLAIN 1
+
 /* ----------------------------------------------------------- memory hook
  * Routes the library's persistent device arrays (graphs and their layouts,
  * sims, Markovian engines) through the caller's allocator, e.g. a framework's
@@ -187,7 +202,7 @@ typedef struct fs_sim_params {
                                 replicas; dt is the cap, used by the first step after
                                 creation or a state load.  FP32 storage only, variants
                                 0/2/3 only, not in batches. */
-    int32_t pad;
+    int32_t columns;         /* FS_COLUMNS_AUTO (0) or FS_COLUMNS_PLAIN (1) */
     double epsilon;          /* adaptive: bound on lambda * dt per step, > 0 */
     double delta;            /* adaptive: added to the largest rate, >= 0 */
     int32_t shedding;        /* FS_SHED_*; age-dependent forms need n * n_replicas < 2^29
@@ -373,6 +388,10 @@ fs_status fs_sim_autotune(fs_sim* s, const fs_tune_params* p, fs_tune_result* ou
 
 /* The sim's current step variant: 1 stream, 2 resident, 3 summary. */
 fs_status fs_sim_get_variant(fs_sim* s, int32_t* variant);
+
+/* Bits per column of the sim's transposed graph copy: 20, 24 or 27 when
+ * packed (FS_COLUMNS_AUTO), else 32. */
+fs_status fs_sim_get_column_bits(fs_sim* s, int32_t* bits);
 
 /* ------------------------------------------------- building-block checks */
 /*

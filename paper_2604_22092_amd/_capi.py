@@ -23,6 +23,7 @@ STATUS_NAMES = {0: "FS_OK", 1: "FS_ERR_INVALID_ARG", 2: "FS_ERR_INVALID_CSR",
 FS_S, FS_E, FS_I, FS_R = 0, 1, 2, 3
 FS_DIST_EXP, FS_DIST_LOGNORMAL, FS_DIST_WEIBULL, FS_DIST_ERLANG = 0, 1, 2, 3
 FS_STORAGE_FP32, FS_STORAGE_COMPACT = 0, 1
+FS_COLUMNS_AUTO, FS_COLUMNS_PLAIN = 0, 1
 FS_SHED_CONSTANT, FS_SHED_DENSITY, FS_SHED_HAZARD = 0, 1, 2
 FS_SEED_NOALLOC_MAX = 65536  # include/fs.h
 SHED_FORMS = {"constant": FS_SHED_CONSTANT, "density": FS_SHED_DENSITY, "hazard": FS_SHED_HAZARD}
@@ -34,7 +35,7 @@ EXPORTS = [
     "fs_graph_get_info", "fs_sim_create", "fs_sim_destroy", "fs_sim_seed", "fs_sim_seed_noalloc", "fs_step",
     "fs_sync", "fs_step_index", "fs_counts", "fs_history", "fs_get_state", "fs_set_state",
     "fs_get_rates", "fs_eval_hazard", "fs_eval_shedding", "fs_eval_philox", "fs_version", "fs_sim_set_bins",
-    "fs_sim_get_bins", "fs_sim_tune", "fs_sim_autotune", "fs_sim_get_variant", "fs_step_sizes",
+    "fs_sim_get_bins", "fs_sim_tune", "fs_sim_autotune", "fs_sim_get_variant", "fs_sim_get_column_bits", "fs_step_sizes",
     "fs_batch_create", "fs_batch_destroy", "fs_batch_add", "fs_batch_remove", "fs_batch_size",
     "fs_batch_step", "fs_batch_sync",
     "fs_server_create", "fs_server_submit", "fs_server_wait", "fs_server_result",
@@ -80,7 +81,7 @@ class fs_sim_params(ctypes.Structure):
                 ("steps_per_graph", ctypes.c_int32), ("history_len", ctypes.c_int32),
                 ("record_rates", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("heavy_degree", ctypes.c_int32), ("segment_edges", ctypes.c_int32),
-                ("stream", ctypes.c_void_p), ("adaptive", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("stream", ctypes.c_void_p), ("adaptive", ctypes.c_int32), ("columns", ctypes.c_int32),
                 ("epsilon", ctypes.c_double), ("delta", ctypes.c_double),
                 ("shedding", ctypes.c_int32), ("compaction", ctypes.c_int32),
                 ("shed_law", fs_dist), ("shed_scale", ctypes.c_double)]
@@ -175,6 +176,7 @@ def _declare(L):
         "fs_sim_tune": ([P, I32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], I32),
         "fs_sim_autotune": ([P, ctypes.POINTER(fs_tune_params), ctypes.POINTER(fs_tune_result)], I32),
         "fs_sim_get_variant": ([P, ctypes.POINTER(ctypes.c_int32)], I32),
+        "fs_sim_get_column_bits": ([P, ctypes.POINTER(ctypes.c_int32)], I32),
         "fs_batch_create": ([I32, P, PP], I32),
         "fs_batch_destroy": ([P], I32),
         "fs_batch_add": ([P, P], I32),
@@ -364,6 +366,12 @@ def fs_sim_get_variant(h) -> str:
     return VARIANT_NAMES[v.value]
 
 
+def fs_sim_get_column_bits(h) -> int:
+    v = ctypes.c_int32()
+    _check(lib().fs_sim_get_column_bits(h, ctypes.byref(v)), "fs_sim_get_column_bits")
+    return v.value
+
+
 def fs_eval_hazard(spec, ages, storage: int = FS_STORAGE_FP32, dt: float = 1.0) -> np.ndarray:
     a = np.ascontiguousarray(ages, dtype=np.float32 if storage == FS_STORAGE_FP32 else np.uint16)
     out = np.empty(len(a), dtype=np.float32)
@@ -420,7 +428,7 @@ def make_params(ei, ir, beta: float, dt: float, seed: int = 0, replicas: int = 1
                 record_rates: bool = False, variant: int = 0, heavy_degree: int = 0,
                 segment_edges: int = 0, stream=None, adaptive: bool = False,
                 epsilon: float = 0.03, delta: float = 0.0, shed=None,
-                compaction: bool = False) -> fs_sim_params:
+                compaction: bool = False, columns: int = FS_COLUMNS_AUTO) -> fs_sim_params:
     """shed: None or ("constant",) for s = 1, else ("density" | "hazard", law, scale)."""
     p = fs_sim_params()
     p.ei = make_dist(ei)
@@ -446,6 +454,7 @@ def make_params(ei, ir, beta: float, dt: float, seed: int = 0, replicas: int = 1
         p.shed_law = make_dist(shed[1])
         p.shed_scale = float(shed[2])
     p.compaction = 1 if compaction else 0
+    p.columns = int(columns)
     return p
 
 
@@ -573,10 +582,10 @@ class Sim:
                  history_len: int = 0, record_rates: bool = False, variant: int = 0,
                  heavy_degree: int = 0, segment_edges: int = 0, stream=None,
                  adaptive: bool = False, epsilon: float = 0.03, delta: float = 0.0, shed=None,
-                 compaction: bool = False):
+                 compaction: bool = False, columns: int = FS_COLUMNS_AUTO):
         p = make_params(ei, ir, beta, dt, seed, replicas, storage, steps_per_graph, history_len,
                         record_rates, variant, heavy_degree, segment_edges, stream, adaptive,
-                        epsilon, delta, shed, compaction)
+                        epsilon, delta, shed, compaction, columns)
         self.graph = graph
         self.n = graph.n
         self.replicas = int(replicas)
@@ -636,6 +645,9 @@ class Sim:
 
     def variant(self) -> str:
         return fs_sim_get_variant(self.handle)
+
+    def column_bits(self) -> int:
+        return fs_sim_get_column_bits(self.handle)
 
     def close(self):
         if self.handle is not None:

@@ -192,7 +192,7 @@ fs_status rebuild_tables(fs_batch* b)
 // streaming step of the batch's storage with fixed steps, constant shedding
 // and no compaction, and the members agree on weights (the batch kernel is
 // instantiated for one of the two).
-fs_status member_check(const fs_batch* b, const fs_sim* s)
+fs_status member_check(const fs_batch* b, const fs_sim* s, bool allow_packed = false)
 {
     if (s->batch) return fail(FS_ERR_BUSY, "sim already belongs to a batch");
     if (s->device != b->device) return fail(FS_ERR_INVALID_ARG, "sim and batch are on different devices");
@@ -203,6 +203,8 @@ fs_status member_check(const fs_batch* b, const fs_sim* s)
     if (s->p.shedding != FS_SHED_CONSTANT)
         return fail(FS_ERR_INVALID_ARG, "sims with age-dependent shedding cannot join a batch");
     if (s->p.compaction) return fail(FS_ERR_INVALID_ARG, "sims with compaction cannot join a batch");
+    if (!allow_packed && s->layout && s->layout->pbits != 0)
+        return fail(FS_ERR_INVALID_ARG, "batch members read 32-bit columns (the sim has packed ones)");
     const int w = s->g->d_weights != nullptr;
     if (!b->members.empty() && w != b->weighted)
         return fail(FS_ERR_INVALID_ARG, "batch members must agree on weights");
@@ -328,10 +330,13 @@ fs_status fs_batch_add(fs_batch* b, fs_sim* s)
 {
     FS_GUARD_BEGIN
     if (!b || !s) return fail(FS_ERR_INVALID_ARG, "NULL argument");
-    const fs_status st = member_check(b, s);
+    fs_status st = member_check(b, s, true);
     if (st != FS_OK) return st;
     DeviceGuard dg(b->device);
     FS_HIP(hipStreamSynchronize(s->stream));
+    // the batch kernel reads 32-bit columns: a sim with packed ones moves to
+    // the graph's layout with plain columns first
+    if ((st = use_plain_columns(s)) != FS_OK) return st;
     return attach(b, s);
     FS_GUARD_END
 }
@@ -485,6 +490,8 @@ fs_status start_request(fs_server* sv, Request& q)
     fs_sim_params p = q.p;
     p.storage = sv->p.storage;
     p.variant = q.solo ? 0 : 1;
+    // batched requests read 32-bit columns; solo ones may take packed ones
+    p.columns = q.solo ? q.p.columns : FS_COLUMNS_PLAIN;
     p.steps_per_graph = 0;
     p.history_len = (int32_t)std::max<int64_t>(q.n_steps, 2);
     p.stream = sv->admit_stream;

@@ -149,7 +149,9 @@ struct StepArgs {
     // every chunk uniform with this degree (<= UNIFORM_MAX_DEG) and no heavy
     // rows: chunk c starts at slot c * (64 / R) * udeg; else -1
     int32_t udeg;
-    int32_t pad2;
+    // bits per column of a uniform layout's packed columns (20, 24 or 27), or
+    // 0 for 32-bit columns; col_t then holds the packed words (see the step)
+    int32_t pbits;
     const int32_t* col_t;
     const float* w_t;
     // MODE_SUMMARY: summary of the step's input bitmap, sum_bits bits

@@ -339,8 +339,16 @@ __global__ __launch_bounds__(WG_REFRESH) void compact_refresh_kernel(const uint8
 
 // ---------------------------------------------------------------- launchers
 
-const void* step_kernel_fn(int storage, bool weighted, int mode, int udeg, bool shed, bool extra, int lgR)
+const void* step_kernel_fn(int storage, bool weighted, int mode, int udeg, bool shed, bool extra, int lgR,
+                           int pbits)
 {
+    if (pbits != 0) {
+        if (weighted || shed || extra || lgR != 0 || udeg <= 0) return nullptr;
+        if (pbits == 20) return step_kernel_fn_r1p20(storage, mode, udeg);
+        if (pbits == 24) return step_kernel_fn_r1p24(storage, mode, udeg);
+        if (pbits == 27) return step_kernel_fn_r1p27(storage, mode, udeg);
+        return nullptr;
+    }
     if (!shed && !extra && lgR == 0) return step_kernel_fn_r1(storage, weighted, mode, udeg);
     if (shed) return extra ? step_kernel_fn_shed_extra(storage, weighted, mode, udeg)
                            : step_kernel_fn_shed(storage, weighted, mode, udeg);

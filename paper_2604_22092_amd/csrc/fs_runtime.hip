@@ -336,7 +336,18 @@ Layout::~Layout()
 }
 
 // Builds the layout of graph g for R replicas (Q = 64/R nodes per chunk).
-fs_status build_layout(const fs_graph* g, int32_t R, int32_t limit, int32_t seg_edges, std::shared_ptr<Layout>& out)
+// Bits per packed column for a graph of n nodes (ids below n), or 0 when
+// 27 bits do not hold them.
+int32_t packed_bits(int64_t n)
+{
+    if (n <= ((int64_t)1 << 20)) return 20;
+    if (n <= ((int64_t)1 << 24)) return 24;
+    if (n <= ((int64_t)1 << 27)) return 27;
+    return 0;
+}
+
+fs_status build_layout(const fs_graph* g, int32_t R, int32_t limit, int32_t seg_edges, bool pack,
+                       std::shared_ptr<Layout>& out)
 {
     auto L = std::make_shared<Layout>();
     L->limit = limit;
@@ -368,6 +379,11 @@ fs_status build_layout(const fs_graph* g, int32_t R, int32_t limit, int32_t seg_
         if ((int32_t)ldeg[i] != ud_all) ud_all = -1;
     if (ud_all > fsi::UNIFORM_MAX_DEG) ud_all = -1;
     L->udeg = ud_all;
+    // packed columns (uniform unweighted layouts of one replica): PB bits per
+    // column, a row's columns one bit stream of W words, word w of row q of
+    // chunk c at c * Q * W + w * Q + q (missing rows of the last chunk hold 0)
+    const int32_t PB = (pack && ud_all > 0 && R == 1 && g->d_weights == nullptr) ? packed_bits(n) : 0;
+    L->pbits = PB;
     std::vector<uint32_t> cbase((size_t)nch + 1);
     std::vector<int32_t> colt;
     std::vector<float> wt;
@@ -377,6 +393,20 @@ fs_status build_layout(const fs_graph* g, int32_t R, int32_t limit, int32_t seg_
     for (int64_t c = 0; c < nch; ++c) {
         cbase[c] = (uint32_t)colt.size();
         const int64_t n0 = c * Q, n1 = std::min(n, n0 + Q);
+        if (PB) {
+            const int32_t W = (ud_all * PB + 31) / 32;
+            std::vector<uint32_t> words((size_t)W * (size_t)Q, 0u);
+            for (int64_t i = n0; i < n1; ++i)
+                for (int32_t j = 0; j < ud_all; ++j) {
+                    const uint64_t v = (uint32_t)g->h_col_ind[rp[i] + j];
+                    const int32_t o = PB * j, lo = o >> 5, sh = o & 31;
+                    words[(size_t)lo * Q + (size_t)(i - n0)] |= (uint32_t)(v << sh);
+                    if (sh + PB > 32) words[(size_t)(lo + 1) * Q + (size_t)(i - n0)] |= (uint32_t)(v >> (32 - sh));
+                }
+            for (uint32_t x : words) colt.push_back((int32_t)x);
+            cdeg[c] = (uint8_t)ud_all;
+            continue;
+        }
         int32_t maxd = 0;
         bool same = n1 - n0 == Q;
         for (int64_t i = n0; i < n1; ++i) {
@@ -471,10 +501,19 @@ int32_t light_limit(int32_t heavy_deg)
     return heavy_deg < 0 ? cap : std::min(heavy_deg, cap);
 }
 
-bool layout_cached(fs_graph* g, int32_t R, int32_t heavy_deg, int32_t seg_edges)
+bool layout_cached(fs_graph* g, int32_t R, int32_t heavy_deg, int32_t seg_edges, bool pack)
 {
     std::lock_guard<std::mutex> lk(g->layout_mu);
-    return g->layouts.count(LayoutKey(R, light_limit(heavy_deg), seg_edges)) != 0;
+    return g->layouts.count(LayoutKey(R, light_limit(heavy_deg), seg_edges, pack ? 1 : 0)) != 0;
+}
+
+// Whether a sim of these parameters may take packed columns: the plain
+// single-replica step of an unweighted graph (no shedding, rate recording
+// or compaction), unless the caller asks for 32-bit columns.
+bool packing_allowed(const fs_graph* g, const fs_sim_params* p)
+{
+    return p->columns == FS_COLUMNS_AUTO && std::max(p->n_replicas, 1) == 1 && g->d_weights == nullptr &&
+           p->shedding == FS_SHED_CONSTANT && !p->record_rates && !p->compaction;
 }
 
 size_t sim_footprint(fs_graph* g, const fs_sim_params* p)
@@ -489,7 +528,8 @@ size_t sim_footprint(fs_graph* g, const fs_sim_params* p)
     b += H * R * 16 + chunk * grid * R * 16;            // history ring, count partials
     const int32_t hd = p->heavy_degree == 0 ? 64 : p->heavy_degree;
     const int32_t se = p->segment_edges == 0 ? 512 : p->segment_edges;
-    if (!layout_cached(g, (int32_t)R, hd, se)) {
+    const bool pk = packing_allowed(g, p);
+    if (!layout_cached(g, (int32_t)R, hd, se, pk)) {
         b += (size_t)g->nnz * 4 * (g->d_weights ? 2 : 1);   // transposed light rows (+ weights)
         b += (size_t)g->n * 2 + ((size_t)g->n * R / 64 + 1) * 5; // degrees, chunk metadata
         b += (size_t)g->nnz / 64 * 16 + (size_t)g->n * 4;   // heavy segments (upper bound)
@@ -499,7 +539,7 @@ size_t sim_footprint(fs_graph* g, const fs_sim_params* p)
         // pushed pressure of binned rows: at most nnz / (hd + 1) rows
         const size_t hubs = std::min<size_t>((size_t)g->n, (size_t)g->nnz / ((size_t)hd + 1));
         b += 5 * hubs * R * 4;
-        if (!layout_cached(g, (int32_t)R, hd, se)) b += ((size_t)g->n + 1) * 4 + (size_t)g->nnz * 4;
+        if (!layout_cached(g, (int32_t)R, hd, se, pk)) b += ((size_t)g->n + 1) * 4 + (size_t)g->nnz * 4;
     }
     if (p->record_rates) b += units * 4;
     if (p->shedding != FS_SHED_CONSTANT) b += units * 8;
@@ -530,7 +570,7 @@ fs_status apply_bins(fs_sim* s, int32_t heavy_deg, int32_t seg_edges)
     fs_graph* g = s->g;
     if (seg_edges < 64 || seg_edges > (1 << 20)) return fail(FS_ERR_INVALID_ARG, "segment_edges must be in [64, 2^20]");
     const int32_t limit = light_limit(heavy_deg);
-    const LayoutKey key(s->R, limit, seg_edges);
+    const LayoutKey key(s->R, limit, seg_edges, s->pack ? 1 : 0);
     std::shared_ptr<Layout> L;
     {
         std::lock_guard<std::mutex> lk(g->layout_mu);
@@ -538,7 +578,7 @@ fs_status apply_bins(fs_sim* s, int32_t heavy_deg, int32_t seg_edges)
         if (it != g->layouts.end()) {
             L = it->second;
         } else {
-            fs_status st = build_layout(g, s->R, limit, seg_edges, L);
+            fs_status st = build_layout(g, s->R, limit, seg_edges, s->pack, L);
             if (st != FS_OK) return st;
             g->layouts[key] = L;
         }
@@ -586,11 +626,21 @@ fs_status apply_bins(fs_sim* s, int32_t heavy_deg, int32_t seg_edges)
     s->args.chunk_meta = L->d_chunk_meta;
     s->args.orig_id = g->d_orig;
     s->args.udeg = L->udeg;
+    s->args.pbits = L->pbits;
     s->kfn = fsk::step_kernel_fn(s->storage, g->d_weights != nullptr, s->mode, L->udeg, s->d_shed[0] != nullptr,
-                                 s->d_rates != nullptr || s->d_act != nullptr, s->lgR);
+                                 s->d_rates != nullptr || s->d_act != nullptr, s->lgR, L->pbits);
+    if (!s->kfn) return fail(FS_ERR_DEVICE, "no step kernel for this configuration");
     s->args.col_t = L->d_col_t;
     s->args.w_t = L->d_w_t;
     return FS_OK;
+}
+
+fs_status use_plain_columns(fs_sim* s)
+{
+    if (!s->pack) return FS_OK;
+    s->pack = false;
+    if (!s->layout || s->layout->pbits == 0) return FS_OK;
+    return apply_bins(s, s->heavy_deg, s->seg_edges);
 }
 
 fsi::SumArgs summary_args(const fs_sim* s, uint32_t after)
@@ -845,7 +895,8 @@ fs_status apply_variant(fs_sim* s, int mode)
     s->args.summary = (const uint32_t*)s->d_summary;
     const bool weighted = s->g->d_weights != nullptr, shed = s->d_shed[0] != nullptr;
     s->kfn = fsk::step_kernel_fn(s->storage, weighted, mode, s->layout ? s->layout->udeg : -1, shed,
-                                 s->d_rates != nullptr || s->d_act != nullptr, s->lgR);
+                                 s->d_rates != nullptr || s->d_act != nullptr, s->lgR,
+                                 s->layout ? s->layout->pbits : 0);
     s->hfn = fsk::heavy_kernel_fn(weighted, shed, mode == fsi::MODE_RESIDENT);
     if (!s->kfn || !s->hfn) return fail(FS_ERR_DEVICE, "no step kernel for this configuration");
     FS_HIP(refresh_summary(s));
@@ -1249,6 +1300,8 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
     if (p->steps_per_graph < 0 || p->steps_per_graph > 100000)
         return fail(FS_ERR_INVALID_ARG, "steps_per_graph out of range");
     if (p->heavy_degree < -1) return fail(FS_ERR_INVALID_ARG, "heavy_degree must be -1, 0 or positive");
+    if (p->columns != FS_COLUMNS_AUTO && p->columns != FS_COLUMNS_PLAIN)
+        return fail(FS_ERR_INVALID_ARG, "columns must be FS_COLUMNS_AUTO or FS_COLUMNS_PLAIN");
     if (p->segment_edges != 0 && (p->segment_edges < 64 || p->segment_edges > (1 << 20)))
         return fail(FS_ERR_INVALID_ARG, "segment_edges must be 0 or in [64, 2^20]");
     if (p->adaptive) {
@@ -1437,8 +1490,9 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
         a.htab_inv = s->storage == 0 ? 1.0f / a.dt : 1.0f;
     }
     s->kfn = fsk::step_kernel_fn(s->storage, g->d_weights != nullptr, s->mode, -1, shedding,
-                                 s->d_rates != nullptr || s->d_act != nullptr, s->lgR);
+                                 s->d_rates != nullptr || s->d_act != nullptr, s->lgR, 0);
     s->hfn = fsk::heavy_kernel_fn(g->d_weights != nullptr, shedding, s->mode == fsi::MODE_RESIDENT);
+    s->pack = packing_allowed(g, p);
     if (!s->kfn || !s->hfn) {
         release_sim(s);
         return fail(FS_ERR_DEVICE, "no step kernel for this configuration");
@@ -1824,6 +1878,13 @@ fs_status fs_sim_get_variant(fs_sim* s, int32_t* variant)
 {
     if (!s || !variant) return fail(FS_ERR_INVALID_ARG, "NULL argument");
     *variant = s->mode + 1;
+    return FS_OK;
+}
+
+fs_status fs_sim_get_column_bits(fs_sim* s, int32_t* bits)
+{
+    if (!s || !bits) return fail(FS_ERR_INVALID_ARG, "NULL argument");
+    *bits = (s->layout && s->layout->pbits) ? s->layout->pbits : 32;
     return FS_OK;
 }
 

@@ -24,14 +24,16 @@ struct fs_batch;
 
 namespace fsr {
 // The degree-binned, wavefront-transposed layout of a graph's rows for one
-// replica count and one pair of bin thresholds (light-degree limit, heavy
-// segment length).  It depends on nothing else, so every sim of the graph
-// with these parameters shares one copy (the graph caches it).
+// replica count, one pair of bin thresholds (light-degree limit, heavy
+// segment length) and whether the columns of a uniform layout may be packed.
+// It depends on nothing else, so every sim of the graph with these
+// parameters shares one copy (the graph caches it).
 struct Layout {
     int32_t limit = 0;           // rows with more edges than this are heavy
     int32_t seg_edges = 0;
     uint32_t nseg = 0;           // heavy-row segments
     int32_t udeg = -1;           // the uniform light degree of every chunk, or -1
+    int32_t pbits = 0;           // packed columns of a uniform layout: bits per column, or 0
     int32_t* d_heavy_first = nullptr;
     fsi::Segment* d_segs = nullptr;
     uint16_t* d_ldeg = nullptr;       // light degree per node, HEAVY_ROW for binned rows
@@ -48,7 +50,7 @@ struct Layout {
     size_t bytes = 0;
     ~Layout();
 };
-using LayoutKey = std::tuple<int32_t, int32_t, int32_t>; // (replicas, limit, seg_edges)
+using LayoutKey = std::tuple<int32_t, int32_t, int32_t, int32_t>; // (replicas, limit, seg_edges, packing allowed)
 } // namespace fsr
 
 struct fs_graph {
@@ -128,6 +130,7 @@ struct fs_sim {
     std::shared_ptr<fsr::Layout> layout; // shared with the graph's other sims
     void* d_seg_part = nullptr;          // this sim's heavy-segment partials [segment][R]
     bool hub_push = false;               // binned rows take pushed pressure (StepArgs::hub_T)
+    bool pack = false;                   // a uniform layout's columns may be packed (StepArgs::pbits)
     uint32_t* d_hub = nullptr;           // hub_T [2][hub units] then hub_D [3][hub units]
     fsi::Segment* d_segs = nullptr;      // = layout->d_segs
     const void* hfn = nullptr;
@@ -204,5 +207,9 @@ size_t sim_footprint(fs_graph* g, const fs_sim_params* p);
 // d_nodes (synchronises the sim's stream, so d_nodes may be reused after).
 fs_status check_seed(const fs_sim* s, int32_t replica, int64_t count, const int64_t* nodes, int32_t compartment);
 fs_status seed_staged(fs_sim* s, int32_t replica, const int64_t* d_nodes, int64_t count, int32_t compartment);
+// Puts a sim whose layout has packed columns on the graph's layout with
+// 32-bit columns (the batch kernel reads only those); the sim's stream must
+// be idle.  Results do not change.
+fs_status use_plain_columns(fs_sim* s);
 
 } // namespace fsr

@@ -192,6 +192,38 @@ __device__ __forceinline__ float unit_hazard(const HazardDev* hz, int32_t same_k
     return isI ? fsd::hazard(hz[1], xa) : fsd::hazard(hz[0], xa);
 }
 
+// Packed columns of uniform layouts with one replica: PB bits per column
+// (enough for every node id of the graph), a row's columns concatenated into
+// one bit stream, column j at bits [PB j, PB j + PB) of the row's words.
+// Words of a row holding d columns (PB = 0: plain 32-bit columns).
+template <int PB>
+__host__ __device__ constexpr uint32_t words_per_row(uint32_t d)
+{
+    return PB ? (d * (uint32_t)PB + 31u) >> 5 : d;
+}
+
+// The first D columns of a row from its loaded words (a copy for PB = 0).
+// Every offset and shift is a compile-time constant: a field within one
+// word is one bit-field extract, one that spans two words a funnel shift
+// and a mask.
+template <int PB, int D>
+__device__ __forceinline__ void unpack_columns(const int32_t (&w)[UMAX], uint32_t (&c)[D])
+{
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        if (PB == 0) {
+            c[j] = (uint32_t)w[j];
+        } else {
+            const int o = PB * j, lo = o >> 5, sh = o & 31;
+            if (sh + PB <= 32)
+                c[j] = __builtin_amdgcn_ubfe((uint32_t)w[lo], (uint32_t)sh, (uint32_t)PB);
+            else
+                c[j] = __builtin_amdgcn_alignbit((uint32_t)w[lo + 1], (uint32_t)w[lo], (uint32_t)sh) &
+                       ((1u << PB) - 1u);
+        }
+    }
+}
+
 // The loads of one pass, as issued: chunk numbers and metadata are
 // wave-uniform; xr, agw and dgr are the raw state, age and degree words
 // (0 for lanes past the chunk's valid units), used only after the pass's
@@ -328,7 +360,7 @@ struct Ahead {
 // mixed layout's chunk comes the same way (without compaction): loaded in
 // this pass's issue it would hold the issue up, the column loads depending
 // on it, until every older load (the pass being processed) had arrived.
-template <int STORAGE, int UD, bool EXTRA, class age_t>
+template <int STORAGE, int UD, bool EXTRA, int PB, class age_t>
 __device__ __forceinline__ void issue_pass(const StepArgs& a, uint32_t first, uint32_t nwaves, uint32_t stride,
                                            uint32_t nchunks, uint32_t walk, uint32_t total, uint32_t lane,
                                            Pass<age_t>& P, Ahead& ah, const HubCtx& H)
@@ -349,7 +381,8 @@ __device__ __forceinline__ void issue_pass(const StepArgs& a, uint32_t first, ui
         }
         P.chk[u] = c;
         if (UNIFORM) {
-            P.base[u] = P.chk[u] * rows * (uint32_t)a.udeg;
+            // (packed columns: a row holds words_per_row(udeg) words)
+            P.base[u] = P.chk[u] * rows * words_per_row<PB>((uint32_t)a.udeg);
             P.ud[u] = P.live[u] ? (uint32_t)a.udeg : 0u;
         } else if (EXTRA && a.act) {
             const uint2 meta = a.chunk_meta[P.chk[u]];
@@ -386,12 +419,16 @@ __device__ __forceinline__ void issue_pass(const StepArgs& a, uint32_t first, ui
             P.ht[u] = ld32(H.tr, hub ? (H.t_prev + h) << 2 : OOB);
             P.hd[u] = ld32(H.tr, hub ? (H.d_cur + h) << 2 : OOB);
         }
-        // every uniform chunk preloads its first UMAX slots (slots past its
-        // degree are out of range)
+        // every uniform chunk preloads its first UMAX slots, or with packed
+        // columns the words that hold its first DEPTH columns (slots and
+        // words past its degree are out of range)
         const bool pre = P.ud[u] != MIXED_CHUNK;
-        const rsrc_t cr = make_rsrc(a.col_t + P.base[u], pre ? P.ud[u] * rows * 4u : 0u);
+        constexpr int LW = (int)words_per_row<PB>((uint32_t)DEPTH);
+        const rsrc_t cr = make_rsrc(a.col_t + P.base[u], pre ? words_per_row<PB>(P.ud[u]) * rows * 4u : 0u);
 #pragma unroll
-        for (int j = 0; j < DEPTH; ++j) P.c[u][j] = (int32_t)ld32(cr, ((uint32_t)j * rows + q) << 2);
+        for (int j = 0; j < LW; ++j) P.c[u][j] = (int32_t)ld32(cr, ((uint32_t)j * rows + q) << 2);
+#pragma unroll
+        for (int j = LW; j < DEPTH; ++j) P.c[u][j] = 0;
     }
 }
 
@@ -442,7 +479,7 @@ __device__ __forceinline__ void shed_pre(const StepArgs& a, const Pass<age_t>& P
 // prefix count), JB slots at a time.  With age-dependent shedding (SHED) a
 // source whose bit is set contributes its s(tau) from `shedr`; the value load
 // of every other slot is out of range and reads nothing.
-template <int MODE, bool WEIGHTED, int UD, bool SHED, class age_t>
+template <int MODE, bool WEIGHTED, int UD, bool SHED, int PB, class age_t>
 __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_t>& P, int u, bool want,
                                               uint32_t dg, const uint32_t* __restrict__ lds, rsrc_t gbits,
                                               rsrc_t shedr, const ShedPre& S, uint32_t lane)
@@ -471,12 +508,13 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
             // its group holds an infectious unit), and not at all when no
             // lane of the wavefront needs one: a load consumed here would
             // also wait for the next pass's prefetched loads
-            uint32_t src[DEPTH], bit[DEPTH];
+            uint32_t src[DEPTH], bit[DEPTH], col[DEPTH];
             bool use[DEPTH];
+            unpack_columns<PB, DEPTH>(P.c[u], col);
 #pragma unroll
             for (int j = 0; j < DEPTH; ++j) {
                 use[j] = (uint32_t)j < P.ud[u] && want;
-                src[j] = ((uint32_t)P.c[u][j] << lgR) + rep;
+                src[j] = (col[j] << lgR) + rep;
             }
             if (MODE == MODE_RESIDENT && !WEIGHTED) {
                 // unit weights: the count of set bits, masked once (slots past
@@ -704,7 +742,7 @@ __device__ __forceinline__ void compact_apply(uint32_t* xch, uint32_t lane, cons
 // hazards), draws, stores, next-infectivity words (and, with SHED, the
 // s(tau') values of the units infectious after the step), counts, and the
 // chunk's live flag for compaction.
-template <int STORAGE, bool WEIGHTED, int MODE, int UD, bool SHED, bool EXTRA, class age_t>
+template <int STORAGE, bool WEIGHTED, int MODE, int UD, bool SHED, bool EXTRA, int PB, class age_t>
 __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t>& P, uint32_t lane,
                                              const uint32_t* __restrict__ s_bits, rsrc_t gbits, rsrc_t shedr,
                                              float* __restrict__ shed_out, const ShedPre& sv,
@@ -739,7 +777,7 @@ __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t
         const bool heavy = !UNIFORM && dg[u] == HEAVY_ROW;
         const bool want = x[u] == ST_S && !heavy;
         const float p =
-            pressure_row<MODE, WEIGHTED, UD, SHED>(a, P, u, want, dg[u], s_bits, gbits, shedr, sv, lane);
+            pressure_row<MODE, WEIGHTED, UD, SHED, PB>(a, P, u, want, dg[u], s_bits, gbits, shedr, sv, lane);
         if (want) lam[u] = a.beta * p;
         if (!UNIFORM && !WEIGHTED && !SHED && H.on) {
             // pushed pressure: every binned unit, whatever its state, carries
@@ -909,13 +947,14 @@ __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t
 //    infection is sparse most neighbours fall in empty groups);
 //  MODE_STREAM: gathers read the bitmap through the caches.
 // The LDS variants run one workgroup of RESIDENT_TPB threads per compute unit.
-template <int STORAGE, bool WEIGHTED, int MODE, int UD, bool SHED, bool EXTRA, int TPB>
+template <int STORAGE, bool WEIGHTED, int MODE, int UD, bool SHED, bool EXTRA, int TPB, int PB = 0>
 __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uint32_t nblocks)
 {
     constexpr bool UNIFORM = UD != 0;
     constexpr bool USE_LDS = MODE != MODE_STREAM;
     using age_t = typename Store<STORAGE>::age_t;
     constexpr int NW = TPB / 64;
+    static_assert(PB == 0 || (UNIFORM && !WEIGHTED && !SHED && !EXTRA), "packed columns: plain uniform steps only");
 
     __shared__ uint32_t s_cnt[4 * 64];
     __shared__ __attribute__((aligned(16))) uint32_t s_bits[USE_LDS ? RESIDENT_BITS / 32 : 4];
@@ -992,7 +1031,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
             ahead.my[u] = m[1];
         }
     }
-    issue_pass<STORAGE, UD, EXTRA>(a, first, nwaves, stride, nchunks, walk, total, lane, P, ahead, H);
+    issue_pass<STORAGE, UD, EXTRA, PB>(a, first, nwaves, stride, nchunks, walk, total, lane, P, ahead, H);
     if (R > 1)
         for (uint32_t i = tid; i < 4 * R; i += TPB) s_cnt[i] = 0;
     if (USE_LDS) {
@@ -1025,26 +1064,26 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
         if (first >= walk) break;
         if (SPLIT) shed_pre<UD>(a, P, lane, s_bits, shedr, sv);
         if (PREFETCH)
-            issue_pass<STORAGE, UD, EXTRA>(a, first + stride, nwaves, stride, nchunks, walk, total, lane, P1,
+            issue_pass<STORAGE, UD, EXTRA, PB>(a, first + stride, nwaves, stride, nchunks, walk, total, lane, P1,
                                                 ahead, H);
-        process_pass<STORAGE, WEIGHTED, MODE, UD, SHED, EXTRA>(a, P, lane, s_bits, gbits, shedr, shed_out, sv,
+        process_pass<STORAGE, WEIGHTED, MODE, UD, SHED, EXTRA, PB>(a, P, lane, s_bits, gbits, shedr, shed_out, sv,
                                                                     s_xch[wave], k, bits_out, s_cnt, c0, c1, c2,
                                                                     c3, dt, lmax, H);
         first += stride;
         if (first >= walk) break;
         if (!PREFETCH)
-            issue_pass<STORAGE, UD, EXTRA>(a, first, nwaves, stride, nchunks, walk, total, lane, P1, ahead, H);
+            issue_pass<STORAGE, UD, EXTRA, PB>(a, first, nwaves, stride, nchunks, walk, total, lane, P1, ahead, H);
         issue_table<UNIFORM>(a, P1, lane);
         if (SPLIT) shed_pre<UD>(a, P1, lane, s_bits, shedr, sv);
         if (PREFETCH)
-            issue_pass<STORAGE, UD, EXTRA>(a, first + stride, nwaves, stride, nchunks, walk, total, lane, P,
+            issue_pass<STORAGE, UD, EXTRA, PB>(a, first + stride, nwaves, stride, nchunks, walk, total, lane, P,
                                                 ahead, H);
-        process_pass<STORAGE, WEIGHTED, MODE, UD, SHED, EXTRA>(a, P1, lane, s_bits, gbits, shedr, shed_out, sv,
+        process_pass<STORAGE, WEIGHTED, MODE, UD, SHED, EXTRA, PB>(a, P1, lane, s_bits, gbits, shedr, shed_out, sv,
                                                                     s_xch[wave], k, bits_out, s_cnt, c0, c1, c2,
                                                                     c3, dt, lmax, H);
         first += stride;
         if (!PREFETCH && first < walk)
-            issue_pass<STORAGE, UD, EXTRA>(a, first, nwaves, stride, nchunks, walk, total, lane, P, ahead, H);
+            issue_pass<STORAGE, UD, EXTRA, PB>(a, first, nwaves, stride, nchunks, walk, total, lane, P, ahead, H);
         if (first < walk) issue_table<UNIFORM>(a, P, lane);
     }
 
@@ -1113,6 +1152,32 @@ __global__ __launch_bounds__(TPB) void step_kernel_r1(StepArgs a)
     StepArgs b = a;
     b.lgR = 0;
     step_body<STORAGE, WEIGHTED, MODE, UD, false, false, TPB>(b, blockIdx.x, gridDim.x);
+}
+
+// The same with packed columns of PB bits (unit weights only).
+template <int STORAGE, int MODE, int UD, int PB, int TPB>
+__global__ __launch_bounds__(TPB) void step_kernel_r1p(StepArgs a)
+{
+    StepArgs b = a;
+    b.lgR = 0;
+    step_body<STORAGE, false, MODE, UD, false, false, TPB, PB>(b, blockIdx.x, gridDim.x);
+}
+
+template <int S, int U, int PB>
+const void* step_kernel_r1p_sel(int mode)
+{
+    if (mode == MODE_RESIDENT) return (const void*)&step_kernel_r1p<S, MODE_RESIDENT, U, PB, RESIDENT_TPB>;
+    if (mode == MODE_SUMMARY) return (const void*)&step_kernel_r1p<S, MODE_SUMMARY, U, PB, RESIDENT_TPB>;
+    return (const void*)&step_kernel_r1p<S, MODE_STREAM, U, PB, STREAM_TPB>;
+}
+
+// udeg: the uniform layout's degree (> 0); pbits: 20, 24 or 27
+template <int S, int PB>
+const void* step_kernel_r1p_depth(int mode, int udeg)
+{
+    if (udeg <= 8) return step_kernel_r1p_sel<S, 8, PB>(mode);
+    if (udeg <= 10) return step_kernel_r1p_sel<S, 10, PB>(mode);
+    return step_kernel_r1p_sel<S, 12, PB>(mode);
 }
 
 template <int S, bool W, int U>

@@ -86,6 +86,30 @@ def assert_matches_oracle(got, rp, ci, model, nseed, steps, compact, label, weig
         np.testing.assert_array_equal(gage, oage, err_msg=f"{label} replica {r} age")
 
 
+def test_packed_sim_joins_a_batch_with_plain_columns(graphs):
+    # a single-replica sim of a uniform unweighted graph starts with packed
+    # columns; joining a batch moves it to 32-bit columns (the batch step
+    # reads those) with its trajectory unchanged: equal to the packed solo
+    # run and to the oracle
+    (rp, ci, g), (_, m, _, ns) = graphs[0], SCEN[0]
+    steps = 60
+    ref = alone(g, rp, m, 1, ns, steps, fs.FS_STORAGE_FP32, variant=fs.VARIANT_STREAM)
+    with fs.Batch(fs.FS_STORAGE_FP32) as b:
+        s = new_sim(g, m, 1)
+        assert s.column_bits() == 20
+        s.seed(W.seed_nodes(len(rp) - 1, ns, 5), replica=-1)
+        s.step(10)  # some steps alone with packed columns first
+        b.add(s)
+        assert s.column_bits() == 32
+        b.step(steps - 10)
+        b.sync()
+        got = snapshot(s, steps)
+        b.remove(s)
+        s.close()
+    assert_same(got, ref, "packed member")
+    assert_matches_oracle(got, rp, ci, m, ns, steps, False, "packed member")
+
+
 @pytest.mark.parametrize("compact", [False, True], ids=["fp32", "compact"])
 def test_batch_members_equal_alone(graphs, compact):
     storage = fs.FS_STORAGE_COMPACT if compact else fs.FS_STORAGE_FP32

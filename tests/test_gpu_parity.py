@@ -409,6 +409,89 @@ def test_weighted_graph_one_step():
     check_one_step({"state": gst, "age": gage, "rates": rates}, ora, st, "weighted")
 
 
+# ------------------------------------------------------------- packed columns
+
+PACKED_CASES = [
+    # (n, degree, variant, compact): 20-bit columns up to 2^20 nodes, 24-bit
+    # above; ragged last chunks; degrees below and at the preload depths
+    (50_000, 10, fs.VARIANT_RESIDENT, False),
+    (50_004, 7, fs.VARIANT_RESIDENT, True),
+    (50_000, 10, fs.VARIANT_SUMMARY, True),
+    (50_000, 12, fs.VARIANT_STREAM, False),
+    (1_100_000, 8, fs.VARIANT_SUMMARY, True),
+    (1_100_002, 9, fs.VARIANT_STREAM, False),
+]
+
+
+@pytest.mark.parametrize("n,d,variant,compact", PACKED_CASES,
+                         ids=[f"n{c[0]}-d{c[1]}-v{c[2]}-{'compact' if c[3] else 'fp32'}" for c in PACKED_CASES])
+def test_packed_columns_match_plain_and_oracle(n, d, variant, compact):
+    # packed columns (the step's transposed copy of the graph with 20 or 24
+    # bits per column) give the trajectory of 32-bit columns bit for bit;
+    # the small graphs match the oracle's whole trajectory, the large ones
+    # its next step on a sample of nodes
+    rp, ci = W.random_regular(n, d, 5)
+    model = {"ei": W.LN_E, "ir": W.LN_I, "beta": 0.08, "dt": 0.1, "seed": 21}
+    seeds = W.seed_nodes(n, 60, 4)
+    steps = 120
+    storage = storage_of(compact)
+    out = {}
+    with fs.Graph(rp, ci) as g:
+        for cols in (fs.FS_COLUMNS_AUTO, fs.FS_COLUMNS_PLAIN):
+            with fs.Sim.from_model(g, model, variant=variant, storage=storage, steps_per_graph=20,
+                                   history_len=steps, columns=cols) as sim:
+                out[cols] = sim.column_bits()
+                sim.seed(seeds, replica=0)
+                sim.step(steps)
+                out[cols, "state"] = sim.get_state(0)
+                out[cols, "hist"] = sim.history(0, steps)
+                if cols == fs.FS_COLUMNS_AUTO:
+                    sim.step(1)
+                    out["next"] = sim.get_state(0)
+    assert out[fs.FS_COLUMNS_AUTO] == (20 if n <= 1 << 20 else 24)
+    assert out[fs.FS_COLUMNS_PLAIN] == 32
+    np.testing.assert_array_equal(out[fs.FS_COLUMNS_AUTO, "hist"], out[fs.FS_COLUMNS_PLAIN, "hist"])
+    for a, b in zip(out[fs.FS_COLUMNS_AUTO, "state"], out[fs.FS_COLUMNS_PLAIN, "state"]):
+        np.testing.assert_array_equal(a, b)
+    st, age, k = out[fs.FS_COLUMNS_AUTO, "state"]
+    assert (st != 0).sum() > 100  # the epidemic is under way
+    if n <= 100_000:
+        ost, oage, ohist = oracle.run((rp, ci), model, W.initial_state(n, seeds), zero_age(n, compact), steps,
+                                      compact=compact)
+        np.testing.assert_array_equal(out[fs.FS_COLUMNS_AUTO, "hist"], ohist)
+        np.testing.assert_array_equal(st, ost)
+        np.testing.assert_array_equal(age, oage)
+    else:
+        gst, gage, _ = out["next"]
+        nodes = np.unique(np.concatenate([np.random.default_rng(1).choice(n, 30_000, replace=False),
+                                          np.flatnonzero(st != 0)[:30_000]]))
+        ora = oracle.step_nodes((rp, ci), model, st, age, (st == 2).astype(np.float64), k, nodes,
+                                compact=compact)
+        nm = guard_band_mismatches(gst[nodes], ora["state"], ora["u"], ora["q"], "packed sample")
+        check_mismatch_budget(nm, len(nodes), "packed sample")
+        same = gst[nodes] == ora["state"]
+        np.testing.assert_array_equal(gage[nodes][same], ora["age"][same])
+
+
+def test_column_bits_follow_the_rules():
+    rp, ci = W.random_regular(3000, 6, 1)
+    model = {"ei": W.LN_E, "ir": W.LN_I, "beta": 0.1, "dt": 0.1, "seed": 1}
+    w = np.full(len(ci), 0.5, np.float32)
+    brp, bci = W.barabasi_albert(3000, 3, 2)
+    with fs.Graph(rp, ci) as g, fs.Graph(rp, ci, w) as gw, fs.Graph(brp, bci) as gb:
+        for graph, kw, bits in [
+            (g, {}, 20), (g, {"variant": fs.VARIANT_STREAM}, 20), (g, {"variant": fs.VARIANT_SUMMARY}, 20),
+            (g, {"storage": fs.FS_STORAGE_COMPACT}, 20), (g, {"adaptive": True}, 20),
+            (g, {"replicas": 4}, 32), (g, {"record_rates": True}, 32), (g, {"compaction": True}, 32),
+            (g, {"columns": fs.FS_COLUMNS_PLAIN}, 32), (g, {"shed": ("density", W.LN_I, 1.0)}, 32),
+            (gw, {}, 32), (gb, {}, 32),
+        ]:
+            with fs.Sim.from_model(graph, model, **kw) as sim:
+                assert sim.column_bits() == bits, kw
+        with pytest.raises(fs.FsError):
+            fs.Sim.from_model(g, model, columns=2)
+
+
 # ------------------------------------------------------------- edge cases
 
 @pytest.mark.gpu
@@ -526,6 +609,16 @@ def test_full_size_regular10_n1e6_sampled_parity():
         gst, gage, _ = sim.get_state(0)
         rates = sim.rates(0)
         sim.close()
+        # the benchmark's own launch (no rate recording) runs the step with
+        # 20-bit packed columns: the same trajectory, bit for bit
+        with fs.Sim.from_model(g, model, steps_per_graph=50) as packed:
+            assert packed.column_bits() == 20
+            packed.seed(seeds, replica=0)
+            packed.step(401)
+            pst, page, _ = packed.get_state(0)
+            np.testing.assert_array_equal(packed.history(0, 400), hist)
+            np.testing.assert_array_equal(pst, gst)
+            np.testing.assert_array_equal(page, gage)
     nodes = np.random.default_rng(0).choice(n, 100_000, replace=False)
     iota = (st == 2).astype(np.float64)
     ora = oracle.step_nodes((rp, ci), model, st, age, iota, k, nodes)

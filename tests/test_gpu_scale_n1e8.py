@@ -81,6 +81,21 @@ def test_n1e8_sampled_one_step_parity(big_graph, compact):
             checked += len(nodes)
             moved += int((gst[nodes] != st[nodes]).sum())
             del st, age, gst, gage, rates, iota
+        # the benchmark's launch configuration (no rate recording) runs the
+        # step with 27-bit packed columns: the same trajectory, bit for bit
+        k_end = sim.step_index()
+        fst, fage, _ = sim.get_state(0)
+        fhist = sim.history(0, k_end)
+        with fs.Sim.from_model(g, model, storage=storage, steps_per_graph=50) as packed:
+            assert packed.column_bits() == 27
+            packed.seed(seeds, replica=0)
+            packed.step(k_end)
+            pst, page, pk = packed.get_state(0)
+            assert pk == k_end
+            np.testing.assert_array_equal(packed.history(0, k_end), fhist)
+            np.testing.assert_array_equal(pst, fst)
+            np.testing.assert_array_equal(page, fage)
+        del fst, fage, pst, page
     finally:
         sim.close()
     check_mismatch_budget(mism, checked, label)
