@@ -108,13 +108,15 @@ typedef struct fs_dist {
 
 /* Column storage of the step's transposed copy of the graph (the gather of
  * Eq. (influence) reads it every step; the caller's CSR is unchanged).
- *   FS_COLUMNS_AUTO:  where the step supports it -- every row of an
- *                     unweighted graph has one degree (at most 12), one
- *                     replica, constant shedding, no rate recording and no
- *                     compaction -- each column takes 20, 24 or 27 bits (the
- *                     fewest of these that hold the node ids: n <= 2^20,
- *                     2^24, 2^27), a row's columns packed into one bit
- *                     stream; else 32 bits.
+ *   FS_COLUMNS_AUTO:  where the step supports it -- an unweighted graph of at
+ *                     most 2^27 nodes, one replica, constant shedding, no rate
+ *                     recording and no compaction -- the rows of every 64-node
+ *                     chunk that share one degree of at most 12 (every chunk of
+ *                     a regular graph; almost all light rows of a degree-sorted
+ *                     one) store each column in 20, 24 or 27 bits (the fewest
+ *                     of these that hold the node ids: n <= 2^20, 2^24, 2^27),
+ *                     a row's columns packed into one bit stream; the other
+ *                     rows keep 32 bits.
  *   FS_COLUMNS_PLAIN: 32 bits per column always.
  * Results are identical.  A sim with packed columns that joins a batch moves
  * to 32-bit columns (the batch step reads those). */

@@ -19,9 +19,9 @@ namespace fsk {
 // active-chunk list of compaction (StepArgs::act, live).
 // lgR: log2 of the replica count; sims with one replica (and neither
 // shedding nor the extra checks) take an instantiation that knows it.
-// pbits (StepArgs::pbits): packed columns of a uniform layout (20, 24 or 27
-// bits; unit weights, one replica, neither shedding nor the extra checks),
-// or 0; nullptr for any other combination with pbits != 0.
+// pbits (StepArgs::pbits): packed columns (20, 24 or 27 bits; unit weights,
+// one replica, neither shedding nor the extra checks), or 0; nullptr for any
+// other combination with pbits != 0.
 const void* step_kernel_fn(int storage, bool weighted, int mode, int udeg, bool shed, bool extra, int lgR,
                            int pbits);
 const void* step_kernel_fn_r1(int storage, bool weighted, int mode, int udeg);

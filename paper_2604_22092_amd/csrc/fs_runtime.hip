@@ -379,10 +379,12 @@ fs_status build_layout(const fs_graph* g, int32_t R, int32_t limit, int32_t seg_
         if ((int32_t)ldeg[i] != ud_all) ud_all = -1;
     if (ud_all > fsi::UNIFORM_MAX_DEG) ud_all = -1;
     L->udeg = ud_all;
-    // packed columns (uniform unweighted layouts of one replica): PB bits per
-    // column, a row's columns one bit stream of W words, word w of row q of
-    // chunk c at c * Q * W + w * Q + q (missing rows of the last chunk hold 0)
-    const int32_t PB = (pack && ud_all > 0 && R == 1 && g->d_weights == nullptr) ? packed_bits(n) : 0;
+    // packed columns (unweighted layouts of one replica): every chunk whose
+    // rows share one degree d <= UNIFORM_MAX_DEG (all of a uniform layout's,
+    // the last one padded with rows of columns 0) stores PB bits per column,
+    // a row's columns one bit stream of W = ceil(d PB / 32) words, word w of
+    // row q at the chunk's base + w * Q + q; other chunks keep 32-bit columns
+    const int32_t PB = (pack && R == 1 && g->d_weights == nullptr) ? packed_bits(n) : 0;
     L->pbits = PB;
     std::vector<uint32_t> cbase((size_t)nch + 1);
     std::vector<int32_t> colt;
@@ -393,18 +395,25 @@ fs_status build_layout(const fs_graph* g, int32_t R, int32_t limit, int32_t seg_
     for (int64_t c = 0; c < nch; ++c) {
         cbase[c] = (uint32_t)colt.size();
         const int64_t n0 = c * Q, n1 = std::min(n, n0 + Q);
-        if (PB) {
-            const int32_t W = (ud_all * PB + 31) / 32;
+        int32_t pd = ud_all; // the packed chunk's degree, or -1
+        if (PB && pd < 0) {
+            pd = n1 - n0 == Q ? (int32_t)ldeg[n0] : -1;
+            for (int64_t i = n0; i < n1 && pd >= 0; ++i)
+                if (ldeg[i] == fsi::HEAVY_ROW || (int32_t)ldeg[i] != pd) pd = -1;
+            if (pd > fsi::UNIFORM_MAX_DEG) pd = -1;
+        }
+        if (PB && pd >= 0) {
+            const int32_t W = (pd * PB + 31) / 32;
             std::vector<uint32_t> words((size_t)W * (size_t)Q, 0u);
             for (int64_t i = n0; i < n1; ++i)
-                for (int32_t j = 0; j < ud_all; ++j) {
+                for (int32_t j = 0; j < pd; ++j) {
                     const uint64_t v = (uint32_t)g->h_col_ind[rp[i] + j];
                     const int32_t o = PB * j, lo = o >> 5, sh = o & 31;
                     words[(size_t)lo * Q + (size_t)(i - n0)] |= (uint32_t)(v << sh);
                     if (sh + PB > 32) words[(size_t)(lo + 1) * Q + (size_t)(i - n0)] |= (uint32_t)(v >> (32 - sh));
                 }
             for (uint32_t x : words) colt.push_back((int32_t)x);
-            cdeg[c] = (uint8_t)ud_all;
+            cdeg[c] = (uint8_t)pd;
             continue;
         }
         int32_t maxd = 0;

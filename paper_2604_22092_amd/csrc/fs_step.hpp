@@ -421,10 +421,12 @@ __device__ __forceinline__ void issue_pass(const StepArgs& a, uint32_t first, ui
         }
         // every uniform chunk preloads its first UMAX slots, or with packed
         // columns the words that hold its first DEPTH columns (slots and
-        // words past its degree are out of range)
+        // words past its degree are out of range).  In a mixed layout, the
+        // chunks deeper than UMAX keep 32-bit columns.
         const bool pre = P.ud[u] != MIXED_CHUNK;
-        constexpr int LW = (int)words_per_row<PB>((uint32_t)DEPTH);
-        const rsrc_t cr = make_rsrc(a.col_t + P.base[u], pre ? words_per_row<PB>(P.ud[u]) * rows * 4u : 0u);
+        constexpr int LW = UNIFORM ? (int)words_per_row<PB>((uint32_t)DEPTH) : DEPTH;
+        const uint32_t rw = (PB && P.ud[u] <= (uint32_t)UMAX) ? words_per_row<PB>(P.ud[u]) : P.ud[u];
+        const rsrc_t cr = make_rsrc(a.col_t + P.base[u], pre ? rw * rows * 4u : 0u);
 #pragma unroll
         for (int j = 0; j < LW; ++j) P.c[u][j] = (int32_t)ld32(cr, ((uint32_t)j * rows + q) << 2);
 #pragma unroll
@@ -510,7 +512,10 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
             // also wait for the next pass's prefetched loads
             uint32_t src[DEPTH], bit[DEPTH], col[DEPTH];
             bool use[DEPTH];
-            unpack_columns<PB, DEPTH>(P.c[u], col);
+            if (PB && !UNIFORM && P.ud[u] > (uint32_t)UMAX)
+                unpack_columns<0, DEPTH>(P.c[u], col); // (a deep chunk: 32-bit columns)
+            else
+                unpack_columns<PB, DEPTH>(P.c[u], col);
 #pragma unroll
             for (int j = 0; j < DEPTH; ++j) {
                 use[j] = (uint32_t)j < P.ud[u] && want;
@@ -954,7 +959,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
     constexpr bool USE_LDS = MODE != MODE_STREAM;
     using age_t = typename Store<STORAGE>::age_t;
     constexpr int NW = TPB / 64;
-    static_assert(PB == 0 || (UNIFORM && !WEIGHTED && !SHED && !EXTRA), "packed columns: plain uniform steps only");
+    static_assert(PB == 0 || (!WEIGHTED && !SHED && !EXTRA), "packed columns: plain unit-weight steps only");
 
     __shared__ uint32_t s_cnt[4 * 64];
     __shared__ __attribute__((aligned(16))) uint32_t s_bits[USE_LDS ? RESIDENT_BITS / 32 : 4];
@@ -1171,10 +1176,11 @@ const void* step_kernel_r1p_sel(int mode)
     return (const void*)&step_kernel_r1p<S, MODE_STREAM, U, PB, STREAM_TPB>;
 }
 
-// udeg: the uniform layout's degree (> 0); pbits: 20, 24 or 27
+// udeg: the uniform layout's degree, or -1 for a mixed layout
 template <int S, int PB>
 const void* step_kernel_r1p_depth(int mode, int udeg)
 {
+    if (udeg < 0) return step_kernel_r1p_sel<S, 0, PB>(mode);
     if (udeg <= 8) return step_kernel_r1p_sel<S, 8, PB>(mode);
     if (udeg <= 10) return step_kernel_r1p_sel<S, 10, PB>(mode);
     return step_kernel_r1p_sel<S, 12, PB>(mode);

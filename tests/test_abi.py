@@ -72,6 +72,7 @@ def test_null_handles_rejected():
     assert L.fs_sim_seed_noalloc(None, 0, 0, None, 1) == 1
     assert L.fs_sim_autotune(None, None, None) == 1
     assert L.fs_sim_get_variant(None, None) == 1
+    assert L.fs_sim_get_column_bits(None, None) == 1
 
 
 def test_seed_noalloc_limit_matches_the_header():

@@ -473,6 +473,49 @@ def test_packed_columns_match_plain_and_oracle(n, d, variant, compact):
         np.testing.assert_array_equal(gage[nodes][same], ora["age"][same])
 
 
+BA_PACKED_CASES = [
+    # (variant, heavy_degree, segment_edges, compact): degree-sorted graphs
+    # pack the chunks whose rows share one degree of at most 12; binned rows
+    # (pushed pressure), deeper uniform chunks and mixed chunks keep 32 bits
+    (fs.VARIANT_RESIDENT, 0, 0, False),
+    (fs.VARIANT_RESIDENT, 12, 512, True),
+    (fs.VARIANT_SUMMARY, 32, 256, False),
+    (fs.VARIANT_STREAM, -1, 0, False),
+]
+
+
+@pytest.mark.parametrize("variant,hd,se,compact", BA_PACKED_CASES,
+                         ids=[f"v{c[0]}-bins{c[1]}-{c[2]}-{'compact' if c[3] else 'fp32'}" for c in BA_PACKED_CASES])
+def test_packed_columns_degree_sorted_graph(variant, hd, se, compact):
+    n = 30_000
+    rp, ci = W.barabasi_albert(n, 4, 8)
+    model = {"ei": ("erlang", 3, 1.0), "ir": ("weibull", 2.0, 6.0), "beta": 0.05, "dt": 0.1, "seed": 17}
+    seeds = W.seed_nodes(n, 30, 3)
+    steps = 150
+    storage = storage_of(compact)
+    out = {}
+    with fs.Graph(rp, ci) as g:
+        for cols in (fs.FS_COLUMNS_AUTO, fs.FS_COLUMNS_PLAIN):
+            with fs.Sim.from_model(g, model, variant=variant, storage=storage, steps_per_graph=25,
+                                   history_len=steps, heavy_degree=hd, segment_edges=se, columns=cols) as sim:
+                out[cols] = sim.column_bits()
+                sim.seed(seeds, replica=0)
+                sim.step(steps)
+                out[cols, "state"] = sim.get_state(0)
+                out[cols, "hist"] = sim.history(0, steps)
+    assert out[fs.FS_COLUMNS_AUTO] == 20 and out[fs.FS_COLUMNS_PLAIN] == 32
+    np.testing.assert_array_equal(out[fs.FS_COLUMNS_AUTO, "hist"], out[fs.FS_COLUMNS_PLAIN, "hist"])
+    for a, b in zip(out[fs.FS_COLUMNS_AUTO, "state"], out[fs.FS_COLUMNS_PLAIN, "state"]):
+        np.testing.assert_array_equal(a, b)
+    ost, oage, ohist = oracle.run((rp, ci), model, W.initial_state(n, seeds), zero_age(n, compact), steps,
+                                  compact=compact)
+    np.testing.assert_array_equal(out[fs.FS_COLUMNS_AUTO, "hist"], ohist)
+    st, age, _ = out[fs.FS_COLUMNS_AUTO, "state"]
+    np.testing.assert_array_equal(st, ost)
+    np.testing.assert_array_equal(age, oage)
+    assert ohist[-1, 0] < n - 1000  # the epidemic spread
+
+
 def test_column_bits_follow_the_rules():
     rp, ci = W.random_regular(3000, 6, 1)
     model = {"ei": W.LN_E, "ir": W.LN_I, "beta": 0.1, "dt": 0.1, "seed": 1}
@@ -484,7 +527,7 @@ def test_column_bits_follow_the_rules():
             (g, {"storage": fs.FS_STORAGE_COMPACT}, 20), (g, {"adaptive": True}, 20),
             (g, {"replicas": 4}, 32), (g, {"record_rates": True}, 32), (g, {"compaction": True}, 32),
             (g, {"columns": fs.FS_COLUMNS_PLAIN}, 32), (g, {"shed": ("density", W.LN_I, 1.0)}, 32),
-            (gw, {}, 32), (gb, {}, 32),
+            (gw, {}, 32), (gb, {}, 20), (gb, {"replicas": 2}, 32),
         ]:
             with fs.Sim.from_model(graph, model, **kw) as sim:
                 assert sim.column_bits() == bits, kw
