@@ -516,13 +516,13 @@ bool layout_cached(fs_graph* g, int32_t R, int32_t heavy_deg, int32_t seg_edges,
     return g->layouts.count(LayoutKey(R, light_limit(heavy_deg), seg_edges, pack ? 1 : 0)) != 0;
 }
 
-// Whether a sim of these parameters may take packed columns: the plain
-// single-replica step of an unweighted graph (no shedding, rate recording
-// or compaction), unless the caller asks for 32-bit columns.
+// Whether a sim of these parameters may take packed columns: the
+// single-replica step of an unweighted graph without rate recording or
+// compaction, unless the caller asks for 32-bit columns.
 bool packing_allowed(const fs_graph* g, const fs_sim_params* p)
 {
     return p->columns == FS_COLUMNS_AUTO && std::max(p->n_replicas, 1) == 1 && g->d_weights == nullptr &&
-           p->shedding == FS_SHED_CONSTANT && !p->record_rates && !p->compaction;
+           !p->record_rates && !p->compaction;
 }
 
 size_t sim_footprint(fs_graph* g, const fs_sim_params* p)

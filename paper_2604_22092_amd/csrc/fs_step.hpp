@@ -238,6 +238,19 @@ struct Pass {
     uint32_t ht[CU], hd[CU]; // pushed pressure of a binned unit: count of the last step, delta
 };
 
+// The first DEPTH columns of chunk u of a pass: unpacked from its words, or
+// (PB = 0, or a chunk of a mixed layout deeper than UMAX, which keeps 32-bit
+// columns) copied.
+template <int PB, int UD, class age_t>
+__device__ __forceinline__ void pass_columns(const Pass<age_t>& P, int u, uint32_t (&col)[UD != 0 ? UD : UMAX])
+{
+    constexpr int DEPTH = UD != 0 ? UD : UMAX;
+    if (PB && UD == 0 && P.ud[u] > (uint32_t)UMAX)
+        unpack_columns<0, DEPTH>(P.c[u], col);
+    else
+        unpack_columns<PB, DEPTH>(P.c[u], col);
+}
+
 // Pushed pressure of binned rows (StepArgs::hub_T) within one step launch:
 // the slots of this step (offsets in units of the hub arrays), and the
 // wavefront's queue of units that enter or leave I, whose pushes are made
@@ -443,7 +456,7 @@ struct ShedPre {
     float v[CU][UMAX];
 };
 
-template <int UD, class age_t>
+template <int UD, int PB, class age_t>
 __device__ __forceinline__ void shed_pre(const StepArgs& a, const Pass<age_t>& P, uint32_t lane,
                                          const uint32_t* __restrict__ lds, rsrc_t shedr, ShedPre& S)
 {
@@ -459,10 +472,11 @@ __device__ __forceinline__ void shed_pre(const StepArgs& a, const Pass<age_t>& P
         const bool want = x == ST_S && (UNIFORM || dg != HEAVY_ROW);
         const bool pre = UNIFORM || P.ud[u] != MIXED_CHUNK;
         // (every LDS word read first, then the value loads of the set bits)
-        uint32_t src[DEPTH], wv[DEPTH];
+        uint32_t src[DEPTH], wv[DEPTH], col[DEPTH];
+        pass_columns<PB, UD>(P, u, col);
 #pragma unroll
         for (int j = 0; j < DEPTH; ++j) {
-            src[j] = ((uint32_t)P.c[u][j] << lgR) + rep;
+            src[j] = (col[j] << lgR) + rep;
             wv[j] = lds[src[j] >> 5];
         }
 #pragma unroll
@@ -503,6 +517,8 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
         const uint32_t q = lane >> lgR;
         const rsrc_t wr = make_rsrc(WEIGHTED ? (const void*)(a.w_t + P.base[u]) : (const void*)a.w_t,
                                     WEIGHTED ? P.ud[u] * rows * 4u : 0u);
+        uint32_t col[DEPTH];
+        pass_columns<PB, UD>(P, u, col);
         if (!SHED) {
             // every slot's LDS word is read before any is used (one wait for
             // all); the global bitmap words, in the variants that need them,
@@ -510,12 +526,8 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
             // its group holds an infectious unit), and not at all when no
             // lane of the wavefront needs one: a load consumed here would
             // also wait for the next pass's prefetched loads
-            uint32_t src[DEPTH], bit[DEPTH], col[DEPTH];
+            uint32_t src[DEPTH], bit[DEPTH];
             bool use[DEPTH];
-            if (PB && !UNIFORM && P.ud[u] > (uint32_t)UMAX)
-                unpack_columns<0, DEPTH>(P.c[u], col); // (a deep chunk: 32-bit columns)
-            else
-                unpack_columns<PB, DEPTH>(P.c[u], col);
 #pragma unroll
             for (int j = 0; j < DEPTH; ++j) {
                 use[j] = (uint32_t)j < P.ud[u] && want;
@@ -593,7 +605,7 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
                 if (SPLIT) {
                     v = S.v[u][j];
                 } else {
-                    const uint32_t src = ((uint32_t)P.c[u][j] << lgR) + rep;
+                    const uint32_t src = (col[j] << lgR) + rep;
                     const uint32_t b = fetch_bit<MODE>(lds, gbits, src, a.lg_gran, use);
                     v = __uint_as_float(ld32(shedr, b ? src << 2 : OOB));
                 }
@@ -959,7 +971,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
     constexpr bool USE_LDS = MODE != MODE_STREAM;
     using age_t = typename Store<STORAGE>::age_t;
     constexpr int NW = TPB / 64;
-    static_assert(PB == 0 || (!WEIGHTED && !SHED && !EXTRA), "packed columns: plain unit-weight steps only");
+    static_assert(PB == 0 || (!WEIGHTED && !EXTRA), "packed columns: unit weights, no extra checks");
 
     __shared__ uint32_t s_cnt[4 * 64];
     __shared__ __attribute__((aligned(16))) uint32_t s_bits[USE_LDS ? RESIDENT_BITS / 32 : 4];
@@ -1067,7 +1079,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
     ShedPre sv;
     for (;;) {
         if (first >= walk) break;
-        if (SPLIT) shed_pre<UD>(a, P, lane, s_bits, shedr, sv);
+        if (SPLIT) shed_pre<UD, PB>(a, P, lane, s_bits, shedr, sv);
         if (PREFETCH)
             issue_pass<STORAGE, UD, EXTRA, PB>(a, first + stride, nwaves, stride, nchunks, walk, total, lane, P1,
                                                 ahead, H);
@@ -1079,7 +1091,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
         if (!PREFETCH)
             issue_pass<STORAGE, UD, EXTRA, PB>(a, first, nwaves, stride, nchunks, walk, total, lane, P1, ahead, H);
         issue_table<UNIFORM>(a, P1, lane);
-        if (SPLIT) shed_pre<UD>(a, P1, lane, s_bits, shedr, sv);
+        if (SPLIT) shed_pre<UD, PB>(a, P1, lane, s_bits, shedr, sv);
         if (PREFETCH)
             issue_pass<STORAGE, UD, EXTRA, PB>(a, first + stride, nwaves, stride, nchunks, walk, total, lane, P,
                                                 ahead, H);
@@ -1159,31 +1171,32 @@ __global__ __launch_bounds__(TPB) void step_kernel_r1(StepArgs a)
     step_body<STORAGE, WEIGHTED, MODE, UD, false, false, TPB>(b, blockIdx.x, gridDim.x);
 }
 
-// The same with packed columns of PB bits (unit weights only).
-template <int STORAGE, int MODE, int UD, int PB, int TPB>
+// The same with packed columns of PB bits (unit weights only), with
+// constant or (SHED) age-dependent shedding.
+template <int STORAGE, int MODE, int UD, int PB, bool SHED, int TPB>
 __global__ __launch_bounds__(TPB) void step_kernel_r1p(StepArgs a)
 {
     StepArgs b = a;
     b.lgR = 0;
-    step_body<STORAGE, false, MODE, UD, false, false, TPB, PB>(b, blockIdx.x, gridDim.x);
+    step_body<STORAGE, false, MODE, UD, SHED, false, TPB, PB>(b, blockIdx.x, gridDim.x);
 }
 
-template <int S, int U, int PB>
+template <int S, int U, int PB, bool SHED>
 const void* step_kernel_r1p_sel(int mode)
 {
-    if (mode == MODE_RESIDENT) return (const void*)&step_kernel_r1p<S, MODE_RESIDENT, U, PB, RESIDENT_TPB>;
-    if (mode == MODE_SUMMARY) return (const void*)&step_kernel_r1p<S, MODE_SUMMARY, U, PB, RESIDENT_TPB>;
-    return (const void*)&step_kernel_r1p<S, MODE_STREAM, U, PB, STREAM_TPB>;
+    if (mode == MODE_RESIDENT) return (const void*)&step_kernel_r1p<S, MODE_RESIDENT, U, PB, SHED, RESIDENT_TPB>;
+    if (mode == MODE_SUMMARY) return (const void*)&step_kernel_r1p<S, MODE_SUMMARY, U, PB, SHED, RESIDENT_TPB>;
+    return (const void*)&step_kernel_r1p<S, MODE_STREAM, U, PB, SHED, STREAM_TPB>;
 }
 
 // udeg: the uniform layout's degree, or -1 for a mixed layout
-template <int S, int PB>
+template <int S, int PB, bool SHED>
 const void* step_kernel_r1p_depth(int mode, int udeg)
 {
-    if (udeg < 0) return step_kernel_r1p_sel<S, 0, PB>(mode);
-    if (udeg <= 8) return step_kernel_r1p_sel<S, 8, PB>(mode);
-    if (udeg <= 10) return step_kernel_r1p_sel<S, 10, PB>(mode);
-    return step_kernel_r1p_sel<S, 12, PB>(mode);
+    if (udeg < 0) return step_kernel_r1p_sel<S, 0, PB, SHED>(mode);
+    if (udeg <= 8) return step_kernel_r1p_sel<S, 8, PB, SHED>(mode);
+    if (udeg <= 10) return step_kernel_r1p_sel<S, 10, PB, SHED>(mode);
+    return step_kernel_r1p_sel<S, 12, PB, SHED>(mode);
 }
 
 template <int S, bool W, int U>

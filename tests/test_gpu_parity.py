@@ -526,7 +526,7 @@ def test_column_bits_follow_the_rules():
             (g, {}, 20), (g, {"variant": fs.VARIANT_STREAM}, 20), (g, {"variant": fs.VARIANT_SUMMARY}, 20),
             (g, {"storage": fs.FS_STORAGE_COMPACT}, 20), (g, {"adaptive": True}, 20),
             (g, {"replicas": 4}, 32), (g, {"record_rates": True}, 32), (g, {"compaction": True}, 32),
-            (g, {"columns": fs.FS_COLUMNS_PLAIN}, 32), (g, {"shed": ("density", W.LN_I, 1.0)}, 32),
+            (g, {"columns": fs.FS_COLUMNS_PLAIN}, 32), (g, {"shed": ("density", W.LN_I, 1.0)}, 20),
             (gw, {}, 32), (gb, {}, 20), (gb, {"replicas": 2}, 32),
         ]:
             with fs.Sim.from_model(graph, model, **kw) as sim:

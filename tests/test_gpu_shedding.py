@@ -205,6 +205,35 @@ def test_unit_exponential_hazard_profile_equals_constant_shedding(gname, variant
     assert out[0][0][2][-1, 0] < n - 100   # the epidemic moved
 
 
+PACKED_CASES = [c for c in CASES if c[0] != "weighted"]
+
+
+@pytest.mark.parametrize("gname,variant,compact,shed", PACKED_CASES,
+                         ids=["-".join([c[0], c[1], "compact" if c[2] else "fp32", c[3]]) for c in PACKED_CASES])
+def test_packed_columns_with_shedding(gname, variant, compact, shed):
+    """Single-replica sims of unweighted graphs take packed columns with
+    age-dependent shedding too: the trajectory of 32-bit columns, bit for
+    bit (the latter are checked against the oracle above)."""
+    rp, ci, _ = graph(gname)
+    n = len(rp) - 1
+    model = {"ei": W.LN_E, "ir": W.LN_I, "beta": 0.3, "dt": 0.1, "seed": 5, "shed": SHEDS[shed]}
+    storage = fs.FS_STORAGE_COMPACT if compact else fs.FS_STORAGE_FP32
+    seeds = W.seed_nodes(n, 25, 2)
+    out = []
+    with fs.Graph(rp, ci) as g:
+        for cols in (fs.FS_COLUMNS_AUTO, fs.FS_COLUMNS_PLAIN):
+            with fs.Sim.from_model(g, model, variant=VARIANTS[variant], storage=storage, steps_per_graph=25,
+                                   history_len=150, columns=cols) as sim:
+                out.append(sim.column_bits())
+                sim.seed(seeds)
+                sim.step(150)
+                out.append((*sim.get_state(0)[:2], sim.history(0, 150)))
+    assert out[0] == 20 and out[2] == 32
+    for x, y in zip(out[1], out[3]):
+        np.testing.assert_array_equal(x, y)
+    assert out[1][2][-1, 0] < n - 75   # the epidemic moved beyond the 25 seeds
+
+
 def test_shedding_changes_the_epidemic_as_the_oracle_does():
     """Replicas 0..7 of one GPU sim against oracle runs of the same replicas:
     final attack rates and peak prevalence agree within 3 standard errors
