@@ -109,8 +109,9 @@ typedef struct fs_dist {
 /* Column storage of the step's transposed copy of the graph (the gather of
  * Eq. (influence) reads it every step; the caller's CSR is unchanged).
  *   FS_COLUMNS_AUTO:  where the step supports it -- an unweighted graph of at
- *                     most 2^27 nodes, one replica, no rate recording and no
- *                     compaction -- the rows of every 64-node
+ *                     most 2^27 nodes, one replica, and not age-dependent
+ *                     shedding together with rate recording or compaction --
+ *                     the rows of every 64-node
  *                     chunk that share one degree of at most 12 (every chunk of
  *                     a regular graph; almost all light rows of a degree-sorted
  *                     one) store each column in 20, 24 or 27 bits (the fewest

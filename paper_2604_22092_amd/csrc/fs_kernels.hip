@@ -343,10 +343,16 @@ const void* step_kernel_fn(int storage, bool weighted, int mode, int udeg, bool 
                            int pbits)
 {
     if (pbits != 0) {
-        if (weighted || extra || lgR != 0) return nullptr;
-        if (pbits == 20) return shed ? step_kernel_fn_shed_r1p20(storage, mode, udeg) : step_kernel_fn_r1p20(storage, mode, udeg);
-        if (pbits == 24) return shed ? step_kernel_fn_shed_r1p24(storage, mode, udeg) : step_kernel_fn_r1p24(storage, mode, udeg);
-        if (pbits == 27) return shed ? step_kernel_fn_shed_r1p27(storage, mode, udeg) : step_kernel_fn_r1p27(storage, mode, udeg);
+        if (weighted || lgR != 0 || (shed && extra)) return nullptr;
+        if (pbits == 20)
+            return shed ? step_kernel_fn_shed_r1p20(storage, mode, udeg)
+                        : extra ? step_kernel_fn_extra_r1p20(storage, mode, udeg) : step_kernel_fn_r1p20(storage, mode, udeg);
+        if (pbits == 24)
+            return shed ? step_kernel_fn_shed_r1p24(storage, mode, udeg)
+                        : extra ? step_kernel_fn_extra_r1p24(storage, mode, udeg) : step_kernel_fn_r1p24(storage, mode, udeg);
+        if (pbits == 27)
+            return shed ? step_kernel_fn_shed_r1p27(storage, mode, udeg)
+                        : extra ? step_kernel_fn_extra_r1p27(storage, mode, udeg) : step_kernel_fn_r1p27(storage, mode, udeg);
         return nullptr;
     }
     if (!shed && !extra && lgR == 0) return step_kernel_fn_r1(storage, weighted, mode, udeg);

@@ -20,8 +20,8 @@ namespace fsk {
 // lgR: log2 of the replica count; sims with one replica (and neither
 // shedding nor the extra checks) take an instantiation that knows it.
 // pbits (StepArgs::pbits): packed columns (20, 24 or 27 bits; unit weights,
-// one replica, not the extra checks), or 0; nullptr for any other
-// combination with pbits != 0.
+// one replica, not shedding together with the extra checks), or 0; nullptr
+// for any other combination with pbits != 0.
 const void* step_kernel_fn(int storage, bool weighted, int mode, int udeg, bool shed, bool extra, int lgR,
                            int pbits);
 const void* step_kernel_fn_r1(int storage, bool weighted, int mode, int udeg);
@@ -31,6 +31,9 @@ const void* step_kernel_fn_r1p27(int storage, int mode, int udeg);
 const void* step_kernel_fn_shed_r1p20(int storage, int mode, int udeg);
 const void* step_kernel_fn_shed_r1p24(int storage, int mode, int udeg);
 const void* step_kernel_fn_shed_r1p27(int storage, int mode, int udeg);
+const void* step_kernel_fn_extra_r1p20(int storage, int mode, int udeg);
+const void* step_kernel_fn_extra_r1p24(int storage, int mode, int udeg);
+const void* step_kernel_fn_extra_r1p27(int storage, int mode, int udeg);
 // (the other (shed, extra) instantiations, each defined by a source of its own)
 const void* step_kernel_fn_extra(int storage, bool weighted, int mode, int udeg);
 const void* step_kernel_fn_shed(int storage, bool weighted, int mode, int udeg);

@@ -1,0 +1,18 @@
+// Constant-shedding step kernels that record rates and/or walk the
+// active-chunk list of compaction, for unit-weight layouts with one replica
+// and columns packed at 27 bits (compiled apart from the others so the
+// instantiations build in parallel).
+#include <hip/hip_runtime.h>
+
+#include "fs_kernels.hpp"
+#include "fs_step.hpp"
+
+namespace fsk {
+
+const void* step_kernel_fn_extra_r1p27(int storage, int mode, int udeg)
+{
+    return storage == 0 ? step_kernel_r1p_depth<0, 27, false, true>(mode, udeg)
+                        : step_kernel_r1p_depth<1, 27, false, true>(mode, udeg);
+}
+
+} // namespace fsk

@@ -10,7 +10,7 @@ namespace fsk {
 
 const void* step_kernel_fn_r1p20(int storage, int mode, int udeg)
 {
-    return storage == 0 ? step_kernel_r1p_depth<0, 20, false>(mode, udeg) : step_kernel_r1p_depth<1, 20, false>(mode, udeg);
+    return storage == 0 ? step_kernel_r1p_depth<0, 20, false, false>(mode, udeg) : step_kernel_r1p_depth<1, 20, false, false>(mode, udeg);
 }
 
 } // namespace fsk

@@ -10,7 +10,7 @@ namespace fsk {
 
 const void* step_kernel_fn_r1p24(int storage, int mode, int udeg)
 {
-    return storage == 0 ? step_kernel_r1p_depth<0, 24, false>(mode, udeg) : step_kernel_r1p_depth<1, 24, false>(mode, udeg);
+    return storage == 0 ? step_kernel_r1p_depth<0, 24, false, false>(mode, udeg) : step_kernel_r1p_depth<1, 24, false, false>(mode, udeg);
 }
 
 } // namespace fsk

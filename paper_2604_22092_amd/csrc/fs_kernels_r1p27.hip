@@ -10,7 +10,7 @@ namespace fsk {
 
 const void* step_kernel_fn_r1p27(int storage, int mode, int udeg)
 {
-    return storage == 0 ? step_kernel_r1p_depth<0, 27, false>(mode, udeg) : step_kernel_r1p_depth<1, 27, false>(mode, udeg);
+    return storage == 0 ? step_kernel_r1p_depth<0, 27, false, false>(mode, udeg) : step_kernel_r1p_depth<1, 27, false, false>(mode, udeg);
 }
 
 } // namespace fsk

@@ -10,7 +10,7 @@ namespace fsk {
 
 const void* step_kernel_fn_shed_r1p27(int storage, int mode, int udeg)
 {
-    return storage == 0 ? step_kernel_r1p_depth<0, 27, true>(mode, udeg) : step_kernel_r1p_depth<1, 27, true>(mode, udeg);
+    return storage == 0 ? step_kernel_r1p_depth<0, 27, true, false>(mode, udeg) : step_kernel_r1p_depth<1, 27, true, false>(mode, udeg);
 }
 
 } // namespace fsk

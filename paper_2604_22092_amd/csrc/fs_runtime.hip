@@ -517,12 +517,13 @@ bool layout_cached(fs_graph* g, int32_t R, int32_t heavy_deg, int32_t seg_edges,
 }
 
 // Whether a sim of these parameters may take packed columns: the
-// single-replica step of an unweighted graph without rate recording or
-// compaction, unless the caller asks for 32-bit columns.
+// single-replica step of an unweighted graph (not age-dependent shedding
+// together with rate recording or compaction), unless the caller asks for
+// 32-bit columns.
 bool packing_allowed(const fs_graph* g, const fs_sim_params* p)
 {
     return p->columns == FS_COLUMNS_AUTO && std::max(p->n_replicas, 1) == 1 && g->d_weights == nullptr &&
-           !p->record_rates && !p->compaction;
+           !(p->shedding != FS_SHED_CONSTANT && (p->record_rates || p->compaction));
 }
 
 size_t sim_footprint(fs_graph* g, const fs_sim_params* p)

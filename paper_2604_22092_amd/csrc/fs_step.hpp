@@ -971,7 +971,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
     constexpr bool USE_LDS = MODE != MODE_STREAM;
     using age_t = typename Store<STORAGE>::age_t;
     constexpr int NW = TPB / 64;
-    static_assert(PB == 0 || (!WEIGHTED && !EXTRA), "packed columns: unit weights, no extra checks");
+    static_assert(PB == 0 || !WEIGHTED, "packed columns: unit weights only");
 
     __shared__ uint32_t s_cnt[4 * 64];
     __shared__ __attribute__((aligned(16))) uint32_t s_bits[USE_LDS ? RESIDENT_BITS / 32 : 4];
@@ -1172,31 +1172,34 @@ __global__ __launch_bounds__(TPB) void step_kernel_r1(StepArgs a)
 }
 
 // The same with packed columns of PB bits (unit weights only), with
-// constant or (SHED) age-dependent shedding.
-template <int STORAGE, int MODE, int UD, int PB, bool SHED, int TPB>
+// constant or (SHED) age-dependent shedding, and (EXTRA) the rate recording
+// and compaction checks.
+template <int STORAGE, int MODE, int UD, int PB, bool SHED, bool EXTRA, int TPB>
 __global__ __launch_bounds__(TPB) void step_kernel_r1p(StepArgs a)
 {
     StepArgs b = a;
     b.lgR = 0;
-    step_body<STORAGE, false, MODE, UD, SHED, false, TPB, PB>(b, blockIdx.x, gridDim.x);
+    step_body<STORAGE, false, MODE, UD, SHED, EXTRA, TPB, PB>(b, blockIdx.x, gridDim.x);
 }
 
-template <int S, int U, int PB, bool SHED>
+template <int S, int U, int PB, bool SHED, bool EXTRA>
 const void* step_kernel_r1p_sel(int mode)
 {
-    if (mode == MODE_RESIDENT) return (const void*)&step_kernel_r1p<S, MODE_RESIDENT, U, PB, SHED, RESIDENT_TPB>;
-    if (mode == MODE_SUMMARY) return (const void*)&step_kernel_r1p<S, MODE_SUMMARY, U, PB, SHED, RESIDENT_TPB>;
-    return (const void*)&step_kernel_r1p<S, MODE_STREAM, U, PB, SHED, STREAM_TPB>;
+    if (mode == MODE_RESIDENT)
+        return (const void*)&step_kernel_r1p<S, MODE_RESIDENT, U, PB, SHED, EXTRA, RESIDENT_TPB>;
+    if (mode == MODE_SUMMARY)
+        return (const void*)&step_kernel_r1p<S, MODE_SUMMARY, U, PB, SHED, EXTRA, RESIDENT_TPB>;
+    return (const void*)&step_kernel_r1p<S, MODE_STREAM, U, PB, SHED, EXTRA, STREAM_TPB>;
 }
 
 // udeg: the uniform layout's degree, or -1 for a mixed layout
-template <int S, int PB, bool SHED>
+template <int S, int PB, bool SHED, bool EXTRA>
 const void* step_kernel_r1p_depth(int mode, int udeg)
 {
-    if (udeg < 0) return step_kernel_r1p_sel<S, 0, PB, SHED>(mode);
-    if (udeg <= 8) return step_kernel_r1p_sel<S, 8, PB, SHED>(mode);
-    if (udeg <= 10) return step_kernel_r1p_sel<S, 10, PB, SHED>(mode);
-    return step_kernel_r1p_sel<S, 12, PB, SHED>(mode);
+    if (udeg < 0) return step_kernel_r1p_sel<S, 0, PB, SHED, EXTRA>(mode);
+    if (udeg <= 8) return step_kernel_r1p_sel<S, 8, PB, SHED, EXTRA>(mode);
+    if (udeg <= 10) return step_kernel_r1p_sel<S, 10, PB, SHED, EXTRA>(mode);
+    return step_kernel_r1p_sel<S, 12, PB, SHED, EXTRA>(mode);
 }
 
 template <int S, bool W, int U>

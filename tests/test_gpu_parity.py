@@ -525,8 +525,10 @@ def test_column_bits_follow_the_rules():
         for graph, kw, bits in [
             (g, {}, 20), (g, {"variant": fs.VARIANT_STREAM}, 20), (g, {"variant": fs.VARIANT_SUMMARY}, 20),
             (g, {"storage": fs.FS_STORAGE_COMPACT}, 20), (g, {"adaptive": True}, 20),
-            (g, {"replicas": 4}, 32), (g, {"record_rates": True}, 32), (g, {"compaction": True}, 32),
+            (g, {"replicas": 4}, 32), (g, {"record_rates": True}, 20), (g, {"compaction": True}, 20),
             (g, {"columns": fs.FS_COLUMNS_PLAIN}, 32), (g, {"shed": ("density", W.LN_I, 1.0)}, 20),
+            (g, {"shed": ("density", W.LN_I, 1.0), "record_rates": True}, 32),
+            (g, {"shed": ("density", W.LN_I, 1.0), "compaction": True}, 32),
             (gw, {}, 32), (gb, {}, 20), (gb, {"replicas": 2}, 32),
         ]:
             with fs.Sim.from_model(graph, model, **kw) as sim:
@@ -641,7 +643,7 @@ def test_full_size_regular10_n1e6_sampled_parity():
     model = wl["model"]
     seeds = W.seed_nodes(n, wl["seeds"], wl["seed_rng"])
     with fs.Graph(rp, ci) as g:
-        sim = fs.Sim.from_model(g, model, steps_per_graph=50, record_rates=True)
+        sim = fs.Sim.from_model(g, model, steps_per_graph=50, record_rates=True, columns=fs.FS_COLUMNS_PLAIN)
         sim.seed(seeds, replica=0)
         sim.step(400)  # the launch configuration of the benchmark: captured b = 50 steps
         st, age, k = sim.get_state(0)

@@ -55,7 +55,8 @@ def test_n1e8_sampled_one_step_parity(big_graph, compact):
     storage = fs.FS_STORAGE_COMPACT if compact else fs.FS_STORAGE_FP32
     label = f"N=1e8 {'compact' if compact else 'fp32'}"
     rng = np.random.default_rng(7)
-    sim = fs.Sim.from_model(g, model, storage=storage, steps_per_graph=50, record_rates=True)
+    sim = fs.Sim.from_model(g, model, storage=storage, steps_per_graph=50, record_rates=True,
+                            columns=fs.FS_COLUMNS_PLAIN)
     checked, mism, moved = 0, 0, 0
     try:
         sim.seed(seeds, replica=0)
