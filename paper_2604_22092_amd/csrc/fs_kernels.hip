@@ -499,11 +499,10 @@ hipError_t launch_set_ctl(Ctl* ctl, unsigned long long step, hipStream_t s)
 // Hazard table of a fixed-step sim (StepArgs::htab): entry m holds the age
 // a_m (written by the host) and receives the hazards of both laws at a_m,
 // evaluated by the step's own code.
-__global__ void hazard_table_kernel(HazardDev h0, HazardDev h1, int32_t same_kind, float4* tab, uint32_t n)
+__global__ void hazard_table_kernel(const HazardDev* hz, int32_t same_kind, float4* tab, uint32_t n)
 {
     const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n) return;
-    const HazardDev hz[2] = {h0, h1};
     const float x = tab[m].x;
     tab[m].y = unit_hazard(hz, same_kind, x, false);
     tab[m].z = unit_hazard(hz, same_kind, x, true);
@@ -513,7 +512,7 @@ __global__ void hazard_table_kernel(HazardDev h0, HazardDev h1, int32_t same_kin
 hipError_t launch_hazard_table(const HazardDev* hz, int32_t same_kind, float4* tab, uint32_t n, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(hazard_table_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, hz[0], hz[1], same_kind, tab, n);
+    hipLaunchKernelGGL(hazard_table_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, hz, same_kind, tab, n);
     return hipGetLastError();
 }
 

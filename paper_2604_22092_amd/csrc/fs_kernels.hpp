@@ -88,7 +88,8 @@ hipError_t launch_clear_u32(uint32_t* p, size_t n, hipStream_t s);
 hipError_t launch_set_ctl(fsi::Ctl* ctl, unsigned long long step, hipStream_t s);
 hipError_t launch_eval_hazard(const fsi::HazardDev& h, int32_t storage, const void* ages, float* out, int64_t n,
                               hipStream_t s);
-// Hazards of both laws (hz[0], hz[1]) at the ages in tab[m].x into tab[m].y, .z (StepArgs::htab).
+// Hazards of both laws (hz: device memory, hz[0] and hz[1]) at the ages in
+// tab[m].x into tab[m].y, .z (StepArgs::htab).
 hipError_t launch_hazard_table(const fsi::HazardDev* hz, int32_t same_kind, float4* tab, uint32_t n, hipStream_t s);
 hipError_t launch_eval_shed(const fsi::ShedDev& sd, int32_t storage, const void* ages, float* out, int64_t n,
                             hipStream_t s);

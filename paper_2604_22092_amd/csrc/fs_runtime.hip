@@ -1492,7 +1492,7 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
         if ((e = sim_alloc(s, (void**)&s->d_htab, tab.size() * sizeof(float4))) != hipSuccess ||
             (e = hipMemcpyAsync(s->d_htab, tab.data(), tab.size() * sizeof(float4), hipMemcpyHostToDevice,
                                 s->stream)) != hipSuccess ||
-            (e = fsk::launch_hazard_table(a.hz, a.same_kind, s->d_htab, fsi::HTAB_LEN, s->stream)) != hipSuccess ||
+            (e = fsk::launch_hazard_table(s->d_hz, a.same_kind, s->d_htab, fsi::HTAB_LEN, s->stream)) != hipSuccess ||
             (e = hipStreamSynchronize(s->stream)) != hipSuccess)
             return bad(e, "hazard table");
         a.htab = s->d_htab;
