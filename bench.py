@@ -631,7 +631,9 @@ def main():
     b_alg = bytes_per_update(d_mean, storage)
     per_launch_s = sec / steps_run
     achieved = b_alg * n / per_launch_s / 1e9
-    plain = args.shed == "none" and not args.compaction
+    # the committed counters were taken in the workload's own configuration
+    plain = (args.shed == "none" and not args.compaction and args.columns == "auto" and args.beta is None
+             and not args.n and args.variant == "auto")
     traffic = measured_traffic(workload if storage == wl["storage"] else f"{workload}_{storage}") if plain else None
     s_frac = float(hist[:, 0].mean() / n)
     copy_gbs = copy_bandwidth(torch, dev)
