@@ -101,8 +101,10 @@ typedef struct fs_dist {
  *                       saturating at 65535)
  * In both, the next-step infectivity of Eq. (infectivity) is kept as one bit
  * per unit, 1{X = I}: with constant shedding s = 1 that bit is its exact value
- * (beta multiplies the pressure instead).  Age-dependent shedding adds a
- * float32 s(tau) per unit, read only where the bit is set. */
+ * (beta multiplies the pressure instead).  Age-dependent shedding adds an
+ * s(tau) per unit, read only where the bit is set: float32 with FP32 storage,
+ * IEEE binary16 (rounded to nearest even; the paper's FP16 infectivity) with
+ * compact storage, summed in FP32 either way. */
 #define FS_STORAGE_FP32 0
 #define FS_STORAGE_COMPACT 1
 

@@ -137,6 +137,7 @@ def _declare(L):
     L.or_hazard_many.argtypes = [ctypes.POINTER(Dist), _I64, _P, _P]
     L.or_density_many.argtypes = [ctypes.POINTER(Dist), _I64, _P, _P]
     L.or_infectivity.argtypes = [_I64, ctypes.POINTER(Params), _P, _P, _P, _P]
+    L.or_binary16_many.argtypes = [_I64, _P, _P]
     L.or_step.argtypes = [_I64, _P, _P, _P, ctypes.POINTER(Params), _U64, _U32, _P, _P, _P,
                           _P, _P, _P, _P, _P, _P]
     L.or_step_nodes.argtypes = [_I64, _P, _P, _P, ctypes.POINTER(Params), _U64, _U32, _P, _P,
@@ -228,8 +229,17 @@ def density(spec, tau) -> np.ndarray:
     return out
 
 
+def binary16(x) -> np.ndarray:
+    """x rounded to the nearest IEEE binary16 value (ties to even), as float64."""
+    a = _c(x, np.float64)
+    out = np.empty_like(a)
+    lib().or_binary16_many(len(a), _ptr(a), _ptr(out))
+    return out
+
+
 def infectivity(model: dict, state, age, compact: bool = False) -> np.ndarray:
-    """iota_i = s(tau_i) 1{X_i = I} of Eq. (infectivity), from a state and age."""
+    """iota_i = s(tau_i) 1{X_i = I} of Eq. (infectivity), from a state and age
+    (stored in binary16 under compact storage)."""
     st = _c(state, np.int32)
     n = len(st)
     p = make_params(model, AGE_STEPS_U16 if compact else AGE_DAYS_F32)

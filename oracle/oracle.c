@@ -41,6 +41,11 @@
  *   - FP32-storage ages advance as (float)((float)tau + (float)dt), mirroring
  *     the single-precision storage the method keeps; compact ages are integer
  *     step counts n with tau = n*dt, saturating at 65535.
+ *   - compact storage keeps the infectivity in IEEE binary16 (Section
+ *     "Mixed-precision storage with an fp32 accumulator", Table
+ *     "mixed_precision_dtypes"): with an age-dependent profile the stored
+ *     value is s(tau) rounded to the nearest binary16 (ties to even); the
+ *     constant profile's 1 is exact.
  */
 #define _DEFAULT_SOURCE 1 /* M_PI, M_SQRT2 */
 #include <math.h>
@@ -311,13 +316,44 @@ double or_shed(const or_params* p, double tau)
     }
 }
 
+/* x rounded to the nearest IEEE 754 binary16 value, ties to even, returned as
+ * a double.  binary16 keeps 11 significant bits: a value in [2^e, 2^(e+1)),
+ * e >= -14, is a multiple of 2^(e-10); below 2^-14 (subnormals) every value
+ * is a multiple of 2^-24.  The largest finite value is 65504; magnitudes from
+ * 65520 up (the midpoint towards 2^16) round to infinity. */
+double or_binary16(double x)
+{
+    if (isnan(x) || isinf(x) || x == 0.0) return x;
+    const double a = fabs(x);
+    if (a >= 65520.0) return copysign(INFINITY, x);
+    int e2;
+    (void)frexp(a, &e2);   /* a in [2^(e2-1), 2^e2) */
+    int e = e2 - 1;
+    if (e < -14) e = -14;
+    const double quantum = ldexp(1.0, e - 10);
+    return copysign(rint(a / quantum) * quantum, x); /* rint: ties to even */
+}
+
+void or_binary16_many(int64_t n, const double* x, double* out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = or_binary16(x[i]);
+}
+
+/* The stored infectivity value of an infectious node: s(tau), in binary16
+ * under compact storage. */
+static double stored_shed(const or_params* p, double tau)
+{
+    const double v = or_shed(p, tau);
+    return p->age_mode == OR_AGE_STEPS_U16 ? or_binary16(v) : v;
+}
+
 /* Infectivity of every node from its state and age: s(tau_i) 1{X_i = I}. */
 void or_infectivity(int64_t n, const or_params* p, const int32_t* state, const float* age_days,
                     const uint16_t* age_steps, double* out)
 {
     for (int64_t i = 0; i < n; ++i) {
         double tau = (p->age_mode == OR_AGE_DAYS_F32) ? (double)age_days[i] : (double)age_steps[i] * p->dt;
-        out[i] = state[i] == OR_I ? or_shed(p, tau) : 0.0;
+        out[i] = state[i] == OR_I ? stored_shed(p, tau) : 0.0;
     }
 }
 
@@ -398,7 +434,7 @@ void or_step(int64_t n, const int32_t* row_ptr, const int32_t* col_ind, const fl
         if (age_steps) age_steps[i] = o.age_steps;
         /* 7. next-step infectivity (Eq. (infectivity)) from the new state and age */
         double tau_new = (p->age_mode == OR_AGE_DAYS_F32) ? (double)o.age_days : (double)o.age_steps * p->dt;
-        iota_out[i] = (o.state == OR_I) ? or_shed(p, tau_new) : 0.0;
+        iota_out[i] = (o.state == OR_I) ? stored_shed(p, tau_new) : 0.0;
         counts[o.state] += 1;
         if (log_lambda) log_lambda[i] = o.lambda;
         if (log_q) log_q[i] = o.q;

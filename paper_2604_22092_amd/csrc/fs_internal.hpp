@@ -170,8 +170,8 @@ struct StepArgs {
     // age-dependent shedding (shedding kernels only): float s(tau) of every
     // unit that is infectious, [n][R], ping-pong like the bitmaps (only units
     // whose bit is set are ever read)
-    float* shed0;
-    float* shed1;
+    void* shed0; // float32 (FP32 storage) or IEEE binary16 (compact) per unit
+    void* shed1;
     ShedDev shed;
     // active-chunk compaction (nullptr act: off): the launch walks the chunks
     // act[2 .. 2 + act[0]) (ascending); every other chunk holds only R units
@@ -230,8 +230,8 @@ struct HeavyArgs {
     int32_t lgR;
     uint32_t step_off;
     uint32_t units;     // N * R: the bits the resident variant copies into LDS
-    const float* shed0; // shedding kernels: the s(tau) buffers of StepArgs
-    const float* shed1;
+    const void* shed0; // shedding kernels: the s(tau) buffers of StepArgs
+    const void* shed1;
     const void* state;  // start-of-step states: segments of rows that are not S
     int32_t storage;    // in any replica are skipped (0: int32 states, 1: uint8)
     int32_t pad2;

@@ -254,13 +254,15 @@ __global__ void eval_shed_kernel(ShedDev sd, int32_t storage, const void* ages, 
 // Shedding values s(tau) of every infectious unit from the state and age
 // (after seeding or a state load); other units are left as they are.
 template <int STORAGE>
-__global__ void rebuild_shed_kernel(const void* state_v, const void* age_v, uint32_t total, ShedDev sd, float* out)
+__global__ void rebuild_shed_kernel(const void* state_v, const void* age_v, uint32_t total, ShedDev sd, void* out)
 {
     using S = Store<STORAGE>;
     const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= total) return;
     if ((int)((const typename S::state_t*)state_v)[u] != ST_I) return;
-    out[u] = fsd::shed(sd, age_units(((const typename S::age_t*)age_v)[u]));
+    const float v = fsd::shed(sd, age_units(((const typename S::age_t*)age_v)[u]));
+    if (STORAGE == 0) ((float*)out)[u] = v;
+    else ((uint16_t*)out)[u] = (uint16_t)float_to_half_bits(v);
 }
 
 // Live flags of every chunk from the state: 1 when the chunk holds a unit
@@ -534,7 +536,7 @@ hipError_t launch_eval_shed(const ShedDev& sd, int32_t storage, const void* ages
 }
 
 hipError_t launch_rebuild_shed(int storage, const void* state, const void* age, uint32_t total, const ShedDev& sd,
-                               float* out, hipStream_t s)
+                               void* out, hipStream_t s)
 {
     if (total == 0) return hipSuccess;
     const unsigned g = grid_for(total, 256);

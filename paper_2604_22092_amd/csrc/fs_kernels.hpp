@@ -95,7 +95,7 @@ hipError_t launch_eval_shed(const fsi::ShedDev& sd, int32_t storage, const void*
                             hipStream_t s);
 // s(tau) of the infectious units into out (others untouched).
 hipError_t launch_rebuild_shed(int storage, const void* state, const void* age, uint32_t total,
-                               const fsi::ShedDev& sd, float* out, hipStream_t s);
+                               const fsi::ShedDev& sd, void* out, hipStream_t s);
 // Live flags of all nchunks chunks from the state.
 hipError_t launch_chunk_live(int storage, const void* state, uint32_t total, uint8_t* live, uint32_t nchunks,
                              hipStream_t s);

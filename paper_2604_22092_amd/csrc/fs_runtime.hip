@@ -239,6 +239,8 @@ fs_status prep_shed(int32_t form, const fs_dist& d, double A, int storage, doubl
 
 size_t state_bytes(int storage) { return storage == FS_STORAGE_FP32 ? 4 : 1; }
 size_t age_bytes(int storage) { return storage == FS_STORAGE_FP32 ? 4 : 2; }
+// bytes of a stored shedding value: float32, or binary16 with compact storage
+size_t shed_bytes(int storage) { return storage == FS_STORAGE_FP32 ? 4 : 2; }
 // 64-bit words of an infectivity bitmap of `units` bits, in whole tiles.
 size_t bitmap_words(size_t units) { return (units + fsi::BITMAP_TILE - 1) / fsi::BITMAP_TILE * (fsi::BITMAP_TILE / 64); }
 
@@ -552,7 +554,7 @@ size_t sim_footprint(fs_graph* g, const fs_sim_params* p)
         if (!layout_cached(g, (int32_t)R, hd, se, pk)) b += ((size_t)g->n + 1) * 4 + (size_t)g->nnz * 4;
     }
     if (p->record_rates) b += units * 4;
-    if (p->shedding != FS_SHED_CONSTANT) b += units * 8;
+    if (p->shedding != FS_SHED_CONSTANT) b += units * 2 * shed_bytes(p->storage);
     if (p->compaction) b += (units / 64 + 1) * 5 + fsi::LIVE_TILE;
     return b + ((size_t)1 << 20);
 }
@@ -1026,8 +1028,8 @@ fs_status autotune(fs_sim* s, const fs_tune_params& tp, fs_tune_result* out)
                   {s->d_ctl, sizeof(fsi::Ctl), {}},
                   {s->d_hist, (size_t)s->H * s->R * 4 * sizeof(uint32_t), {}},
                   {s->d_lam_part, 2 * (size_t)s->G * sizeof(float), {}},
-                  {s->d_shed[0], (size_t)s->g->n * s->R * sizeof(float), {}},
-                  {s->d_shed[1], (size_t)s->g->n * s->R * sizeof(float), {}},
+                  {s->d_shed[0], (size_t)s->g->n * s->R * shed_bytes(s->storage), {}},
+                  {s->d_shed[1], (size_t)s->g->n * s->R * shed_bytes(s->storage), {}},
                   {s->d_live, s->live_bytes, {}},
                   {s->d_act, (2 + (size_t)s->nchunks) * sizeof(uint32_t), {}},
                   {s->d_dt_hist, (size_t)s->H * sizeof(float), {}}};
@@ -1416,8 +1418,8 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
          (e = sim_alloc(s, (void**)&s->d_summary, ((size_t)s->sum_bits + 511) / 512 * 64)) != hipSuccess) ||
         (p->adaptive && ((e = sim_alloc(s, (void**)&s->d_lam_part, 2 * (size_t)s->G * sizeof(float))) != hipSuccess ||
                          (e = sim_alloc(s, (void**)&s->d_dt_hist, (size_t)s->H * sizeof(float))) != hipSuccess)) ||
-        (shedding && ((e = sim_alloc(s, (void**)&s->d_shed[0], units * sizeof(float))) != hipSuccess ||
-                      (e = sim_alloc(s, (void**)&s->d_shed[1], units * sizeof(float))) != hipSuccess)) ||
+        (shedding && ((e = sim_alloc(s, (void**)&s->d_shed[0], units * shed_bytes(s->storage))) != hipSuccess ||
+                      (e = sim_alloc(s, (void**)&s->d_shed[1], units * shed_bytes(s->storage))) != hipSuccess)) ||
         (p->compaction && ((e = sim_alloc(s, (void**)&s->d_live, s->live_bytes)) != hipSuccess ||
                            (e = sim_alloc(s, (void**)&s->d_act, (2 + chunks) * sizeof(uint32_t))) != hipSuccess)))
         return bad(e, "device allocation");
@@ -1430,8 +1432,8 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
         (e = hipMemsetAsync(s->d_hist, 0, hist_words * sizeof(uint32_t), s->stream)) != hipSuccess ||
         (s->d_summary &&
          (e = hipMemsetAsync(s->d_summary, 0, ((size_t)s->sum_bits + 511) / 512 * 64, s->stream)) != hipSuccess) ||
-        (s->d_shed[0] && (e = hipMemsetAsync(s->d_shed[0], 0, units * sizeof(float), s->stream)) != hipSuccess) ||
-        (s->d_shed[1] && (e = hipMemsetAsync(s->d_shed[1], 0, units * sizeof(float), s->stream)) != hipSuccess) ||
+        (s->d_shed[0] && (e = hipMemsetAsync(s->d_shed[0], 0, units * shed_bytes(s->storage), s->stream)) != hipSuccess) ||
+        (s->d_shed[1] && (e = hipMemsetAsync(s->d_shed[1], 0, units * shed_bytes(s->storage), s->stream)) != hipSuccess) ||
         // every unit starts in S: every chunk is live; the padding never is
         (s->d_live && (e = hipMemsetAsync(s->d_live, 0, s->live_bytes, s->stream)) != hipSuccess) ||
         (s->d_live && (e = hipMemsetAsync(s->d_live, 1, chunks, s->stream)) != hipSuccess) ||

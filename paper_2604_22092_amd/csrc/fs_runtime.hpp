@@ -101,7 +101,8 @@ struct fs_sim {
     uint32_t* d_cnt4 = nullptr;
     float* d_lam_part = nullptr;   // adaptive step: per-workgroup rate maxima [2][G]
     float* d_dt_hist = nullptr;    // adaptive step: step size of each step, ring of H
-    float* d_shed[2] = {nullptr, nullptr}; // age-dependent shedding: s(tau) per unit, ping-pong
+    void* d_shed[2] = {nullptr, nullptr}; // age-dependent shedding: s(tau) per unit (float32, or binary16
+                                          // with compact storage), ping-pong
     uint8_t* d_live = nullptr;     // compaction: live flag per chunk, zero-padded to LIVE_TILE
     uint32_t* d_act = nullptr;     // compaction: [2 + nchunks] active-chunk list
     float4* d_htab = nullptr;      // fixed steps: hazard table (StepArgs::htab)
@@ -195,6 +196,7 @@ struct StreamBuf {
 void release_sim(fs_sim* s);
 size_t state_bytes(int storage);
 size_t age_bytes(int storage);
+size_t shed_bytes(int storage); // a stored shedding value: float32, or binary16 with compact storage
 uint32_t heavy_grid(const fs_sim* s);       // WG-thread heavy workgroups (batches too)
 uint32_t sim_heavy_grid(const fs_sim* s);   // the sim's own heavy launch
 uint32_t sim_heavy_block(const fs_sim* s);

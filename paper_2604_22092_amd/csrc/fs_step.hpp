@@ -20,11 +20,13 @@ template <>
 struct Store<0> {
     using state_t = int32_t;
     using age_t = float;
+    static constexpr uint32_t shed_bytes = 4; // s(tau) as float32
 };
 template <>
 struct Store<1> {
     using state_t = uint8_t;
     using age_t = uint16_t;
+    static constexpr uint32_t shed_bytes = 2; // s(tau) as IEEE binary16
 };
 
 __device__ __forceinline__ uint32_t age_bits(float a) { return __float_as_uint(a); }
@@ -77,6 +79,25 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes)
 }
 __device__ __forceinline__ uint32_t ld32(rsrc_t r, uint32_t off) { return __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0); }
 __device__ __forceinline__ void st32(rsrc_t r, uint32_t off, uint32_t v) { __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)off, 0, 0); }
+
+// Stored shedding values (age-dependent shedding): float32 with FP32 storage,
+// IEEE binary16 with compact storage (its value rounded to nearest even;
+// every binary16 value is exact in float).  shed_at reads unit `unit` when
+// `take` is set, else nothing (0).
+__device__ __forceinline__ float half_bits_to_float(uint32_t h) { return (float)__builtin_bit_cast(_Float16, (uint16_t)h); }
+__device__ __forceinline__ uint32_t float_to_half_bits(float f) { return __builtin_bit_cast(uint16_t, (_Float16)f); }
+template <int STORAGE>
+__device__ __forceinline__ float shed_at(rsrc_t r, uint32_t unit, bool take)
+{
+    if (STORAGE == 0) return __uint_as_float(ld32(r, take ? unit << 2 : OOB));
+    return half_bits_to_float(__builtin_amdgcn_raw_buffer_load_b16(r, take ? (int)(unit << 1) : (int)OOB, 0, 0));
+}
+template <int STORAGE>
+__device__ __forceinline__ void shed_put(rsrc_t r, uint32_t unit, bool put, float v)
+{
+    if (STORAGE == 0) st32(r, put ? unit << 2 : OOB, __float_as_uint(v));
+    else __builtin_amdgcn_raw_buffer_store_b16((uint16_t)float_to_half_bits(v), r, put ? (int)(unit << 1) : (int)OOB, 0, 0);
+}
 
 // Element access of the storage types through a buffer descriptor.
 template <class T>
@@ -456,7 +477,7 @@ struct ShedPre {
     float v[CU][UMAX];
 };
 
-template <int UD, int PB, class age_t>
+template <int STORAGE, int UD, int PB, class age_t>
 __device__ __forceinline__ void shed_pre(const StepArgs& a, const Pass<age_t>& P, uint32_t lane,
                                          const uint32_t* __restrict__ lds, rsrc_t shedr, ShedPre& S)
 {
@@ -483,7 +504,7 @@ __device__ __forceinline__ void shed_pre(const StepArgs& a, const Pass<age_t>& P
         for (int j = 0; j < DEPTH; ++j) {
             const bool use = pre && (uint32_t)j < P.ud[u] && want;
             const uint32_t b = use ? __builtin_amdgcn_ubfe(wv[j], src[j] & 31u, 1) : 0u;
-            S.v[u][j] = __uint_as_float(ld32(shedr, b ? src[j] << 2 : OOB));
+            S.v[u][j] = shed_at<STORAGE>(shedr, src[j], b != 0u);
         }
     }
 }
@@ -495,7 +516,7 @@ __device__ __forceinline__ void shed_pre(const StepArgs& a, const Pass<age_t>& P
 // prefix count), JB slots at a time.  With age-dependent shedding (SHED) a
 // source whose bit is set contributes its s(tau) from `shedr`; the value load
 // of every other slot is out of range and reads nothing.
-template <int MODE, bool WEIGHTED, int UD, bool SHED, int PB, class age_t>
+template <int STORAGE, int MODE, bool WEIGHTED, int UD, bool SHED, int PB, class age_t>
 __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_t>& P, int u, bool want,
                                               uint32_t dg, const uint32_t* __restrict__ lds, rsrc_t gbits,
                                               rsrc_t shedr, const ShedPre& S, uint32_t lane)
@@ -607,7 +628,7 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
                 } else {
                     const uint32_t src = (col[j] << lgR) + rep;
                     const uint32_t b = fetch_bit<MODE>(lds, gbits, src, a.lg_gran, use);
-                    v = __uint_as_float(ld32(shedr, b ? src << 2 : OOB));
+                    v = shed_at<STORAGE>(shedr, src, b != 0u);
                 }
                 if (WEIGHTED) {
                     const float w = __uint_as_float(ld32(wr, use ? ((uint32_t)j * rows + q) << 2 : OOB));
@@ -635,7 +656,7 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
                     const bool use = want && j0 + jj < P.ud[u];
                     const uint32_t src = ((uint32_t)c[jj] << lgR) + rep;
                     const uint32_t b = fetch_bit<MODE>(lds, gbits, src, a.lg_gran, use);
-                    const float v = SHED ? __uint_as_float(ld32(shedr, b ? src << 2 : OOB)) : (float)b;
+                    const float v = SHED ? shed_at<STORAGE>(shedr, src, b != 0u) : (float)b;
                     if (WEIGHTED) pw = __builtin_fmaf(wv[jj], v, pw);
                     else if (SHED) pw += v;
                     else pi += b;
@@ -666,7 +687,7 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
                 if (want && d > j0 + jj) {
                     const uint32_t src = ((uint32_t)c[jj] << lgR) + rep;
                     const uint32_t b = fetch_bit<MODE>(lds, gbits, src, a.lg_gran, true);
-                    const float v = SHED ? __uint_as_float(ld32(shedr, b ? src << 2 : OOB)) : (float)b;
+                    const float v = SHED ? shed_at<STORAGE>(shedr, src, b != 0u) : (float)b;
                     if (WEIGHTED) pw = __builtin_fmaf(wv[jj], v, pw);
                     else if (SHED) pw += v;
                     else pi += b;
@@ -762,7 +783,7 @@ __device__ __forceinline__ void compact_apply(uint32_t* xch, uint32_t lane, cons
 template <int STORAGE, bool WEIGHTED, int MODE, int UD, bool SHED, bool EXTRA, int PB, class age_t>
 __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t>& P, uint32_t lane,
                                              const uint32_t* __restrict__ s_bits, rsrc_t gbits, rsrc_t shedr,
-                                             float* __restrict__ shed_out, const ShedPre& sv,
+                                             void* __restrict__ shed_out, const ShedPre& sv,
                                              uint32_t* xch, unsigned long long k,
                                              unsigned long long* __restrict__ bits_out, uint32_t* s_cnt,
                                              uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, float dt,
@@ -794,7 +815,7 @@ __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t
         const bool heavy = !UNIFORM && dg[u] == HEAVY_ROW;
         const bool want = x[u] == ST_S && !heavy;
         const float p =
-            pressure_row<MODE, WEIGHTED, UD, SHED, PB>(a, P, u, want, dg[u], s_bits, gbits, shedr, sv, lane);
+            pressure_row<STORAGE, MODE, WEIGHTED, UD, SHED, PB>(a, P, u, want, dg[u], s_bits, gbits, shedr, sv, lane);
         if (want) lam[u] = a.beta * p;
         if (!UNIFORM && !WEIGHTED && !SHED && H.on) {
             // pushed pressure: every binned unit, whatever its state, carries
@@ -949,7 +970,9 @@ __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t
         });
 #pragma unroll
         for (int u = 0; u < CU; ++u)
-            st32(make_rsrc(shed_out + (P.chk[u] << 6), P.nvalid[u] * 4u), need[u] ? lane << 2 : OOB, res[u]);
+            shed_put<STORAGE>(make_rsrc((char*)shed_out + (size_t)(P.chk[u] << 6) * Store<STORAGE>::shed_bytes,
+                                        P.nvalid[u] * Store<STORAGE>::shed_bytes),
+                              lane, need[u], __uint_as_float(res[u]));
     }
 }
 
@@ -994,8 +1017,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
     // the input bitmap: whole 512-unit tiles of 64 bytes
     const rsrc_t gbits = make_rsrc(bits_in, ((total + 511u) >> 9) << 6);
     // shedding values: read from the step's input, written to the other buffer
-    const rsrc_t shedr = make_rsrc((k & 1) ? a.shed1 : a.shed0, SHED ? total * 4u : 0u);
-    float* __restrict__ shed_out = (k & 1) ? a.shed0 : a.shed1;
+    const rsrc_t shedr = make_rsrc((k & 1) ? a.shed1 : a.shed0, SHED ? total * Store<STORAGE>::shed_bytes : 0u);
+    void* __restrict__ shed_out = (k & 1) ? a.shed0 : a.shed1;
     // the chunks this launch walks: all, or the active list
     const uint32_t walk = (EXTRA && a.act) ? a.act[0] : nchunks;
     // this step's size: fixed, or (adaptive) from the largest rate of the
@@ -1079,7 +1102,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
     ShedPre sv;
     for (;;) {
         if (first >= walk) break;
-        if (SPLIT) shed_pre<UD, PB>(a, P, lane, s_bits, shedr, sv);
+        if (SPLIT) shed_pre<STORAGE, UD, PB>(a, P, lane, s_bits, shedr, sv);
         if (PREFETCH)
             issue_pass<STORAGE, UD, EXTRA, PB>(a, first + stride, nwaves, stride, nchunks, walk, total, lane, P1,
                                                 ahead, H);
@@ -1091,7 +1114,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
         if (!PREFETCH)
             issue_pass<STORAGE, UD, EXTRA, PB>(a, first, nwaves, stride, nchunks, walk, total, lane, P1, ahead, H);
         issue_table<UNIFORM>(a, P1, lane);
-        if (SPLIT) shed_pre<UD, PB>(a, P1, lane, s_bits, shedr, sv);
+        if (SPLIT) shed_pre<STORAGE, UD, PB>(a, P1, lane, s_bits, shedr, sv);
         if (PREFETCH)
             issue_pass<STORAGE, UD, EXTRA, PB>(a, first + stride, nwaves, stride, nchunks, walk, total, lane, P,
                                                 ahead, H);
@@ -1299,7 +1322,7 @@ __device__ __forceinline__ void heavy_body(const HeavyArgs& h, uint32_t block, u
     const uint32_t rep = lane & (R - 1);
     const unsigned long long k = h.ctl->step + h.step_off;
     const uint32_t* __restrict__ bits = (const uint32_t*)((k & 1) ? h.iota1 : h.iota0);
-    const float* __restrict__ shv = (k & 1) ? h.shed1 : h.shed0;
+    const void* __restrict__ shv = (k & 1) ? h.shed1 : h.shed0;
     const uint32_t nwaves = nblocks * (WG / 64);
     unsigned long long rmask = 1ull; // lanes of replica 0: every R-th lane
     for (uint32_t sh = R; sh < 64u; sh <<= 1) rmask |= rmask << sh;
@@ -1317,7 +1340,10 @@ __device__ __forceinline__ void heavy_body(const HeavyArgs& h, uint32_t block, u
         for (int32_t e = sg.e_begin + (int32_t)eoff; e < sg.e_end; e += (int32_t)per) {
             const uint32_t src = ((uint32_t)h.col_ind[e] << h.lgR) + rep;
             const uint32_t b = bit_at(bits, src);
-            const float v = SHED ? (b ? shv[src] : 0.0f) : (float)b;
+            const float v = SHED ? (b ? (h.storage ? half_bits_to_float(((const uint16_t*)shv)[src])
+                                                   : ((const float*)shv)[src])
+                                      : 0.0f)
+                                 : (float)b;
             if (WEIGHTED) cw = __builtin_fmaf(h.weights[e], v, cw);
             else if (SHED) cw += v;
             else ci += (uint32_t)__popcll(__ballot(b != 0u) & (rmask << rep));
@@ -1375,7 +1401,7 @@ __device__ __forceinline__ void heavy_resident_body(const HeavyArgs& h, uint32_t
     const uint32_t rep = lane & (R - 1);
     const unsigned long long k = h.ctl->step + h.step_off;
     const uint32_t* __restrict__ bits = (const uint32_t*)((k & 1) ? h.iota1 : h.iota0);
-    const rsrc_t shedr = make_rsrc((k & 1) ? h.shed1 : h.shed0, SHED ? h.units * 4u : 0u);
+    const rsrc_t shedr = make_rsrc((k & 1) ? h.shed1 : h.shed0, SHED ? h.units * (h.storage ? 2u : 4u) : 0u);
     const uint32_t nw = nblocks * NW;
     const uint32_t s0 = block * NW + wave;
     // lanes of replica 0: every R-th lane
@@ -1441,7 +1467,8 @@ __device__ __forceinline__ void heavy_resident_body(const HeavyArgs& h, uint32_t
         auto add = [&](int32_t c, float w) {
             const uint32_t src = ((uint32_t)c << lgR) + rep;
             const uint32_t b = lds_bit(s_bits, src);
-            const float v = SHED ? __uint_as_float(ld32(shedr, b ? src << 2 : OOB)) : (float)b;
+            const float v = SHED ? (h.storage ? shed_at<1>(shedr, src, b != 0u) : shed_at<0>(shedr, src, b != 0u))
+                                 : (float)b;
             if (WEIGHTED) cw = __builtin_fmaf(w, v, cw);
             else if (SHED) cw += v;
             else ci += (uint32_t)__popcll(__ballot(b != 0u) & (rmask << rep));

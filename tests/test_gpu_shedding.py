@@ -15,7 +15,12 @@ is itself an FP32 exponential, w = (tau / scale)^shape: its rounding
 (<= 2 ulp) moves the exponent by up to 2^-22 w, so there the bound grows by
 that much (w ~ 70 before the density leaves the FP32 range).  A pressure
 sums such values in FP32, so S rates agree to RATE_TOL, and a draw may flip
-where |u - q| is within GUARD_REL * q of the threshold.
+where |u - q| is within GUARD_REL * q of the threshold.  Compact storage keeps
+the values in binary16 on both sides (the oracle rounds its FP64 value, the
+step its FP32 one): where the FP32 value falls within its error of a binary16
+rounding boundary the two stored values differ by one unit in the last place
+(2^-11 relative), and since a pressure sums non-negative terms, it then moves
+by at most 2^-11 relative: COMPACT_TOL for rates and the guard band.
 """
 import math
 import zlib
@@ -33,6 +38,7 @@ pytestmark = pytest.mark.gpu
 PROFILE_TOL = 1e-5
 RATE_TOL = 2e-5
 GUARD_REL = 5e-5
+COMPACT_TOL = 2.0**-11 + RATE_TOL
 FLOOR = 1e-30
 
 SMALL = W.WORKLOADS["regular10_n1e4"]
@@ -93,10 +99,11 @@ def test_device_profile_matches_oracle(name):
                       oracle_profile(shed, n * dt), profile_tol(shed, n * dt), f"{name} steps dt={dt}")
 
 
-def compare_step(gst, gage, grates, ora, label):
+def compare_step(gst, gage, grates, ora, label, compact=False):
     """Node-by-node check of one step; returns the number of guard-band flips."""
+    guard = COMPACT_TOL if compact else GUARD_REL
     mism = np.flatnonzero(gst != ora["state"])
-    bad = [int(i) for i in mism if not (ora["u"][i] >= 0 and abs(ora["u"][i] - ora["q"][i]) < GUARD_REL * ora["q"][i] + 1e-6)]
+    bad = [int(i) for i in mism if not (ora["u"][i] >= 0 and abs(ora["u"][i] - ora["q"][i]) < guard * ora["q"][i] + 1e-6)]
     assert not bad, f"{label}: {len(bad)} mismatches outside the guard band, first {bad[:5]}"
     same = gst == ora["state"]
     np.testing.assert_array_equal(gage[same], ora["age"][same], err_msg=label)
@@ -104,7 +111,7 @@ def compare_step(gst, gage, grates, ora, label):
     o = ora["lam"]
     big = o >= FLOOR
     rel = np.abs(g[big] - o[big]) / o[big]
-    assert rel.max() <= RATE_TOL, (label, float(rel.max()))
+    assert rel.max() <= (COMPACT_TOL if compact else RATE_TOL), (label, float(rel.max()))
     assert np.all(np.abs(g[~big]) <= 1e-29), label
     return len(mism)
 
@@ -175,7 +182,7 @@ def test_two_steps_match_the_oracle(gname, variant, compact, shed):
                     ora = oracle.step(gtuple, model, cur_st, cur_age, iota, k + j, compact=compact)
                     sim.step(1)
                     gst, gage, _ = sim.get_state(0)
-                    mism += compare_step(gst, gage, sim.rates(0), ora, f"k={k + j}")
+                    mism += compare_step(gst, gage, sim.rates(0), ora, f"k={k + j}", compact)
                     total += n
                     assert ora["lam"][cur_st == 0].max() > 0
         finally:

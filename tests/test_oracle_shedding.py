@@ -62,10 +62,32 @@ def test_infectivity_values_per_mode():
     got = oracle.infectivity(dict(base, shed=("hazard", wb, 0.4)), st, age)
     a64 = age.astype(np.float64)
     np.testing.assert_allclose(got, np.where(isI, 0.4 * d.pdf(a64) / d.sf(a64), 0.0), rtol=1e-12)
-    # compact ages: tau = n * dt
+    # compact storage: ages are whole steps (tau = n * dt) and the stored
+    # value is binary16 (numpy's float64 -> float16 conversion rounds to
+    # nearest even)
     steps = rng.integers(0, 300, n).astype(np.uint16)
     got = oracle.infectivity(dict(base, dt=0.2, shed=("density", law, 1.0)), st, steps, compact=True)
-    np.testing.assert_allclose(got, np.where(isI, scipy_law(law).pdf(steps * 0.2), 0.0), rtol=1e-12)
+    want = scipy_law(law).pdf(steps * 0.2).astype(np.float16).astype(np.float64)
+    np.testing.assert_allclose(got, np.where(isI, want, 0.0), rtol=1e-12)
+    np.testing.assert_array_equal(oracle.infectivity(base, st, steps, compact=True), isI.astype(float))
+
+
+def test_binary16_rounding_matches_numpy():
+    # the oracle's storage rounding of compact infectivity values against
+    # numpy's conversion: random magnitudes over the whole range, exact
+    # midpoints (ties go to even), the subnormal range, the overflow edge
+    rng = np.random.default_rng(11)
+    x = np.exp(rng.uniform(math.log(1e-9), math.log(1e6), 200_000))
+    x = np.concatenate([x, -x[:1000]])
+    h = np.arange(0, 0x7BFF, dtype=np.uint16).view(np.float16).astype(np.float64)
+    mid = (h[:-1] + h[1:]) / 2.0                          # exact in float64
+    edge = np.array([0.0, -0.0, 2.0**-24, 2.0**-25, 3 * 2.0**-26, 2.0**-14, 65504.0, 65519.99, 65520.0,
+                     65536.0, 1e9, np.inf, -np.inf])
+    for v in (x, mid, edge):
+        with np.errstate(over="ignore"):  # (the overflow edge: float16 infinity is expected)
+            want = v.astype(np.float16).astype(np.float64)
+        np.testing.assert_array_equal(oracle.binary16(v), want)
+    assert np.isnan(oracle.binary16(np.array([np.nan]))[0])
 
 
 def test_write_back_uses_the_age_after_the_step():
@@ -186,7 +208,8 @@ def test_star_compact_ages():
     K = 12
     _, ag, hist = oracle.run((rp, ci), model, st, age, K, compact=True)
     assert ag[0] == 2 + K
-    f = lambda t: 1.5 * scipy_law(law).pdf(t)
+    # the stored values are binary16 (compact storage)
+    f = lambda t: (1.5 * scipy_law(law).pdf(t)).astype(np.float16).astype(np.float64)
     for k in [4, 12]:
         taus = (2 + np.arange(k)) * dt
         p = 1 - math.exp(-beta * dt * f(taus).sum())
