@@ -14,7 +14,7 @@ constexpr int WG = 256;
 // Step kernel variants, all walking 64-unit chunks per wavefront:
 //  MODE_STREAM   bitmap read through the caches; STREAM_TPB threads per workgroup;
 //  MODE_RESIDENT the whole bitmap (up to RESIDENT_BITS units) held in LDS;
-//  MODE_SUMMARY  an LDS summary with one bit per 2^lg_gran units (set when any
+//  MODE_SUMMARY  an LDS summary with one bit per group of units (set when any
 //                unit of the group is infectious; at most SUMMARY_BITS bits)
 //                screens the reads of the bitmap, which stays in global memory.
 // The two LDS variants run one RESIDENT_TPB-thread workgroup per compute unit.
@@ -102,7 +102,9 @@ struct StepArgs {
     int32_t n;
     int32_t lgR;          // R = 1 << lgR replicas
     uint32_t step_off;    // j: this launch runs step ctl->step + j, partial slot j
-    int32_t lg_gran;      // MODE_SUMMARY: units per summary bit = 1 << lg_gran (>= 6)
+    // MODE_SUMMARY: one summary bit per group of 32 * 2^sum_shift units
+    // (2^sum_shift 32-bit bitmap words)
+    int32_t sum_shift;
     int32_t same_kind;    // E and I laws share a kind: one hazard call per lane
     int32_t pad0;
     HazardDev hz[2];      // [0] E -> I, [1] I -> R
@@ -204,7 +206,7 @@ struct SumArgs {
     unsigned long long* summary;
     uint32_t words;     // 64-bit words per bitmap
     uint32_t sum_words; // 64-bit words of the summary
-    int32_t lg_gran;
+    int32_t sum_shift;  // groups of 32 * 2^sum_shift units, as in StepArgs
     uint32_t step_off;
     uint32_t after;     // 1: the bitmap written by step ctl->step + step_off
     uint32_t pad;

@@ -73,19 +73,20 @@ __global__ void advance_batch_kernel(Ctl* const* __restrict__ ctls, uint32_t mem
     if (m < members) ctls[m]->step = ctls[m]->step + r;
 }
 
-// Summary of an infectivity bitmap: bit s is set when any of the 2^lg_gran
-// units of group s is infectious, i.e. when one of its 2^(lg_gran - 6) bitmap
-// words is nonzero.  One thread per summary bit, one summary word per wave.
+// Summary of an infectivity bitmap: bit s is set when any of the 32 w units
+// of group s is infectious, i.e. when one of its w = 2^sum_shift 32-bit
+// bitmap words is nonzero.  One thread per summary bit, one summary word per
+// wave.
 __global__ __launch_bounds__(WG) void summary_kernel(SumArgs q)
 {
     const unsigned long long k = q.ctl->step + q.step_off + q.after;
-    const unsigned long long* __restrict__ bits = (k & 1) ? q.iota1 : q.iota0;
+    const uint32_t* __restrict__ bits = (const uint32_t*)((k & 1) ? q.iota1 : q.iota0);
     const uint32_t s = blockIdx.x * WG + threadIdx.x;
-    const uint32_t gw = 1u << (q.lg_gran - 6);
-    const uint64_t w0 = (uint64_t)s * gw;
+    const uint32_t gw = 1u << q.sum_shift;
+    const uint64_t w0 = (uint64_t)s * gw, nw = 2ull * q.words;
     bool any = false;
     for (uint32_t i = 0; i < gw; ++i)
-        if (w0 + i < q.words && bits[w0 + i] != 0ull) any = true;
+        if (w0 + i < nw && bits[w0 + i] != 0u) any = true;
     const unsigned long long m = __ballot(any);
     if ((threadIdx.x & 63) == 0 && (s >> 6) < q.sum_words) q.summary[s >> 6] = m;
 }

@@ -664,7 +664,7 @@ fsi::SumArgs summary_args(const fs_sim* s, uint32_t after)
     a.summary = s->d_summary;
     a.words = s->bit_words;
     a.sum_words = s->sum_words;
-    a.lg_gran = s->lg_gran;
+    a.sum_shift = s->sum_shift;
     a.step_off = 0;
     a.after = after;
     return a;
@@ -1380,9 +1380,14 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
             : p->variant == 3 ? fsi::MODE_SUMMARY
             : fits_lds ? fsi::MODE_RESIDENT
             : summary_auto ? fsi::MODE_SUMMARY : fsi::MODE_STREAM;
-    s->lg_gran = 6;
-    while (((units + ((size_t)1 << s->lg_gran) - 1) >> s->lg_gran) > fsi::SUMMARY_BITS) ++s->lg_gran;
-    s->sum_bits = (uint32_t)((units + ((size_t)1 << s->lg_gran) - 1) >> s->lg_gran);
+    // summary groups: the fewest 32-bit bitmap words per group, a power of
+    // two, whose groups fit SUMMARY_BITS (one word per group up to 2^25 units)
+    {
+        const size_t words32 = (units + 31) / 32;
+        s->sum_shift = 0;
+        while (((words32 + ((size_t)1 << s->sum_shift) - 1) >> s->sum_shift) > fsi::SUMMARY_BITS) ++s->sum_shift;
+        s->sum_bits = (uint32_t)((words32 + ((size_t)1 << s->sum_shift) - 1) >> s->sum_shift);
+    }
     s->sum_words = (s->sum_bits + 63) / 64;
     s->tpb = s->mode == fsi::MODE_STREAM ? fsi::STREAM_TPB : fsi::RESIDENT_TPB;
     const size_t chunks = (units + 63) / 64;
@@ -1455,7 +1460,7 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
     a.n = (int32_t)g->n;
     a.lgR = s->lgR;
     a.step_off = 0;
-    a.lg_gran = s->lg_gran;
+    a.sum_shift = s->sum_shift;
     a.adaptive = p->adaptive ? 1 : 0;
     a.lam_part = s->d_lam_part;
     a.dt_hist = s->d_dt_hist;

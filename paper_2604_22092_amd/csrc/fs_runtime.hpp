@@ -117,7 +117,7 @@ struct fs_sim {
     int mode = fsi::MODE_STREAM;   // step kernel variant
     unsigned long long* d_summary = nullptr; // MODE_SUMMARY: summary of the current bitmap
     uint32_t sum_bits = 0, sum_words = 0;
-    int32_t lg_gran = 6;
+    int32_t sum_shift = 0;   // summary groups of 32 * 2^sum_shift units
     uint32_t bit_words = 0;        // 64-bit words per infectivity bitmap
     uint32_t chunk = 0;            // steps per launch sequence (partial slots)
     int64_t step = 0;      // index of the next step (host mirror of ctl->step)

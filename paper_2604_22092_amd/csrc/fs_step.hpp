@@ -134,6 +134,7 @@ struct BufIO<uint16_t> {
 // Element index that is out of range for every descriptor built here.
 constexpr uint32_t OOB_ELEM = OOB >> 2;
 
+
 // Infectivity bit b of the step's input for a lane that wants it (use):
 // from the LDS copy (MODE_RESIDENT), from global memory (MODE_STREAM), or
 // from global memory only when the LDS summary says its group holds an
@@ -144,7 +145,7 @@ constexpr uint32_t OOB_ELEM = OOB >> 2;
 // gathered slot and waits for each read on its own.
 template <int MODE>
 __device__ __forceinline__ uint32_t fetch_bit(const uint32_t* __restrict__ lds, rsrc_t gbits, uint32_t b,
-                                              int32_t lg_gran, bool use)
+                                              int32_t sum_shift, bool use)
 {
     if (MODE == MODE_RESIDENT) {
         const uint32_t w = lds_bit(lds, b);
@@ -152,7 +153,7 @@ __device__ __forceinline__ uint32_t fetch_bit(const uint32_t* __restrict__ lds, 
     }
     bool go = use;
     if (MODE == MODE_SUMMARY) {
-        const uint32_t sb = lds_bit(lds, b >> lg_gran);
+        const uint32_t sb = lds_bit(lds, b >> (5 + sum_shift));
         go = use & (sb != 0u);
     }
     const uint32_t w = ld32(gbits, go ? (b >> 5) << 2 : OOB);
@@ -587,10 +588,10 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
                     uint32_t sw[DEPTH];
 #pragma unroll
                     for (int j = 0; j < DEPTH; ++j)
-                        sw[j] = (UNIFORM || (uint32_t)j < P.ud[u]) ? lds[src[j] >> (a.lg_gran + 5)] : 0u;
+                        sw[j] = (UNIFORM || (uint32_t)j < P.ud[u]) ? lds[src[j] >> (a.sum_shift + 10)] : 0u;
 #pragma unroll
                     for (int j = 0; j < DEPTH; ++j)
-                        go[j] = use[j] & (__builtin_amdgcn_ubfe(sw[j], (src[j] >> a.lg_gran) & 31u, 1) != 0u);
+                        go[j] = use[j] & (__builtin_amdgcn_ubfe(sw[j], src[j] >> (a.sum_shift + 5), 1) != 0u);
                 } else {
 #pragma unroll
                     for (int j = 0; j < DEPTH; ++j) go[j] = use[j];
@@ -627,7 +628,7 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
                     v = S.v[u][j];
                 } else {
                     const uint32_t src = (col[j] << lgR) + rep;
-                    const uint32_t b = fetch_bit<MODE>(lds, gbits, src, a.lg_gran, use);
+                    const uint32_t b = fetch_bit<MODE>(lds, gbits, src, a.sum_shift, use);
                     v = shed_at<STORAGE>(shedr, src, b != 0u);
                 }
                 if (WEIGHTED) {
@@ -655,7 +656,7 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
                 for (int jj = 0; jj < JT; ++jj) {
                     const bool use = want && j0 + jj < P.ud[u];
                     const uint32_t src = ((uint32_t)c[jj] << lgR) + rep;
-                    const uint32_t b = fetch_bit<MODE>(lds, gbits, src, a.lg_gran, use);
+                    const uint32_t b = fetch_bit<MODE>(lds, gbits, src, a.sum_shift, use);
                     const float v = SHED ? shed_at<STORAGE>(shedr, src, b != 0u) : (float)b;
                     if (WEIGHTED) pw = __builtin_fmaf(wv[jj], v, pw);
                     else if (SHED) pw += v;
@@ -686,7 +687,7 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
             for (int jj = 0; jj < JB; ++jj) {
                 if (want && d > j0 + jj) {
                     const uint32_t src = ((uint32_t)c[jj] << lgR) + rep;
-                    const uint32_t b = fetch_bit<MODE>(lds, gbits, src, a.lg_gran, true);
+                    const uint32_t b = fetch_bit<MODE>(lds, gbits, src, a.sum_shift, true);
                     const float v = SHED ? shed_at<STORAGE>(shedr, src, b != 0u) : (float)b;
                     if (WEIGHTED) pw = __builtin_fmaf(wv[jj], v, pw);
                     else if (SHED) pw += v;
