@@ -97,7 +97,6 @@ struct fs_batch {
     fsi::HeavyArgs* d_htable = nullptr;
     uint32_t* d_hfirst = nullptr;
     fsi::RedArgs* d_red = nullptr;
-    fsi::Ctl** d_ctls = nullptr;
     uint32_t blocks = 0, hblocks = 0, hmembers = 0;
     uint32_t chunk = 0; // longest launch sequence (partial slots of the members)
     Staging staging;
@@ -126,7 +125,6 @@ fs_status rebuild_tables(fs_batch* b)
     std::vector<uint32_t> first(1, 0u), hfirst(1, 0u);
     std::vector<fsi::HeavyArgs> htable;
     std::vector<fsi::RedArgs> red;
-    std::vector<fsi::Ctl*> ctls;
     b->chunk = 1u << 30;
     for (fs_sim* s : b->members) {
         table.push_back(s->args);
@@ -143,7 +141,6 @@ fs_status rebuild_tables(fs_batch* b)
         r.C = 4u * (uint32_t)s->R;
         r.H = (uint32_t)s->H;
         red.push_back(r);
-        ctls.push_back(s->d_ctl);
         b->chunk = std::min(b->chunk, s->chunk);
     }
     b->blocks = first.back();
@@ -156,8 +153,7 @@ fs_status rebuild_tables(fs_batch* b)
     const size_t o_htable = align_up(o_first + (M + 1) * sizeof(uint32_t));
     const size_t o_hfirst = align_up(o_htable + std::max<size_t>(htable.size(), 1) * sizeof(fsi::HeavyArgs));
     const size_t o_red = align_up(o_hfirst + hfirst.size() * sizeof(uint32_t));
-    const size_t o_ctls = align_up(o_red + M * sizeof(fsi::RedArgs));
-    const size_t bytes = align_up(o_ctls + M * sizeof(fsi::Ctl*));
+    const size_t bytes = align_up(o_red + M * sizeof(fsi::RedArgs));
     void* host = nullptr;
     int slot = 0;
     fs_status st = b->staging.take(bytes, &host, &slot);
@@ -168,7 +164,6 @@ fs_status rebuild_tables(fs_batch* b)
     if (!htable.empty()) std::memcpy(h + o_htable, htable.data(), htable.size() * sizeof(fsi::HeavyArgs));
     std::memcpy(h + o_hfirst, hfirst.data(), hfirst.size() * sizeof(uint32_t));
     std::memcpy(h + o_red, red.data(), M * sizeof(fsi::RedArgs));
-    std::memcpy(h + o_ctls, ctls.data(), M * sizeof(fsi::Ctl*));
     if (bytes > b->d_cap) {
         if (b->d_tables) (void)hipFreeAsync(b->d_tables, b->stream);
         b->d_tables = nullptr;
@@ -184,7 +179,6 @@ fs_status rebuild_tables(fs_batch* b)
     b->d_htable = (fsi::HeavyArgs*)(d + o_htable);
     b->d_hfirst = (uint32_t*)(d + o_hfirst);
     b->d_red = (fsi::RedArgs*)(d + o_red);
-    b->d_ctls = (fsi::Ctl**)(d + o_ctls);
     return FS_OK;
 }
 
@@ -259,9 +253,6 @@ fs_status batch_sequence(fs_batch* b, uint32_t r)
     }
     void* rargv[] = {&b->d_red};
     FS_HIP(hipLaunchKernel(fsk::reduce_batch_kernel_fn(), dim3(r, M), dim3(WG), rargv, 0, b->stream));
-    uint32_t members = M, rr = r;
-    void* aargv[] = {&b->d_ctls, &members, &rr};
-    FS_HIP(hipLaunchKernel(fsk::advance_batch_kernel_fn(), dim3((M + 63) / 64), dim3(64), aargv, 0, b->stream));
     return FS_OK;
 }
 

@@ -79,12 +79,15 @@ struct ShedDev {
 
 // Device-resident control block of a simulation.  `step` is the index of the
 // first step of the launch sequence being run: step launch j of a sequence
-// runs step (step + j), and a single-thread advance kernel at the end of the
-// sequence adds its length.  Captured sequences therefore need no per-replay
-// arguments and no step kernel touches a shared counter.
+// runs step (step + j), and the reduce launch that ends the sequence adds its
+// length (its last block to finish, counted in `done`).  Captured sequences
+// therefore need no per-replay arguments and no step kernel touches a shared
+// counter.
 struct Ctl {
     unsigned long long step;
     unsigned long long adapt_from; // adaptive step: the step that uses the cap (creation, state load)
+    uint32_t done;                 // blocks of the running reduce launch that have finished; 0 between launches
+    uint32_t pad;
 };
 
 // Kernel arguments of one fused step launch.
@@ -242,7 +245,7 @@ struct HeavyArgs {
 // One member's count reduction in a batch: per-workgroup partials of G
 // workgroups, C = 4R counters each, summed into the H-slot history ring.
 struct RedArgs {
-    const Ctl* ctl;
+    Ctl* ctl;
     const uint32_t* part;
     uint32_t* hist;
     uint32_t G, C, H, pad;

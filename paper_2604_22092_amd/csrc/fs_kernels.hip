@@ -25,30 +25,45 @@ namespace fsk {
 // counters from G workgroups, part[j][g][c]; the totals go to
 // out[((base + j) mod H)][c] where base = ctl->step (0 without ctl).
 // Requires C <= WG and WG % C == 0 (C = 4R with R a power of two <= 64).
-__device__ __forceinline__ void reduce_body(const Ctl* ctl, const uint32_t* part, uint32_t G, uint32_t C,
+// With a ctl, the r blocks of the launch end the launch sequence: each takes
+// a ticket in ctl->done once its reads of ctl->step are done, and the last
+// one adds r to ctl->step and clears the count (so the sequence needs no
+// launch of its own for the advance).
+__device__ __forceinline__ void reduce_body(Ctl* ctl, const uint32_t* part, uint32_t G, uint32_t C,
                                             uint32_t* out, uint32_t H, uint32_t j, uint32_t r)
 {
     __shared__ uint32_t s[WG];
     const uint32_t t = threadIdx.x;
     // of a sequence longer than the ring only the last H steps are kept, so
     // no two blocks write one slot
-    if ((size_t)j + H < (size_t)r) return;
-    const uint32_t groups = WG / C;
-    const uint32_t c = t % C;
-    const uint32_t* p = part + (size_t)j * G * C;
-    uint32_t sum = 0;
-    for (uint32_t g = t / C; g < G; g += groups) sum += p[(size_t)g * C + c];
-    s[t] = sum;
-    __syncthreads();
-    if (t < C) {
-        uint32_t tot = 0;
-        for (uint32_t i = 0; i < groups; ++i) tot += s[i * C + t];
-        const unsigned long long base = ctl ? ctl->step : 0ull;
-        out[(size_t)((base + j) % H) * C + t] = tot;
+    if ((size_t)j + H >= (size_t)r) {
+        const uint32_t groups = WG / C;
+        const uint32_t c = t % C;
+        const uint32_t* p = part + (size_t)j * G * C;
+        uint32_t sum = 0;
+        for (uint32_t g = t / C; g < G; g += groups) sum += p[(size_t)g * C + c];
+        s[t] = sum;
+        __syncthreads();
+        if (t < C) {
+            uint32_t tot = 0;
+            for (uint32_t i = 0; i < groups; ++i) tot += s[i * C + t];
+            const unsigned long long base = ctl ? ctl->step : 0ull;
+            out[(size_t)((base + j) % H) * C + t] = tot;
+        }
+    }
+    if (ctl) {
+        __syncthreads();
+        if (t == 0) {
+            const uint32_t prior = __hip_atomic_fetch_add(&ctl->done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (prior + 1u == r) {
+                __hip_atomic_store(&ctl->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&ctl->step, ctl->step + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
     }
 }
 
-__global__ __launch_bounds__(WG) void reduce_kernel(const Ctl* ctl, const uint32_t* part, uint32_t G,
+__global__ __launch_bounds__(WG) void reduce_kernel(Ctl* ctl, const uint32_t* part, uint32_t G,
                                                      uint32_t C, uint32_t* out, uint32_t H)
 {
     reduce_body(ctl, part, G, C, out, H, blockIdx.x, gridDim.x);
@@ -59,18 +74,6 @@ __global__ __launch_bounds__(WG) void reduce_batch_kernel(const RedArgs* __restr
 {
     const RedArgs q = table[blockIdx.y];
     reduce_body(q.ctl, q.part, q.G, q.C, q.hist, q.H, blockIdx.x, gridDim.x);
-}
-
-__global__ void advance_kernel(Ctl* ctl, uint32_t r)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) ctl->step = ctl->step + r;
-}
-
-// Batched advance: thread m adds r to member m's step index.
-__global__ void advance_batch_kernel(Ctl* const* __restrict__ ctls, uint32_t members, uint32_t r)
-{
-    const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m < members) ctls[m]->step = ctls[m]->step + r;
 }
 
 // Summary of an infectivity bitmap: bit s is set when any of the 32 w units
@@ -388,7 +391,7 @@ hipError_t launch_recount(int storage, const void* state, int32_t n, int32_t lgR
         hipLaunchKernelGGL(recount_kernel<0>, dim3(g), dim3(WG), 0, s, state, n, lgR, replica, part);
     else
         hipLaunchKernelGGL(recount_kernel<1>, dim3(g), dim3(WG), 0, s, state, n, lgR, replica, part);
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(WG), 0, s, (const Ctl*)nullptr, (const uint32_t*)part,
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(WG), 0, s, (Ctl*)nullptr, (const uint32_t*)part,
                        (uint32_t)g, 4u, out4, 1u);
     return hipGetLastError();
 }
@@ -401,7 +404,6 @@ const void* heavy_kernel_fn(bool weighted, bool shed, bool resident)
         return weighted ? (const void*)&heavy_resident_kernel<true, false> : (const void*)&heavy_resident_kernel<false, false>;
     return weighted ? (const void*)&heavy_pressure_kernel<true, false> : (const void*)&heavy_pressure_kernel<false, false>;
 }
-const void* advance_kernel_fn() { return (const void*)&advance_kernel; }
 const void* summary_kernel_fn() { return (const void*)&summary_kernel; }
 
 const void* step_batch_kernel_fn(int storage, bool weighted, bool extra)
@@ -420,7 +422,6 @@ const void* heavy_batch_kernel_fn(bool weighted)
     return weighted ? (const void*)&heavy_batch_kernel<true> : (const void*)&heavy_batch_kernel<false>;
 }
 const void* reduce_batch_kernel_fn() { return (const void*)&reduce_batch_kernel; }
-const void* advance_batch_kernel_fn() { return (const void*)&advance_batch_kernel; }
 
 hipError_t launch_put_replica(int storage, void* state, void* age, const int32_t* src_state, const void* src_age,
                               int32_t n, int32_t lgR, int32_t replica, hipStream_t s)

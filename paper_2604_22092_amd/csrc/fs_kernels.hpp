@@ -49,16 +49,15 @@ hipError_t launch_recount(int storage, const void* state, int32_t n, int32_t lgR
 // the row in replica r (StepArgs::hub_T).
 hipError_t launch_hub_recount(const int32_t* row_ptr, const int32_t* col_ind, int32_t hub_base, uint32_t hubs,
                               int32_t lgR, const uint32_t* bits, uint32_t* out, hipStream_t s);
-// reduce_kernel(const Ctl*, const uint32_t* part, uint32_t G, uint32_t C, uint32_t* out, uint32_t H):
-// one block per slot, WG threads.
+// reduce_kernel(Ctl*, const uint32_t* part, uint32_t G, uint32_t C, uint32_t* out, uint32_t H):
+// one block per slot, WG threads; with a ctl it also adds the slot count (its
+// grid) to the step index, which ends a launch sequence.
 const void* reduce_kernel_fn();
 // Segment partials of degree-binned rows (HeavyArgs): heavy_pressure_kernel
 // (WG threads, bits from global memory), or with resident set
 // heavy_resident_kernel (RESIDENT_TPB threads, at most one workgroup per CU,
 // the bitmap copied into LDS).
 const void* heavy_kernel_fn(bool weighted, bool shed, bool resident);
-// advance_kernel(Ctl*, uint32_t r): adds r to the step index; one thread.
-const void* advance_kernel_fn();
 // summary_kernel(SumArgs): one thread per summary bit (sum_words * 64 threads
 // in WG-thread workgroups).
 const void* summary_kernel_fn();
@@ -71,9 +70,8 @@ const void* step_batch_kernel_fn(int storage, bool weighted, bool extra);
 // heavy_batch_kernel(const HeavyArgs* table, const uint32_t* first, uint32_t members, uint32_t step_off), WG threads;
 const void* heavy_batch_kernel_fn(bool weighted);
 // reduce_batch_kernel(const RedArgs* table): grid (r, members), WG threads;
+// advances every member's step index by r
 const void* reduce_batch_kernel_fn();
-// advance_batch_kernel(Ctl* const* ctls, uint32_t members, uint32_t r): one thread per member.
-const void* advance_batch_kernel_fn();
 hipError_t launch_put_replica(int storage, void* state, void* age, const int32_t* src_state, const void* src_age,
                               int32_t n, int32_t lgR, int32_t replica, hipStream_t s);
 hipError_t launch_rebuild_bits(int storage, const void* state, uint32_t total, unsigned long long* bits,

@@ -23,7 +23,8 @@
 // Both modes give the same integer influences on every node that can still
 // read them (every susceptible node; every node under SIS), so results do not
 // depend on which ran.  Per-step counts, tau and event totals go to rings on the
-// device; a launch sequence ends with the count reduce and the step advance.
+// device; a launch sequence ends with the count reduce, which also advances
+// the step index.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -428,7 +429,6 @@ hipError_t refresh(fs_markov* m)
 
 struct MkSeq {
     std::vector<MkArgs> step;
-    const fsi::Ctl* ctl_c;
     fsi::Ctl* ctl;
     const uint32_t* part;
     uint32_t G, C, H, r;
@@ -439,7 +439,6 @@ void make_seq(fs_markov* m, uint32_t r, MkSeq& q)
 {
     q.step.assign(r, m->args);
     for (uint32_t j = 0; j < r; ++j) q.step[j].step_off = j;
-    q.ctl_c = m->d_ctl;
     q.ctl = m->d_ctl;
     q.part = m->d_part;
     q.G = m->G;
@@ -475,10 +474,8 @@ fs_status build_exec(fs_markov* m, uint32_t b)
         if ((st = add((const void*)&fsm::mk_push_kernel, dim3(push_grid(m)), dim3(fsm::PTPB), argv)) != FS_OK) return st;
         if ((st = add((const void*)&fsm::mk_rates_kernel, dim3(m->G), dim3(fsm::MTPB), argv)) != FS_OK) return st;
     }
-    void* rargv[] = {&q.ctl_c, &q.part, &q.G, &q.C, &q.hist, &q.H};
+    void* rargv[] = {&q.ctl, &q.part, &q.G, &q.C, &q.hist, &q.H};
     if ((st = add(fsk::reduce_kernel_fn(), dim3(q.r), dim3(WG), rargv)) != FS_OK) return st;
-    void* aargv[] = {&q.ctl, &q.r};
-    if ((st = add(fsk::advance_kernel_fn(), dim3(1), dim3(64), aargv)) != FS_OK) return st;
     FS_HIP(hipGraphInstantiate(&m->exec, m->graph, nullptr, nullptr, 0));
     return FS_OK;
 }
@@ -494,10 +491,8 @@ fs_status launch_seq(fs_markov* m, uint32_t r)
                                m->stream));
         FS_HIP(hipLaunchKernel((const void*)&fsm::mk_rates_kernel, dim3(m->G), dim3(fsm::MTPB), argv, 0, m->stream));
     }
-    void* rargv[] = {&q.ctl_c, &q.part, &q.G, &q.C, &q.hist, &q.H};
+    void* rargv[] = {&q.ctl, &q.part, &q.G, &q.C, &q.hist, &q.H};
     FS_HIP(hipLaunchKernel(fsk::reduce_kernel_fn(), dim3(r), dim3(WG), rargv, 0, m->stream));
-    void* aargv[] = {&q.ctl, &q.r};
-    FS_HIP(hipLaunchKernel(fsk::advance_kernel_fn(), dim3(1), dim3(64), aargv, 0, m->stream));
     return FS_OK;
 }
 

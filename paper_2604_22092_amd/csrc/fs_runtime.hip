@@ -275,13 +275,12 @@ fs_status check_replica(const fs_sim* s, int32_t replica, bool allow_all)
 constexpr uint32_t RC_GRID = 1024;
 
 // Launch sequence of r steps: (with compaction: a rates clear when rates are
-// recorded, and the active-list refresh) r step launches, one reduce, one
-// advance.
+// recorded, and the active-list refresh) r step launches, and one reduce,
+// which also advances the device step index.
 struct SeqArgs {
     std::vector<StepArgs> step;
     std::vector<fsi::HeavyArgs> heavy;
     std::vector<fsi::SumArgs> sum;
-    const fsi::Ctl* ctl_c;
     fsi::Ctl* ctl;
     const uint32_t* part;
     uint32_t G, C, H, r;
@@ -743,7 +742,6 @@ void make_seq(fs_sim* s, uint32_t r, SeqArgs& q)
         q.sum.assign(r, summary_args(s, 1));
         for (uint32_t j = 0; j < r; ++j) q.sum[j].step_off = j;
     }
-    q.ctl_c = s->d_ctl;
     q.ctl = s->d_ctl;
     q.part = s->d_part;
     q.G = s->G;
@@ -801,10 +799,8 @@ fs_status build_graph_exec(fs_sim* s, int b)
             if ((st = add(fsk::summary_kernel_fn(), dim3(summary_grid(s)), dim3(WG), sargv)) != FS_OK) return st;
         }
     }
-    void* rargv[] = {&q.ctl_c, &q.part, &q.G, &q.C, &q.hist, &q.H};
+    void* rargv[] = {&q.ctl, &q.part, &q.G, &q.C, &q.hist, &q.H};
     if ((st = add(fsk::reduce_kernel_fn(), dim3(q.r), dim3(WG), rargv)) != FS_OK) return st;
-    void* aargv[] = {&q.ctl, &q.r};
-    if ((st = add(fsk::advance_kernel_fn(), dim3(1), dim3(64), aargv)) != FS_OK) return st;
     FS_HIP(hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0));
     return FS_OK;
 }
@@ -834,10 +830,8 @@ fs_status launch_sequence(fs_sim* s, uint32_t r)
             FS_HIP(hipLaunchKernel(fsk::summary_kernel_fn(), dim3(summary_grid(s)), dim3(WG), sargv, 0, s->stream));
         }
     }
-    void* rargv[] = {&q.ctl_c, &q.part, &q.G, &q.C, &q.hist, &q.H};
+    void* rargv[] = {&q.ctl, &q.part, &q.G, &q.C, &q.hist, &q.H};
     FS_HIP(hipLaunchKernel(fsk::reduce_kernel_fn(), dim3(r), dim3(WG), rargv, 0, s->stream));
-    void* aargv[] = {&q.ctl, &q.r};
-    FS_HIP(hipLaunchKernel(fsk::advance_kernel_fn(), dim3(1), dim3(64), aargv, 0, s->stream));
     return FS_OK;
 }
 
