@@ -197,6 +197,17 @@ __device__ __forceinline__ T* opaque_uniform(T* p)
     return (T*)(((unsigned long long)hi << 32) | lo);
 }
 
+// A wave-uniform offset held in a vector register: every use of it is
+// per-lane address arithmetic, and in a scalar register it would be one more
+// value held through the walk (spilled to vector lanes and read back with lane
+// reads in every pass).
+template <class T>
+__device__ __forceinline__ T in_vgpr(T x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // The rate of an E (isI false) or I unit of age xa: the hazard of its law.
 // With both laws of one kind the E/I choice only selects parameters, so one
 // hazard evaluation serves a wavefront holding both.  hz points to device
@@ -287,6 +298,7 @@ struct HubCtx {
     uint32_t* pb;  // LDS: 64 list starts (flush)
     uint32_t* px;  // LDS: 64 exclusive prefix sums (flush)
     uint32_t n;    // queued entries (wave-uniform)
+    uint32_t base; // the first binned unit, hub_base << lgR (in a vector register)
 };
 
 // The pushes of the queued units: +1 (entering I) or -1 (leaving I) into the
@@ -349,24 +361,44 @@ __device__ __forceinline__ void flush_pushes(const StepArgs& a, HubCtx& H, uint3
     H.n = 0;
 }
 
+// The hazard table (StepArgs::htab) as the kernels of mixed layouts read it:
+// its address, scale and length held in vector registers (their walks hold
+// more wave-uniform values than the scalar registers take), and no table as
+// length 0.
+struct TabRef {
+    const float4* p;
+    float inv, len;
+};
+
 // Hazard-table loads of a pass's E/I lanes (StepArgs::htab), issued once its
 // state and age have arrived and before the next pass's loads, so that
 // waiting for them never waits for a later pass.  Lanes without an entry
-// read nothing (0).
+// read nothing: their age field holds 0 (uniform layouts) or NaN (mixed
+// layouts, where it also stands for a missing table).
 template <bool UNIFORM, class age_t>
-__device__ __forceinline__ void issue_table(const StepArgs& a, Pass<age_t>& P, uint32_t lane)
+__device__ __forceinline__ void issue_table(const StepArgs& a, const TabRef& tv, Pass<age_t>& P, uint32_t lane)
 {
     const rsrc_t tr = make_rsrc(a.htab, a.htab ? a.htab_len * 16u : 0u);
 #pragma unroll
     for (int u = 0; u < CU; ++u) {
         const int x = lane < P.nvalid[u] ? (int)P.xr[u] : ST_R;
         const float af = age_units(age_from_raw<age_t>(P.agw[u]));
-        const float mf = rintf(af * a.htab_inv);
-        const bool want = (x == ST_E || x == ST_I) && mf < (float)a.htab_len;
-        const auto t = __builtin_amdgcn_raw_buffer_load_b128(tr, want ? (int)((uint32_t)mf << 4) : (int)OOB, 0, 0);
-        P.tab[u][0] = __uint_as_float(t[0]);
-        P.tab[u][1] = __uint_as_float(t[1]);
-        P.tab[u][2] = __uint_as_float(t[2]);
+        if (UNIFORM) {
+            const float mf = rintf(af * a.htab_inv);
+            const bool want = (x == ST_E || x == ST_I) && mf < (float)a.htab_len;
+            const auto t = __builtin_amdgcn_raw_buffer_load_b128(tr, want ? (int)((uint32_t)mf << 4) : (int)OOB, 0, 0);
+            P.tab[u][0] = __uint_as_float(t[0]);
+            P.tab[u][1] = __uint_as_float(t[1]);
+            P.tab[u][2] = __uint_as_float(t[2]);
+        } else {
+            const float mf = rintf(af * tv.inv);
+            const bool want = (x == ST_E || x == ST_I) && mf < tv.len;
+            float4 t = make_float4(__builtin_nanf(""), 0.0f, 0.0f, 0.0f);
+            if (want) t = tv.p[(uint32_t)mf];
+            P.tab[u][0] = t.x;
+            P.tab[u][1] = t.y;
+            P.tab[u][2] = t.z;
+        }
     }
     // (keep the scheduler from moving the next pass's loads above these)
     __builtin_amdgcn_sched_barrier(0);
@@ -377,6 +409,7 @@ __device__ __forceinline__ void issue_table(const StepArgs& a, Pass<age_t>& P, u
 struct Ahead {
     uint32_t chunk[CU];
     uint32_t mx[CU], my[CU];
+    const uint2* meta; // StepArgs::chunk_meta, held in vector registers
 };
 
 // Issues every load of a pass that does not depend on the state: chunk
@@ -429,10 +462,9 @@ __device__ __forceinline__ void issue_pass(const StepArgs& a, uint32_t first, ui
             P.base[u] = __builtin_amdgcn_readfirstlane(ah.mx[u]);
             P.ud[u] = P.live[u] ? __builtin_amdgcn_readfirstlane(ah.my[u]) : 0u;
             const uint32_t nxt = min(pos + stride, nchunks - 1u);
-            const auto m = __builtin_amdgcn_raw_buffer_load_b64(make_rsrc(a.chunk_meta, nchunks * 8u), (int)(nxt << 3),
-                                                                0, 0);
-            ah.mx[u] = m[0];
-            ah.my[u] = m[1];
+            const uint2 m = ah.meta[nxt];
+            ah.mx[u] = m.x;
+            ah.my[u] = m.y;
         }
         const uint32_t u0 = P.chk[u] << 6;
         P.nvalid[u] = P.live[u] ? min(64u, total - u0) : 0u;
@@ -449,8 +481,10 @@ __device__ __forceinline__ void issue_pass(const StepArgs& a, uint32_t first, ui
         // binned rows with pushed pressure are the nodes from hub_base on:
         // their last count and this step's delta come with the pass
         if (!UNIFORM && H.on) {
-            const bool hub = lane < P.nvalid[u] && n0 + q >= (uint32_t)a.hub_base;
-            const uint32_t h = hub ? u0 + lane - ((uint32_t)a.hub_base << a.lgR) : 0u;
+            // (unit u0 + lane belongs to a binned row exactly when it is at
+            // least the first binned unit)
+            const bool hub = lane < P.nvalid[u] && u0 + lane >= H.base;
+            const uint32_t h = hub ? u0 + lane - H.base : 0u;
             P.ht[u] = ld32(H.tr, hub ? (H.t_prev + h) << 2 : OOB);
             P.hd[u] = ld32(H.tr, hub ? (H.d_cur + h) << 2 : OOB);
         }
@@ -823,7 +857,7 @@ __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t
             // its count into this step's slot and clears the delta slot that
             // the next step's pushes do not use
             if (__ballot(heavy) != 0ull) {
-                const uint32_t h = heavy ? unit[u] - ((uint32_t)a.hub_base << a.lgR) : 0u;
+                const uint32_t h = heavy ? unit[u] - H.base : 0u;
                 const uint32_t pp = P.ht[u] + P.hd[u];
                 st32(H.tr, heavy ? (H.t_cur + h) << 2 : OOB, pp);
                 st32(H.tr, heavy ? (H.d_clr + h) << 2 : OOB, 0u);
@@ -850,7 +884,7 @@ __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t
         bool hit[CU];
 #pragma unroll
         for (int u = 0; u < CU; ++u) {
-            hit[u] = a.htab != nullptr && need[u] && P.tab[u][0] == age_units(ag[u]);
+            hit[u] = (!UNIFORM || a.htab != nullptr) && need[u] && P.tab[u][0] == age_units(ag[u]);
             if (hit[u]) lam[u] = x[u] == ST_I ? P.tab[u][2] : P.tab[u][1];
             need[u] = need[u] && !hit[u];
         }
@@ -932,8 +966,13 @@ __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t
         // 7. next-step infectivity bits (one 64-bit word per chunk, written by
         // lanes 0 and 1) and 8. counts
         const unsigned long long mI = __ballot(valid[u] && xn == ST_I);
-        st32(make_rsrc(bits_out + P.chk[u], P.live[u] ? 8u : 0u), lane < 2 ? lane << 2 : OOB,
-             lane == 0 ? (uint32_t)mI : (uint32_t)(mI >> 32));
+        if (UNIFORM) {
+            st32(make_rsrc(bits_out + P.chk[u], P.live[u] ? 8u : 0u), lane < 2 ? lane << 2 : OOB,
+                 lane == 0 ? (uint32_t)mI : (uint32_t)(mI >> 32));
+        } else if (P.live[u] && lane < 2) {
+            // (mixed layouts: bits_out is held in vector registers)
+            ((uint32_t*)bits_out)[2 * P.chk[u] + lane] = lane == 0 ? (uint32_t)mI : (uint32_t)(mI >> 32);
+        }
         if (R == 1) {
             c0 += (uint32_t)__popcll(__ballot(valid[u] && xn == ST_S));
             c1 += (uint32_t)__popcll(__ballot(valid[u] && xn == ST_E));
@@ -1041,16 +1080,17 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
     H.q = s_pq[HUBS ? wave : 0];
     H.pb = s_pb[HUBS ? wave : 0];
     H.px = s_xch[wave];
-    H.t_prev = H.t_cur = H.d_cur = H.d_clr = H.d_next = 0;
+    H.t_prev = H.t_cur = H.d_cur = H.d_clr = H.d_next = H.base = 0;
     if (H.on) {
         const uint32_t HU = a.hub_units;
         const uint32_t k2 = (uint32_t)(k & 1ull), k3 = (uint32_t)(k % 3ull);
         H.tr = make_rsrc(a.hub_T, 5u * HU * 4u);
-        H.t_prev = (k2 ^ 1u) * HU;
-        H.t_cur = k2 * HU;
-        H.d_cur = (2u + k3) * HU;
-        H.d_next = (2u + (k3 + 1u) % 3u) * HU;
-        H.d_clr = (2u + (k3 + 2u) % 3u) * HU;
+        H.t_prev = in_vgpr((k2 ^ 1u) * HU);
+        H.t_cur = in_vgpr(k2 * HU);
+        H.d_cur = in_vgpr((2u + k3) * HU);
+        H.d_next = in_vgpr((2u + (k3 + 1u) % 3u) * HU);
+        H.d_clr = in_vgpr((2u + (k3 + 2u) % 3u) * HU);
+        H.base = in_vgpr((uint32_t)a.hub_base << a.lgR);
     } else {
         H.tr = make_rsrc(nullptr, 0u);
     }
@@ -1060,16 +1100,16 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
     uint32_t first = wave_id;
     const uint32_t stride = nwaves * CU;
     Ahead ahead;
+    ahead.meta = UNIFORM ? a.chunk_meta : in_vgpr(a.chunk_meta);
 #pragma unroll
     for (int u = 0; u < CU; ++u) {
         const uint32_t pos = first + (uint32_t)u * nwaves;
         ahead.chunk[u] = (EXTRA && a.act && pos < walk) ? a.act[2 + pos] : 0u;
         ahead.mx[u] = ahead.my[u] = 0u;
         if (!UNIFORM) {
-            const auto m = __builtin_amdgcn_raw_buffer_load_b64(make_rsrc(a.chunk_meta, nchunks * 8u),
-                                                                (int)(min(pos, nchunks - 1u) << 3), 0, 0);
-            ahead.mx[u] = m[0];
-            ahead.my[u] = m[1];
+            const uint2 m = ahead.meta[min(pos, nchunks - 1u)];
+            ahead.mx[u] = m.x;
+            ahead.my[u] = m.y;
         }
     }
     issue_pass<STORAGE, UD, EXTRA, PB>(a, first, nwaves, stride, nchunks, walk, total, lane, P, ahead, H);
@@ -1089,7 +1129,14 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
         __builtin_amdgcn_s_waitcnt(0);
     }
     if (R > 1 || USE_LDS) __syncthreads();
-    issue_table<UNIFORM>(a, P, lane);
+    TabRef tv{nullptr, 0.0f, 0.0f};
+    if (!UNIFORM) {
+        tv.p = in_vgpr(a.htab);
+        tv.inv = in_vgpr(a.htab_inv);
+        tv.len = in_vgpr(a.htab ? (float)a.htab_len : 0.0f);
+    }
+    unsigned long long* __restrict__ bo = UNIFORM ? bits_out : in_vgpr(bits_out);
+    issue_table<UNIFORM>(a, tv, P, lane);
 
     uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0; // per-wave counts (R == 1)
 
@@ -1108,24 +1155,24 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
             issue_pass<STORAGE, UD, EXTRA, PB>(a, first + stride, nwaves, stride, nchunks, walk, total, lane, P1,
                                                 ahead, H);
         process_pass<STORAGE, WEIGHTED, MODE, UD, SHED, EXTRA, PB>(a, P, lane, s_bits, gbits, shedr, shed_out, sv,
-                                                                    s_xch[wave], k, bits_out, s_cnt, c0, c1, c2,
+                                                                    s_xch[wave], k, bo, s_cnt, c0, c1, c2,
                                                                     c3, dt, lmax, H);
         first += stride;
         if (first >= walk) break;
         if (!PREFETCH)
             issue_pass<STORAGE, UD, EXTRA, PB>(a, first, nwaves, stride, nchunks, walk, total, lane, P1, ahead, H);
-        issue_table<UNIFORM>(a, P1, lane);
+        issue_table<UNIFORM>(a, tv, P1, lane);
         if (SPLIT) shed_pre<STORAGE, UD, PB>(a, P1, lane, s_bits, shedr, sv);
         if (PREFETCH)
             issue_pass<STORAGE, UD, EXTRA, PB>(a, first + stride, nwaves, stride, nchunks, walk, total, lane, P,
                                                 ahead, H);
         process_pass<STORAGE, WEIGHTED, MODE, UD, SHED, EXTRA, PB>(a, P1, lane, s_bits, gbits, shedr, shed_out, sv,
-                                                                    s_xch[wave], k, bits_out, s_cnt, c0, c1, c2,
+                                                                    s_xch[wave], k, bo, s_cnt, c0, c1, c2,
                                                                     c3, dt, lmax, H);
         first += stride;
         if (!PREFETCH && first < walk)
             issue_pass<STORAGE, UD, EXTRA, PB>(a, first, nwaves, stride, nchunks, walk, total, lane, P, ahead, H);
-        if (first < walk) issue_table<UNIFORM>(a, P, lane);
+        if (first < walk) issue_table<UNIFORM>(a, tv, P, lane);
     }
 
     // the queued pushes of binned rows, after the walk (no prefetched load is
