@@ -184,6 +184,17 @@ constexpr int CU = FS_CU;
 #endif
 constexpr bool PREFETCH = FS_PREFETCH != 0;
 
+// A device-memory pointer rebuilt from its bits.  It goes through a pointer
+// to the global address space, so that the accesses through it are global
+// ones (a pointer made from an integer is generic, and generic accesses
+// count against the LDS counter too, so that an LDS wait would also wait
+// for them).
+template <class T>
+__device__ __forceinline__ T* as_global(unsigned long long v)
+{
+    return (T*)(__attribute__((address_space(1))) T*)v;
+}
+
 // A wave-uniform pointer passed through an empty asm where it is used, so
 // that neither it nor the addresses formed from it are hoisted out of the
 // walk (held through the walk they would be spilled to vector lanes, and
@@ -194,7 +205,7 @@ __device__ __forceinline__ T* opaque_uniform(T* p)
     const unsigned long long v = (unsigned long long)p;
     uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v), hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
     asm volatile("" : "+s"(lo), "+s"(hi));
-    return (T*)(((unsigned long long)hi << 32) | lo);
+    return as_global<T>(((unsigned long long)hi << 32) | lo);
 }
 
 // A wave-uniform offset held in a vector register: every use of it is
@@ -206,6 +217,14 @@ __device__ __forceinline__ T in_vgpr(T x)
 {
     asm volatile("" : "+v"(x));
     return x;
+}
+
+template <class T>
+__device__ __forceinline__ T* in_vgpr(T* p)
+{
+    unsigned long long v = (unsigned long long)p;
+    asm volatile("" : "+v"(v));
+    return as_global<T>(v);
 }
 
 // The rate of an E (isI false) or I unit of age xa: the hazard of its law.
