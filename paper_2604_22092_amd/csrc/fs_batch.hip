@@ -252,7 +252,7 @@ fs_status batch_sequence(fs_batch* b, uint32_t r)
         FS_HIP(hipLaunchKernel(kfn, dim3(b->blocks), dim3(fsi::STREAM_TPB), argv, 0, b->stream));
     }
     void* rargv[] = {&b->d_red};
-    FS_HIP(hipLaunchKernel(fsk::reduce_batch_kernel_fn(), dim3(r, M), dim3(WG), rargv, 0, b->stream));
+    FS_HIP(hipLaunchKernel(fsk::reduce_batch_kernel_fn(), dim3(r, M), dim3(fsi::RED_TPB), rargv, 0, b->stream));
     return FS_OK;
 }
 

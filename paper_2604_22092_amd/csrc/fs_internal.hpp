@@ -11,6 +11,10 @@ enum : int32_t { K_EXP = 0, K_LN = 1, K_WB = 2, K_ERL = 3 };
 
 // Workgroup size of the helper kernels (four wave64 wavefronts).
 constexpr int WG = 256;
+// Workgroup size of the count reduce (sixteen wavefronts: a step of the
+// streaming variant with many replicas leaves up to max_step_grid(R) * 4R
+// partial counts, one block reads them all).
+constexpr int RED_TPB = 1024;
 // Step kernel variants, all walking 64-unit chunks per wavefront:
 //  MODE_STREAM   bitmap read through the caches; STREAM_TPB threads per workgroup;
 //  MODE_RESIDENT the whole bitmap (up to RESIDENT_BITS units) held in LDS;

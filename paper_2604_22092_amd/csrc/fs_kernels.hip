@@ -24,7 +24,10 @@ namespace fsk {
 // Sums per-workgroup count partials.  Block j handles slot j: rows of C
 // counters from G workgroups, part[j][g][c]; the totals go to
 // out[((base + j) mod H)][c] where base = ctl->step (0 without ctl).
-// Requires C <= WG and WG % C == 0 (C = 4R with R a power of two <= 64).
+// Requires C <= RED_TPB and RED_TPB % C == 0 (C = 4R with R a power of two
+// <= 64).  Each thread keeps eight independent sums of the rows it reads (so
+// eight loads are in flight), and the block's sums are folded by a tree in
+// LDS (integer sums: the order does not change them).
 // With a ctl, the r blocks of the launch end the launch sequence: each takes
 // a ticket in ctl->done once its reads of ctl->step are done, and the last
 // one adds r to ctl->step and clears the count (so the sequence needs no
@@ -32,23 +35,31 @@ namespace fsk {
 __device__ __forceinline__ void reduce_body(Ctl* ctl, const uint32_t* part, uint32_t G, uint32_t C,
                                             uint32_t* out, uint32_t H, uint32_t j, uint32_t r)
 {
-    __shared__ uint32_t s[WG];
+    __shared__ uint32_t s[RED_TPB];
     const uint32_t t = threadIdx.x;
     // of a sequence longer than the ring only the last H steps are kept, so
     // no two blocks write one slot
     if ((size_t)j + H >= (size_t)r) {
-        const uint32_t groups = WG / C;
+        const uint32_t groups = RED_TPB / C;
         const uint32_t c = t % C;
-        const uint32_t* p = part + (size_t)j * G * C;
-        uint32_t sum = 0;
-        for (uint32_t g = t / C; g < G; g += groups) sum += p[(size_t)g * C + c];
-        s[t] = sum;
+        const uint32_t* p = part + (size_t)j * G * C + c;
+        uint32_t acc[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+        uint32_t g = t / C;
+        for (; g + 7u * groups < G; g += 8u * groups) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) acc[i] += p[(size_t)(g + (uint32_t)i * groups) * C];
+        }
+        for (; g < G; g += groups) acc[0] += p[(size_t)g * C];
+        s[t] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
         __syncthreads();
+        // (w is a multiple of C, so s[t] and s[t + w] hold the same counter)
+        for (uint32_t w = RED_TPB / 2; w >= C; w >>= 1) {
+            if (t < w) s[t] += s[t + w];
+            __syncthreads();
+        }
         if (t < C) {
-            uint32_t tot = 0;
-            for (uint32_t i = 0; i < groups; ++i) tot += s[i * C + t];
             const unsigned long long base = ctl ? ctl->step : 0ull;
-            out[(size_t)((base + j) % H) * C + t] = tot;
+            out[(size_t)((base + j) % H) * C + t] = s[t];
         }
     }
     if (ctl) {
@@ -63,14 +74,14 @@ __device__ __forceinline__ void reduce_body(Ctl* ctl, const uint32_t* part, uint
     }
 }
 
-__global__ __launch_bounds__(WG) void reduce_kernel(Ctl* ctl, const uint32_t* part, uint32_t G,
+__global__ __launch_bounds__(RED_TPB) void reduce_kernel(Ctl* ctl, const uint32_t* part, uint32_t G,
                                                      uint32_t C, uint32_t* out, uint32_t H)
 {
     reduce_body(ctl, part, G, C, out, H, blockIdx.x, gridDim.x);
 }
 
 // Batched reduce: block (j, m) sums slot j of member m (grid r x members).
-__global__ __launch_bounds__(WG) void reduce_batch_kernel(const RedArgs* __restrict__ table)
+__global__ __launch_bounds__(RED_TPB) void reduce_batch_kernel(const RedArgs* __restrict__ table)
 {
     const RedArgs q = table[blockIdx.y];
     reduce_body(q.ctl, q.part, q.G, q.C, q.hist, q.H, blockIdx.x, gridDim.x);
@@ -391,7 +402,7 @@ hipError_t launch_recount(int storage, const void* state, int32_t n, int32_t lgR
         hipLaunchKernelGGL(recount_kernel<0>, dim3(g), dim3(WG), 0, s, state, n, lgR, replica, part);
     else
         hipLaunchKernelGGL(recount_kernel<1>, dim3(g), dim3(WG), 0, s, state, n, lgR, replica, part);
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(WG), 0, s, (Ctl*)nullptr, (const uint32_t*)part,
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(RED_TPB), 0, s, (Ctl*)nullptr, (const uint32_t*)part,
                        (uint32_t)g, 4u, out4, 1u);
     return hipGetLastError();
 }

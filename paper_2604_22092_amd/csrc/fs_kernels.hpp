@@ -50,7 +50,7 @@ hipError_t launch_recount(int storage, const void* state, int32_t n, int32_t lgR
 hipError_t launch_hub_recount(const int32_t* row_ptr, const int32_t* col_ind, int32_t hub_base, uint32_t hubs,
                               int32_t lgR, const uint32_t* bits, uint32_t* out, hipStream_t s);
 // reduce_kernel(Ctl*, const uint32_t* part, uint32_t G, uint32_t C, uint32_t* out, uint32_t H):
-// one block per slot, WG threads; with a ctl it also adds the slot count (its
+// one block per slot, RED_TPB threads; with a ctl it also adds the slot count (its
 // grid) to the step index, which ends a launch sequence.
 const void* reduce_kernel_fn();
 // Segment partials of degree-binned rows (HeavyArgs): heavy_pressure_kernel
@@ -69,7 +69,7 @@ const void* summary_kernel_fn();
 const void* step_batch_kernel_fn(int storage, bool weighted, bool extra);
 // heavy_batch_kernel(const HeavyArgs* table, const uint32_t* first, uint32_t members, uint32_t step_off), WG threads;
 const void* heavy_batch_kernel_fn(bool weighted);
-// reduce_batch_kernel(const RedArgs* table): grid (r, members), WG threads;
+// reduce_batch_kernel(const RedArgs* table): grid (r, members), RED_TPB threads;
 // advances every member's step index by r
 const void* reduce_batch_kernel_fn();
 hipError_t launch_put_replica(int storage, void* state, void* age, const int32_t* src_state, const void* src_age,

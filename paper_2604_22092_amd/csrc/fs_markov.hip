@@ -475,7 +475,7 @@ fs_status build_exec(fs_markov* m, uint32_t b)
         if ((st = add((const void*)&fsm::mk_rates_kernel, dim3(m->G), dim3(fsm::MTPB), argv)) != FS_OK) return st;
     }
     void* rargv[] = {&q.ctl, &q.part, &q.G, &q.C, &q.hist, &q.H};
-    if ((st = add(fsk::reduce_kernel_fn(), dim3(q.r), dim3(WG), rargv)) != FS_OK) return st;
+    if ((st = add(fsk::reduce_kernel_fn(), dim3(q.r), dim3(fsi::RED_TPB), rargv)) != FS_OK) return st;
     FS_HIP(hipGraphInstantiate(&m->exec, m->graph, nullptr, nullptr, 0));
     return FS_OK;
 }
@@ -492,7 +492,7 @@ fs_status launch_seq(fs_markov* m, uint32_t r)
         FS_HIP(hipLaunchKernel((const void*)&fsm::mk_rates_kernel, dim3(m->G), dim3(fsm::MTPB), argv, 0, m->stream));
     }
     void* rargv[] = {&q.ctl, &q.part, &q.G, &q.C, &q.hist, &q.H};
-    FS_HIP(hipLaunchKernel(fsk::reduce_kernel_fn(), dim3(r), dim3(WG), rargv, 0, m->stream));
+    FS_HIP(hipLaunchKernel(fsk::reduce_kernel_fn(), dim3(r), dim3(fsi::RED_TPB), rargv, 0, m->stream));
     return FS_OK;
 }
 

@@ -800,7 +800,7 @@ fs_status build_graph_exec(fs_sim* s, int b)
         }
     }
     void* rargv[] = {&q.ctl, &q.part, &q.G, &q.C, &q.hist, &q.H};
-    if ((st = add(fsk::reduce_kernel_fn(), dim3(q.r), dim3(WG), rargv)) != FS_OK) return st;
+    if ((st = add(fsk::reduce_kernel_fn(), dim3(q.r), dim3(fsi::RED_TPB), rargv)) != FS_OK) return st;
     FS_HIP(hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0));
     return FS_OK;
 }
@@ -831,7 +831,7 @@ fs_status launch_sequence(fs_sim* s, uint32_t r)
         }
     }
     void* rargv[] = {&q.ctl, &q.part, &q.G, &q.C, &q.hist, &q.H};
-    FS_HIP(hipLaunchKernel(fsk::reduce_kernel_fn(), dim3(r), dim3(WG), rargv, 0, s->stream));
+    FS_HIP(hipLaunchKernel(fsk::reduce_kernel_fn(), dim3(r), dim3(fsi::RED_TPB), rargv, 0, s->stream));
     return FS_OK;
 }
 
