@@ -81,6 +81,14 @@ struct ShedDev {
     float lf_hi, lf_lo;
 };
 
+// The laws of a sim in device memory (StepArgs::hz_dev, shed_dev): the step
+// reads them there, where a hazard or a shedding value is evaluated, so they
+// hold no registers through the walk.
+struct LawsDev {
+    HazardDev hz[2]; // [0] E -> I, [1] I -> R
+    ShedDev shed;
+};
+
 // Device-resident control block of a simulation.  `step` is the index of the
 // first step of the launch sequence being run: step launch j of a sequence
 // runs step (step + j), and the reduce launch that ends the sequence adds its
@@ -115,8 +123,7 @@ struct StepArgs {
     int32_t same_kind;    // E and I laws share a kind: one hazard call per lane
     int32_t pad0;
     HazardDev hz[2];      // [0] E -> I, [1] I -> R
-    // the same two laws in device memory: the step reads them from there,
-    // where a hazard is evaluated, so they hold no registers for the walk
+    // the same two laws in device memory (LawsDev::hz)
     const HazardDev* hz_dev;
     float beta;
     float dt;
@@ -181,7 +188,7 @@ struct StepArgs {
     // whose bit is set are ever read)
     void* shed0; // float32 (FP32 storage) or IEEE binary16 (compact) per unit
     void* shed1;
-    ShedDev shed;
+    const ShedDev* shed_dev; // the profile s, in device memory (LawsDev::shed)
     // active-chunk compaction (nullptr act: off): the launch walks the chunks
     // act[2 .. 2 + act[0]) (ascending); every other chunk holds only R units
     // and is skipped, and act[1] R units per replica are added to the counts

@@ -256,7 +256,7 @@ void release_sim(fs_sim* s)
                         (void*)s->d_hist, (void*)s->d_part, (void*)s->d_rc_part, (void*)s->d_cnt4,
                         (void*)s->d_summary, s->d_seg_part, (void*)s->d_lam_part, (void*)s->d_dt_hist,
                         (void*)s->d_shed[0], (void*)s->d_shed[1], (void*)s->d_live, (void*)s->d_act,
-                        (void*)s->d_htab, (void*)s->d_hz, (void*)s->d_hub})
+                        (void*)s->d_htab, (void*)s->d_laws, (void*)s->d_hub})
             sim_free(s, p);
     }
     s->layout.reset();
@@ -1466,19 +1466,24 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
     a.same_kind = hz[0].kind == hz[1].kind;
     a.hz[0] = hz[0];
     a.hz[1] = hz[1];
-    if ((e = sim_alloc(s, (void**)&s->d_hz, 2 * sizeof(fsi::HazardDev))) != hipSuccess ||
-        (e = hipMemcpyAsync(s->d_hz, a.hz, 2 * sizeof(fsi::HazardDev), hipMemcpyHostToDevice, s->stream)) !=
+    fsi::LawsDev laws{};
+    laws.hz[0] = hz[0];
+    laws.hz[1] = hz[1];
+    laws.shed = shed;
+    if ((e = sim_alloc(s, (void**)&s->d_laws, sizeof(fsi::LawsDev))) != hipSuccess ||
+        (e = hipMemcpyAsync(s->d_laws, &laws, sizeof(fsi::LawsDev), hipMemcpyHostToDevice, s->stream)) !=
             hipSuccess ||
         (e = hipStreamSynchronize(s->stream)) != hipSuccess)
         return bad(e, "hazard laws");
-    a.hz_dev = s->d_hz;
+    // (the laws sit at the start of the block)
+    a.hz_dev = (const fsi::HazardDev*)s->d_laws;
+    a.shed_dev = (const fsi::ShedDev*)((const char*)s->d_laws + offsetof(fsi::LawsDev, shed));
     a.beta = (float)p->beta;
     a.dt = (float)p->dt;
     a.key0 = (uint32_t)p->seed;
     a.key1 = (uint32_t)(p->seed >> 32);
     a.shed0 = s->d_shed[0];
     a.shed1 = s->d_shed[1];
-    a.shed = shed;
     a.act = s->d_act;
     a.live = s->d_live;
     if (!p->adaptive) {
@@ -1493,7 +1498,7 @@ fs_status fs_sim_create(fs_graph* g, const fs_sim_params* p, fs_sim** out)
         if ((e = sim_alloc(s, (void**)&s->d_htab, tab.size() * sizeof(float4))) != hipSuccess ||
             (e = hipMemcpyAsync(s->d_htab, tab.data(), tab.size() * sizeof(float4), hipMemcpyHostToDevice,
                                 s->stream)) != hipSuccess ||
-            (e = fsk::launch_hazard_table(s->d_hz, a.same_kind, s->d_htab, fsi::HTAB_LEN, s->stream)) != hipSuccess ||
+            (e = fsk::launch_hazard_table(a.hz_dev, a.same_kind, s->d_htab, fsi::HTAB_LEN, s->stream)) != hipSuccess ||
             (e = hipStreamSynchronize(s->stream)) != hipSuccess)
             return bad(e, "hazard table");
         a.htab = s->d_htab;

@@ -106,7 +106,7 @@ struct fs_sim {
     uint8_t* d_live = nullptr;     // compaction: live flag per chunk, zero-padded to LIVE_TILE
     uint32_t* d_act = nullptr;     // compaction: [2 + nchunks] active-chunk list
     float4* d_htab = nullptr;      // fixed steps: hazard table (StepArgs::htab)
-    fsi::HazardDev* d_hz = nullptr; // both laws (StepArgs::hz_dev)
+    fsi::LawsDev* d_laws = nullptr; // both laws and the shedding profile (StepArgs::hz_dev, shed_dev)
     uint32_t nchunks = 0;          // 64-unit chunks
     size_t live_bytes = 0;
     fsi::ShedDev shed{};

@@ -837,7 +837,7 @@ __device__ __forceinline__ void compact_apply(uint32_t* xch, uint32_t lane, cons
 template <int STORAGE, bool WEIGHTED, int MODE, int UD, bool SHED, bool EXTRA, int PB, class age_t>
 __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t>& P, uint32_t lane,
                                              const uint32_t* __restrict__ s_bits, rsrc_t gbits, rsrc_t shedr,
-                                             void* __restrict__ shed_out, const ShedPre& sv,
+                                             void* __restrict__ shed_out, const ShedPre& sv, const ShedDev& sdv,
                                              uint32_t* xch, unsigned long long k,
                                              unsigned long long* __restrict__ bits_out, uint32_t* s_cnt,
                                              uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, float dt,
@@ -1025,7 +1025,7 @@ __device__ __forceinline__ void process_pass(const StepArgs& a, const Pass<age_t
             res[u] = 0;
         }
         compact_apply<CU>(xch, lane, need, pay, res, [&](uint32_t w) {
-            return __float_as_uint(fsd::shed(a.shed, age_from_bits<age_t>(w)));
+            return __float_as_uint(fsd::shed(sdv, age_from_bits<age_t>(w)));
         });
 #pragma unroll
         for (int u = 0; u < CU; ++u)
@@ -1155,6 +1155,18 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
         tv.len = in_vgpr(a.htab ? (float)a.htab_len : 0.0f);
     }
     unsigned long long* __restrict__ bo = UNIFORM ? bits_out : in_vgpr(bits_out);
+    // the shedding profile (shedding kernels): read once, its parameters held
+    // in vector registers for the walk (its kinds stay scalar); in scalar
+    // registers they would be spilled and read back in every pass, and read
+    // from memory where used, their loads would wait for the next pass's
+    ShedDev sdv{};
+    if (SHED) {
+        sdv = *a.shed_dev;
+        float* f[] = {&sdv.hz.K, &sdv.hz.c_hi, &sdv.hz.c_lo, &sdv.hz.g_hi, &sdv.hz.g_lo, &sdv.hz.x_hi,
+                      &sdv.hz.x_lo, &sdv.s0, &sdv.m_hi, &sdv.m_lo, &sdv.lf_hi, &sdv.lf_lo};
+#pragma unroll
+        for (float* x : f) *x = in_vgpr(*x);
+    }
     issue_table<UNIFORM>(a, tv, P, lane);
 
     uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0; // per-wave counts (R == 1)
@@ -1174,7 +1186,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
             issue_pass<STORAGE, UD, EXTRA, PB>(a, first + stride, nwaves, stride, nchunks, walk, total, lane, P1,
                                                 ahead, H);
         process_pass<STORAGE, WEIGHTED, MODE, UD, SHED, EXTRA, PB>(a, P, lane, s_bits, gbits, shedr, shed_out, sv,
-                                                                    s_xch[wave], k, bo, s_cnt, c0, c1, c2,
+                                                                    sdv, s_xch[wave], k, bo, s_cnt, c0, c1, c2,
                                                                     c3, dt, lmax, H);
         first += stride;
         if (first >= walk) break;
@@ -1186,7 +1198,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, uint32_t block, uin
             issue_pass<STORAGE, UD, EXTRA, PB>(a, first + stride, nwaves, stride, nchunks, walk, total, lane, P,
                                                 ahead, H);
         process_pass<STORAGE, WEIGHTED, MODE, UD, SHED, EXTRA, PB>(a, P1, lane, s_bits, gbits, shedr, shed_out, sv,
-                                                                    s_xch[wave], k, bo, s_cnt, c0, c1, c2,
+                                                                    sdv, s_xch[wave], k, bo, s_cnt, c0, c1, c2,
                                                                     c3, dt, lmax, H);
         first += stride;
         if (!PREFETCH && first < walk)
