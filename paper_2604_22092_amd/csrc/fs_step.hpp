@@ -290,17 +290,16 @@ struct Pass {
     uint32_t ht[CU], hd[CU]; // pushed pressure of a binned unit: count of the last step, delta
 };
 
-// The first DEPTH columns of chunk u of a pass: unpacked from its words, or
+// The first D columns of chunk u of a pass: unpacked from its words, or
 // (PB = 0, or a chunk of a mixed layout deeper than UMAX, which keeps 32-bit
 // columns) copied.
-template <int PB, int UD, class age_t>
-__device__ __forceinline__ void pass_columns(const Pass<age_t>& P, int u, uint32_t (&col)[UD != 0 ? UD : UMAX])
+template <int PB, int UD, int D = (UD != 0 ? UD : UMAX), class age_t>
+__device__ __forceinline__ void pass_columns(const Pass<age_t>& P, int u, uint32_t (&col)[D])
 {
-    constexpr int DEPTH = UD != 0 ? UD : UMAX;
     if (PB && UD == 0 && P.ud[u] > (uint32_t)UMAX)
-        unpack_columns<0, DEPTH>(P.c[u], col);
+        unpack_columns<0, D>(P.c[u], col);
     else
-        unpack_columns<PB, DEPTH>(P.c[u], col);
+        unpack_columns<PB, D>(P.c[u], col);
 }
 
 // Pushed pressure of binned rows (StepArgs::hub_T) within one step launch:
@@ -515,10 +514,28 @@ __device__ __forceinline__ void issue_pass(const StepArgs& a, uint32_t first, ui
         constexpr int LW = UNIFORM ? (int)words_per_row<PB>((uint32_t)DEPTH) : DEPTH;
         const uint32_t rw = (PB && P.ud[u] <= (uint32_t)UMAX) ? words_per_row<PB>(P.ud[u]) : P.ud[u];
         const rsrc_t cr = make_rsrc(a.col_t + P.base[u], pre ? rw * rows * 4u : 0u);
+        if (UNIFORM) {
 #pragma unroll
-        for (int j = 0; j < LW; ++j) P.c[u][j] = (int32_t)ld32(cr, ((uint32_t)j * rows + q) << 2);
+            for (int j = 0; j < LW; ++j) P.c[u][j] = (int32_t)ld32(cr, ((uint32_t)j * rows + q) << 2);
 #pragma unroll
-        for (int j = LW; j < DEPTH; ++j) P.c[u][j] = 0;
+            for (int j = LW; j < DEPTH; ++j) P.c[u][j] = 0;
+        } else {
+            // (mixed layouts: the loads in groups of four, as far as the
+            // chunk's preloaded words reach; a wave-uniform choice)
+            const uint32_t nw = pre ? min(rw, (uint32_t)UMAX) : 0u;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) P.c[u][j] = (int32_t)ld32(cr, ((uint32_t)j * rows + q) << 2);
+#pragma unroll
+            for (int g = 4; g < UMAX; g += 4) {
+                if (nw > (uint32_t)g) {
+#pragma unroll
+                    for (int j = g; j < g + 4; ++j) P.c[u][j] = (int32_t)ld32(cr, ((uint32_t)j * rows + q) << 2);
+                } else {
+#pragma unroll
+                    for (int j = g; j < g + 4; ++j) P.c[u][j] = 0;
+                }
+            }
+        }
     }
 }
 
@@ -563,6 +580,95 @@ __device__ __forceinline__ void shed_pre(const StepArgs& a, const Pass<age_t>& P
     }
 }
 
+// The preloaded slots of a light row (the first D of a uniform chunk's
+// columns, col[]): their count of infectious sources (unit weights) or
+// weighted sum.  In a mixed layout D is the smallest bucket that holds the
+// chunk's degree, and slots past the degree read nothing.
+template <int MODE, bool WEIGHTED, bool UNIFORM, int D, class age_t>
+__device__ __forceinline__ void preloaded_slots(const StepArgs& a, const Pass<age_t>& P, int u, bool want,
+                                                const uint32_t (&col)[D], const uint32_t* __restrict__ lds,
+                                                rsrc_t gbits, rsrc_t wr, uint32_t rows, uint32_t q, uint32_t rep,
+                                                int32_t lgR, uint32_t& pi, float& pw)
+{
+    // every slot's LDS word is read before any is used (one wait for
+    // all); the global bitmap words, in the variants that need them,
+    // are loaded only where the slot is used (and, with the summary,
+    // its group holds an infectious unit), and not at all when no
+    // lane of the wavefront needs one: a load consumed here would
+    // also wait for the next pass's prefetched loads
+    uint32_t src[D], bit[D];
+    bool use[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        use[j] = (uint32_t)j < P.ud[u] && want;
+        src[j] = (col[j] << lgR) + rep;
+    }
+    if (MODE == MODE_RESIDENT && !WEIGHTED) {
+        // unit weights: the count of set bits, masked once (slots past
+        // a mixed chunk's degree read nothing and hold 0; the bit
+        // extract uses the low five bits of its offset)
+        uint32_t wv[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) wv[j] = (UNIFORM || (uint32_t)j < P.ud[u]) ? lds[src[j] >> 5] : 0u;
+        uint32_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) sum += __builtin_amdgcn_ubfe(wv[j], src[j], 1);
+        if (UNIFORM) {
+            // the slots of a uniform chunk past its degree loaded no
+            // column (out of range: 0), so they counted unit `rep`
+            // (node 0 of this replica): take those counts back
+            sum -= ((uint32_t)D - P.ud[u]) * __builtin_amdgcn_ubfe(lds[rep >> 5], rep, 1);
+        }
+#pragma unroll
+        for (int j = 0; j < D; ++j) bit[j] = 0u;
+        pi += want ? sum : 0u;
+    } else if (MODE == MODE_RESIDENT) {
+        uint32_t wv[D];
+        // (a mixed layout's chunk reads only its degree's slots: a
+        // wave-uniform test)
+#pragma unroll
+        for (int j = 0; j < D; ++j) wv[j] = (UNIFORM || (uint32_t)j < P.ud[u]) ? lds[src[j] >> 5] : 0u;
+#pragma unroll
+        for (int j = 0; j < D; ++j) bit[j] = __builtin_amdgcn_ubfe(wv[j], src[j] & 31u, 1) & (uint32_t)use[j];
+    } else {
+        bool go[D];
+        if (MODE == MODE_SUMMARY) {
+            uint32_t sw[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+                sw[j] = (UNIFORM || (uint32_t)j < P.ud[u]) ? lds[src[j] >> (a.sum_shift + 10)] : 0u;
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+                go[j] = use[j] & (__builtin_amdgcn_ubfe(sw[j], src[j] >> (a.sum_shift + 5), 1) != 0u);
+        } else {
+#pragma unroll
+            for (int j = 0; j < D; ++j) go[j] = use[j];
+        }
+        bool anyg = false;
+#pragma unroll
+        for (int j = 0; j < D; ++j) anyg = anyg | go[j];
+#pragma unroll
+        for (int j = 0; j < D; ++j) bit[j] = 0u;
+        if (__ballot(anyg) != 0ull) {
+            uint32_t w[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) w[j] = ld32(gbits, go[j] ? (src[j] >> 5) << 2 : OOB);
+            // (slots not loaded read 0)
+#pragma unroll
+            for (int j = 0; j < D; ++j) bit[j] = __builtin_amdgcn_ubfe(w[j], src[j], 1);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        if (WEIGHTED) {
+            const float w = __uint_as_float(ld32(wr, use[j] ? ((uint32_t)j * rows + q) << 2 : OOB));
+            pw = __builtin_fmaf(w, (float)bit[j], pw);
+        } else {
+            pi += bit[j];
+        }
+    }
+}
+
 // Pressure of one chunk's light row for this lane (Eq. (influence) without
 // beta).  Uniform chunks use the preloaded slots (and load any further ones
 // in batches of JT, each batch's loads issued together); mixed chunks find a row's
@@ -592,87 +698,33 @@ __device__ __forceinline__ float pressure_row(const StepArgs& a, const Pass<age_
         const uint32_t q = lane >> lgR;
         const rsrc_t wr = make_rsrc(WEIGHTED ? (const void*)(a.w_t + P.base[u]) : (const void*)a.w_t,
                                     WEIGHTED ? P.ud[u] * rows * 4u : 0u);
-        uint32_t col[DEPTH];
-        pass_columns<PB, UD>(P, u, col);
         if (!SHED) {
-            // every slot's LDS word is read before any is used (one wait for
-            // all); the global bitmap words, in the variants that need them,
-            // are loaded only where the slot is used (and, with the summary,
-            // its group holds an infectious unit), and not at all when no
-            // lane of the wavefront needs one: a load consumed here would
-            // also wait for the next pass's prefetched loads
-            uint32_t src[DEPTH], bit[DEPTH];
-            bool use[DEPTH];
-#pragma unroll
-            for (int j = 0; j < DEPTH; ++j) {
-                use[j] = (uint32_t)j < P.ud[u] && want;
-                src[j] = (col[j] << lgR) + rep;
-            }
-            if (MODE == MODE_RESIDENT && !WEIGHTED) {
-                // unit weights: the count of set bits, masked once (slots past
-                // a mixed chunk's degree read nothing and hold 0; the bit
-                // extract uses the low five bits of its offset)
-                uint32_t wv[DEPTH];
-#pragma unroll
-                for (int j = 0; j < DEPTH; ++j) wv[j] = (UNIFORM || (uint32_t)j < P.ud[u]) ? lds[src[j] >> 5] : 0u;
-                uint32_t sum = 0;
-#pragma unroll
-                for (int j = 0; j < DEPTH; ++j) sum += __builtin_amdgcn_ubfe(wv[j], src[j], 1);
-                if (UNIFORM) {
-                    // the slots of a uniform chunk past its degree loaded no
-                    // column (out of range: 0), so they counted unit `rep`
-                    // (node 0 of this replica): take those counts back
-                    sum -= ((uint32_t)DEPTH - P.ud[u]) * __builtin_amdgcn_ubfe(lds[rep >> 5], rep, 1);
-                }
-#pragma unroll
-                for (int j = 0; j < DEPTH; ++j) bit[j] = 0u;
-                pi += want ? sum : 0u;
-            } else if (MODE == MODE_RESIDENT) {
-                uint32_t wv[DEPTH];
-                // (a mixed layout's chunk reads only its degree's slots: a
-                // wave-uniform test)
-#pragma unroll
-                for (int j = 0; j < DEPTH; ++j) wv[j] = (UNIFORM || (uint32_t)j < P.ud[u]) ? lds[src[j] >> 5] : 0u;
-#pragma unroll
-                for (int j = 0; j < DEPTH; ++j) bit[j] = __builtin_amdgcn_ubfe(wv[j], src[j] & 31u, 1) & (uint32_t)use[j];
+            if (UNIFORM) {
+                uint32_t col[DEPTH];
+                pass_columns<PB, UD, DEPTH>(P, u, col);
+                preloaded_slots<MODE, WEIGHTED, UNIFORM, DEPTH>(a, P, u, want, col, lds, gbits, wr, rows, q, rep, lgR,
+                                                                pi, pw);
+            } else if (P.ud[u] <= 6u) {
+                // (mixed layouts: the preloaded slots a chunk of this degree
+                // uses, a wave-uniform choice)
+                uint32_t col[6];
+                pass_columns<PB, UD, 6>(P, u, col);
+                preloaded_slots<MODE, WEIGHTED, UNIFORM, 6>(a, P, u, want, col, lds, gbits, wr, rows, q, rep, lgR, pi,
+                                                            pw);
+            } else if (P.ud[u] <= 9u) {
+                uint32_t col[9];
+                pass_columns<PB, UD, 9>(P, u, col);
+                preloaded_slots<MODE, WEIGHTED, UNIFORM, 9>(a, P, u, want, col, lds, gbits, wr, rows, q, rep, lgR, pi,
+                                                            pw);
             } else {
-                bool go[DEPTH];
-                if (MODE == MODE_SUMMARY) {
-                    uint32_t sw[DEPTH];
-#pragma unroll
-                    for (int j = 0; j < DEPTH; ++j)
-                        sw[j] = (UNIFORM || (uint32_t)j < P.ud[u]) ? lds[src[j] >> (a.sum_shift + 10)] : 0u;
-#pragma unroll
-                    for (int j = 0; j < DEPTH; ++j)
-                        go[j] = use[j] & (__builtin_amdgcn_ubfe(sw[j], src[j] >> (a.sum_shift + 5), 1) != 0u);
-                } else {
-#pragma unroll
-                    for (int j = 0; j < DEPTH; ++j) go[j] = use[j];
-                }
-                bool anyg = false;
-#pragma unroll
-                for (int j = 0; j < DEPTH; ++j) anyg = anyg | go[j];
-#pragma unroll
-                for (int j = 0; j < DEPTH; ++j) bit[j] = 0u;
-                if (__ballot(anyg) != 0ull) {
-                    uint32_t w[DEPTH];
-#pragma unroll
-                    for (int j = 0; j < DEPTH; ++j) w[j] = ld32(gbits, go[j] ? (src[j] >> 5) << 2 : OOB);
-                    // (slots not loaded read 0)
-#pragma unroll
-                    for (int j = 0; j < DEPTH; ++j) bit[j] = __builtin_amdgcn_ubfe(w[j], src[j], 1);
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < DEPTH; ++j) {
-                if (WEIGHTED) {
-                    const float w = __uint_as_float(ld32(wr, use[j] ? ((uint32_t)j * rows + q) << 2 : OOB));
-                    pw = __builtin_fmaf(w, (float)bit[j], pw);
-                } else {
-                    pi += bit[j];
-                }
+                uint32_t col[DEPTH];
+                pass_columns<PB, UD, DEPTH>(P, u, col);
+                preloaded_slots<MODE, WEIGHTED, UNIFORM, DEPTH>(a, P, u, want, col, lds, gbits, wr, rows, q, rep, lgR,
+                                                                pi, pw);
             }
         } else {
+            uint32_t col[DEPTH];
+            pass_columns<PB, UD, DEPTH>(P, u, col);
 #pragma unroll
             for (int j = 0; j < DEPTH; ++j) {
                 const bool use = (uint32_t)j < P.ud[u] && want;
