@@ -373,6 +373,7 @@ const void* step_kernel_fn(int storage, bool weighted, int mode, int udeg, bool 
         return nullptr;
     }
     if (!shed && !extra && lgR == 0) return step_kernel_fn_r1(storage, weighted, mode, udeg);
+    if (!shed && !extra && !weighted && lgR == 4) return step_kernel_fn_r16(storage, mode, udeg);
     if (shed) return extra ? step_kernel_fn_shed_extra(storage, weighted, mode, udeg)
                            : step_kernel_fn_shed(storage, weighted, mode, udeg);
     if (extra) return step_kernel_fn_extra(storage, weighted, mode, udeg);

@@ -25,6 +25,7 @@ namespace fsk {
 const void* step_kernel_fn(int storage, bool weighted, int mode, int udeg, bool shed, bool extra, int lgR,
                            int pbits);
 const void* step_kernel_fn_r1(int storage, bool weighted, int mode, int udeg);
+const void* step_kernel_fn_r16(int storage, int mode, int udeg);
 const void* step_kernel_fn_r1p20(int storage, int mode, int udeg);
 const void* step_kernel_fn_r1p24(int storage, int mode, int udeg);
 const void* step_kernel_fn_r1p27(int storage, int mode, int udeg);

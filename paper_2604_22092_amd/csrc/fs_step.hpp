@@ -1374,6 +1374,35 @@ const void* step_kernel_r1_depth(int mode, int udeg)
     return step_kernel_r1_sel<S, W, 12>(mode);
 }
 
+// Plain step kernels of unit-weight sims with 16 replicas (the scenario
+// server's replica count): the replica shift is a compile-time constant, which
+// frees the scalar registers that the general kernel's walk spills.
+template <int STORAGE, int MODE, int UD, int TPB>
+__global__ __launch_bounds__(TPB) void step_kernel_r16(StepArgs a)
+{
+    StepArgs b = a;
+    b.lgR = 4;
+    step_body<STORAGE, false, MODE, UD, false, false, TPB>(b, blockIdx.x, gridDim.x);
+}
+
+template <int S, int U>
+const void* step_kernel_r16_sel(int mode)
+{
+    if (mode == MODE_RESIDENT) return (const void*)&step_kernel_r16<S, MODE_RESIDENT, U, RESIDENT_TPB>;
+    if (mode == MODE_SUMMARY) return (const void*)&step_kernel_r16<S, MODE_SUMMARY, U, RESIDENT_TPB>;
+    return (const void*)&step_kernel_r16<S, MODE_STREAM, U, STREAM_TPB>;
+}
+
+// udeg: the uniform layout's degree, or -1 for a mixed layout
+template <int S>
+const void* step_kernel_r16_depth(int mode, int udeg)
+{
+    if (udeg < 0) return step_kernel_r16_sel<S, 0>(mode);
+    if (udeg <= 8) return step_kernel_r16_sel<S, 8>(mode);
+    if (udeg <= 10) return step_kernel_r16_sel<S, 10>(mode);
+    return step_kernel_r16_sel<S, 12>(mode);
+}
+
 // Address of the step kernel of one configuration (each (SHED, EXTRA)
 // combination is instantiated by a kernel source of its own).
 template <bool SHED, bool EXTRA, int S, bool W, int U>
