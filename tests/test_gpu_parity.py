@@ -352,6 +352,28 @@ def test_checkpoint_resume_is_bit_exact(small_graph):
     assert resumed[2] == final[2] == 200
 
 
+@pytest.mark.parametrize("compact", [False, True], ids=["fp32", "compact"])
+@pytest.mark.parametrize("variant", list(VARIANTS))
+def test_sixteen_replicas_on_a_degree_sorted_graph(variant, compact):
+    # 16 replicas of a unit-weight graph run the instantiations that know the
+    # replica count; on a BA graph (degree-sorted, mixed layout with binned
+    # rows) every variant must still give each replica the oracle's trajectory
+    n = 3000
+    rp, ci = W.barabasi_albert(n, 3, 17)
+    model = {"ei": W.LN_E, "ir": W.LN_I, "beta": 0.12, "dt": 0.1, "seed": 23}
+    seeds = W.seed_nodes(n, 20, 4)
+    steps = 120
+    with fs.Graph(rp, ci) as g:
+        res = run_gpu(g, model, seeds, steps, n, compact, b=30, replicas=16, variant=VARIANTS[variant])
+    for r in [0, 7, 15]:
+        ost, oage, ohist = oracle.run((rp, ci), model, W.initial_state(n, seeds), zero_age(n, compact), steps,
+                                      replica=r, compact=compact)
+        np.testing.assert_array_equal(res[r][2], ohist, err_msg=f"replica {r}")
+        np.testing.assert_array_equal(res[r][0], ost)
+        np.testing.assert_array_equal(res[r][1], oage)
+    assert ohist[-1][0] < n - 100  # the epidemic spread
+
+
 @pytest.mark.parametrize("variant", list(VARIANTS))
 @pytest.mark.parametrize("replicas", [4, 16, 64])
 def test_replicas_match_oracle_per_replica(replicas, variant):
