@@ -339,7 +339,12 @@ __device__ __forceinline__ void flush_pushes(const StepArgs& a, HubCtx& H, uint3
         const uint32_t e = has ? H.q[i0 + lane] : 0u;
         const uint32_t node = (e & 0x7FFFFFFFu) >> a.lgR;
         const uint32_t b = has ? (uint32_t)optr[node] : 0u;
-        const uint32_t len = has ? (uint32_t)optr[node + 1] - b : 0u;
+        const uint32_t len0 = has ? (uint32_t)optr[node + 1] - b : 0u;
+        // a list of more than 64 entries (a hub's own, which can run to
+        // thousands) goes by itself below; the others are flattened over the
+        // wavefront
+        const bool lng = len0 > 64u;
+        const uint32_t len = lng ? 0u : len0;
         // inclusive prefix sum of the list lengths over the wavefront
         uint32_t inc = len;
 #pragma unroll
@@ -370,6 +375,27 @@ __device__ __forceinline__ void flush_pushes(const StepArgs& a, HubCtx& H, uint3
                 __hip_atomic_fetch_add(hub + H.d_next + (row << a.lgR) + rep,
                                        (eo & 0x80000000u) ? 0xFFFFFFFFu : 1u, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        // the long lists, one at a time: rounds of LU x 64 entries whose
+        // (coalesced) list loads are all issued before their pushes
+        constexpr uint32_t LU = 4;
+        for (unsigned long long lm = __ballot(lng); lm != 0ull; lm &= lm - 1ull) {
+            const int l = __builtin_ctzll(lm);
+            const uint32_t lb = (uint32_t)__shfl((int)b, l, 64), ll = (uint32_t)__shfl((int)len0, l, 64);
+            const uint32_t le = (uint32_t)__shfl((int)e, l, 64);
+            const uint32_t slot = H.d_next + ((le & 0x7FFFFFFFu) & ((1u << a.lgR) - 1u));
+            const uint32_t v = (le & 0x80000000u) ? 0xFFFFFFFFu : 1u;
+            const rsrc_t lr = make_rsrc(oidx + lb, ll * 4u);
+            for (uint32_t o = 0; o < ll; o += 64u * LU) {
+                uint32_t row[LU];
+#pragma unroll
+                for (uint32_t k = 0; k < LU; ++k) row[k] = ld32(lr, (o + k * 64u + lane) << 2); // (past the list: 0)
+#pragma unroll
+                for (uint32_t k = 0; k < LU; ++k)
+                    if (o + k * 64u + lane < ll)
+                        __hip_atomic_fetch_add(hub + slot + (row[k] << a.lgR), v, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
