@@ -379,7 +379,7 @@ __device__ __forceinline__ void flush_pushes(const StepArgs& a, HubCtx& H, uint3
         }
         // the long lists, one at a time: rounds of LU x 64 entries whose
         // (coalesced) list loads are all issued before their pushes
-        constexpr uint32_t LU = 4;
+        constexpr uint32_t LU = 8;
         for (unsigned long long lm = __ballot(lng); lm != 0ull; lm &= lm - 1ull) {
             const int l = __builtin_ctzll(lm);
             const uint32_t lb = (uint32_t)__shfl((int)b, l, 64), ll = (uint32_t)__shfl((int)len0, l, 64);
