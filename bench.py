@@ -156,9 +156,9 @@ def load_graph(spec, cache_dir=None):
     np.save(base + "_ci.npy", ci)
     return rp, ci
 
-    """Cores this process may use, capped at 16 (the host CPU share of one GPU on a shared node)."""
+
 def host_cores() -> int:
-    """Cores this process may use, capped at 16 (a one-GPU machine's CPU share)."""
+    """Cores this process may use, capped at 16 (the host CPU share of one GPU on a shared node)."""
     try:
         c = len(os.sched_getaffinity(0))
     except AttributeError:
