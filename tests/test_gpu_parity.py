@@ -254,6 +254,37 @@ def test_all_variants_identical_weighted_hubs():
     assert runs["stream"][2][-1, 1:].sum() > 300   # the epidemic grew from its 30 seeds
 
 
+@pytest.mark.parametrize("variant", list(VARIANTS))
+def test_long_push_list_of_a_hub(variant):
+    """A center joined to 1200 sub-hubs of 20 leaves each: with bins (12, 512)
+    the center and the sub-hubs are binned rows, and the center's own push
+    list (the 1200 sub-hubs) is longer than 64 entries, so its changes of
+    state are pushed in rounds of coalesced list loads (three rounds of 512).
+    The trajectory, seeded at the center, matches the oracle."""
+    hubs, leaves = 1200, 20
+    n = 1 + hubs + hubs * leaves
+    sub = np.arange(1, hubs + 1)
+    src = np.concatenate([np.zeros(hubs, np.int64), np.repeat(sub, leaves)])
+    dst = np.concatenate([sub, np.arange(hubs + 1, n)])
+    rp, ci = W.csr_from_edges(n, src, dst)
+    model = {"ei": W.LN_E, "ir": W.LN_I, "beta": 0.3, "dt": 0.1, "seed": 9}
+    seeds = np.array([0], np.int64)
+    steps = 200
+    with fs.Graph(rp, ci) as g:
+        sim = fs.Sim.from_model(g, model, steps_per_graph=25, variant=VARIANTS[variant], heavy_degree=12,
+                                segment_edges=512)
+        sim.seed(seeds, replica=-1, compartment=fs.FS_E)
+        sim.step(steps)
+        gst, gage = sim.get_state(0)[:2]
+        ghist = sim.history(0, steps, 0)
+        sim.close()
+    ost, oage, ohist = oracle.run((rp, ci), model, W.initial_state(n, seeds), zero_age(n, False), steps)
+    np.testing.assert_array_equal(ghist, ohist)
+    np.testing.assert_array_equal(gst, ost)
+    np.testing.assert_array_equal(gage, oage)
+    assert ost[0] == fs.FS_R and ohist[-1][3] > hubs  # the center recovered after infecting sub-hubs
+
+
 def test_summary_variant_with_coarse_groups():
     """N*R just above 2^26 units makes each summary bit cover 128 units (two
     bitmap words).  Contacts form a random 8-regular graph on 200k nodes spread
